@@ -1,0 +1,368 @@
+"""Seeded synthetic workloads shared by the kernels' tests, the oracle's tests and the benchmark.
+
+This module only builds inputs: mesh incidence, renumberings, face velocities, cell fields and
+time steps.  It holds none of the flux-limiter arithmetic (no face selection, gradient ratio,
+limiter, flux or divergence); both the HIP library and the CPU oracle receive the arrays built
+here and nothing else from it.
+
+Mesh model (Section 2 of the paper): a mesh is given by its oriented face-to-cell incidence.
+Every face f joins the two cells ``face_cells[f] = (own, nbr)`` and carries a unit normal
+``face_normal[f]`` that points from ``own`` into ``nbr``; the oriented incidence is then
+``E[f, nbr] = +1`` and ``E[f, own] = -1`` (the difference ``E theta`` is taken along the normal).
+All meshes built here are periodic, so every face has two cells.
+
+Workload recipes (sizes and distributions of the paper's advection study, Section 4):
+
+* 1-D periodic line of N uniform cells: square wave on [0.2, 0.4] plus a Gaussian of width
+  0.05 at x = 0.7, unit velocity, Euler step at CFL 0.5.
+* 3-D periodic hexahedral box n^3 in natural or seeded random cell/face numbering with random
+  face orientation flips: a solenoidal face velocity from the discrete curl of a seeded random
+  edge potential built from Fourier modes with max-norm wavenumber <= 4, and a Gaussian blob at
+  the paper's sphere centre (0.35, 0.35, 0.35) plus a sharp tanh step in x.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+SEED_VELOCITY = 0
+SEED_RENUMBER = 1
+SEED_TARGET = 2
+SEED_BATCH = 3
+
+
+@dataclasses.dataclass
+class MeshArrays:
+    """Plain arrays describing a mesh by its face-to-cell incidence."""
+
+    face_cells: np.ndarray  # int32 [F, 2] (own, nbr)
+    face_normal: np.ndarray  # float64 [F, 3], unit, own -> nbr
+    face_area: np.ndarray  # float64 [F]
+    cell_volume: np.ndarray  # float64 [C]
+    n: int = 0  # cells per side of the box it was built from
+    dim: int = 0
+    # Maps from the natural (lexicographic) numbering to this numbering; identity if None.
+    cell_new_of_old: Optional[np.ndarray] = None  # int64 [C]
+    face_new_of_old: Optional[np.ndarray] = None  # int64 [F]
+    face_flip_old: Optional[np.ndarray] = None  # bool [F], indexed by old face
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_volume.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.face_cells.shape[0])
+
+    def cell_field_from_natural(self, x: np.ndarray) -> np.ndarray:
+        """Re-index a cell field given in natural numbering (axis 0) into this mesh's numbering."""
+        if self.cell_new_of_old is None:
+            return np.ascontiguousarray(x)
+        out = np.empty_like(x)
+        out[self.cell_new_of_old] = x
+        return out
+
+    def cell_field_to_natural(self, x: np.ndarray) -> np.ndarray:
+        if self.cell_new_of_old is None:
+            return np.ascontiguousarray(x)
+        return np.ascontiguousarray(x[self.cell_new_of_old])
+
+    def face_velocity_from_natural(self, u: np.ndarray) -> np.ndarray:
+        """Re-index a normal face velocity from natural numbering; flipped faces change sign."""
+        if self.face_new_of_old is None:
+            return np.ascontiguousarray(u)
+        v = np.where(self.face_flip_old, -u, u) if self.face_flip_old is not None else u
+        out = np.empty_like(v)
+        out[self.face_new_of_old] = v
+        return out
+
+
+def periodic_box(n: int, dim: int = 3) -> MeshArrays:
+    """Periodic box [0,1)^dim with n cells per side in natural numbering.
+
+    Cell (i0, i1, i2) has index i0 + n*i1 + n*n*i2.  Faces come in ``dim`` blocks of C faces:
+    face ``a*C + c`` joins cell c (own) to its +e_a neighbour (nbr, wrapped), normal +e_a.
+    """
+    if dim not in (1, 2, 3):
+        raise ValueError("dim must be 1, 2 or 3")
+    if n < 1:
+        raise ValueError("n must be positive")
+    C = n**dim
+    c = np.arange(C, dtype=np.int64)
+    idx = [(c // n**a) % n for a in range(dim)]
+    own = np.empty(dim * C, dtype=np.int32)
+    nbr = np.empty(dim * C, dtype=np.int32)
+    nrm = np.zeros((dim * C, 3), dtype=np.float64)
+    for a in range(dim):
+        sl = slice(a * C, (a + 1) * C)
+        own[sl] = c
+        nbr[sl] = c - idx[a] * n**a + ((idx[a] + 1) % n) * n**a
+        nrm[sl, a] = 1.0
+    h = 1.0 / n
+    face_cells = np.stack([own, nbr], axis=1)
+    area = np.full(dim * C, h ** (dim - 1), dtype=np.float64)
+    vol = np.full(C, h**dim, dtype=np.float64)
+    return MeshArrays(face_cells, nrm, area, vol, n=n, dim=dim)
+
+
+def renumber(mesh: MeshArrays, seed: int = SEED_RENUMBER, flip: bool = True) -> MeshArrays:
+    """Randomly renumber cells and faces (and flip each face's orientation with probability 1/2).
+
+    The result describes the same mesh; fields move with ``cell_field_from_natural`` and
+    ``face_velocity_from_natural``.
+    """
+    rng = np.random.default_rng(seed)
+    C, F = mesh.n_cells, mesh.n_faces
+    cnew = rng.permutation(C).astype(np.int64)
+    fnew = rng.permutation(F).astype(np.int64)
+    flips = (rng.random(F) < 0.5) if flip else np.zeros(F, dtype=bool)
+    own = cnew[mesh.face_cells[:, 0]]
+    nbr = cnew[mesh.face_cells[:, 1]]
+    own2 = np.where(flips, nbr, own)
+    nbr2 = np.where(flips, own, nbr)
+    fc = np.empty((F, 2), dtype=np.int32)
+    fc[fnew, 0] = own2
+    fc[fnew, 1] = nbr2
+    nrm = np.empty_like(mesh.face_normal)
+    nrm[fnew] = np.where(flips[:, None], -mesh.face_normal, mesh.face_normal)
+    area = np.empty_like(mesh.face_area)
+    area[fnew] = mesh.face_area
+    vol = np.empty_like(mesh.cell_volume)
+    vol[cnew] = mesh.cell_volume
+    return MeshArrays(fc, nrm, area, vol, n=mesh.n, dim=mesh.dim,
+                      cell_new_of_old=cnew, face_new_of_old=fnew, face_flip_old=flips)
+
+
+# ---------------------------------------------------------------------------------------------
+# Velocities
+# ---------------------------------------------------------------------------------------------
+
+def velocity_uniform(mesh: MeshArrays, direction=(1.0, 0.0, 0.0), speed: float = 1.0) -> np.ndarray:
+    """Normal face velocity u_f = speed * (direction . n_f) of a constant vector field."""
+    d = np.asarray(direction, dtype=np.float64)
+    return speed * (mesh.face_normal @ d)
+
+
+def _edge_potential(n: int, seed: int, kmax: int) -> list:
+    """Seeded random edge potential A_d sampled at the midpoints of the d-directed edges.
+
+    A_d(x) = sum over integer wavevectors k with 1 <= |k|_inf <= kmax of Re(a_{d,k} e^{2 pi i k.x}),
+    a_{d,k} complex standard normal.  Edge (d, v) runs from vertex v*h to v*h + h*e_d; its
+    midpoint carries the half-cell phase shift along d.
+    """
+    rng = np.random.default_rng(seed)
+    K = 2 * kmax + 1
+    ks = np.arange(-kmax, kmax + 1)
+    out = []
+    for d in range(3):
+        coef = rng.standard_normal((K, K, K)) + 1j * rng.standard_normal((K, K, K))
+        coef[kmax, kmax, kmax] = 0.0
+        kd = [ks, ks, ks][d]
+        shape = [1, 1, 1]
+        shape[d] = K
+        coef = coef * np.exp(1j * math.pi * kd / n).reshape(shape)  # midpoint shift along d
+        spec = np.zeros((n, n, n), dtype=np.complex128)
+        ii = np.mod(ks, n)
+        np.add.at(spec, np.ix_(ii, ii, ii), coef)
+        field = np.fft.ifftn(spec) * float(n**3)
+        out.append(np.ascontiguousarray(field.real))  # indexed [i0, i1, i2]
+        del spec, field
+    return out
+
+
+def velocity_curl(n: int, seed: int = SEED_VELOCITY, kmax: int = 4) -> np.ndarray:
+    """Solenoidal normal face velocity of ``periodic_box(n, 3)`` (natural face numbering).
+
+    u_f is the circulation of the edge potential around face f divided by the face area: the
+    discrete curl, so the discrete divergence of u vanishes (exact sequence, Section 2).  The
+    potential is scaled so max|u_f| is about 1 and rounded to multiples of 2^-40 so that every
+    circulation, and every cell's flux balance, is computed without rounding.
+    """
+    if n < 3:
+        raise ValueError("n must be >= 3")
+    A = _edge_potential(n, seed, kmax)
+
+    def circulation(A):
+        circ = []
+        for a in range(3):
+            b, c = (a + 1) % 3, (a + 2) % 3
+            # face (a, cell i) sits at vertex v = i + e_a; edges b at v, c at v+e_b, b at v+e_c, c at v
+            v = lambda arr, sh: np.roll(arr, shift=[-s for s in sh], axis=(0, 1, 2))
+            ea = [0, 0, 0]; ea[a] = 1
+            eab = list(ea); eab[b] += 1
+            eac = list(ea); eac[c] += 1
+            s = v(A[b], ea) + v(A[c], eab) - v(A[b], eac) - v(A[c], ea)
+            circ.append(s)
+        return circ
+
+    circ = circulation(A)
+    umax = max(float(np.abs(cc).max()) for cc in circ) * n
+    q = 2.0**-40
+    A = [np.round(a / umax / q) * q for a in A]
+    circ = circulation(A)
+    # natural face numbering: face a*C + c with c = i0 + n*i1 + n^2*i2 -> Fortran order of [i0,i1,i2]
+    u = np.concatenate([(cc * n).ravel(order="F") for cc in circ])
+    return u
+
+
+def velocity_1d(mesh: MeshArrays, speed: float = 1.0) -> np.ndarray:
+    return velocity_uniform(mesh, (1.0, 0.0, 0.0), speed)
+
+
+# ---------------------------------------------------------------------------------------------
+# Fields
+# ---------------------------------------------------------------------------------------------
+
+def cell_centres(n: int, dim: int) -> np.ndarray:
+    """Cell centres [C, dim] of periodic_box(n, dim) in natural numbering."""
+    C = n**dim
+    c = np.arange(C, dtype=np.int64)
+    return np.stack([((c // n**a) % n + 0.5) / n for a in range(dim)], axis=1)
+
+
+def field_square_gauss_1d(n: int) -> np.ndarray:
+    """Square wave on [0.2, 0.4] plus a Gaussian (sigma 0.05) centred at 0.7."""
+    x = cell_centres(n, 1)[:, 0]
+    sq = ((x >= 0.2) & (x <= 0.4)).astype(np.float64)
+    return sq + np.exp(-((x - 0.7) ** 2) / (2 * 0.05**2))
+
+
+def field_blob_step(n: int, centre=(0.35, 0.35, 0.35), sigma: float = 0.08, width: float = 0.01,
+                    step_at: float = 0.5) -> np.ndarray:
+    """Periodic Gaussian blob plus a tanh step in x (natural numbering of periodic_box(n, 3))."""
+    x = cell_centres(n, 3)
+    d = np.abs(x - np.asarray(centre)[None, :])
+    d = np.minimum(d, 1.0 - d)
+    r2 = (d * d).sum(axis=1)
+    return np.exp(-r2 / (2 * sigma**2)) + 0.5 * (1.0 + np.tanh((x[:, 0] - step_at) / width))
+
+
+def field_sphere(n: int, centre=(0.35, 0.35, 0.35), radius: float = 0.15) -> np.ndarray:
+    """Indicator of the sphere used by the paper's deformation benchmark (Section 4.1)."""
+    x = cell_centres(n, 3)
+    r2 = ((x - np.asarray(centre)[None, :]) ** 2).sum(axis=1)
+    return (r2 <= radius * radius).astype(np.float64)
+
+
+def field_smooth_random(n: int, dim: int, seed: int, kmax: int = 3) -> np.ndarray:
+    """Seeded smooth periodic field: a few low Fourier modes, O(1) amplitude."""
+    rng = np.random.default_rng(seed)
+    x = cell_centres(n, dim)
+    out = np.zeros(x.shape[0])
+    for _ in range(8):
+        k = rng.integers(-kmax, kmax + 1, size=dim)
+        ph = rng.uniform(0, 2 * math.pi)
+        out += rng.standard_normal() * np.cos(2 * math.pi * (x @ k) + ph)
+    return 0.25 * out
+
+
+def multi_scalar(fields: list) -> np.ndarray:
+    """Stack S cell fields into the [C][S] layout (scalar index fastest)."""
+    return np.ascontiguousarray(np.stack(fields, axis=1))
+
+
+# ---------------------------------------------------------------------------------------------
+# Time step
+# ---------------------------------------------------------------------------------------------
+
+def cfl_dt(mesh: MeshArrays, u: np.ndarray, cfl: float) -> float:
+    """dt = cfl / max_c (1/V_c) * sum of the outgoing volumetric fluxes of cell c."""
+    own = mesh.face_cells[:, 0].astype(np.int64)
+    nbr = mesh.face_cells[:, 1].astype(np.int64)
+    q = mesh.face_area * u
+    out = np.zeros(mesh.n_cells)
+    np.add.at(out, own, np.maximum(q, 0.0))
+    np.add.at(out, nbr, np.maximum(-q, 0.0))
+    rate = float((out / mesh.cell_volume).max())
+    if rate <= 0.0:
+        raise ValueError("velocity is zero everywhere")
+    return cfl / rate
+
+
+# ---------------------------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    mesh: MeshArrays
+    theta0: np.ndarray  # [C] or [C][S], mesh numbering
+    u: np.ndarray  # [F], mesh numbering
+    dt: float
+    steps: int
+    scheme: str  # "euler" | "ssprk3"
+    name: str
+
+
+def workload_line(n: int = 200, cfl: float = 0.5, steps: int = 400) -> Workload:
+    """1-D periodic line, square wave + Gaussian, u = 1, Euler, dt = cfl*h (one period at 400)."""
+    mesh = periodic_box(n, 1)
+    u = velocity_1d(mesh)
+    return Workload(mesh, field_square_gauss_1d(n), u, cfl / n, steps, "euler", f"line{n}")
+
+
+def workload_box(n: int, renumbered: bool = False, cfl: float = 0.4, steps: int = 100,
+                 seed_velocity: int = SEED_VELOCITY, seed_renumber: int = SEED_RENUMBER) -> Workload:
+    """3-D periodic hex box with the curl velocity and the blob + step field, SSP-RK3."""
+    mesh = periodic_box(n, 3)
+    u = velocity_curl(n, seed_velocity)
+    th = field_blob_step(n)
+    if renumbered:
+        mesh = renumber(mesh, seed_renumber)
+        u = mesh.face_velocity_from_natural(u)
+        th = mesh.cell_field_from_natural(th)
+    dt = cfl_dt(mesh, u, cfl)
+    name = f"box{n}" + ("_random" if renumbered else "")
+    return Workload(mesh, th, u, dt, steps, "ssprk3", name)
+
+
+def box_shared_cache(n: int) -> MeshArrays:
+    """periodic_box(n, 3), memoised: batched workloads reuse one mesh per side length."""
+    m = _BOX_CACHE.get(n)
+    if m is None:
+        m = periodic_box(n, 3)
+        _BOX_CACHE[n] = m
+    return m
+
+
+_BOX_CACHE: dict = {}
+
+
+@dataclasses.dataclass
+class BatchProblem:
+    n: int
+    n_scalars: int
+    limiter: int
+    cfl: float
+    seed: int
+
+
+def batch_recipe(count: int = 512, side_min: int = 12, side_max: int = 96, s_max: int = 8,
+                 limiters=(1, 2, 3, 4, 5), cfl_range=(0.2, 0.5), seed: int = SEED_BATCH) -> list:
+    """Per-problem side, scalar count, limiter id, CFL and velocity seed of a batched workload."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        out.append(BatchProblem(
+            n=int(rng.integers(side_min, side_max + 1)),
+            n_scalars=int(rng.integers(1, s_max + 1)),
+            limiter=int(rng.choice(np.asarray(limiters))),
+            cfl=float(rng.uniform(*cfl_range)),
+            seed=1000 + i,
+        ))
+    return out
+
+
+def batch_fields(p: BatchProblem) -> np.ndarray:
+    """[C][S] initial fields of one batched problem: shifted blobs plus steps, seeded."""
+    rng = np.random.default_rng(p.seed)
+    fs = []
+    for s in range(p.n_scalars):
+        c = tuple(rng.uniform(0.2, 0.8, size=3))
+        fs.append(field_blob_step(p.n, centre=c, sigma=0.08 + 0.02 * s, width=0.02,
+                                  step_at=float(rng.uniform(0.3, 0.7))))
+    return multi_scalar(fs)

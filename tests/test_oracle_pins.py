@@ -1,0 +1,521 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test ties the oracle to something other than itself: values printed in the paper, closed
+forms of linear special cases, the one-dimensional stencil algorithm of the paper evaluated in
+exact rational arithmetic, lattice geometry, conservation/TVD invariants, an independent sparse
+matrix evaluation of the paper's algebraic chain, and finite differences for the derivatives.
+"""
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.mini_oracle import AlgebraicMesh, psi_np
+from paper_2110_03044_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LIMS = ["upwind", "minmod", "vanleer", "vanalbada", "superbee", "smart", "central"]
+TVD_LIMS = ["upwind", "minmod", "vanleer", "superbee"]
+
+
+def read_matrices(path):
+    mats, cur, rows = {}, None, []
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("matrix"):
+            if cur:
+                mats[cur] = np.array(rows, dtype=float)
+            cur, rows = line.split()[1], []
+        else:
+            rows.append([float(x) for x in line.split()])
+    mats[cur] = np.array(rows, dtype=float)
+    return mats
+
+
+# ------------------------------------------------------------------------------------------
+# Limiters
+# ------------------------------------------------------------------------------------------
+
+def test_superbee_matches_table1():
+    """Table 1, superbeexty: F(r) = (psi(r) - 1)/2 at hand-evaluated points."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "superbee_table1.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 10
+    for r, p, F in rows:
+        r, p, F = float(r), float(p), float(F)
+        assert O.psi("superbee", r) == p
+        assert 0.5 * (O.psi("superbee", r) - 1.0) == F
+
+
+@pytest.mark.parametrize("lim,points", [
+    ("minmod", [(-1, 0), (0.5, 0.5), (1, 1), (4, 1)]),
+    ("vanleer", [(-1, 0), (1, 1), (3, 1.5), (0.5, 2 / 3)]),
+    ("vanalbada", [(1, 1), (-0.5, -0.2), (0, 0), (2, 1.2), (-1, 0)]),
+    ("smart", [(-1, 0), (0.1, 0.2), (1, 1), (3, 2.5), (5, 4), (10, 4)]),
+    ("upwind", [(-1, 0), (1, 0), (5, 0)]),
+    ("central", [(-1, 1), (1, 1), (5, 1)]),
+])
+def test_limiter_textbook_points(lim, points):
+    for r, v in points:
+        assert O.psi(lim, r) == pytest.approx(v, abs=1e-15)
+
+
+@pytest.mark.parametrize("lim", ["minmod", "vanleer", "vanalbada", "superbee"])
+def test_limiter_symmetry(lim):
+    """Symmetric limiters satisfy psi(r)/r = psi(1/r) (Sweby)."""
+    for r in [0.1, 0.3, 0.7, 1.3, 2.5, 7.0]:
+        assert O.psi(lim, r) / r == pytest.approx(O.psi(lim, 1.0 / r), rel=1e-14)
+
+
+def test_limiters_in_second_order_tvd_region():
+    """Sweby's region: psi(1) = 1 and 0 <= psi <= min(2r, 2) for r > 0; SMART leaves it."""
+    rs = np.linspace(1e-3, 10, 2001)
+    for lim in ["minmod", "vanleer", "superbee"]:
+        assert O.psi(lim, 1.0) == 1.0
+        v = np.array([O.psi(lim, r) for r in rs])
+        assert (v >= 0).all() and (v <= np.minimum(2 * rs, 2.0) + 1e-15).all()
+    v = np.array([O.psi("smart", r) for r in rs])
+    assert v.max() == 4.0  # beyond Sweby's bound 2
+
+
+def test_limiter_infinity_limits():
+    for lim in LIMS:
+        assert O.psi(lim, 1e30) == pytest.approx(O.psi(lim, 1e17), abs=1e-15)
+        assert O.psi(lim, -1e30) == pytest.approx(O.psi(lim, -1e17), abs=1e-15)
+        assert O.psi(lim, math.inf) == O.psi(lim, 1e30)
+
+
+@pytest.mark.parametrize("lim", LIMS)
+def test_dpsi_matches_finite_difference(lim):
+    for r in [-2.3, -0.4, 0.13, 0.37, 0.8, 1.4, 2.7, 4.1, 6.3]:
+        h = 1e-7
+        fd = (O.psi(lim, r + h) - O.psi(lim, r - h)) / (2 * h)
+        assert O.dpsi(lim, r) == pytest.approx(fd, abs=1e-6)
+
+
+def test_mini_oracle_limiters_agree_with_oracle():
+    rs = np.concatenate([np.linspace(-5, 8, 1301), [1e20, -1e20, 0.0]])
+    for lim in LIMS:
+        a = psi_np(lim, rs)
+        b = np.array([O.psi(lim, r) for r in rs])
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------------------------------
+# The paper's printed example (Section 2 and Section 3.1)
+# ------------------------------------------------------------------------------------------
+
+def test_printed_adjacency_matrices():
+    """A_FF = B B^T - W reproduces the printed face adjacency exactly; A^D = offdiag(E B^T)
+    reproduces the printed directed adjacency once E is oriented +1 on the cell the normal
+    enters (the printed E_{C->F} carries the opposite sign)."""
+    M = read_matrices(os.path.join(GOLDEN, "paper_example_2d.txt"))
+    E_printed = M["E_CF"]
+    am = AlgebraicMesh.from_incidence(-E_printed)
+    np.testing.assert_array_equal(am.A.toarray(), M["A_FF"])
+    np.testing.assert_array_equal(am.AD.toarray(), M["AD_FF"])
+    # A_FF is non-negative and symmetric, A^D has A_FF's pattern (text of Section 3.1)
+    assert (M["A_FF"] >= 0).all() and (M["A_FF"] == M["A_FF"].T).all()
+    np.testing.assert_array_equal(np.abs(M["AD_FF"]), M["A_FF"])
+    # with the printed sign the formula gives the negated matrix: the reading is recorded here
+    am2 = AlgebraicMesh.from_incidence(E_printed)
+    np.testing.assert_array_equal(am2.AD.toarray(), -M["AD_FF"])
+
+
+def test_printed_exact_sequence_has_one_typo():
+    """E_{F->V} E_{C->F} should vanish (Section 2); the printed pair leaves one entry."""
+    M = read_matrices(os.path.join(GOLDEN, "paper_example_2d.txt"))
+    P = M["E_FV"] @ M["E_CF"]
+    nz = np.argwhere(P != 0)
+    assert nz.tolist() == [[3, 2]] and P[3, 2] == -2
+
+
+def test_exact_sequence_of_generated_velocity():
+    """Discrete curl => zero discrete divergence in every cell, exactly (Section 2): the face
+    areas are uniform, so the signed sum of the normal velocities of each cell vanishes."""
+    for n in (4, 7, 16):
+        m = W.periodic_box(n, 3)
+        u = W.velocity_curl(n, seed=5)
+        div = np.zeros(m.n_cells)
+        np.add.at(div, m.face_cells[:, 0], u)
+        np.add.at(div, m.face_cells[:, 1], -u)
+        assert np.abs(div).max() == 0.0
+        assert 0.99 < np.abs(u).max() < 1.01
+
+
+# ------------------------------------------------------------------------------------------
+# Face selection against lattice geometry
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("renum", [False, True])
+def test_far_upwind_is_the_lattice_cell_behind(renum):
+    n = 5
+    nat = W.periodic_box(n, 3)
+    m = W.renumber(nat, seed=11) if renum else nat
+    u_nat = W.velocity_curl(n, seed=3)
+    u = m.face_velocity_from_natural(u_nat)
+    cdu = O.OracleMesh.from_arrays(m).select(u)
+    # back to natural numbering
+    cnew = m.cell_new_of_old if renum else np.arange(nat.n_cells)
+    old_of_new = np.empty_like(cnew)
+    old_of_new[cnew] = np.arange(cnew.size)
+    fnew = m.face_new_of_old if renum else np.arange(nat.n_faces)
+    ijk = lambda c: np.array([c % n, (c // n) % n, c // (n * n)])
+    lin = lambda v: int(v[0] % n + n * (v[1] % n) + n * n * (v[2] % n))
+    for f_old in range(nat.n_faces):
+        C, D, U = (old_of_new[x] for x in cdu[fnew[f_old]])
+        a, c_own = divmod(f_old, nat.n_cells)
+        own, nbr = nat.face_cells[f_old]
+        if u_nat[f_old] > 0:
+            assert (C, D) == (own, nbr)
+        else:
+            assert (C, D) == (nbr, own)
+        assert U == lin(2 * ijk(C) - ijk(D)), f_old
+        assert U not in (C, D)
+
+
+def test_zero_velocity_takes_the_negative_sign():
+    """Table 1, signxty: x > 0 ? +1 : -1, so u_f = 0 (and -0.0) selects C = nbr."""
+    m = W.periodic_box(6, 2)
+    u = np.zeros(m.n_faces)
+    u[::3] = -0.0
+    u[1::3] = 1.0
+    cdu = O.OracleMesh.from_arrays(m).select(u)
+    pos = u > 0
+    np.testing.assert_array_equal(cdu[pos, 0], m.face_cells[pos, 0])
+    np.testing.assert_array_equal(cdu[~pos, 0], m.face_cells[~pos, 1])
+    np.testing.assert_array_equal(cdu[~pos, 1], m.face_cells[~pos, 0])
+
+
+def test_hex_weights_are_zero_or_one():
+    m = W.renumber(W.periodic_box(4, 3), seed=2)
+    om = O.OracleMesh.from_arrays(m)
+    for f in range(0, m.n_faces, 7):
+        for side in (False, True):
+            faces, w = om.side_weights(f, side)
+            assert len(w) == 6
+            assert sorted(w.tolist()) == [0.0] * 5 + [1.0]
+
+
+# ------------------------------------------------------------------------------------------
+# Algorithm 1D in exact arithmetic
+# ------------------------------------------------------------------------------------------
+
+def _psi_exact(lim, r):
+    if lim == "minmod":
+        return max(Fraction(0), min(Fraction(1), r))
+    if lim == "superbee":
+        return max(Fraction(0), max(min(Fraction(1), 2 * r), min(r, Fraction(2))))
+    if lim == "smart":
+        return max(Fraction(0), min(2 * r, Fraction(1, 4) + Fraction(3, 4) * r, Fraction(4)))
+    if lim == "vanleer":
+        return (r + abs(r)) / (1 + abs(r))
+    if lim == "vanalbada":
+        return (r * r + r) / (r * r + 1)
+    raise ValueError(lim)
+
+
+@pytest.mark.parametrize("lim", ["minmod", "superbee", "smart", "vanleer", "vanalbada"])
+def test_face_values_follow_algorithm_1d(lim):
+    """Algorithm 1D (Section 3.3) on a uniform periodic line, evaluated in rationals."""
+    th = [0, 1, 3, 4, 2, 2, -1, 5, 5, 6, 2, 0]
+    n = len(th)
+    m = W.periodic_box(n, 1)
+    rng = np.random.default_rng(4)
+    u = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    got = O.OracleMesh.from_arrays(m).face_values(lim, np.array(th, float), u)
+    T = [Fraction(x) for x in th]
+    for i in range(n):
+        if u[i] > 0:
+            tC, tU, tD = T[i], T[i - 1], T[(i + 1) % n]
+        else:
+            tC, tU, tD = T[(i + 1) % n], T[(i + 2) % n], T[i]
+        if tD == tC:
+            want = tC
+        else:
+            r = (tC - tU) / (tD - tC)
+            want = (tC + tD) / 2 + (_psi_exact(lim, r) - 1) * (tD - tC) / 2
+        assert abs(float(want) - got[i]) <= 1e-15 * max(1.0, abs(float(want))), (i, want, got[i])
+
+
+# ------------------------------------------------------------------------------------------
+# Literal algebraic chain (Algorithm 3) vs the gather oracle
+# ------------------------------------------------------------------------------------------
+
+def _tiny_meshes():
+    out = []
+    for n, d in [(7, 1), (5, 2), (4, 3), (5, 3)]:
+        nat = W.periodic_box(n, d)
+        out.append((f"{d}d{n}", nat))
+        out.append((f"{d}d{n}r", W.renumber(nat, seed=n + d)))
+    return out
+
+
+@pytest.mark.parametrize("name,mesh", _tiny_meshes(), ids=lambda x: x if isinstance(x, str) else "")
+def test_algebraic_chain_matches_gather_oracle(name, mesh):
+    rng = np.random.default_rng(7)
+    th = rng.standard_normal(mesh.n_cells)
+    u = rng.standard_normal(mesh.n_faces)
+    am = AlgebraicMesh.from_arrays(mesh)
+    om = O.OracleMesh.from_arrays(mesh)
+    # the unsimplified and precomputed forms of d_U coincide
+    np.testing.assert_allclose(am.upstream_difference(th, u),
+                               am.upstream_difference_unsimplified(th, u), rtol=0, atol=1e-14)
+    for lim in LIMS:
+        tf_a = am.face_values(lim, th, u)
+        tf_o = om.face_values(lim, th, u)
+        np.testing.assert_allclose(tf_a, tf_o, rtol=0, atol=2e-14)
+        np.testing.assert_allclose(am.rhs(lim, th, u), om.rhs(lim, th, u), rtol=0,
+                                   atol=2e-13 * np.abs(om.rhs(lim, th, u)).max())
+
+
+def test_algebraic_chain_euler_run_matches_oracle():
+    wl = W.workload_line(n=50, steps=40)
+    am = AlgebraicMesh.from_arrays(wl.mesh)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    for lim in LIMS[:6]:
+        a = am.euler_run(lim, wl.dt, wl.theta0, wl.u, wl.steps)
+        b = om.run(lim, "euler", wl.dt, wl.theta0, wl.u, wl.steps)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+
+
+def test_printed_simplified_form_picks_downstream_faces():
+    """The printed d_U = (Q S + T) theta equals theta_{D'} - theta_D (the faces beyond D) on a
+    uniform line, which is why the corrected (Q T - S) form is used."""
+    n = 9
+    m = W.periodic_box(n, 1)
+    am = AlgebraicMesh.from_arrays(m)
+    th = np.arange(n, dtype=float) ** 2
+    u = np.ones(n)
+    printed = u * (am.S @ th) + am.T @ th
+    want_down = np.array([th[(i + 2) % n] - th[(i + 1) % n] for i in range(n)])
+    np.testing.assert_array_equal(printed, want_down)
+    want_up = np.array([th[i] - th[i - 1] for i in range(n)])
+    np.testing.assert_array_equal(am.upstream_difference(th, u), want_up)
+
+
+# ------------------------------------------------------------------------------------------
+# Closed forms of the linear special cases
+# ------------------------------------------------------------------------------------------
+
+def test_upwind_line_is_binomial_convolution():
+    """psi = 0 (paper's F = -1/2) at CFL 1/2: theta^N_i = sum_k C(N,k) 2^-N theta^0_{i-k}."""
+    wl = W.workload_line()
+    th = O.OracleMesh.from_arrays(wl.mesh).run("upwind", "euler", wl.dt, wl.theta0, wl.u, wl.steps)
+    N, n = wl.steps, wl.mesh.n_cells
+    wts = np.array([math.comb(N, k) for k in range(N + 1)], dtype=float) * 2.0**-N
+    want = np.zeros(n)
+    for k in range(N + 1):
+        want += wts[k] * np.roll(wl.theta0, k)
+    np.testing.assert_allclose(th, want, rtol=0, atol=2e-15)
+
+
+def _fft_closed_form(n, vel, lim, scheme, dt, steps, th0):
+    """Linear schemes with constant velocity on a periodic box are circulant: evolve in Fourier."""
+    h = 1.0 / n
+    k = 2 * np.pi * np.fft.fftfreq(n, d=1.0 / n) / n  # kappa = 2 pi m / n
+    K = np.meshgrid(k, k, k, indexing="ij")
+    sym = np.zeros((n, n, n), dtype=complex)
+    for d in range(3):
+        v = vel[d]
+        e = np.exp(1j * K[d])  # shift +e_d
+        if lim == "upwind":
+            # v>0: -v/h (theta_c - theta_{c-e}); v<0: -v/h (theta_{c+e} - theta_c)
+            sym += -(v / h) * (1 - 1 / e) if v > 0 else -(v / h) * (e - 1)
+        else:  # central
+            sym += -(v / h) * (e - 1 / e) / 2
+    z = dt * sym
+    amp = 1 + z if scheme == "euler" else 1 + z + z * z / 2 + z**3 / 6
+    T = np.fft.fftn(th0.reshape((n, n, n), order="F"))
+    return np.real(np.fft.ifftn(T * amp**steps)).ravel(order="F")
+
+
+@pytest.mark.parametrize("lim", ["upwind", "central"])
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+def test_linear_schemes_match_fourier_closed_form(lim, scheme):
+    n = 8
+    m = W.periodic_box(n, 3)
+    vel = (0.7, -0.4, 0.25)
+    u = W.velocity_uniform(m, vel)
+    th0 = W.field_smooth_random(n, 3, seed=9) + W.field_blob_step(n)
+    dt = 0.2 / n
+    got = O.OracleMesh.from_arrays(m).run(lim, scheme, dt, th0, u, 12)
+    want = _fft_closed_form(n, vel, lim, scheme, dt, 12, th0)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("lim", LIMS)
+def test_3d_with_axis_flow_reduces_to_1d(lim):
+    """Orthogonal meshes recover the one-dimensional formulation (Section 3.1, Conclusions)."""
+    n = 16
+    m3 = W.periodic_box(n, 3)
+    m1 = W.periodic_box(n, 1)
+    line = W.field_square_gauss_1d(n) + 0.1 * W.field_smooth_random(n, 1, 3)
+    th3 = np.tile(line, n * n)  # theta depends on x only
+    u3 = W.velocity_uniform(m3, (1.0, 0, 0))
+    u1 = W.velocity_uniform(m1, (1.0, 0, 0))
+    dt = 0.4 / n
+    a = O.OracleMesh.from_arrays(m3).run(lim, "ssprk3", dt, th3, u3, 20)
+    b = O.OracleMesh.from_arrays(m1).run(lim, "ssprk3", dt, line, u1, 20)
+    np.testing.assert_array_equal(a.reshape(n * n, n), np.tile(b, (n * n, 1)))
+
+
+# ------------------------------------------------------------------------------------------
+# Invariants
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lim", LIMS[:6])
+def test_renumbering_and_orientation_invariance(lim):
+    n = 8
+    nat = W.periodic_box(n, 3)
+    rn = W.renumber(nat, seed=21)
+    u = W.velocity_curl(n, seed=1)
+    th = W.field_blob_step(n)
+    dt = W.cfl_dt(nat, u, 0.4)
+    a = O.OracleMesh.from_arrays(nat).run(lim, "ssprk3", dt, th, u, 10)
+    b = O.OracleMesh.from_arrays(rn).run(lim, "ssprk3", dt, rn.cell_field_from_natural(th),
+                                          rn.face_velocity_from_natural(u), 10)
+    np.testing.assert_allclose(rn.cell_field_to_natural(b), a, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("lim", LIMS[:6])
+def test_conservation_on_periodic_mesh(lim):
+    wl = W.workload_box(12, renumbered=True, steps=30)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    th = om.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, wl.steps)
+    V = wl.mesh.cell_volume
+    m0 = (V * wl.theta0).sum()
+    assert abs((V * th).sum() - m0) <= 1e-13 * (V * np.abs(wl.theta0)).sum()
+
+
+def test_conservation_multi_scalar_matches_single():
+    wl = W.workload_box(6, renumbered=True, steps=5)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    th2 = W.multi_scalar([wl.theta0, 1.0 - 2.0 * wl.theta0, wl.theta0**2])
+    out = om.run("vanleer", "ssprk3", wl.dt, th2, wl.u, 5)
+    for s in range(3):
+        np.testing.assert_array_equal(out[:, s], om.run("vanleer", "ssprk3", wl.dt, th2[:, s], wl.u, 5))
+
+
+def _tv(x):
+    return np.abs(np.diff(np.append(x, x[0]))).sum()
+
+
+@pytest.mark.parametrize("lim", TVD_LIMS)
+def test_tvd_and_bounded_in_1d(lim):
+    """Harten/Sweby: 0 <= psi <= 2, 0 <= psi/r <= 2 and CFL <= 1/2 give a TVD forward-Euler step."""
+    wl = W.workload_line()
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    th = wl.theta0.copy()
+    tv0, lo, hi = _tv(th), th.min(), th.max()
+    for _ in range(wl.steps):
+        nxt = om.run(lim, "euler", wl.dt, th, wl.u, 1)
+        assert _tv(nxt) <= _tv(th) + 1e-12 * tv0
+        assert nxt.min() >= lo - 1e-12 * (hi - lo) and nxt.max() <= hi + 1e-12 * (hi - lo)
+        th = nxt
+
+
+def test_smart_is_not_tvd_with_euler():
+    """SMART (psi up to 4) lies outside Sweby's region: the forward-Euler run overshoots."""
+    wl = W.workload_line()
+    th = O.OracleMesh.from_arrays(wl.mesh).run("smart", "euler", wl.dt, wl.theta0, wl.u, wl.steps)
+    assert th.max() > wl.theta0.max() + 0.1
+
+
+def test_free_stream_preservation():
+    wl = W.workload_box(10, renumbered=True, steps=20)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    th = np.full(wl.mesh.n_cells, 0.75)
+    for lim in ["vanleer", "superbee", "smart"]:
+        out = om.run(lim, "ssprk3", wl.dt, th, wl.u, 20)
+        assert np.abs(out - 0.75).max() <= 1e-13
+
+
+def test_sampled_rhs_equals_full_rhs():
+    wl = W.workload_box(7, renumbered=True)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    full = om.rhs("superbee", wl.theta0, wl.u)
+    cells = np.array([0, 5, 17, 100, wl.mesh.n_cells - 1])
+    np.testing.assert_array_equal(om.rhs_cells("superbee", wl.theta0, wl.u, cells), full[cells])
+
+
+# ------------------------------------------------------------------------------------------
+# Derivatives
+# ------------------------------------------------------------------------------------------
+
+def _fd_setup(n=5, seed=0):
+    wl = W.workload_box(n, renumbered=True)
+    rng = np.random.default_rng(seed)
+    th = wl.theta0 + 1e-2 * rng.standard_normal(wl.mesh.n_cells)  # no flat neighbours
+    return wl, th, rng
+
+
+@pytest.mark.parametrize("lim", ["vanalbada", "upwind", "central", "vanleer"])
+def test_rhs_jvp_matches_finite_difference(lim):
+    wl, th, rng = _fd_setup()
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    v = rng.standard_normal(th.size)
+    du = rng.standard_normal(wl.u.size)
+    eps = 1e-6
+    umin = np.abs(wl.u).min()
+    du *= 0.5 * umin / (eps * np.abs(du).max())  # no face changes sign
+    jv = om.rhs_jvp(lim, th, wl.u, v, du)
+    fd = (om.rhs(lim, th + eps * v, wl.u + eps * du) - om.rhs(lim, th - eps * v, wl.u - eps * du)) / (2 * eps)
+    np.testing.assert_allclose(jv, fd, rtol=0, atol=1e-6 * np.abs(jv).max())
+
+
+@pytest.mark.parametrize("lim", LIMS)
+def test_rhs_vjp_is_transpose_of_jvp(lim):
+    wl, th, rng = _fd_setup(seed=1)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    v = rng.standard_normal(th.size)
+    du = rng.standard_normal(wl.u.size)
+    w = rng.standard_normal(th.size)
+    jv = om.rhs_jvp(lim, th, wl.u, v, du)
+    tb, ub = om.rhs_vjp(lim, th, wl.u, w)
+    lhs = jv @ w
+    rhs = v @ tb + du @ ub
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.abs(jv).max() * np.abs(w).sum())
+
+
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+@pytest.mark.parametrize("lim", ["vanalbada", "superbee", "smart"])
+def test_run_adjoint_is_transpose_of_run_tangent(lim, scheme):
+    wl, th, rng = _fd_setup(seed=2)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    v = rng.standard_normal(th.size)
+    du = rng.standard_normal(wl.u.size)
+    w = rng.standard_normal(th.size)
+    _, jv = om.run_tangent(lim, scheme, wl.dt, th, wl.u, 4, v, du)
+    tb, ub = om.run_adjoint(lim, scheme, wl.dt, th, wl.u, 4, w)
+    lhs, rhs = jv @ w, v @ tb + du @ ub
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(jv) @ np.abs(w))
+
+
+def test_run_adjoint_matches_finite_difference_of_loss():
+    """d/d(theta0) and d/du of J = |theta_N - target|^2 / 2 for the smooth van Albada limiter."""
+    wl, th, rng = _fd_setup(seed=3)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    target = wl.theta0 * 0.5
+    steps = 6
+
+    def J(t0, u):
+        tn = om.run("vanalbada", "ssprk3", wl.dt, t0, u, steps)
+        return 0.5 * ((tn - target) ** 2).sum()
+
+    tn = om.run("vanalbada", "ssprk3", wl.dt, th, wl.u, steps)
+    tb, ub = om.run_adjoint("vanalbada", "ssprk3", wl.dt, th, wl.u, steps, tn - target)
+    for k in range(3):
+        v = rng.standard_normal(th.size)
+        du = rng.standard_normal(wl.u.size)
+        eps = 1e-6
+        du *= 0.5 * np.abs(wl.u).min() / (eps * np.abs(du).max())
+        fd = (J(th + eps * v, wl.u + eps * du) - J(th - eps * v, wl.u - eps * du)) / (2 * eps)
+        ad = v @ tb + du @ ub
+        assert ad == pytest.approx(fd, rel=1e-6)
