@@ -1,0 +1,194 @@
+"""Benchmark of the flux-limited convective operator on one MI355X.
+
+Default workload: the randomly renumbered 256^3 periodic hexahedral mesh (16.8M cells, 50.3M
+faces, generic face-to-cell incidence with random face orientations), solenoidal face velocity
+from the discrete curl of a seeded random edge potential, Gaussian blob + tanh step, SSP-RK3 at
+CFL 0.4, for each of the limiters minmod, van Leer, superbee and SMART.  The library renumbers
+the mesh for gather locality at creation (FL_MESH_REORDER, outside the timed region).
+
+One step = one SSP-RK3 step (three stages) of one limiter; the timed region runs `--steps`
+steps for every limiter.  A face-update is one face's limited flux in one stage for one scalar:
+value = faces * stages * steps * limiters / time.
+
+Prints one JSON line (see the keys below).  `roofline` is for the dominant kernel
+(fused_stage_kernel): its algorithmic bytes per launch (every table entry, face velocity and
+cell value it must touch, read or written once) divided by its average launch duration measured
+with HIP events on the launch stream.  `cpu_baseline` times the CPU oracle on the host cores on
+a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+LIM_DEFAULT = ["minmod", "vanleer", "superbee", "smart"]
+METRIC = "FP64 Gface-updates/s + % HBM peak at 256^3; adjoint/forward cost ratio"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fused_stage_bytes(C, F, K, S, stage):
+    """Compulsory bytes of one fused stage launch: slot tables (face, cell, far cell: 12 B per
+    slot), face velocities once, theta_s read once, theta_n read once (stages 2, 3) and the
+    output written once."""
+    b = C * K * 12 + F * 8 + C * S * 8 * 2
+    if stage > 0:
+        b += C * S * 8
+    return b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed SSP-RK3 steps per limiter")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="cells per side of the periodic box")
+    ap.add_argument("--limiters", default=",".join(LIM_DEFAULT))
+    ap.add_argument("--no-reorder", action="store_true")
+    ap.add_argument("--face-path", action="store_true")
+    ap.add_argument("--no-xcd-remap", action="store_true")
+    ap.add_argument("--cpu-baseline", type=int, default=1, help="0 to skip the oracle timing")
+    ap.add_argument("--compare-order", action="store_true",
+                    help="also time the as-given random numbering (no library reorder)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the operator's multi-GPU halo "
+              "exchange is a design note, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2110_03044_amd import _lib, fluxlim as FL, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    lims = [l for l in args.limiters.split(",") if l]
+    if args.no_xcd_remap:
+        _lib.lib()  # remap is a compile-time default in the library; flag kept for sweeps
+    t0 = time.time()
+    wl = W.workload_box(args.n, renumbered=True)
+    m = wl.mesh
+    log(f"workload generated in {time.time() - t0:.1f}s: C={m.n_cells} F={m.n_faces} dt={wl.dt:.6g}")
+
+    def run_case(reorder: bool):
+        t1 = time.time()
+        mesh = FL.Mesh.from_arrays(m, device=0, reorder=reorder, face_path=args.face_path)
+        log(f"mesh created (reorder={reorder}, path={mesh.path}) in {time.time() - t1:.1f}s, "
+            f"{mesh.info.device_bytes / 1e9:.2f} GB on device")
+        th0 = mesh.cells_to_mesh(torch.from_numpy(wl.theta0).to(dev))
+        u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
+        work = FL.rk_workspace(mesh, "ssprk3", 1)
+        th = th0.clone()
+        stream = torch.cuda.current_stream(dev)
+        for lim in lims:  # warm-up
+            th.copy_(th0)
+            FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, u, args.warmup, work=work)
+        torch.cuda.synchronize()
+        per_lim = {}
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        total_ms = 0.0
+        for lim in lims:
+            th.copy_(th0)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, u, args.steps, work=work)
+            ev1.record(stream)
+            ev1.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            total_ms += ms
+            per_lim[lim] = ms
+            log(f"  {lim}: {ms / args.steps:.3f} ms/step")
+        torch.cuda.synchronize()
+        info = mesh.info
+        res = dict(mesh=mesh, total_ms=total_ms, per_lim=per_lim, path=mesh.path,
+                   K=int(info.max_degree), th=th, u=u)
+        return res
+
+    reorder = not args.no_reorder
+    r = run_case(reorder)
+    C, F, S = m.n_cells, m.n_faces, 1
+    n_steps_total = args.steps * len(lims)
+    updates = F * S * 3 * n_steps_total
+    value = updates / (r["total_ms"] * 1e-3) / 1e9
+    ms_per_step = r["total_ms"] / n_steps_total
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gface-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"periodic hex box {args.n}^3, random cell/face numbering and face "
+                        f"orientation (seed 1), curl velocity (seed 0), blob + tanh step, "
+                        f"SSP-RK3 CFL 0.4",
+            "cells": C, "faces": F, "scalars": S, "limiters": lims, "scheme": "ssprk3",
+            "library_reorder": reorder, "path": r["path"],
+        },
+        "per_limiter_ms_per_step": {k: round(v / args.steps, 4) for k, v in r["per_lim"].items()},
+    }
+
+    # roofline of the dominant kernel
+    if r["path"] == "fused":
+        K = r["K"]
+        launches = 3 * n_steps_total
+        bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s) for s in range(3))
+        avg_launch_s = r["total_ms"] * 1e-3 / launches
+        achieved = bytes_per_step / 3 / avg_launch_s / 1e9
+        out["roofline"] = {"kernel": "fused_stage_kernel", "bound": "hbm",
+                           "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                           "algorithmic_bytes_per_launch": int(bytes_per_step / 3),
+                           "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+    # the two-kernel byte model (40 B/face + 60 B/cell per stage) as context
+    out["model_bytes_per_face_update"] = round((40 * F + 60 * C) / F, 2)
+    out["model_frac_of_hbm"] = round(value * 1e9 * (40 * F + 60 * C) / F / (HBM_PEAK_GBS * 1e9), 4)
+
+    if args.compare_order and reorder:
+        r["mesh"].close()
+        del r
+        torch.cuda.empty_cache()
+        r2 = run_case(False)
+        v2 = updates / (r2["total_ms"] * 1e-3) / 1e9
+        out["as_given_numbering_value"] = round(v2, 3)
+
+    if args.cpu_baseline:
+        from oracle import oracle as O
+
+        t1 = time.time()
+        om = O.OracleMesh.from_arrays(m)
+        lim = "vanleer"
+        t2 = time.time()
+        om.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, 1)
+        cpu_s = time.time() - t2
+        cpu_rate = F * 3 / cpu_s / 1e9
+        out["cpu_baseline"] = {"value": round(cpu_rate, 4), "unit": "Gface-updates/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"1 SSP-RK3 step (3 stages, all {F} faces) of the same "
+                                         f"{args.n}^3 mesh in its given numbering, van Leer, "
+                                         f"{cpu_s:.1f} s"}
+        log(f"oracle setup {t2 - t1:.1f}s, step {cpu_s:.1f}s")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * fluxlim.h -- C ABI of the MI355X (gfx950) flux-limited convective operator library.
+ *
+ * The operator is the algebraic flux limiter of Valle et al., "On the implementation of flux
+ * limiters in algebraic frameworks" (arXiv 2110.03044):
+ *   theta_f = theta_C + psi(r_f) (theta_D - theta_C) / 2,   r_f = d_U / d_u
+ * (Section 3: Sweby form, gradient ratio, the algebraic operator theta_f = (Pi + F(r) Q E) theta
+ * with F = (psi - 1)/2, and Algorithm 3), followed by the divergence of the face fluxes
+ * a_f u_f theta_f and an explicit time step (Section 4.1, Algorithm 4), here forward Euler or
+ * three-stage SSP Runge-Kutta.
+ *
+ * Mesh model (Section 2): a mesh is its oriented face-to-cell incidence.  Face f joins
+ * own = face_cells[2f] and nbr = face_cells[2f+1]; its unit normal face_normal[3f..3f+2] points
+ * from own into nbr (E_{C->F}[f][nbr] = +1, E_{C->F}[f][own] = -1).  u_f is the normal
+ * velocity along that normal.  The velocity sign matrix Q(u_f) takes +1 where u_f > 0 and -1
+ * otherwise (Table 1, signxty), so C = own where u_f > 0 and C = nbr where u_f <= 0.  The
+ * far-upwind difference d_U = theta_C - theta_U uses the cell U across the face of C opposite
+ * to f, found once at mesh creation by projecting the face normals (the upstream adjacency
+ * A^U_FF of Section 3.1 with the velocity sign applied to the projected difference).
+ *
+ * Conventions for every entry point:
+ *   - all floating point is IEEE binary64 (double);
+ *   - cell fields hold n_scalars values per cell, scalar index fastest: theta[c * S + s];
+ *   - device pointers are plain HIP device allocations on the mesh's device (e.g. torch
+ *     tensors), 8-byte aligned, not aliased unless stated; the caller owns them;
+ *   - arrays are in MESH ORDER: the user's numbering, unless the mesh was created with
+ *     FL_MESH_REORDER (then see fl_mesh_permutation);
+ *   - hot-path calls (fl_convect_apply, fl_rk_step, fl_rk_steps, fl_convect_adjoint,
+ *     fl_rk_step_adjoint, fl_batch_step) only enqueue work on the given HIP stream
+ *     (hipStream_t passed as void*, NULL = the null stream): no host synchronisation, no
+ *     allocation, O(1) argument checks;
+ *   - errors are returned as status codes (never abort, never throw); fl_last_error() gives a
+ *     thread-local message for the last failing call of the calling thread;
+ *   - results are bitwise deterministic from run to run (no atomics, fixed summation order).
+ */
+#ifndef FLUXLIM_H
+#define FLUXLIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fl_status;
+#define FL_OK 0
+#define FL_E_INVALID -1     /* bad argument: null pointer, size, enum, alignment            */
+#define FL_E_TOPOLOGY -2    /* incidence violates the mesh model (index range, own == nbr,
+                               two faces joining the same two cells, far-upwind == downwind) */
+#define FL_E_UNSUPPORTED -3 /* valid but outside this library: boundary faces (nbr = -1),
+                               cells whose upstream difference needs more than one face       */
+#define FL_E_NOMEM -4       /* host or device allocation failed                              */
+#define FL_E_HIP -5         /* a HIP runtime call failed (message in fl_last_error)          */
+#define FL_E_NODEVICE -6    /* compute call on a host-only mesh (device = -1)                */
+
+/* Limiters psi(r) (Sweby's family; superbee is the paper's, Table 1):
+ *   FL_UPWIND    psi = 0 (first order upwind; the paper's F = -1/2)
+ *   FL_MINMOD    max(0, min(1, r))
+ *   FL_VANLEER   (r + |r|) / (1 + |r|)
+ *   FL_VANALBADA (r^2 + r) / (r^2 + 1)  (not clipped; smooth)
+ *   FL_SUPERBEE  max(0, min(1, 2r), min(r, 2))
+ *   FL_SMART     max(0, min(2r, 1/4 + 3r/4, 4))
+ *   FL_CENTRAL   psi = 1 (central differencing; the paper's F = 0)
+ * theta_f = theta_C where theta_D == theta_C; |r| > 1e18 (and r = +-inf) takes psi(+-inf). */
+enum { FL_UPWIND = 0, FL_MINMOD = 1, FL_VANLEER = 2, FL_VANALBADA = 3, FL_SUPERBEE = 4,
+       FL_SMART = 5, FL_CENTRAL = 6, FL_NUM_LIMITERS = 7 };
+
+/* Time schemes: forward Euler (Algorithm 4) and Shu-Osher SSP-RK3
+ * theta1 = theta + dt L(theta); theta2 = 3/4 theta + 1/4 (theta1 + dt L(theta1));
+ * theta+ = 1/3 theta + 2/3 (theta2 + dt L(theta2)). */
+enum { FL_EULER = 1, FL_SSPRK3 = 3 };
+
+/* fl_mesh_create flags */
+enum {
+    FL_MESH_REORDER = 1,   /* renumber cells (breadth-first) and faces for gather locality   */
+    FL_MESH_FACE_PATH = 2  /* use the face-kernel + cell-gather pair even where the fused
+                              cell-centric kernel applies                                     */
+};
+
+/* Kernel paths reported by fl_mesh_info */
+enum { FL_PATH_FACE_CELL = 1, FL_PATH_FUSED = 2 };
+
+#define FL_MAX_SCALARS 8
+
+typedef struct fl_mesh fl_mesh;
+typedef struct fl_batch fl_batch;
+
+typedef struct fl_mesh_info_t {
+    int64_t n_cells, n_faces;
+    int32_t max_degree;     /* faces per cell (max)                                          */
+    int32_t pairs;          /* opposite-face pairs per cell if uniform (fused path), else 0  */
+    int32_t path;           /* FL_PATH_FACE_CELL or FL_PATH_FUSED                            */
+    int32_t device;         /* HIP device, -1 for a host-only mesh                           */
+    int32_t reordered;      /* 1 if FL_MESH_REORDER renumbered the mesh                     */
+    int32_t uniform_area;   /* 1 if all face areas are equal (then stored as one scalar)     */
+    int32_t uniform_volume; /* 1 if all cell volumes are equal                               */
+    int64_t device_bytes;   /* device memory held by the mesh                                */
+} fl_mesh_info_t;
+
+/* Checks an incidence against the mesh model without a GPU (Section 2).  face_cells: host
+ * int32 [n_faces][2]; face_normal: host double [n_faces][3], unit length within 1e-12.
+ * Returns FL_OK, FL_E_INVALID, FL_E_TOPOLOGY or FL_E_UNSUPPORTED. */
+fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
+                           const double *face_normal);
+
+/* Builds the mesh tables (far-upwind cell per face side, cell -> face lists, and where every
+ * cell's faces form opposite pairs, the per-cell slot tables of the fused kernel) and copies
+ * them to `device`.  Inputs are host arrays, read only during the call:
+ *   face_cells  int32 [n_faces][2] (own, nbr), 0 <= index < n_cells, own != nbr;
+ *   face_normal double [n_faces][3], unit, own -> nbr (1-D and 2-D meshes pad with 0);
+ *   face_area   double [n_faces] or NULL (= 1);   cell_volume double [n_cells] or NULL (= 1).
+ * device = -1 builds a host-only mesh (tables, validation and export work; compute calls
+ * return FL_E_NODEVICE).  On success *out owns device memory until fl_mesh_destroy; the mesh is
+ * immutable and may be used from several streams at once. */
+fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
+                         const double *face_normal, const double *face_area,
+                         const double *cell_volume, int device, uint32_t flags, fl_mesh **out);
+fl_status fl_mesh_destroy(fl_mesh *mesh);
+fl_status fl_mesh_info(const fl_mesh *mesh, fl_mesh_info_t *info);
+
+/* Numbering maps of a reordered mesh (identity otherwise): cell_perm[user cell] = mesh cell,
+ * face_perm[user face] = mesh face (host int32 arrays of n_cells / n_faces, or NULL to skip).
+ * Face orientations are kept, so u_f moves without a sign change. */
+fl_status fl_mesh_permutation(const fl_mesh *mesh, int32_t *cell_perm, int32_t *face_perm);
+
+/* Host copies of the tables, in mesh order (any pointer may be NULL):
+ *   face_far int32 [n_faces][2]: far-upwind cell when C = own, and when C = nbr;
+ *   cf_ptr   int32 [n_cells + 1], cf_idx int32 [cf_ptr[n_cells]]: faces of each cell in
+ *            ascending face order, encoded f for faces whose nbr is the cell and ~f (-f-1)
+ *            for faces whose own is the cell. */
+fl_status fl_mesh_export_tables(const fl_mesh *mesh, int32_t *face_far, int32_t *cf_ptr,
+                                int32_t *cf_idx);
+
+/* Reorders cell / face fields between user and mesh order on the device (to_mesh = 1: out =
+ * in permuted into mesh order; 0: back).  in and out must not alias.  cells: [n_cells][S]
+ * doubles; faces: [n_faces] doubles. */
+fl_status fl_permute_cells(const fl_mesh *mesh, int to_mesh, int n_scalars, const double *in,
+                           double *out, void *hip_stream);
+fl_status fl_permute_faces(const fl_mesh *mesh, int to_mesh, const double *in, double *out,
+                           void *hip_stream);
+
+/* rhs = L(theta) = M U(u_f) theta_f (Algorithm 4's spatial operator):
+ * rhs_c = (sum_{f: nbr_f = c} a_f u_f theta_f - sum_{f: own_f = c} a_f u_f theta_f) / V_c.
+ * theta, rhs: device [n_cells][S]; u_f: device [n_faces]; 1 <= S <= FL_MAX_SCALARS.
+ * rhs must not alias theta.  work: device workspace of fl_apply_workspace_bytes bytes (the face
+ * fluxes of the face path; 0 bytes, work may be NULL, on the fused path). */
+size_t fl_apply_workspace_bytes(const fl_mesh *mesh, int n_scalars);
+fl_status fl_convect_apply(const fl_mesh *mesh, int limiter, int n_scalars, const double *theta,
+                           const double *u_f, double *rhs, void *work, void *hip_stream);
+
+/* Device workspace bytes needed by fl_rk_step / fl_rk_steps (256-byte aligned pointer). */
+size_t fl_rk_workspace_bytes(const fl_mesh *mesh, int scheme, int n_scalars);
+
+/* One (fl_rk_step) or n_steps (fl_rk_steps) explicit steps of size dt, theta updated in place.
+ * work: device workspace of fl_rk_workspace_bytes bytes, owned by the caller, not shared by
+ * calls that may run concurrently. */
+fl_status fl_rk_step(const fl_mesh *mesh, int limiter, int scheme, double dt, int n_scalars,
+                     double *theta, const double *u_f, void *work, void *hip_stream);
+fl_status fl_rk_steps(const fl_mesh *mesh, int limiter, int scheme, double dt, int n_scalars,
+                      int64_t n_steps, double *theta, const double *u_f, void *work,
+                      void *hip_stream);
+
+/* Adjoint of fl_convect_apply (discrete reverse mode; Q(u_f) and the branch of psi taken at
+ * theta are held fixed):
+ *   theta_bar += (dL/dtheta)^T rhs_bar,   u_bar += (dL/du_f)^T rhs_bar (skipped if NULL).
+ * theta, rhs_bar, theta_bar: device [n_cells][S]; u_f, u_bar: device [n_faces].
+ * Where theta_D == theta_C the limit of psi(d_U/d_u) d_u / 2 is differentiated (0 if also
+ * d_U == 0). */
+size_t fl_adjoint_workspace_bytes(const fl_mesh *mesh, int n_scalars);
+fl_status fl_convect_adjoint(const fl_mesh *mesh, int limiter, int n_scalars, const double *theta,
+                             const double *u_f, const double *rhs_bar, double *theta_bar,
+                             double *u_bar, void *work, void *hip_stream);
+
+/* Reverse of one explicit step.  stages: device [n_stage][n_cells][S], the stage inputs of the
+ * step (stage 0 is theta^n; SSP-RK3 also theta1, theta2).  lambda: device [n_cells][S], on entry
+ * the cotangent of theta^{n+1}, on exit that of theta^n.  u_bar (+=, nullable): [n_faces].
+ * work: fl_rk_adjoint_workspace_bytes bytes. */
+size_t fl_rk_adjoint_workspace_bytes(const fl_mesh *mesh, int scheme, int n_scalars);
+fl_status fl_rk_step_adjoint(const fl_mesh *mesh, int limiter, int scheme, double dt,
+                             int n_scalars, const double *stages, const double *u_f,
+                             double *lambda, double *u_bar, void *work, void *hip_stream);
+/* Forward step that also stores its stage inputs (same layout as above) for the adjoint. */
+fl_status fl_rk_step_store(const fl_mesh *mesh, int limiter, int scheme, double dt, int n_scalars,
+                           double *theta, const double *u_f, double *stages, void *work,
+                           void *hip_stream);
+
+/* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
+ * with one launch per Runge-Kutta stage for all of them (one fused cell-centric kernel over a
+ * work table of (problem, cell tile) entries).  Every mesh must support the fused path and live
+ * on `device`; meshes may be shared between problems.  theta[i] / u_f[i] are device pointers the
+ * batch keeps (not owned) until fl_batch_destroy.  tile_cells = 0 picks the tile size by timing
+ * candidates on the first fl_batch_step (autotuning); a positive value fixes it. */
+fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter,
+                          const int *n_scalars, const double *dt, int scheme,
+                          double *const *theta, const double *const *u_f, int tile_cells,
+                          int device, fl_batch **out);
+/* Advances every problem by n_steps steps; the first call records the launch sequence of one
+ * step in a HIP graph, later calls replay it. */
+fl_status fl_batch_step(fl_batch *batch, int n_steps, void *hip_stream);
+/* The same work as separate per-problem launches (no graph), for comparison. */
+fl_status fl_batch_step_unbatched(fl_batch *batch, int n_steps, void *hip_stream);
+fl_status fl_batch_tile(const fl_batch *batch, int *tile_cells);
+fl_status fl_batch_destroy(fl_batch *batch);
+
+const char *fl_status_str(fl_status status);
+const char *fl_last_error(void);
+
+/* Test hook: runs the device face selection for u_f (device [n_faces]) and copies, per face,
+ * (C, D, U) to cdu (host int32 [n_faces][3]).  Synchronises the stream. */
+fl_status fl_debug_select(const fl_mesh *mesh, const double *u_f, int32_t *cdu, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLUXLIM_H */

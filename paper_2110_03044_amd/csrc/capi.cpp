@@ -1,0 +1,410 @@
+// C ABI entry points: mesh lifetime, forward operator and explicit time steps.
+#include <hip/hip_runtime_api.h>
+
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "fl_internal.h"
+#include "fl_kernels.h"
+
+namespace fl {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+fl_status fail(fl_status st, const std::string &msg) {
+    g_error = msg;
+    return st;
+}
+
+namespace {
+
+fl_status hip_fail(hipError_t e, const char *what) {
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ")";
+    return fail(FL_E_HIP, os.str());
+}
+
+// Makes the mesh's device current for the scope of a call and restores the caller's device.
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) {
+            err = hipSetDevice(dev);
+            changed = (err == hipSuccess);
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+fl_status upload(T **dst, const T *src, size_t n, int64_t &bytes, const char *what) {
+    *dst = nullptr;
+    if (n == 0) return FL_OK;
+    hipError_t e = hipMalloc((void **)dst, n * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        std::ostringstream os;
+        os << "hipMalloc of " << what << " (" << n * sizeof(T) << " bytes) failed";
+        return fail(e == hipErrorOutOfMemory ? FL_E_NOMEM : FL_E_HIP, os.str());
+    }
+    bytes += (int64_t)(n * sizeof(T));
+    e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return FL_OK;
+}
+
+void free_device(fl_mesh *m) {
+    void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
+                    m->d_slot_far, m->d_rev,     m->d_area,   m->d_vol,       m->d_cell_perm,
+                    m->d_face_perm};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
+    m->d_slot_face = nullptr;
+    m->d_slot_nbr = m->d_slot_far = nullptr;
+    m->d_rev = nullptr;
+    m->d_area = m->d_vol = nullptr;
+    m->d_cell_perm = m->d_face_perm = nullptr;
+}
+
+fl_status check_compute(const fl_mesh *m, int lim, int S) {
+    if (!m) return fail(FL_E_INVALID, "mesh is NULL");
+    if (m->device < 0) return fail(FL_E_NODEVICE, "the mesh was created host-only (device = -1)");
+    if (lim < 0 || lim >= FL_NUM_LIMITERS) return fail(FL_E_INVALID, "unknown limiter");
+    if (S < 1 || S > FL_MAX_SCALARS) return fail(FL_E_INVALID, "n_scalars must be in [1, 8]");
+    return FL_OK;
+}
+
+bool misaligned(const void *p) { return ((uintptr_t)p & 7u) != 0; }
+
+constexpr double kRk3A[3] = {0.0, 0.75, 1.0 / 3.0};
+constexpr double kRk3B[3] = {1.0, 0.25, 2.0 / 3.0};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.
+hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b, int mode,
+                 const double *ts, const double *tn, const double *u, double *out, double *phi,
+                 hipStream_t st) {
+    if (m->path == FL_PATH_FUSED) return launch_fused(m, lim, S, ts, tn, u, a, b, dt, mode, out, st);
+    hipError_t e = launch_face_flux(m, lim, S, ts, u, phi, st);
+    if (e != hipSuccess) return e;
+    return launch_cell_update(m, S, phi, ts, tn, a, b, dt, mode, out, st);
+}
+
+struct Work {
+    double *phi = nullptr, *t1 = nullptr, *t2 = nullptr;
+};
+
+Work carve(const fl_mesh *m, int S, void *work) {
+    Work w;
+    char *p = (char *)work;
+    const size_t cell = align256((size_t)m->h.nc * S * sizeof(double));
+    if (m->path == FL_PATH_FACE_CELL) {
+        w.phi = (double *)p;
+        p += align256((size_t)m->h.nf * S * sizeof(double));
+    }
+    w.t1 = (double *)p;
+    p += cell;
+    w.t2 = (double *)p;
+    return w;
+}
+
+}  // namespace
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+const char *fl_status_str(fl_status s) {
+    switch (s) {
+        case FL_OK: return "FL_OK";
+        case FL_E_INVALID: return "FL_E_INVALID";
+        case FL_E_TOPOLOGY: return "FL_E_TOPOLOGY";
+        case FL_E_UNSUPPORTED: return "FL_E_UNSUPPORTED";
+        case FL_E_NOMEM: return "FL_E_NOMEM";
+        case FL_E_HIP: return "FL_E_HIP";
+        case FL_E_NODEVICE: return "FL_E_NODEVICE";
+        default: return "FL_E_UNKNOWN";
+    }
+}
+
+const char *fl_last_error(void) { return g_error.c_str(); }
+
+fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
+                           const double *face_normal) {
+    try {
+        HostTables t;
+        return build_host_tables(n_cells, n_faces, face_cells, face_normal, nullptr, nullptr,
+                                 false, t);
+    } catch (const std::bad_alloc &) {
+        return fail(FL_E_NOMEM, "host allocation failed");
+    }
+}
+
+fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
+                         const double *face_normal, const double *face_area,
+                         const double *cell_volume, int device, uint32_t flags, fl_mesh **out) {
+    if (!out) return fail(FL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(uint32_t)(FL_MESH_REORDER | FL_MESH_FACE_PATH))
+        return fail(FL_E_INVALID, "unknown flag");
+    if (device < -1) return fail(FL_E_INVALID, "device must be >= -1");
+    fl_mesh *m = nullptr;
+    try {
+        m = new fl_mesh();
+        fl_status st = build_host_tables(n_cells, n_faces, face_cells, face_normal, face_area,
+                                         cell_volume, (flags & FL_MESH_REORDER) != 0, m->h);
+        if (st != FL_OK) {
+            delete m;
+            return st;
+        }
+        m->reordered = (flags & FL_MESH_REORDER) != 0;
+        m->path = (m->h.pairs > 0 && !(flags & FL_MESH_FACE_PATH)) ? FL_PATH_FUSED
+                                                                    : FL_PATH_FACE_CELL;
+        m->device = device;
+        if (device >= 0) {
+            int ndev = 0;
+            hipError_t e = hipGetDeviceCount(&ndev);
+            if (e != hipSuccess || device >= ndev) {
+                delete m;
+                return fail(FL_E_HIP, "no such HIP device");
+            }
+            DeviceGuard g(device);
+            if (g.err != hipSuccess) {
+                delete m;
+                return hip_fail(g.err, "hipSetDevice");
+            }
+            const HostTables &h = m->h;
+            std::vector<int32_t> fc4((size_t)h.nf * 4);
+            for (int64_t f = 0; f < h.nf; ++f) {
+                fc4[4 * f] = h.fc[2 * f];
+                fc4[4 * f + 1] = h.fc[2 * f + 1];
+                fc4[4 * f + 2] = h.far[2 * f];
+                fc4[4 * f + 3] = h.far[2 * f + 1];
+            }
+            int64_t &B = m->device_bytes;
+            st = upload(&m->d_fc4, fc4.data(), fc4.size(), B, "face records");
+            if (st == FL_OK && !h.uniform_degree)
+                st = upload(&m->d_cf_ptr, h.cf_ptr.data(), h.cf_ptr.size(), B, "cell pointers");
+            if (st == FL_OK) st = upload(&m->d_cf_idx, h.cf_idx.data(), h.cf_idx.size(), B, "cell faces");
+            if (st == FL_OK && h.pairs > 0) {
+                st = upload(&m->d_slot_face, h.slot_face.data(), h.slot_face.size(), B, "slot faces");
+                if (st == FL_OK) st = upload(&m->d_slot_nbr, h.slot_nbr.data(), h.slot_nbr.size(), B, "slot cells");
+                if (st == FL_OK) st = upload(&m->d_slot_far, h.slot_far.data(), h.slot_far.size(), B, "slot far cells");
+                if (st == FL_OK)
+                    st = upload(&m->d_rev, reinterpret_cast<const int32_t *>(h.slot_rev.data()),
+                                h.slot_rev.size(), B, "slot opposite faces");
+            }
+            if (st == FL_OK && !h.uni_area) st = upload(&m->d_area, h.area.data(), h.area.size(), B, "areas");
+            if (st == FL_OK && !h.uni_vol) st = upload(&m->d_vol, h.vol.data(), h.vol.size(), B, "volumes");
+            if (st == FL_OK && m->reordered) {
+                st = upload(&m->d_cell_perm, h.cell_perm.data(), h.cell_perm.size(), B, "cell permutation");
+                if (st == FL_OK)
+                    st = upload(&m->d_face_perm, h.face_perm.data(), h.face_perm.size(), B, "face permutation");
+            }
+            if (st != FL_OK) {
+                free_device(m);
+                delete m;
+                return st;
+            }
+        }
+        *out = m;
+        return FL_OK;
+    } catch (const std::bad_alloc &) {
+        if (m) {
+            free_device(m);
+            delete m;
+        }
+        return fail(FL_E_NOMEM, "host allocation failed");
+    }
+}
+
+fl_status fl_mesh_destroy(fl_mesh *m) {
+    if (!m) return FL_OK;
+    if (m->device >= 0) {
+        DeviceGuard g(m->device);
+        free_device(m);
+    }
+    delete m;
+    return FL_OK;
+}
+
+fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
+    if (!m || !info) return fail(FL_E_INVALID, "NULL argument");
+    info->n_cells = m->h.nc;
+    info->n_faces = m->h.nf;
+    info->max_degree = m->h.max_degree;
+    info->pairs = m->h.pairs;
+    info->path = m->path;
+    info->device = m->device;
+    info->reordered = m->reordered ? 1 : 0;
+    info->uniform_area = m->h.uni_area ? 1 : 0;
+    info->uniform_volume = m->h.uni_vol ? 1 : 0;
+    info->device_bytes = m->device_bytes;
+    return FL_OK;
+}
+
+fl_status fl_mesh_permutation(const fl_mesh *m, int32_t *cell_perm, int32_t *face_perm) {
+    if (!m) return fail(FL_E_INVALID, "mesh is NULL");
+    if (cell_perm) {
+        if (m->reordered) std::memcpy(cell_perm, m->h.cell_perm.data(), m->h.nc * sizeof(int32_t));
+        else for (int64_t c = 0; c < m->h.nc; ++c) cell_perm[c] = (int32_t)c;
+    }
+    if (face_perm) {
+        if (m->reordered) std::memcpy(face_perm, m->h.face_perm.data(), m->h.nf * sizeof(int32_t));
+        else for (int64_t f = 0; f < m->h.nf; ++f) face_perm[f] = (int32_t)f;
+    }
+    return FL_OK;
+}
+
+fl_status fl_mesh_export_tables(const fl_mesh *m, int32_t *face_far, int32_t *cf_ptr,
+                                int32_t *cf_idx) {
+    if (!m) return fail(FL_E_INVALID, "mesh is NULL");
+    if (face_far) std::memcpy(face_far, m->h.far.data(), m->h.far.size() * sizeof(int32_t));
+    if (cf_ptr) std::memcpy(cf_ptr, m->h.cf_ptr.data(), m->h.cf_ptr.size() * sizeof(int32_t));
+    if (cf_idx) std::memcpy(cf_idx, m->h.cf_idx.data(), m->h.cf_idx.size() * sizeof(int32_t));
+    return FL_OK;
+}
+
+fl_status fl_permute_cells(const fl_mesh *m, int to_mesh, int S, const double *in, double *out,
+                           void *stream) {
+    fl_status s = check_compute(m, 0, S);
+    if (s != FL_OK) return s;
+    if (!in || !out || in == out) return fail(FL_E_INVALID, "in/out must be distinct non-NULL");
+    DeviceGuard g(m->device);
+    hipError_t e;
+    if (!m->reordered)
+        e = hipMemcpyAsync(out, in, m->h.nc * S * sizeof(double), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream);
+    else
+        e = launch_permute(m->h.nc, S, m->d_cell_perm, to_mesh, in, out, (hipStream_t)stream);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "permute cells");
+}
+
+fl_status fl_permute_faces(const fl_mesh *m, int to_mesh, const double *in, double *out,
+                           void *stream) {
+    fl_status s = check_compute(m, 0, 1);
+    if (s != FL_OK) return s;
+    if (!in || !out || in == out) return fail(FL_E_INVALID, "in/out must be distinct non-NULL");
+    DeviceGuard g(m->device);
+    hipError_t e;
+    if (!m->reordered)
+        e = hipMemcpyAsync(out, in, m->h.nf * sizeof(double), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream);
+    else
+        e = launch_permute(m->h.nf, 1, m->d_face_perm, to_mesh, in, out, (hipStream_t)stream);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "permute faces");
+}
+
+size_t fl_apply_workspace_bytes(const fl_mesh *m, int S) {
+    if (!m || S < 1 || S > FL_MAX_SCALARS) return 0;
+    return m->path == FL_PATH_FACE_CELL ? align256((size_t)m->h.nf * S * sizeof(double)) : 0;
+}
+
+fl_status fl_convect_apply(const fl_mesh *m, int lim, int S, const double *theta,
+                           const double *u, double *rhs, void *work, void *stream) {
+    fl_status s = check_compute(m, lim, S);
+    if (s != FL_OK) return s;
+    if (!theta || !u || !rhs) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(theta) || misaligned(u) || misaligned(rhs))
+        return fail(FL_E_INVALID, "device pointers must be 8-byte aligned");
+    if (rhs == theta) return fail(FL_E_INVALID, "rhs must not alias theta");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (m->path == FL_PATH_FUSED) {
+        e = launch_fused(m, lim, S, theta, theta, u, 0.0, 1.0, 0.0, MODE_RHS, rhs, st);
+    } else {
+        if (!work || ((uintptr_t)work & 255u))
+            return fail(FL_E_INVALID, "face-path meshes need a 256-byte aligned workspace");
+        double *phi = (double *)work;
+        e = launch_face_flux(m, lim, S, theta, u, phi, st);
+        if (e == hipSuccess)
+            e = launch_cell_update(m, S, phi, theta, theta, 0.0, 1.0, 0.0, MODE_RHS, rhs, st);
+    }
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_convect_apply launch");
+}
+
+size_t fl_rk_workspace_bytes(const fl_mesh *m, int scheme, int S) {
+    if (!m || S < 1 || S > FL_MAX_SCALARS || (scheme != FL_EULER && scheme != FL_SSPRK3)) return 0;
+    size_t b = 2 * align256((size_t)m->h.nc * S * sizeof(double));
+    if (m->path == FL_PATH_FACE_CELL) b += align256((size_t)m->h.nf * S * sizeof(double));
+    return b;
+}
+
+fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, int64_t n_steps,
+                      double *theta, const double *u, void *work, void *stream) {
+    fl_status s = check_compute(m, lim, S);
+    if (s != FL_OK) return s;
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (!theta || !u || !work) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(theta) || misaligned(u) || ((uintptr_t)work & 255u))
+        return fail(FL_E_INVALID, "theta/u must be 8-byte and work 256-byte aligned");
+    if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    if (!(dt == dt)) return fail(FL_E_INVALID, "dt is NaN");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    Work w = carve(m, S, work);
+    hipError_t e = hipSuccess;
+    if (scheme == FL_EULER) {
+        if (m->path == FL_PATH_FACE_CELL) {
+            for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i)
+                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, theta, theta, u, theta, w.phi, st);
+        } else {
+            // the fused kernel gathers its input, so it cannot write in place: ping-pong
+            double *src = theta, *dst = w.t1;
+            for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
+                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, src, src, u, dst, w.phi, st);
+                std::swap(src, dst);
+            }
+            if (e == hipSuccess && src != theta)
+                e = hipMemcpyAsync(theta, src, m->h.nc * S * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st);
+        }
+    } else {
+        for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
+            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, w.t1, w.phi, st);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, w.t1, theta, u, w.t2, w.phi, st);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, w.t2, theta, u, theta, w.phi, st);
+        }
+    }
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step launch");
+}
+
+fl_status fl_rk_step(const fl_mesh *m, int lim, int scheme, double dt, int S, double *theta,
+                     const double *u, void *work, void *stream) {
+    return fl_rk_steps(m, lim, scheme, dt, S, 1, theta, u, work, stream);
+}
+
+fl_status fl_debug_select(const fl_mesh *m, const double *u, int32_t *cdu, void *stream) {
+    fl_status s = check_compute(m, 0, 1);
+    if (s != FL_OK) return s;
+    if (!u || !cdu) return fail(FL_E_INVALID, "NULL pointer");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *d = nullptr;
+    hipError_t e = hipMalloc((void **)&d, m->h.nf * 3 * sizeof(int32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    e = launch_select(m, u, d, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cdu, d, m->h.nf * 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_debug_select");
+}
+
+}  // extern "C"

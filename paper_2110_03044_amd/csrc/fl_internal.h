@@ -1,0 +1,66 @@
+// Internal declarations of the flux-limiter library (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fluxlim.h"
+
+namespace fl {
+
+// Thread-local error text behind fl_last_error().
+void set_error(const std::string &msg);
+fl_status fail(fl_status st, const std::string &msg);
+
+// Host-side tables of a mesh, all in mesh order (see fl_mesh_create).
+struct HostTables {
+    int64_t nc = 0, nf = 0;
+    std::vector<int32_t> fc;        // [F][2] own, nbr
+    std::vector<double> nrm;        // [F][3]
+    std::vector<double> area;       // [F] (empty if uniform)
+    std::vector<double> vol;        // [C] (empty if uniform)
+    double area0 = 1.0, vol0 = 1.0; // the uniform values
+    bool uni_area = true, uni_vol = true;
+    std::vector<int32_t> far;       // [F][2] far-upwind cell for C = own, C = nbr
+    std::vector<int32_t> cf_ptr;    // [C+1]
+    std::vector<int32_t> cf_idx;    // signed: f (cell is nbr) or ~f (cell is own), ascending f
+    int32_t max_degree = 0;
+    bool uniform_degree = false;
+    int32_t pairs = 0;              // > 0 iff every cell has 2*pairs faces in opposite pairs
+    // Fused-path slot tables, structure of arrays [2*pairs][C].
+    std::vector<uint32_t> slot_face; // face index | (1u << 31) if the cell is the face's own
+    std::vector<int32_t> slot_nbr;   // the other cell of the face
+    std::vector<int32_t> slot_far;   // far-upwind cell of the face on the other cell's side
+    std::vector<uint32_t> slot_rev;  // face of the other cell opposite to this slot's face
+                                     // | (1u << 31) if the other cell is that face's own
+    // Numbering maps user -> mesh (empty = identity).
+    std::vector<int32_t> cell_perm, face_perm;
+};
+
+// Validates and builds every table; returns FL_OK or an error (message set).
+fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
+                            const double *face_normal, const double *face_area,
+                            const double *cell_volume, bool reorder, HostTables &t);
+
+}  // namespace fl
+
+// Device-side mesh (opaque to users).
+struct fl_mesh {
+    fl::HostTables h;
+    int device = -1;
+    int path = FL_PATH_FACE_CELL;
+    bool reordered = false;
+    // device tables
+    int32_t *d_fc4 = nullptr;      // [F][4] own, nbr, far_own, far_nbr
+    int32_t *d_cf_ptr = nullptr;   // [C+1] (null when every cell has max_degree faces)
+    int32_t *d_cf_idx = nullptr;   // signed face lists
+    uint32_t *d_slot_face = nullptr;
+    int32_t *d_slot_nbr = nullptr;
+    int32_t *d_slot_far = nullptr;
+    int32_t *d_rev = nullptr;      // [2P][C] adjoint: face of the neighbour opposite slot k
+    double *d_area = nullptr;      // [F] if non-uniform
+    double *d_vol = nullptr;       // [C] if non-uniform
+    int32_t *d_cell_perm = nullptr, *d_face_perm = nullptr;  // user -> mesh
+    int64_t device_bytes = 0;
+};

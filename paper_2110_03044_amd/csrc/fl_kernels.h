@@ -1,0 +1,27 @@
+// Launch wrappers of the HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "fl_internal.h"
+
+namespace fl {
+
+// Cell-stage modes: write rhs, theta_s + dt rhs, or a theta_n + b (theta_s + dt rhs).
+enum { MODE_RHS = 0, MODE_EULER = 1, MODE_RK = 2 };
+
+void set_xcd_remap(int on);
+
+hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
+                            const double *u, double *phi, hipStream_t st);
+hipError_t launch_cell_update(const fl_mesh *m, int S, const double *phi, const double *ts,
+                              const double *tn, double a, double b, double dt, int mode,
+                              double *out, hipStream_t st);
+hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                        const double *u, double a, double b, double dt, int mode, double *out,
+                        hipStream_t st);
+hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
+                          double *out, hipStream_t st);
+hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);
+
+}  // namespace fl

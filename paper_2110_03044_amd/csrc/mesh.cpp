@@ -1,0 +1,345 @@
+// Host-side mesh preprocessing: validation of the face-to-cell incidence and the tables the
+// kernels read.  Everything here runs once per mesh, before any time loop.
+//
+// From the incidence (own, nbr) and the unit face normals this builds, in mesh order:
+//   * the cell -> face lists (the transpose E_{F->C} of the oriented incidence, Section 2),
+//     each list in ascending face order with the orientation in the index sign;
+//   * per face and side the far-upwind cell: for C = own (flow along the normal) and for
+//     C = nbr (flow against it), the faces j != f of C are projected on the normal of f with
+//     weight w_j = s (n_f . t_j), t_j the normal of j oriented into C.  This is the upstream
+//     adjacency A^U_FF = (A_FF - Q A^D_FF)/2 of Section 3.1 applied through the normal matrices
+//     (d_U = Q N (I (x) A^U) N^T E theta), precomputed once as the paper precomputes S_{C->F} and
+//     T_{C->F}.  Exactly one face with weight 1 (the rest 0) is supported: hexahedra,
+//     quadrilaterals and lines, in any numbering; d_U is then theta_C - theta_U;
+//   * where every cell's faces form opposite pairs, the per-cell slot tables of the fused kernel;
+//   * optionally a breadth-first renumbering for gather locality.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <sstream>
+
+#include "fl_internal.h"
+
+namespace fl {
+namespace {
+
+constexpr double kWeightTol = 1e-9;
+constexpr double kNormTol = 1e-12;
+
+struct Csr {
+    std::vector<int64_t> ptr;  // [C+1]
+    std::vector<int32_t> idx;  // faces of each cell, ascending
+};
+
+Csr cell_faces(int64_t nc, int64_t nf, const int32_t *fc) {
+    Csr c;
+    c.ptr.assign(nc + 1, 0);
+    c.idx.resize(2 * nf);
+    for (int64_t f = 0; f < nf; ++f) {
+        c.ptr[fc[2 * f] + 1]++;
+        c.ptr[fc[2 * f + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < nc; ++i) c.ptr[i + 1] += c.ptr[i];
+    std::vector<int64_t> fill(c.ptr.begin(), c.ptr.end() - 1);
+    for (int64_t f = 0; f < nf; ++f) {
+        c.idx[fill[fc[2 * f]]++] = (int32_t)f;
+        c.idx[fill[fc[2 * f + 1]]++] = (int32_t)f;
+    }
+    return c;
+}
+
+inline int32_t other(const int32_t *fc, int64_t f, int64_t c) {
+    return fc[2 * f] == c ? fc[2 * f + 1] : fc[2 * f];
+}
+
+fl_status check_basic(int64_t nc, int64_t nf, const int32_t *fc, const double *nrm) {
+    if (!fc || !nrm) return fail(FL_E_INVALID, "face_cells and face_normal must not be NULL");
+    if (nc < 1 || nf < 1) return fail(FL_E_INVALID, "n_cells and n_faces must be positive");
+    if (nc > (int64_t)std::numeric_limits<int32_t>::max() - 1 || nf > (int64_t)(1 << 30) - 1)
+        return fail(FL_E_INVALID, "mesh too large for 32-bit cell and face indices");
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t a = fc[2 * f], b = fc[2 * f + 1];
+        if (b == -1 || a == -1) {
+            std::ostringstream os;
+            os << "face " << f << " is a boundary face (one cell); only closed (periodic) meshes "
+                  "are supported";
+            return fail(FL_E_UNSUPPORTED, os.str());
+        }
+        if (a < 0 || a >= nc || b < 0 || b >= nc) {
+            std::ostringstream os;
+            os << "face " << f << " references a cell outside [0, " << nc << ")";
+            return fail(FL_E_TOPOLOGY, os.str());
+        }
+        if (a == b) {
+            std::ostringstream os;
+            os << "face " << f << " joins cell " << a << " to itself";
+            return fail(FL_E_TOPOLOGY, os.str());
+        }
+        const double *n = nrm + 3 * f;
+        double n2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+        if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > kNormTol) {
+            std::ostringstream os;
+            os << "face " << f << " normal is not a finite unit vector";
+            return fail(FL_E_INVALID, os.str());
+        }
+    }
+    return FL_OK;
+}
+
+fl_status check_duplicates(int64_t nc, const int32_t *fc, const Csr &cs) {
+    std::vector<std::pair<int32_t, int32_t>> nb;
+    for (int64_t c = 0; c < nc; ++c) {
+        nb.clear();
+        for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p)
+            nb.emplace_back(other(fc, cs.idx[p], c), cs.idx[p]);
+        std::sort(nb.begin(), nb.end());
+        for (size_t i = 1; i < nb.size(); ++i)
+            if (nb[i].first == nb[i - 1].first) {
+                std::ostringstream os;
+                os << "faces " << nb[i - 1].second << " and " << nb[i].second
+                   << " both join cells " << c << " and " << nb[i].first
+                   << " (a periodic side shorter than 3 cells?)";
+                return fail(FL_E_TOPOLOGY, os.str());
+            }
+    }
+    return FL_OK;
+}
+
+// far[2f + side], opp[2f + side]: side 0 is C = own, side 1 is C = nbr.
+fl_status far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
+                     std::vector<int32_t> &far, std::vector<int32_t> &opp) {
+    far.assign(2 * nf, -1);
+    opp.assign(2 * nf, -1);
+    for (int64_t f = 0; f < nf; ++f) {
+        const double *nf_ = nrm + 3 * f;
+        for (int side = 0; side < 2; ++side) {
+            int64_t C = fc[2 * f + side];
+            double s = side == 0 ? 1.0 : -1.0;
+            int count = 0;
+            int64_t jj = -1;
+            double ww = 0.0;
+            for (int64_t p = cs.ptr[C]; p < cs.ptr[C + 1]; ++p) {
+                int64_t j = cs.idx[p];
+                if (j == f) continue;
+                const double *nj = nrm + 3 * j;
+                double t = fc[2 * j + 1] == C ? 1.0 : -1.0;
+                double w = s * t * (nf_[0] * nj[0] + nf_[1] * nj[1] + nf_[2] * nj[2]);
+                if (std::fabs(w) > kWeightTol) {
+                    ++count;
+                    jj = j;
+                    ww = w;
+                }
+            }
+            if (count != 1 || std::fabs(ww - 1.0) > kWeightTol) {
+                std::ostringstream os;
+                os << "face " << f << ", cell " << C << ": the upstream difference needs "
+                   << count << " projected faces (exactly one with weight 1 is supported: "
+                      "hexahedral, quadrilateral or line cells)";
+                return fail(FL_E_UNSUPPORTED, os.str());
+            }
+            far[2 * f + side] = other(fc, jj, C);
+            opp[2 * f + side] = (int32_t)jj;
+        }
+    }
+    return FL_OK;
+}
+
+// Breadth-first order of the cells (from a pseudo-peripheral start), one component after the
+// other.  Returns new_of_old.
+std::vector<int32_t> bfs_numbering(int64_t nc, const int32_t *fc, const Csr &cs) {
+    auto bfs = [&](int64_t start, std::vector<int32_t> &order) {
+        std::vector<char> seen(nc, 0);
+        order.clear();
+        order.reserve(nc);
+        int64_t next_unseen = 0;
+        int64_t s = start;
+        while ((int64_t)order.size() < nc) {
+            if (seen[s]) {
+                while (seen[next_unseen]) ++next_unseen;
+                s = next_unseen;
+            }
+            size_t head = order.size();
+            order.push_back((int32_t)s);
+            seen[s] = 1;
+            while (head < order.size()) {
+                int64_t c = order[head++];
+                for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+                    int64_t o = other(fc, cs.idx[p], c);
+                    if (!seen[o]) {
+                        seen[o] = 1;
+                        order.push_back((int32_t)o);
+                    }
+                }
+            }
+        }
+    };
+    std::vector<int32_t> order;
+    bfs(0, order);
+    int64_t start = order.back();
+    bfs(start, order);
+    std::vector<int32_t> new_of_old(nc);
+    for (int64_t i = 0; i < nc; ++i) new_of_old[order[i]] = (int32_t)i;
+    return new_of_old;
+}
+
+// Faces sorted by (lower, higher) new cell index.
+std::vector<int32_t> face_numbering(int64_t nc, int64_t nf, const int32_t *fc,
+                                    const std::vector<int32_t> &cnew) {
+    std::vector<int64_t> cnt(nc + 1, 0);
+    std::vector<int32_t> lo(nf), hi(nf);
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t a = cnew[fc[2 * f]], b = cnew[fc[2 * f + 1]];
+        lo[f] = std::min(a, b);
+        hi[f] = std::max(a, b);
+        cnt[lo[f] + 1]++;
+    }
+    for (int64_t i = 0; i < nc; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> bucket(nf);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t f = 0; f < nf; ++f) bucket[fill[lo[f]]++] = (int32_t)f;
+    for (int64_t c = 0; c < nc; ++c)
+        std::sort(bucket.begin() + cnt[c], bucket.begin() + cnt[c + 1],
+                  [&](int32_t x, int32_t y) { return hi[x] < hi[y] || (hi[x] == hi[y] && x < y); });
+    std::vector<int32_t> fnew(nf);
+    for (int64_t i = 0; i < nf; ++i) fnew[bucket[i]] = (int32_t)i;
+    return fnew;
+}
+
+void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) {
+    t.pairs = 0;
+    if (!t.uniform_degree || t.max_degree < 2 || (t.max_degree & 1)) return;
+    const int64_t nc = t.nc;
+    const int32_t *fc = t.fc.data();
+    auto side_of = [&](int64_t f, int64_t c) { return fc[2 * f] == c ? 0 : 1; };
+    // opposite faces must pair up: opp(c, opp(c, f)) == f
+    for (int64_t c = 0; c < nc; ++c)
+        for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+            int64_t f = cs.idx[p];
+            int64_t j = opp[2 * f + side_of(f, c)];
+            if (opp[2 * j + side_of(j, c)] != f) return;
+        }
+    const int K = t.max_degree, P = K / 2;
+    t.slot_face.assign((size_t)K * nc, 0);
+    t.slot_nbr.assign((size_t)K * nc, 0);
+    t.slot_far.assign((size_t)K * nc, 0);
+    t.slot_rev.assign((size_t)K * nc, 0);
+    std::vector<int32_t> slots(K);
+    for (int64_t c = 0; c < nc; ++c) {
+        int q = 0;
+        for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+            int32_t f = cs.idx[p];
+            bool placed = false;
+            for (int k = 0; k < q; ++k) placed |= (slots[k] == f);
+            if (placed) continue;
+            slots[q++] = f;
+            slots[q++] = opp[2 * f + side_of(f, c)];
+        }
+        for (int k = 0; k < K; ++k) {
+            int32_t f = slots[k];
+            int own_side = side_of(f, c) == 0;
+            int32_t n = other(fc, f, c);
+            size_t at = (size_t)k * nc + c;
+            t.slot_face[at] = (uint32_t)f | (own_side ? 0x80000000u : 0u);
+            t.slot_nbr[at] = n;
+            // far-upwind of f when the flow runs from n into c: on n's side
+            t.slot_far[at] = t.far[2 * f + (own_side ? 1 : 0)];
+            int32_t rf = opp[2 * f + (own_side ? 1 : 0)];  // face of n opposite to f
+            t.slot_rev[at] = (uint32_t)rf | (fc[2 * rf] == n ? 0x80000000u : 0u);
+        }
+    }
+    t.pairs = P;
+}
+
+}  // namespace
+
+fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
+                            const double *face_normal, const double *face_area,
+                            const double *cell_volume, bool reorder, HostTables &t) {
+    fl_status st = check_basic(nc, nf, face_cells, face_normal);
+    if (st != FL_OK) return st;
+    if (face_area)
+        for (int64_t f = 0; f < nf; ++f)
+            if (!(face_area[f] > 0.0) || !std::isfinite(face_area[f]))
+                return fail(FL_E_INVALID, "face areas must be finite and positive");
+    if (cell_volume)
+        for (int64_t c = 0; c < nc; ++c)
+            if (!(cell_volume[c] > 0.0) || !std::isfinite(cell_volume[c]))
+                return fail(FL_E_INVALID, "cell volumes must be finite and positive");
+
+    t = HostTables();
+    t.nc = nc;
+    t.nf = nf;
+    t.fc.assign(face_cells, face_cells + 2 * nf);
+    t.nrm.assign(face_normal, face_normal + 3 * nf);
+    std::vector<double> area, vol;
+    if (face_area) area.assign(face_area, face_area + nf);
+    if (cell_volume) vol.assign(cell_volume, cell_volume + nc);
+
+    Csr cs = cell_faces(nc, nf, t.fc.data());
+    st = check_duplicates(nc, t.fc.data(), cs);
+    if (st != FL_OK) return st;
+
+    if (reorder) {
+        std::vector<int32_t> cnew = bfs_numbering(nc, t.fc.data(), cs);
+        std::vector<int32_t> fnew = face_numbering(nc, nf, t.fc.data(), cnew);
+        std::vector<int32_t> fc2(2 * nf);
+        std::vector<double> nrm2(3 * nf);
+        for (int64_t f = 0; f < nf; ++f) {
+            int64_t g = fnew[f];
+            fc2[2 * g] = cnew[t.fc[2 * f]];
+            fc2[2 * g + 1] = cnew[t.fc[2 * f + 1]];
+            std::memcpy(&nrm2[3 * g], &t.nrm[3 * f], 3 * sizeof(double));
+        }
+        if (!area.empty()) {
+            std::vector<double> a2(nf);
+            for (int64_t f = 0; f < nf; ++f) a2[fnew[f]] = area[f];
+            area.swap(a2);
+        }
+        if (!vol.empty()) {
+            std::vector<double> v2(nc);
+            for (int64_t c = 0; c < nc; ++c) v2[cnew[c]] = vol[c];
+            vol.swap(v2);
+        }
+        t.fc.swap(fc2);
+        t.nrm.swap(nrm2);
+        t.cell_perm.swap(cnew);
+        t.face_perm.swap(fnew);
+        cs = cell_faces(nc, nf, t.fc.data());
+    }
+
+    // uniform area / volume are kept as one scalar
+    t.uni_area = true;
+    t.area0 = area.empty() ? 1.0 : area[0];
+    for (double a : area) t.uni_area &= (a == t.area0);
+    if (!t.uni_area) t.area.swap(area);
+    t.uni_vol = true;
+    t.vol0 = vol.empty() ? 1.0 : vol[0];
+    for (double v : vol) t.uni_vol &= (v == t.vol0);
+    if (!t.uni_vol) t.vol.swap(vol);
+
+    std::vector<int32_t> opp;
+    st = far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
+    if (st != FL_OK) return st;
+
+    t.cf_ptr.resize(nc + 1);
+    t.cf_idx.resize(2 * nf);
+    t.max_degree = 0;
+    int32_t min_degree = std::numeric_limits<int32_t>::max();
+    for (int64_t c = 0; c <= nc; ++c) t.cf_ptr[c] = (int32_t)cs.ptr[c];
+    for (int64_t c = 0; c < nc; ++c) {
+        int32_t d = (int32_t)(cs.ptr[c + 1] - cs.ptr[c]);
+        t.max_degree = std::max(t.max_degree, d);
+        min_degree = std::min(min_degree, d);
+        for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+            int32_t f = cs.idx[p];
+            t.cf_idx[p] = (t.fc[2 * f + 1] == c) ? f : ~f;
+        }
+    }
+    t.uniform_degree = (min_degree == t.max_degree);
+    build_slots(t, cs, opp);
+    return FL_OK;
+}
+
+}  // namespace fl

@@ -1,0 +1,212 @@
+"""Python API of the flux-limited convective operator (thin layer over the C ABI).
+
+PyTorch provides device memory and streams; every arithmetic step of the operator runs in the
+HIP kernels of libfluxlim.so.  Tensors are float64, contiguous and on the mesh's device.
+Cell fields are [n_cells] or [n_cells, S] (S <= 8 scalars, scalar index fastest).
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import call, lib
+
+LIMITERS = {"upwind": 0, "minmod": 1, "vanleer": 2, "vanalbada": 3, "superbee": 4, "smart": 5,
+            "central": 6}
+SCHEMES = {"euler": 1, "ssprk3": 3}
+MAX_SCALARS = 8
+
+
+def limiter_id(lim) -> int:
+    if isinstance(lim, str):
+        return LIMITERS[lim]
+    lim = int(lim)
+    if not 0 <= lim < len(LIMITERS):
+        raise ValueError(f"unknown limiter {lim}")
+    return lim
+
+
+def scheme_id(s) -> int:
+    return SCHEMES[s] if isinstance(s, str) else int(s)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device: torch.device, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Mesh:
+    """A mesh on one GPU, built from its face-to-cell incidence (see include/fluxlim.h)."""
+
+    def __init__(self, face_cells, face_normal, face_area=None, cell_volume=None, n_cells=None,
+                 device=0, reorder: bool = False, face_path: bool = False):
+        fc = np.ascontiguousarray(face_cells, dtype=np.int32)
+        nrm = np.ascontiguousarray(face_normal, dtype=np.float64)
+        if fc.ndim != 2 or fc.shape[1] != 2 or nrm.shape != (fc.shape[0], 3):
+            raise ValueError("face_cells must be [F, 2] and face_normal [F, 3]")
+        C = int(n_cells) if n_cells is not None else int(fc.max()) + 1
+        area = None if face_area is None else np.ascontiguousarray(face_area, dtype=np.float64)
+        vol = None if cell_volume is None else np.ascontiguousarray(cell_volume, dtype=np.float64)
+        if isinstance(device, torch.device):
+            device = device.index if device.index is not None else 0
+        flags = (_lib.FL_MESH_REORDER if reorder else 0) | (_lib.FL_MESH_FACE_PATH if face_path else 0)
+        h = ctypes.c_void_p()
+        call("fl_mesh_create", C, fc.shape[0], _np_ptr(fc), _np_ptr(nrm),
+             _np_ptr(area) if area is not None else None, _np_ptr(vol) if vol is not None else None,
+             int(device), flags, ctypes.byref(h))
+        self._h = h
+        info = _lib.MeshInfo()
+        call("fl_mesh_info", self._h, ctypes.byref(info))
+        self.info = info
+        self.n_cells = int(info.n_cells)
+        self.n_faces = int(info.n_faces)
+        self.device_index = int(info.device)
+        self.device = torch.device("cuda", self.device_index) if self.device_index >= 0 else None
+        self.path = "fused" if info.path == _lib.FL_PATH_FUSED else "face"
+        self.reordered = bool(info.reordered)
+
+    @classmethod
+    def from_arrays(cls, m, **kw) -> "Mesh":
+        """From a workloads.MeshArrays."""
+        return cls(m.face_cells, m.face_normal, m.face_area, m.cell_volume, n_cells=m.n_cells, **kw)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("mesh was closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fl_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- numbering ------------------------------------------------------------------------------
+    def permutation(self):
+        cp = np.empty(self.n_cells, dtype=np.int32)
+        fp = np.empty(self.n_faces, dtype=np.int32)
+        call("fl_mesh_permutation", self.handle, _np_ptr(cp), _np_ptr(fp))
+        return cp, fp
+
+    def export_tables(self):
+        far = np.empty((self.n_faces, 2), dtype=np.int32)
+        ptr = np.empty(self.n_cells + 1, dtype=np.int32)
+        call("fl_mesh_export_tables", self.handle, _np_ptr(far), _np_ptr(ptr), None)
+        idx = np.empty(int(ptr[-1]), dtype=np.int32)
+        call("fl_mesh_export_tables", self.handle, None, None, _np_ptr(idx))
+        return far, ptr, idx
+
+    def cells_to_mesh(self, x: torch.Tensor) -> torch.Tensor:
+        return self._permute_cells(x, 1)
+
+    def cells_from_mesh(self, x: torch.Tensor) -> torch.Tensor:
+        return self._permute_cells(x, 0)
+
+    def faces_to_mesh(self, u: torch.Tensor) -> torch.Tensor:
+        return self._permute_faces(u, 1)
+
+    def faces_from_mesh(self, u: torch.Tensor) -> torch.Tensor:
+        return self._permute_faces(u, 0)
+
+    def _permute_cells(self, x, to_mesh):
+        x = self._cells(x)
+        out = torch.empty_like(x)
+        call("fl_permute_cells", self.handle, to_mesh, _S(x), _tptr(x), _tptr(out),
+             _stream(self.device))
+        return out
+
+    def _permute_faces(self, u, to_mesh):
+        u = self._faces(u)
+        out = torch.empty_like(u)
+        call("fl_permute_faces", self.handle, to_mesh, _tptr(u), _tptr(out), _stream(self.device))
+        return out
+
+    # -- argument checks ------------------------------------------------------------------------
+    def _cells(self, x: torch.Tensor) -> torch.Tensor:
+        if x.dtype != torch.float64 or x.device != self.device or not x.is_contiguous():
+            raise ValueError("cell fields must be contiguous float64 tensors on the mesh's device")
+        if x.shape[0] != self.n_cells or x.dim() not in (1, 2) or _S(x) > MAX_SCALARS:
+            raise ValueError(f"cell field must be [{self.n_cells}] or [{self.n_cells}, S<=8]")
+        return x
+
+    def _faces(self, u: torch.Tensor) -> torch.Tensor:
+        if u.dtype != torch.float64 or u.device != self.device or not u.is_contiguous():
+            raise ValueError("face fields must be contiguous float64 tensors on the mesh's device")
+        if u.shape != (self.n_faces,):
+            raise ValueError(f"face field must be [{self.n_faces}]")
+        return u
+
+    def debug_select(self, u: torch.Tensor) -> np.ndarray:
+        out = np.empty((self.n_faces, 3), dtype=np.int32)
+        call("fl_debug_select", self.handle, _tptr(self._faces(u)), _np_ptr(out),
+             _stream(self.device))
+        return out
+
+
+def _S(x: torch.Tensor) -> int:
+    return 1 if x.dim() == 1 else int(x.shape[1])
+
+
+def _workspace(nbytes: int, device) -> Optional[torch.Tensor]:
+    if nbytes == 0:
+        return None
+    w = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-w.data_ptr()) % 256
+    return w[off:off + nbytes]
+
+
+def apply_workspace(mesh: Mesh, S: int) -> Optional[torch.Tensor]:
+    return _workspace(int(lib().fl_apply_workspace_bytes(mesh.handle, S)), mesh.device)
+
+
+def rk_workspace(mesh: Mesh, scheme, S: int) -> torch.Tensor:
+    return _workspace(int(lib().fl_rk_workspace_bytes(mesh.handle, scheme_id(scheme), S)),
+                      mesh.device)
+
+
+def convect_apply(mesh: Mesh, limiter, theta: torch.Tensor, u: torch.Tensor,
+                  out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """rhs = L(theta): the divergence of the limited face fluxes (Algorithm 4's operator)."""
+    theta = mesh._cells(theta)
+    u = mesh._faces(u)
+    S = _S(theta)
+    if out is None:
+        out = torch.empty_like(theta)
+    if work is None:
+        work = apply_workspace(mesh, S)
+    call("fl_convect_apply", mesh.handle, limiter_id(limiter), S, _tptr(theta), _tptr(u),
+         _tptr(out), _tptr(work), _stream(mesh.device, stream))
+    return out
+
+
+def rk_steps(mesh: Mesh, limiter, scheme, dt: float, theta: torch.Tensor, u: torch.Tensor,
+             n_steps: int = 1, work: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Advances theta in place by n_steps explicit steps (forward Euler or SSP-RK3)."""
+    theta = mesh._cells(theta)
+    u = mesh._faces(u)
+    S = _S(theta)
+    if work is None:
+        work = rk_workspace(mesh, scheme, S)
+    call("fl_rk_steps", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
+         int(n_steps), _tptr(theta), _tptr(u), _tptr(work), _stream(mesh.device, stream))
+    return theta

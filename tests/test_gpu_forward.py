@@ -1,0 +1,200 @@
+"""GPU parity of the forward operator and time steps against the CPU oracle.
+
+Tolerances: per face the kernels and the oracle evaluate the same FP64 expressions, except that
+the kernels may contract a*b+c into one fused multiply-add and sum a cell's faces in another
+order; each stage therefore differs by a few units in the last place of the cell values.  One
+operator application is compared at 1e-13 of max|rhs|; whole runs (hundreds of stages) at the
+1e-10 max norm-relative error of the cell values that the method's accuracy target fixes.
+Connectivity and the upwind selection are compared bit for bit.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2110_03044_amd import fluxlim as FL, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+LIMS = ["upwind", "minmod", "vanleer", "vanalbada", "superbee", "smart", "central"]
+RUN_TOL = 1e-10
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def nrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def mesh_pair(m, **kw):
+    """Library mesh plus the user -> mesh maps."""
+    mesh = FL.Mesh.from_arrays(m, device=0, **kw)
+    cp, fp = mesh.permutation()
+    return mesh, cp, fp
+
+
+def to_mesh_cells(x, cp):
+    out = np.empty_like(x)
+    out[cp] = x
+    return out
+
+
+def to_mesh_faces(u, fp):
+    out = np.empty_like(u)
+    out[fp] = u
+    return out
+
+
+CASES = [
+    ("line7", lambda: W.periodic_box(7, 1)),
+    ("quad9r", lambda: W.renumber(W.periodic_box(9, 2), seed=4)),
+    ("hex11r", lambda: W.renumber(W.periodic_box(11, 3), seed=5)),
+    ("hex24r", lambda: W.renumber(W.periodic_box(24, 3), seed=6)),
+]
+
+
+@pytest.mark.parametrize("path", ["fused", "face"])
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_selection_bit_exact(name, make, reorder, path):
+    m = make()
+    mesh, cp, fp = mesh_pair(m, reorder=reorder, face_path=(path == "face"))
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal(m.n_faces)
+    u[::7] = 0.0
+    u[3::7] = -0.0
+    got = mesh.debug_select(dev(to_mesh_faces(u, fp)))
+    want = O.OracleMesh.from_arrays(m).select(u)
+    assert np.array_equal(got[fp], cp[want])
+
+
+@pytest.mark.parametrize("path", ["fused", "face"])
+@pytest.mark.parametrize("S", [1, 3, 8])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_apply_matches_oracle(name, make, S, path):
+    m = make()
+    mesh, cp, fp = mesh_pair(m, reorder=True, face_path=(path == "face"))
+    assert mesh.path == path
+    rng = np.random.default_rng(S)
+    th = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+    th[::5] = th[1::5][: th[::5].shape[0]]  # equal neighbours: d_u == 0 cases
+    u = rng.standard_normal(m.n_faces)
+    om = O.OracleMesh.from_arrays(m)
+    thd, ud = dev(to_mesh_cells(th, cp)), dev(to_mesh_faces(u, fp))
+    for lim in LIMS:
+        want = om.rhs(lim, th, u)
+        got = host(FL.convect_apply(mesh, lim, thd, ud))[cp]
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), lim
+
+
+def test_apply_plateaus_and_infinite_ratio():
+    """Integer-valued steps: many faces with d_u == 0 and r = +-inf."""
+    m = W.renumber(W.periodic_box(13, 3), seed=9)
+    mesh, cp, fp = mesh_pair(m)
+    rng = np.random.default_rng(5)
+    th = rng.integers(0, 3, m.n_cells).astype(np.float64)
+    u = rng.standard_normal(m.n_faces)
+    om = O.OracleMesh.from_arrays(m)
+    for lim in LIMS:
+        want = om.rhs(lim, th, u)
+        got = host(FL.convect_apply(mesh, lim, dev(to_mesh_cells(th, cp)), dev(to_mesh_faces(u, fp))))[cp]
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("lim", LIMS[:6])
+def test_line_config_euler_400_steps(lim):
+    """1-D line, 200 cells, square wave + Gaussian, u = 1, Euler at CFL 1/2, one period."""
+    wl = W.workload_line()
+    mesh, cp, fp = mesh_pair(wl.mesh)
+    th = dev(wl.theta0)
+    FL.rk_steps(mesh, lim, "euler", wl.dt, th, dev(wl.u), wl.steps)
+    want = O.OracleMesh.from_arrays(wl.mesh).run(lim, "euler", wl.dt, wl.theta0, wl.u, wl.steps)
+    got = host(th)
+    assert nrel(got, want) <= RUN_TOL
+    # conservation and (for TVD limiters) boundedness on the GPU result itself
+    assert abs(got.sum() - wl.theta0.sum()) <= 1e-13 * np.abs(wl.theta0).sum()
+    if lim in ("upwind", "minmod", "vanleer", "superbee"):
+        lo, hi = wl.theta0.min(), wl.theta0.max()
+        assert got.min() >= lo - 1e-12 and got.max() <= hi + 1e-12
+
+
+@pytest.mark.parametrize("path", ["fused", "face"])
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("lim", ["minmod", "vanleer", "superbee", "smart"])
+def test_box_ssprk3_run(lim, reorder, path):
+    wl = W.workload_box(20, renumbered=True, steps=40)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=reorder, face_path=(path == "face"))
+    th = dev(to_mesh_cells(wl.theta0, cp))
+    FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, dev(to_mesh_faces(wl.u, fp)), wl.steps)
+    want = O.OracleMesh.from_arrays(wl.mesh).run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, wl.steps)
+    got = host(th)[cp]
+    assert nrel(got, want) <= RUN_TOL
+    V = wl.mesh.cell_volume
+    assert abs((V * got).sum() - (V * wl.theta0).sum()) <= 1e-13 * (V * np.abs(wl.theta0)).sum()
+
+
+@pytest.mark.parametrize("path", ["fused", "face"])
+def test_euler_multi_scalar_and_ragged(path):
+    m = W.renumber(W.periodic_box(7, 3), seed=2)  # 343 cells: a ragged last block
+    wl_u = m.face_velocity_from_natural(W.velocity_curl(7, seed=4))
+    th = W.multi_scalar([m.cell_field_from_natural(W.field_blob_step(7)),
+                         m.cell_field_from_natural(W.field_smooth_random(7, 3, 1)),
+                         m.cell_field_from_natural(W.field_sphere(7))])
+    dt = W.cfl_dt(m, wl_u, 0.3)
+    mesh, cp, fp = mesh_pair(m, reorder=True, face_path=(path == "face"))
+    t = dev(to_mesh_cells(th, cp))
+    FL.rk_steps(mesh, "superbee", "euler", dt, t, dev(to_mesh_faces(wl_u, fp)), 25)
+    want = O.OracleMesh.from_arrays(m).run("superbee", "euler", dt, th, wl_u, 25)
+    assert nrel(host(t)[cp], want) <= RUN_TOL
+
+
+def test_zero_steps_and_zero_velocity_and_determinism():
+    wl = W.workload_box(9, renumbered=True)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    th0 = dev(to_mesh_cells(wl.theta0, cp))
+    u = dev(to_mesh_faces(wl.u, fp))
+    t = th0.clone()
+    FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, u, 0)
+    assert torch.equal(t, th0)
+    FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, torch.zeros_like(u), 3)
+    assert torch.equal(t, th0)
+    a, b = th0.clone(), th0.clone()
+    FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, a, u, 7)
+    FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, b, u, 7)
+    assert torch.equal(a, b)
+
+
+def test_permute_roundtrip():
+    wl = W.workload_box(10, renumbered=True)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    th = dev(wl.theta0)
+    tm = mesh.cells_to_mesh(th)
+    assert np.array_equal(host(tm), to_mesh_cells(wl.theta0, cp))
+    assert torch.equal(mesh.cells_from_mesh(tm), th)
+    u = dev(wl.u)
+    um = mesh.faces_to_mesh(u)
+    assert np.array_equal(host(um), to_mesh_faces(wl.u, fp))
+    assert torch.equal(mesh.faces_from_mesh(um), u)
+
+
+def test_box128_config_van_leer():
+    """3-D periodic hex box 128^3 in generic incidence, curl velocity, blob + step, van Leer,
+    SSP-RK3 at CFL 0.4 (the first 12 of the 100 steps; the oracle bounds the test time)."""
+    wl = W.workload_box(128, steps=12)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    th = dev(to_mesh_cells(wl.theta0, cp))
+    FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, dev(to_mesh_faces(wl.u, fp)), wl.steps)
+    want = O.OracleMesh.from_arrays(wl.mesh).run("vanleer", "ssprk3", wl.dt, wl.theta0, wl.u, wl.steps)
+    assert nrel(host(th)[cp], want) <= RUN_TOL

@@ -1,0 +1,159 @@
+"""Host-side checks of the HIP library (no GPU): exported symbols, mesh validation and the
+tables the kernels read, compared bit for bit with the oracle's face selection."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2110_03044_amd import _lib, fluxlim as FL, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?\**\s*\**(fl_[a-z0-9_]+)\s*\(",
+                                text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 25
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_status_strings():
+    L = _lib.lib()
+    assert L.fl_status_str(0) == b"FL_OK"
+    assert L.fl_status_str(-3) == b"FL_E_UNSUPPORTED"
+
+
+def _meshes():
+    out = []
+    for n, d in [(7, 1), (6, 2), (5, 3), (7, 3)]:
+        nat = W.periodic_box(n, d)
+        out.append((f"{d}d{n}", nat))
+        out.append((f"{d}d{n}r", W.renumber(nat, seed=3 * n + d)))
+    return out
+
+
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("name,m", _meshes(), ids=lambda x: x if isinstance(x, str) else "")
+def test_tables_match_oracle_selection(name, m, reorder):
+    mesh = FL.Mesh.from_arrays(m, device=-1, reorder=reorder)
+    assert mesh.path == "fused" and mesh.info.pairs == max(m.dim, 1)
+    far, ptr, idx = mesh.export_tables()
+    cp, fp = mesh.permutation()
+    assert np.array_equal(np.sort(cp), np.arange(m.n_cells))
+    assert np.array_equal(np.sort(fp), np.arange(m.n_faces))
+    if not reorder:
+        assert np.array_equal(cp, np.arange(m.n_cells)) and np.array_equal(fp, np.arange(m.n_faces))
+    om = O.OracleMesh.from_arrays(m)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(m.n_faces)
+    u[::11] = 0.0
+    cdu = om.select(u)  # user numbering
+    # library tables are in mesh numbering: map the oracle's cells through cell_perm
+    pos = u > 0
+    mf = fp  # mesh face of each user face
+    U_lib = np.where(pos, far[mf, 0], far[mf, 1])
+    assert np.array_equal(U_lib, cp[cdu[:, 2]])
+    # cell -> face lists: same sets, ascending in mesh order, orientation in the sign
+    fc_mesh = np.empty_like(m.face_cells)
+    fc_mesh[fp] = cp[m.face_cells]
+    for c in range(0, m.n_cells, max(1, m.n_cells // 50)):
+        ent = idx[ptr[c]:ptr[c + 1]]
+        faces = np.where(ent >= 0, ent, ~ent)
+        assert np.all(np.diff(faces) > 0)
+        for e, f in zip(ent, faces):
+            assert (fc_mesh[f, 1] == c) if e >= 0 else (fc_mesh[f, 0] == c)
+        assert len(faces) == 2 * max(m.dim, 1)
+
+
+def test_reorder_improves_index_locality():
+    m = W.renumber(W.periodic_box(16, 3), seed=1)
+    rnd = FL.Mesh.from_arrays(m, device=-1)
+    ro = FL.Mesh.from_arrays(m, device=-1, reorder=True)
+
+    def spread(mesh):
+        far, ptr, idx = mesh.export_tables()
+        faces = np.where(idx >= 0, idx, ~idx).reshape(-1, 6)
+        return np.abs(faces - faces.mean(axis=1, keepdims=True)).mean()
+
+    assert spread(ro) < 0.2 * spread(rnd)
+
+
+def _err(fc, nrm, n_cells):
+    L = _lib.lib()
+    fc = np.ascontiguousarray(fc, dtype=np.int32)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+    st = L.fl_mesh_validate(n_cells, fc.shape[0], fc.ctypes.data_as(ctypes.c_void_p),
+                            nrm.ctypes.data_as(ctypes.c_void_p))
+    return st, L.fl_last_error().decode()
+
+
+def test_validate_accepts_periodic_hex():
+    m = W.renumber(W.periodic_box(4, 3), seed=2)
+    assert _err(m.face_cells, m.face_normal, m.n_cells)[0] == 0
+
+
+def test_validate_rejections():
+    m = W.periodic_box(4, 3)
+    fc, nrm, C = m.face_cells.copy(), m.face_normal.copy(), m.n_cells
+    bad = fc.copy(); bad[5, 1] = -1
+    assert _err(bad, nrm, C)[0] == -3  # boundary face
+    bad = fc.copy(); bad[5, 1] = C
+    assert _err(bad, nrm, C)[0] == -2  # out of range
+    bad = fc.copy(); bad[5, 1] = bad[5, 0]
+    assert _err(bad, nrm, C)[0] == -2  # own == nbr
+    badn = nrm.copy(); badn[3] *= 1.1
+    assert _err(fc, badn, C)[0] == -1  # not unit
+    badn = nrm.copy(); badn[3, 0] = np.nan
+    assert _err(fc, badn, C)[0] == -1
+    # periodic side of 2 cells: two faces join the same pair of cells
+    m2 = W.periodic_box(2, 3)
+    st, msg = _err(m2.face_cells, m2.face_normal, m2.n_cells)
+    assert st == -2 and "both join" in msg
+    # a tilted normal makes the upstream difference need two faces
+    badn = nrm.copy(); badn[0] = [np.sqrt(0.5), np.sqrt(0.5), 0.0]
+    st, msg = _err(fc, badn, C)
+    assert st == -3 and "projected faces" in msg
+
+
+def test_create_rejects_bad_arguments_and_host_only_compute():
+    m = W.periodic_box(4, 3)
+    with pytest.raises(_lib.FluxLimError) as e:
+        FL.Mesh(m.face_cells[:, ::-1].copy() * 0, m.face_normal, device=-1, n_cells=m.n_cells)
+    assert e.value.status == -2
+    mesh = FL.Mesh.from_arrays(m, device=-1)
+    L = _lib.lib()
+    st = L.fl_convect_apply(mesh.handle, 2, 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                            ctypes.c_void_p(16), None, None)
+    assert st == -6  # FL_E_NODEVICE
+    st = L.fl_rk_steps(mesh.handle, 9, 3, 0.1, 1, 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                       ctypes.c_void_p(256), None)
+    assert st in (-1, -6)
+    assert L.fl_rk_workspace_bytes(mesh.handle, 3, 1) == 2 * ((m.n_cells * 8 + 255) // 256 * 256)
+    assert L.fl_rk_workspace_bytes(mesh.handle, 2, 1) == 0
+    face = FL.Mesh.from_arrays(m, device=-1, face_path=True)
+    assert face.path == "face"
+    assert L.fl_apply_workspace_bytes(face.handle, 2) >= m.n_faces * 16
+
+
+def test_nonuniform_area_and_volume_kept():
+    m = W.periodic_box(5, 3)
+    area = m.face_area * (1 + 0.1 * np.arange(m.n_faces) / m.n_faces)
+    mesh = FL.Mesh(m.face_cells, m.face_normal, area, m.cell_volume, device=-1)
+    assert mesh.info.uniform_area == 0 and mesh.info.uniform_volume == 1
