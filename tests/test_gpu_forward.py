@@ -89,7 +89,7 @@ def test_apply_matches_oracle(name, make, S, path):
     assert mesh.path == path
     rng = np.random.default_rng(S)
     th = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
-    th[::5] = th[1::5][: th[::5].shape[0]]  # equal neighbours: d_u == 0 cases
+    th[::3] = np.round(th[::3])  # repeated values: d_u == 0 and infinite-ratio cases
     u = rng.standard_normal(m.n_faces)
     om = O.OracleMesh.from_arrays(m)
     thd, ud = dev(to_mesh_cells(th, cp)), dev(to_mesh_faces(u, fp))
@@ -168,8 +168,10 @@ def test_zero_steps_and_zero_velocity_and_determinism():
     t = th0.clone()
     FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, u, 0)
     assert torch.equal(t, th0)
+    FL.rk_steps(mesh, "vanleer", "euler", wl.dt, t, torch.zeros_like(u), 3)
+    assert torch.equal(t, th0)  # zero flux: theta + dt * 0 is theta
     FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, torch.zeros_like(u), 3)
-    assert torch.equal(t, th0)
+    assert (t - th0).abs().max().item() <= 4e-16 * th0.abs().max().item()
     a, b = th0.clone(), th0.clone()
     FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, a, u, 7)
     FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, b, u, 7)
