@@ -73,9 +73,12 @@ enum { FL_EULER = 1, FL_SSPRK3 = 3 };
 
 /* fl_mesh_create flags */
 enum {
-    FL_MESH_REORDER = 1,   /* renumber cells (breadth-first) and faces for gather locality   */
-    FL_MESH_FACE_PATH = 2  /* use the face-kernel + cell-gather pair even where the fused
-                              cell-centric kernel applies                                     */
+    FL_MESH_REORDER = 1,     /* renumber cells along a space-filling (Morton) curve of the
+                                lattice coordinates found by walking the face normals, and
+                                faces by their lower cell, for gather locality                */
+    FL_MESH_FACE_PATH = 2,   /* use the face-kernel + cell-gather pair even where the fused
+                                cell-centric kernel applies                                   */
+    FL_MESH_REORDER_BFS = 4  /* renumber cells breadth-first instead (any connected mesh)    */
 };
 
 /* Kernel paths reported by fl_mesh_info */

@@ -17,6 +17,7 @@ STATUS = {0: "FL_OK", -1: "FL_E_INVALID", -2: "FL_E_TOPOLOGY", -3: "FL_E_UNSUPPO
 
 FL_MESH_REORDER = 1
 FL_MESH_FACE_PATH = 2
+FL_MESH_REORDER_BFS = 4
 FL_PATH_FACE_CELL = 1
 FL_PATH_FUSED = 2
 

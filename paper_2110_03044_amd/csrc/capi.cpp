@@ -147,7 +147,7 @@ fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face
     try {
         HostTables t;
         return build_host_tables(n_cells, n_faces, face_cells, face_normal, nullptr, nullptr,
-                                 false, t);
+                                 REORDER_NONE, t);
     } catch (const std::bad_alloc &) {
         return fail(FL_E_NOMEM, "host allocation failed");
     }
@@ -158,19 +158,23 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                          const double *cell_volume, int device, uint32_t flags, fl_mesh **out) {
     if (!out) return fail(FL_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (flags & ~(uint32_t)(FL_MESH_REORDER | FL_MESH_FACE_PATH))
+    if (flags & ~(uint32_t)(FL_MESH_REORDER | FL_MESH_FACE_PATH | FL_MESH_REORDER_BFS))
         return fail(FL_E_INVALID, "unknown flag");
+    if ((flags & FL_MESH_REORDER) && (flags & FL_MESH_REORDER_BFS))
+        return fail(FL_E_INVALID, "FL_MESH_REORDER and FL_MESH_REORDER_BFS are exclusive");
+    const int reorder = (flags & FL_MESH_REORDER) ? REORDER_CURVE
+                        : (flags & FL_MESH_REORDER_BFS) ? REORDER_BFS : REORDER_NONE;
     if (device < -1) return fail(FL_E_INVALID, "device must be >= -1");
     fl_mesh *m = nullptr;
     try {
         m = new fl_mesh();
         fl_status st = build_host_tables(n_cells, n_faces, face_cells, face_normal, face_area,
-                                         cell_volume, (flags & FL_MESH_REORDER) != 0, m->h);
+                                         cell_volume, reorder, m->h);
         if (st != FL_OK) {
             delete m;
             return st;
         }
-        m->reordered = (flags & FL_MESH_REORDER) != 0;
+        m->reordered = reorder != REORDER_NONE;
         m->path = (m->h.pairs > 0 && !(flags & FL_MESH_FACE_PATH)) ? FL_PATH_FUSED
                                                                     : FL_PATH_FACE_CELL;
         m->device = device;

@@ -38,10 +38,12 @@ struct HostTables {
     std::vector<int32_t> cell_perm, face_perm;
 };
 
+enum { REORDER_NONE = 0, REORDER_CURVE = 1, REORDER_BFS = 2 };
+
 // Validates and builds every table; returns FL_OK or an error (message set).
 fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
                             const double *face_normal, const double *face_area,
-                            const double *cell_volume, bool reorder, HostTables &t);
+                            const double *cell_volume, int reorder, HostTables &t);
 
 }  // namespace fl
 

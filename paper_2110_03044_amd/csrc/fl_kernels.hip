@@ -13,9 +13,10 @@
 //     cell computing the fluxes of its own faces from the slot tables; every face is evaluated by
 //     both of its cells with identical arithmetic, so the two contributions cancel exactly in
 //     the global sum and no flux array is written.
-// Launches use 256-thread workgroups; the grid is padded to a multiple of the 8 XCDs and block
-// ids are remapped so each XCD sweeps one contiguous eighth of the mesh (its L2 then holds the
-// neighbourhood of the cells it works on).
+// Launches use 256-thread workgroups, one thread per face or cell.  The fused kernel is bound by
+// its gathers, not by arithmetic: at 256^3 with a locality-ordered mesh the bytes it fetches
+// past L2 equal its compulsory traffic, so the mesh ordering (see mesh.cpp) is what keeps it
+// near the memory roofline.
 #include <hip/hip_runtime.h>
 
 #include "fl_kernels.h"
@@ -164,63 +165,54 @@ __global__ __launch_bounds__(kBlock) void cell_update_kernel(
 // ------------------------------------------------------------------------------------------
 // Fused path
 // ------------------------------------------------------------------------------------------
-// Contribution of one face of cell c: n is the other cell, g the far-upwind cell on n's side,
-// o the neighbour across the opposite face of c (far-upwind on c's side).
-template <int S>
-__device__ __forceinline__ void fused_face(int lim, uint32_t fw, double uf, double au,
-                                           const double *tc, const double *tn_,
-                                           const double *to, const double *__restrict__ theta,
-                                           int64_t g, double *acc) {
-    const bool c_is_own = (fw >> 31) != 0;
-    const bool pos = uf > 0.0;
-    // Q(u_f): C = own where u_f > 0, nbr otherwise
-    const bool c_upwind = (pos == c_is_own);
-    double tf[S];
-    if (c_upwind) {
-#pragma unroll
-        for (int k = 0; k < S; ++k) tf[k] = face_value(lim, tc[k], tn_[k], to[k]);
-    } else if (lim == FL_UPWIND) {
-#pragma unroll
-        for (int k = 0; k < S; ++k) tf[k] = tn_[k];
-    } else {
-        double tg[S];
-        load_cell<S>(theta, g, tg);
-#pragma unroll
-        for (int k = 0; k < S; ++k) tf[k] = face_value(lim, tn_[k], tc[k], tg[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const double ph = au * tf[k];
-        if (c_is_own) acc[k] -= ph;
-        else acc[k] += ph;
-    }
-}
-
-template <int S>
+// One thread per cell c with P opposite-face pairs (slots 2p and 2p+1 are opposite faces).
+// Slot k gives the face f_k (bit 31: c is its own), the other cell n_k and the far-upwind cell
+// g_k on n_k's side; the far-upwind cell on c's side of f_k is n_{k^1}.  Every table entry and
+// gather is issued before any arithmetic so all of a thread's memory requests are in flight at
+// once (the kernel is bound by gather latency and L2 misses, not by arithmetic).
+template <int S, int P>
 __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
-    int64_t nc, int P, const uint32_t *__restrict__ sface, const int32_t *__restrict__ snbr,
+    int64_t nc, const uint32_t *__restrict__ sface, const int32_t *__restrict__ snbr,
     const int32_t *__restrict__ sfar, const double *__restrict__ u,
     const double *__restrict__ area, double area0, const double *__restrict__ vol, double vol0,
     const double *__restrict__ ts, const double *__restrict__ tn, double a, double b, double dt,
     int mode, int lim, double *__restrict__ out, int remap) {
+    constexpr int K = 2 * P;
     const int64_t c = block_id(remap) * kBlock + threadIdx.x;
     if (c >= nc) return;
-    double tc[S], acc[S];
+    uint32_t fw[K];
+    int64_t nb[K], gf[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        fw[k] = sface[(int64_t)k * nc + c];
+        nb[k] = snbr[(int64_t)k * nc + c];
+        gf[k] = sfar[(int64_t)k * nc + c];
+    }
+    double tc[S], tnb[K][S], tg[K][S], uu[K], au[K];
     load_cell<S>(ts, c, tc);
 #pragma unroll
-    for (int k = 0; k < S; ++k) acc[k] = 0.0;
-    for (int p = 0; p < P; ++p) {
-        const int64_t s0 = (int64_t)(2 * p) * nc + c, s1 = s0 + nc;
-        const uint32_t f0 = sface[s0], f1 = sface[s1];
-        const int64_t n0 = snbr[s0], n1 = snbr[s1];
-        const int64_t i0 = f0 & 0x7fffffffu, i1 = f1 & 0x7fffffffu;
-        const double u0 = u[i0], u1 = u[i1];
-        double t0[S], t1[S];
-        load_cell<S>(ts, n0, t0);
-        load_cell<S>(ts, n1, t1);
-        const double a0 = area ? area[i0] : area0, a1 = area ? area[i1] : area0;
-        fused_face<S>(lim, f0, u0, a0 * u0, tc, t0, t1, ts, sfar[s0], acc);
-        fused_face<S>(lim, f1, u1, a1 * u1, tc, t1, t0, ts, sfar[s1], acc);
+    for (int k = 0; k < K; ++k) {
+        const int64_t f = fw[k] & 0x7fffffffu;
+        uu[k] = u[f];
+        au[k] = (area ? area[f] : area0) * uu[k];
+        load_cell<S>(ts, nb[k], tnb[k]);
+        if (lim != FL_UPWIND) load_cell<S>(ts, gf[k], tg[k]);
+    }
+    double acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const bool c_is_own = (fw[k] >> 31) != 0;
+        // Q(u_f): C = own where u_f > 0, C = nbr otherwise
+        const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double tf = c_upwind ? face_value(lim, tc[s], tnb[k][s], tnb[k ^ 1][s])
+                                       : face_value(lim, tnb[k][s], tc[s], tg[k][s]);
+            const double ph = au[k] * tf;
+            acc[s] = c_is_own ? acc[s] - ph : acc[s] + ph;
+        }
     }
     finish_cell<S>(c, acc, vol ? vol[c] : vol0, ts, tn, a, b, dt, mode, out);
 }
@@ -288,7 +280,11 @@ Grid grid_for(int64_t n, bool remap) {
         default: return hipErrorInvalidValue;    \
     }
 
-int g_remap = 1;
+// Block ids map to cells in launch order by default: with a locality-ordered mesh the
+// round-robin spread of consecutive blocks over the 8 XCDs measured ~7% faster at 256^3 than
+// giving each XCD a contiguous eighth of the mesh (the MALL, shared by all XCDs, serves the
+// neighbourhood reuse either way).  The remapped order stays available for tuning.
+int g_remap = 0;
 void set_xcd_remap(int on) { g_remap = on; }
 
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
@@ -316,10 +312,18 @@ hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, cons
                         const double *u, double a, double b, double dt, int mode, double *out,
                         hipStream_t st) {
     Grid g = grid_for(m->h.nc, g_remap);
-    FL_DISPATCH_S(S, (dev::fused_stage_kernel<kS><<<g.blocks, dev::kBlock, 0, st>>>(
-                         m->h.nc, m->h.pairs, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, u,
-                         m->d_area, m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim,
-                         out, g.remap)));
+#define FL_FUSED(P)                                                                           \
+    FL_DISPATCH_S(S, (dev::fused_stage_kernel<kS, P><<<g.blocks, dev::kBlock, 0, st>>>(       \
+                         m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, u, m->d_area, \
+                         m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out,   \
+                         g.remap)))
+    switch (m->h.pairs) {
+        case 1: FL_FUSED(1); break;
+        case 2: FL_FUSED(2); break;
+        case 3: FL_FUSED(3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FL_FUSED
     return hipGetLastError();
 }
 

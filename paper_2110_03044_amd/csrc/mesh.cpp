@@ -12,7 +12,7 @@
 //     T_{C->F}.  Exactly one face with weight 1 (the rest 0) is supported: hexahedra,
 //     quadrilaterals and lines, in any numbering; d_U is then theta_C - theta_U;
 //   * where every cell's faces form opposite pairs, the per-cell slot tables of the fused kernel;
-//   * optionally a breadth-first renumbering for gather locality.
+//   * optionally a renumbering for gather locality (space-filling curve or breadth-first).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -184,6 +184,66 @@ std::vector<int32_t> bfs_numbering(int64_t nc, const int32_t *fc, const Csr &cs)
     return new_of_old;
 }
 
+// Space-filling-curve order.  Cell positions are recovered by a breadth-first walk that steps by
+// the unit face normal across every face (+n_f from own to nbr): on hexahedral, quadrilateral
+// and line meshes this gives the integer lattice coordinates of every cell (a periodic mesh is
+// cut open opposite the root).  Cells are then sorted by the Morton (bit-interleaved) code of
+// their coordinates, so any run of consecutive cells is a compact block of the mesh and the
+// cells a workgroup gathers from lie in it or in the blocks next to it.  Returns new_of_old.
+std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double *nrm,
+                                     const Csr &cs) {
+    std::vector<double> pos(3 * nc, 0.0);
+    std::vector<char> seen(nc, 0);
+    std::vector<int32_t> queue;
+    queue.reserve(nc);
+    double lo[3] = {0, 0, 0};
+    int64_t next_unseen = 0;
+    double comp_shift = 0.0;  // separate components along x
+    while ((int64_t)queue.size() < nc) {
+        while (seen[next_unseen]) ++next_unseen;
+        size_t head = queue.size();
+        queue.push_back((int32_t)next_unseen);
+        seen[next_unseen] = 1;
+        pos[3 * next_unseen] = comp_shift;
+        double hi_x = comp_shift;
+        while (head < queue.size()) {
+            int64_t c = queue[head++];
+            for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+                int64_t f = cs.idx[p];
+                int64_t o = other(fc, f, c);
+                if (seen[o]) continue;
+                seen[o] = 1;
+                double s = fc[2 * f] == c ? 1.0 : -1.0;
+                for (int d = 0; d < 3; ++d) pos[3 * o + d] = pos[3 * c + d] + s * nrm[3 * f + d];
+                hi_x = std::max(hi_x, pos[3 * o]);
+                queue.push_back((int32_t)o);
+            }
+        }
+        comp_shift = hi_x + 2.0;
+    }
+    for (int64_t c = 0; c < nc; ++c)
+        for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], pos[3 * c + d]);
+    auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffULL;
+        v = (v | v << 16) & 0x1f0000ff0000ffULL;
+        v = (v | v << 8) & 0x100f00f00f00f00fULL;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+        v = (v | v << 2) & 0x1249249249249249ULL;
+        return v;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> key(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        uint64_t q[3];
+        for (int d = 0; d < 3; ++d) q[d] = (uint64_t)std::llround(pos[3 * c + d] - lo[d]);
+        key[c] = {spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2, (int32_t)c};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> new_of_old(nc);
+    for (int64_t i = 0; i < nc; ++i) new_of_old[key[i].second] = (int32_t)i;
+    return new_of_old;
+}
+
 // Faces sorted by (lower, higher) new cell index.
 std::vector<int32_t> face_numbering(int64_t nc, int64_t nf, const int32_t *fc,
                                     const std::vector<int32_t> &cnew) {
@@ -209,7 +269,8 @@ std::vector<int32_t> face_numbering(int64_t nc, int64_t nf, const int32_t *fc,
 
 void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) {
     t.pairs = 0;
-    if (!t.uniform_degree || t.max_degree < 2 || (t.max_degree & 1)) return;
+    // the fused kernel is instantiated for 1, 2 and 3 pairs (lines, quadrilaterals, hexahedra)
+    if (!t.uniform_degree || t.max_degree < 2 || (t.max_degree & 1) || t.max_degree > 6) return;
     const int64_t nc = t.nc;
     const int32_t *fc = t.fc.data();
     auto side_of = [&](int64_t f, int64_t c) { return fc[2 * f] == c ? 0 : 1; };
@@ -256,7 +317,7 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
 
 fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
                             const double *face_normal, const double *face_area,
-                            const double *cell_volume, bool reorder, HostTables &t) {
+                            const double *cell_volume, int reorder, HostTables &t) {
     fl_status st = check_basic(nc, nf, face_cells, face_normal);
     if (st != FL_OK) return st;
     if (face_area)
@@ -282,7 +343,9 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     if (st != FL_OK) return st;
 
     if (reorder) {
-        std::vector<int32_t> cnew = bfs_numbering(nc, t.fc.data(), cs);
+        std::vector<int32_t> cnew = reorder == REORDER_BFS
+                                        ? bfs_numbering(nc, t.fc.data(), cs)
+                                        : curve_numbering(nc, t.fc.data(), t.nrm.data(), cs);
         std::vector<int32_t> fnew = face_numbering(nc, nf, t.fc.data(), cnew);
         std::vector<int32_t> fc2(2 * nf);
         std::vector<double> nrm2(3 * nf);

@@ -52,7 +52,7 @@ class Mesh:
     """A mesh on one GPU, built from its face-to-cell incidence (see include/fluxlim.h)."""
 
     def __init__(self, face_cells, face_normal, face_area=None, cell_volume=None, n_cells=None,
-                 device=0, reorder: bool = False, face_path: bool = False):
+                 device=0, reorder=False, face_path: bool = False):
         fc = np.ascontiguousarray(face_cells, dtype=np.int32)
         nrm = np.ascontiguousarray(face_normal, dtype=np.float64)
         if fc.ndim != 2 or fc.shape[1] != 2 or nrm.shape != (fc.shape[0], 3):
@@ -62,7 +62,10 @@ class Mesh:
         vol = None if cell_volume is None else np.ascontiguousarray(cell_volume, dtype=np.float64)
         if isinstance(device, torch.device):
             device = device.index if device.index is not None else 0
-        flags = (_lib.FL_MESH_REORDER if reorder else 0) | (_lib.FL_MESH_FACE_PATH if face_path else 0)
+        if reorder not in (False, True, "curve", "bfs"):
+            raise ValueError("reorder must be False, True/'curve' or 'bfs'")
+        flags = ((_lib.FL_MESH_REORDER_BFS if reorder == "bfs" else _lib.FL_MESH_REORDER if reorder else 0)
+                 | (_lib.FL_MESH_FACE_PATH if face_path else 0))
         h = ctypes.c_void_p()
         call("fl_mesh_create", C, fc.shape[0], _np_ptr(fc), _np_ptr(nrm),
              _np_ptr(area) if area is not None else None, _np_ptr(vol) if vol is not None else None,
