@@ -394,6 +394,112 @@ fl_status fl_rk_step(const fl_mesh *m, int lim, int scheme, double dt, int S, do
     return fl_rk_steps(m, lim, scheme, dt, S, 1, theta, u, work, stream);
 }
 
+// ------------------------------------------------------------------------------------------
+// Adjoint
+// ------------------------------------------------------------------------------------------
+size_t fl_adjoint_workspace_bytes(const fl_mesh *m, int S) {
+    (void)m;
+    (void)S;
+    return 0;  // the fused adjoint kernel gathers everything it needs
+}
+
+static fl_status check_adjoint(const fl_mesh *m, int lim, int S) {
+    fl_status s = check_compute(m, lim, S);
+    if (s != FL_OK) return s;
+    if (m->h.pairs == 0)
+        return fail(FL_E_UNSUPPORTED,
+                    "the adjoint needs cells whose faces form opposite pairs (uniform degree)");
+    return FL_OK;
+}
+
+fl_status fl_convect_adjoint(const fl_mesh *m, int lim, int S, const double *theta,
+                             const double *u, const double *rhs_bar, double *theta_bar,
+                             double *u_bar, void *work, void *stream) {
+    (void)work;
+    fl_status s = check_adjoint(m, lim, S);
+    if (s != FL_OK) return s;
+    if (!theta || !u || !rhs_bar || !theta_bar) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(theta) || misaligned(u) || misaligned(rhs_bar) || misaligned(theta_bar) ||
+        misaligned(u_bar))
+        return fail(FL_E_INVALID, "device pointers must be 8-byte aligned");
+    if (theta_bar == rhs_bar || theta_bar == theta)
+        return fail(FL_E_INVALID, "theta_bar must not alias theta or rhs_bar");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_adjoint(m, lim, S, u, theta, rhs_bar, 0.0, 1.0, 0.0, ADJ_APPLY,
+                                  theta_bar, nullptr, u_bar, (hipStream_t)stream);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_convect_adjoint launch");
+}
+
+size_t fl_rk_adjoint_workspace_bytes(const fl_mesh *m, int scheme, int S) {
+    if (!m || S < 1 || S > FL_MAX_SCALARS || (scheme != FL_EULER && scheme != FL_SSPRK3)) return 0;
+    return 2 * align256((size_t)m->h.nc * S * sizeof(double));
+}
+
+fl_status fl_rk_step_store(const fl_mesh *m, int lim, int scheme, double dt, int S,
+                           double *theta, const double *u, double *stages, void *work,
+                           void *stream) {
+    fl_status s = check_compute(m, lim, S);
+    if (s != FL_OK) return s;
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (!theta || !u || !stages || !work) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(theta) || misaligned(u) || misaligned(stages) || ((uintptr_t)work & 255u))
+        return fail(FL_E_INVALID, "theta/u/stages must be 8-byte and work 256-byte aligned");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cell = (size_t)m->h.nc * S;
+    Work w = carve(m, S, work);
+    hipError_t e = hipMemcpyAsync(stages, theta, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        if (scheme == FL_EULER) {
+            // stage input is theta^n itself (already stored); out of place, then back
+            e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, stages, stages, u, theta, w.phi, st);
+        } else {
+            double *t1 = stages + cell, *t2 = stages + 2 * cell;
+            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, t1, w.phi, st);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, t1, theta, u, t2, w.phi, st);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, t2, theta, u, theta, w.phi, st);
+        }
+    }
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step_store launch");
+}
+
+fl_status fl_rk_step_adjoint(const fl_mesh *m, int lim, int scheme, double dt, int S,
+                             const double *stages, const double *u, double *lambda,
+                             double *u_bar, void *work, void *stream) {
+    fl_status s = check_adjoint(m, lim, S);
+    if (s != FL_OK) return s;
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (!stages || !u || !lambda || !work) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(stages) || misaligned(u) || misaligned(lambda) || misaligned(u_bar) ||
+        ((uintptr_t)work & 255u))
+        return fail(FL_E_INVALID, "pointers must be 8-byte and work 256-byte aligned");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cell = (size_t)m->h.nc * S;
+    double *w1 = (double *)work;
+    double *w2 = (double *)((char *)work + align256(cell * sizeof(double)));
+    hipError_t e;
+    if (scheme == FL_EULER) {
+        e = launch_adjoint(m, lim, S, u, stages, lambda, 0.0, 1.0, dt, ADJ_EULER, w1, nullptr,
+                           u_bar, st);
+    } else {
+        // stage 3 reads lambda, stage 2 reads w1 and writes lambda, stage 1 reads lambda
+        e = launch_adjoint(m, lim, S, u, stages + 2 * cell, lambda, kRk3A[2], kRk3B[2], dt,
+                           ADJ_LAST, w1, w2, u_bar, st);
+        if (e == hipSuccess)
+            e = launch_adjoint(m, lim, S, u, stages + cell, w1, kRk3A[1], kRk3B[1], dt, ADJ_MID,
+                               lambda, w2, u_bar, st);
+        if (e == hipSuccess)
+            e = launch_adjoint(m, lim, S, u, stages, lambda, kRk3A[0], kRk3B[0], dt, ADJ_FIRST,
+                               w1, w2, u_bar, st);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(lambda, w1, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step_adjoint launch");
+}
+
 fl_status fl_debug_select(const fl_mesh *m, const double *u, int32_t *cdu, void *stream) {
     fl_status s = check_compute(m, 0, 1);
     if (s != FL_OK) return s;

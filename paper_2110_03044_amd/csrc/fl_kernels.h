@@ -10,7 +10,14 @@ namespace fl {
 // Cell-stage modes: write rhs, theta_s + dt rhs, or a theta_n + b (theta_s + dt rhs).
 enum { MODE_RHS = 0, MODE_EULER = 1, MODE_RK = 2 };
 
+// Adjoint-stage modes (see fl_adjoint.hip).
+enum { ADJ_APPLY = 0, ADJ_EULER = 1, ADJ_LAST = 2, ADJ_MID = 3, ADJ_FIRST = 4 };
+
 void set_xcd_remap(int on);
+
+hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, const double *th,
+                          const double *lam, double a, double b, double dt, int mode, double *out,
+                          double *acc, double *ubar, hipStream_t st);
 
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
                             const double *u, double *phi, hipStream_t st);

@@ -4,20 +4,6 @@
 using namespace fl;
 
 extern "C" {
-size_t fl_adjoint_workspace_bytes(const fl_mesh *, int) { return 0; }
-fl_status fl_convect_adjoint(const fl_mesh *, int, int, const double *, const double *,
-                             const double *, double *, double *, void *, void *) {
-    return fail(FL_E_UNSUPPORTED, "not implemented");
-}
-size_t fl_rk_adjoint_workspace_bytes(const fl_mesh *, int, int) { return 0; }
-fl_status fl_rk_step_adjoint(const fl_mesh *, int, int, double, int, const double *,
-                             const double *, double *, double *, void *, void *) {
-    return fail(FL_E_UNSUPPORTED, "not implemented");
-}
-fl_status fl_rk_step_store(const fl_mesh *, int, int, double, int, double *, const double *,
-                           double *, void *, void *) {
-    return fail(FL_E_UNSUPPORTED, "not implemented");
-}
 fl_status fl_batch_create(int, fl_mesh *const *, const int *, const int *, const double *, int,
                           double *const *, const double *const *, int, int, fl_batch **) {
     return fail(FL_E_UNSUPPORTED, "not implemented");

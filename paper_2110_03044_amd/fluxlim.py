@@ -213,3 +213,122 @@ def rk_steps(mesh: Mesh, limiter, scheme, dt: float, theta: torch.Tensor, u: tor
     call("fl_rk_steps", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
          int(n_steps), _tptr(theta), _tptr(u), _tptr(work), _stream(mesh.device, stream))
     return theta
+
+
+# ---------------------------------------------------------------------------------------------
+# Adjoint
+# ---------------------------------------------------------------------------------------------
+
+def n_stages(scheme) -> int:
+    return 1 if scheme_id(scheme) == SCHEMES["euler"] else 3
+
+
+def convect_adjoint(mesh: Mesh, limiter, theta: torch.Tensor, u: torch.Tensor,
+                    rhs_bar: torch.Tensor, theta_bar: Optional[torch.Tensor] = None,
+                    u_bar: Optional[torch.Tensor] = None, stream=None):
+    """theta_bar += (dL/dtheta)^T rhs_bar and u_bar += (dL/du)^T rhs_bar (fresh zeros if None)."""
+    theta = mesh._cells(theta)
+    u = mesh._faces(u)
+    rhs_bar = mesh._cells(rhs_bar)
+    if theta_bar is None:
+        theta_bar = torch.zeros_like(theta)
+    if u_bar is None:
+        u_bar = torch.zeros_like(u)
+    call("fl_convect_adjoint", mesh.handle, limiter_id(limiter), _S(theta), _tptr(theta), _tptr(u),
+         _tptr(rhs_bar), _tptr(mesh._cells(theta_bar)), _tptr(mesh._faces(u_bar)), None,
+         _stream(mesh.device, stream))
+    return theta_bar, u_bar
+
+
+def stage_buffer(mesh: Mesh, scheme, S: int, n_steps: int = 1) -> torch.Tensor:
+    """Storage for the stage inputs of n_steps steps: [n_steps, stages, n_cells(, S)]."""
+    shape = (n_steps, n_stages(scheme), mesh.n_cells) + ((S,) if S > 1 else ())
+    return torch.empty(shape, dtype=torch.float64, device=mesh.device)
+
+
+def rk_adjoint_workspace(mesh: Mesh, scheme, S: int) -> torch.Tensor:
+    return _workspace(int(lib().fl_rk_adjoint_workspace_bytes(mesh.handle, scheme_id(scheme), S)),
+                      mesh.device)
+
+
+def rk_step_store(mesh: Mesh, limiter, scheme, dt, theta, u, stages, work=None, stream=None):
+    """One step in place on theta, storing its stage inputs in stages ([stages, C(, S)])."""
+    theta = mesh._cells(theta)
+    S = _S(theta)
+    if work is None:
+        work = rk_workspace(mesh, scheme, S)
+    if not stages.is_contiguous() or stages.numel() != n_stages(scheme) * theta.numel():
+        raise ValueError("stages must be a contiguous [stages, n_cells(, S)] float64 buffer")
+    call("fl_rk_step_store", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
+         _tptr(theta), _tptr(mesh._faces(u)), _tptr(stages), _tptr(work),
+         _stream(mesh.device, stream))
+    return theta
+
+
+def rk_step_adjoint(mesh: Mesh, limiter, scheme, dt, stages, u, lam, u_bar=None, work=None,
+                    stream=None):
+    """Reverse of one step: lam (cotangent of theta^{n+1}) becomes that of theta^n in place;
+    u_bar += the step's contribution to d/du."""
+    lam = mesh._cells(lam)
+    S = _S(lam)
+    if work is None:
+        work = rk_adjoint_workspace(mesh, scheme, S)
+    if not stages.is_contiguous() or stages.numel() != n_stages(scheme) * lam.numel():
+        raise ValueError("stages must be a contiguous [stages, n_cells(, S)] float64 buffer")
+    call("fl_rk_step_adjoint", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
+         _tptr(stages), _tptr(mesh._faces(u)), _tptr(lam),
+         _tptr(mesh._faces(u_bar)) if u_bar is not None else None, _tptr(work),
+         _stream(mesh.device, stream))
+    return lam
+
+
+def checkpoint_interval(n_steps: int) -> int:
+    """ceil(sqrt(n_steps)): sqrt(N) checkpoints, each segment recomputed once in the backward."""
+    import math
+    return max(1, math.isqrt(max(n_steps - 1, 0)) + 1) if n_steps > 0 else 1
+
+
+class _Advect(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta0, u, mesh, limiter, scheme, dt, n_steps, every):
+        theta = mesh._cells(theta0.detach()).clone()
+        u_d = mesh._faces(u.detach())
+        S = _S(theta)
+        work = rk_workspace(mesh, scheme, S)
+        ckpts = []
+        for start in range(0, n_steps, every):
+            ckpts.append(theta.clone())
+            rk_steps(mesh, limiter, scheme, dt, theta, u_d, min(every, n_steps - start), work=work)
+        ctx.mesh, ctx.limiter, ctx.scheme, ctx.dt = mesh, limiter, scheme, dt
+        ctx.n_steps, ctx.every, ctx.ckpts = n_steps, every, ckpts
+        ctx.save_for_backward(u_d)
+        return theta
+
+    @staticmethod
+    def backward(ctx, grad):
+        (u_d,) = ctx.saved_tensors
+        mesh, lim, scheme, dt = ctx.mesh, ctx.limiter, ctx.scheme, ctx.dt
+        lam = grad.detach().to(torch.float64).contiguous().clone()
+        S = _S(lam)
+        u_bar = torch.zeros_like(u_d)
+        work = rk_workspace(mesh, scheme, S)
+        awork = rk_adjoint_workspace(mesh, scheme, S)
+        stages = stage_buffer(mesh, scheme, S, min(ctx.every, max(ctx.n_steps, 1)))
+        for seg in reversed(range(len(ctx.ckpts))):
+            start = seg * ctx.every
+            count = min(ctx.every, ctx.n_steps - start)
+            th = ctx.ckpts[seg].clone()
+            for j in range(count):  # recompute the segment, storing every stage input
+                rk_step_store(mesh, lim, scheme, dt, th, u_d, stages[j], work=work)
+            for j in reversed(range(count)):
+                rk_step_adjoint(mesh, lim, scheme, dt, stages[j], u_d, lam, u_bar, work=awork)
+        ctx.ckpts = None
+        return lam, u_bar, None, None, None, None, None, None
+
+
+def advect(mesh: Mesh, limiter, scheme, dt: float, theta0: torch.Tensor, u: torch.Tensor,
+           n_steps: int, checkpoint_every: Optional[int] = None) -> torch.Tensor:
+    """theta after n_steps explicit steps, differentiable w.r.t. theta0 and u (hand-written
+    discrete adjoint, ceil(sqrt(n_steps))-step checkpoints recomputed in the backward pass)."""
+    every = checkpoint_every or checkpoint_interval(n_steps)
+    return _Advect.apply(theta0, u, mesh, limiter, scheme, float(dt), int(n_steps), int(every))

@@ -1,0 +1,214 @@
+"""GPU parity of the discrete adjoint against the CPU oracle's reverse sweep, tangent and finite
+differences.
+
+Tolerances: the adjoint kernels sum a cell's contributions in another order than the oracle's
+serial scatter, so one reverse application agrees to a few ulps of the largest contribution
+(compared at 1e-12 of max|grad|); reverse sweeps over many steps at 1e-10 norm-relative, as the
+forward runs.  Finite differences (central, eps = 1e-6 relative) carry O(eps^2) truncation and
+O(1e-16/eps) rounding error, hence the 1e-6 relative bar on a smooth (van Albada) run whose
+field has no two equal neighbours (no d_u = 0 kinks) and whose velocity perturbation flips no
+face's sign.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2110_03044_amd import fluxlim as FL, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+LIMS = ["upwind", "minmod", "vanleer", "vanalbada", "superbee", "smart", "central"]
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def maps(mesh):
+    cp, fp = mesh.permutation()
+    return cp, fp
+
+
+def cells_in(x, cp):
+    out = np.empty_like(x)
+    out[cp] = x
+    return out
+
+
+def noisy_box(n, seed=0, renumbered=True):
+    wl = W.workload_box(n, renumbered=renumbered)
+    rng = np.random.default_rng(seed)
+    th = wl.theta0 + 1e-3 * rng.standard_normal(wl.mesh.n_cells)
+    return wl, th, rng
+
+
+@pytest.mark.parametrize("S", [1, 3])
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("lim", LIMS)
+def test_operator_adjoint_matches_oracle(lim, reorder, S):
+    wl, th1, rng = noisy_box(9, seed=S)
+    m = wl.mesh
+    th = np.stack([th1] + [rng.standard_normal(m.n_cells) for _ in range(S - 1)], 1) if S > 1 else th1
+    th[::4] = np.round(th[::4])  # plateaus: d_u == 0 and infinite ratios
+    lam = rng.standard_normal(th.shape)
+    u = wl.u.copy()
+    u[::9] = 0.0
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=reorder)
+    cp, fp = maps(mesh)
+    uf = np.empty_like(u)
+    uf[fp] = u
+    tb, ub = FL.convect_adjoint(mesh, lim, dev(cells_in(th, cp)), dev(uf), dev(cells_in(lam, cp)))
+    tb_o, ub_o = O.OracleMesh.from_arrays(m).rhs_vjp(lim, th, u, lam)
+    got_t, got_u = host(tb)[cp], host(ub)[fp]
+    assert np.abs(got_t - tb_o).max() <= 1e-12 * np.abs(tb_o).max()
+    assert np.abs(got_u - ub_o).max() <= 1e-12 * np.abs(ub_o).max()
+
+
+def test_operator_adjoint_accumulates_and_skips_null_u_bar():
+    wl, th, rng = noisy_box(6)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0)
+    lam = dev(rng.standard_normal(th.shape))
+    t, u = dev(th), dev(wl.u)
+    tb1, ub1 = FL.convect_adjoint(mesh, "vanalbada", t, u, lam)
+    tb2 = tb1.clone()
+    ub2 = ub1.clone()
+    FL.convect_adjoint(mesh, "vanalbada", t, u, lam, tb2, ub2)
+    assert torch.allclose(tb2, 2 * tb1, rtol=1e-15, atol=0) and torch.allclose(ub2, 2 * ub1, rtol=1e-15, atol=0)
+    from paper_2110_03044_amd._lib import lib
+    import ctypes
+    tb3 = torch.zeros_like(t)
+    st = lib().fl_convect_adjoint(mesh.handle, 3, 1, ctypes.c_void_p(t.data_ptr()),
+                                  ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                  ctypes.c_void_p(tb3.data_ptr()), None, None, None)
+    torch.cuda.synchronize()
+    assert st == 0 and torch.equal(tb3, tb1)
+
+
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+@pytest.mark.parametrize("lim", ["vanalbada", "superbee", "minmod", "smart"])
+def test_run_adjoint_matches_oracle_reverse_sweep(lim, scheme):
+    wl, th, rng = noisy_box(10, seed=4)
+    steps = 8
+    lam_N = rng.standard_normal(th.shape)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    cp, fp = maps(mesh)
+    uf = np.empty_like(wl.u)
+    uf[fp] = wl.u
+    t0 = dev(cells_in(th, cp)).requires_grad_(True)
+    u = dev(uf).requires_grad_(True)
+    out = FL.advect(mesh, lim, scheme, wl.dt, t0, u, steps)
+    out.backward(dev(cells_in(lam_N, cp)))
+    tb_o, ub_o = O.OracleMesh.from_arrays(wl.mesh).run_adjoint(lim, scheme, wl.dt, th, wl.u, steps, lam_N)
+    g_t, g_u = host(t0.grad)[cp], host(u.grad)[fp]
+    assert np.abs(g_t - tb_o).max() <= 1e-10 * np.abs(tb_o).max()
+    assert np.abs(g_u - ub_o).max() <= 1e-10 * np.abs(ub_o).max()
+    # forward value also matches the oracle
+    want = O.OracleMesh.from_arrays(wl.mesh).run(lim, scheme, wl.dt, th, wl.u, steps)
+    assert np.abs(host(out)[cp] - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def test_dot_product_against_oracle_tangent():
+    """<J v, w> from the oracle's forward-mode tangent equals <v, J^T w> from the GPU reverse."""
+    wl, th, rng = noisy_box(8, seed=5)
+    steps = 6
+    v = rng.standard_normal(th.shape)
+    du = rng.standard_normal(wl.u.shape)
+    w = rng.standard_normal(th.shape)
+    _, jv = O.OracleMesh.from_arrays(wl.mesh).run_tangent("vanalbada", "ssprk3", wl.dt, th, wl.u,
+                                                           steps, v, du)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0)
+    t0 = dev(th).requires_grad_(True)
+    u = dev(wl.u).requires_grad_(True)
+    FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, u, steps).backward(dev(w))
+    lhs = float(jv @ w)
+    rhs = float(v @ host(t0.grad) + du @ host(u.grad))
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(jv) @ np.abs(w))
+
+
+def test_finite_difference_16cubed():
+    """The adjoint configuration's FD check on a 16^3 copy: van Albada, SSP-RK3, misfit loss."""
+    wl, th, rng = noisy_box(16, seed=6, renumbered=False)
+    steps = 40
+    target = 0.5 * W.field_smooth_random(16, 3, seed=W.SEED_TARGET) + 0.5
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    cp, fp = maps(mesh)
+    uf = np.empty_like(wl.u)
+    uf[fp] = wl.u
+    tgt = dev(cells_in(target, cp))
+    t0 = dev(cells_in(th, cp)).requires_grad_(True)
+    u = dev(uf).requires_grad_(True)
+    loss = 0.5 * ((FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, u, steps) - tgt) ** 2).sum()
+    loss.backward()
+
+    def J(tt, uu):
+        x = tt.clone()
+        FL.rk_steps(mesh, "vanalbada", "ssprk3", wl.dt, x, uu, steps)
+        return float(0.5 * ((x - tgt) ** 2).sum())
+
+    eps = 1e-6
+    umin = float(u.detach().abs().min())
+    for k in range(3):
+        v = dev(rng.standard_normal(th.shape))
+        dv = dev(rng.standard_normal(wl.u.shape))
+        dv *= 0.5 * umin / (eps * float(dv.abs().max()))  # no face changes sign
+        fd = (J(t0.detach() + eps * v, u.detach() + eps * dv)
+              - J(t0.detach() - eps * v, u.detach() - eps * dv)) / (2 * eps)
+        ad = float((t0.grad * v).sum() + (u.grad * dv).sum())
+        assert ad == pytest.approx(fd, rel=1e-6), (k, ad, fd)
+
+
+@pytest.mark.parametrize("every", [1, 3, 7])
+def test_checkpointing_matches_full_storage(every):
+    """sqrt(N) checkpoint-and-recompute gives the gradient of full stage storage, bit for bit."""
+    wl, th, rng = noisy_box(12, seed=7)
+    steps = 20
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    w = dev(rng.standard_normal(th.shape))
+    grads = []
+    for e in (every, steps):
+        t0 = dev(th).requires_grad_(True)
+        u = dev(wl.u).requires_grad_(True)
+        FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, u, steps, checkpoint_every=e).backward(w)
+        grads.append((t0.grad.clone(), u.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
+def test_adjoint_config_128_consistency():
+    """128^3, van Albada, SSP-RK3 with sqrt(N) checkpoints: the reverse-mode directional
+    derivative of the misfit matches a central difference of the GPU forward (the forward is
+    itself checked against the oracle elsewhere).  60 of the configuration's 400 steps keep the
+    test short; the benchmark times the full 400."""
+    n, steps = 128, 60
+    wl, th, rng = noisy_box(n, seed=8, renumbered=False)
+    target = 0.5 * W.field_smooth_random(n, 3, seed=W.SEED_TARGET) + 0.5
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    cp, fp = maps(mesh)
+    uf = np.empty_like(wl.u)
+    uf[fp] = wl.u
+    tgt = dev(cells_in(target, cp))
+    t0 = dev(cells_in(th, cp)).requires_grad_(True)
+    u = dev(uf)
+    loss = 0.5 * ((FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, u, steps) - tgt) ** 2).sum()
+    loss.backward()
+    v = dev(rng.standard_normal(th.shape))
+
+    def J(tt):
+        x = tt.clone()
+        FL.rk_steps(mesh, "vanalbada", "ssprk3", wl.dt, x, u, steps)
+        return float(0.5 * ((x - tgt) ** 2).sum())
+
+    eps = 1e-5
+    fd = (J(t0.detach() + eps * v) - J(t0.detach() - eps * v)) / (2 * eps)
+    ad = float((t0.grad * v).sum())
+    assert ad == pytest.approx(fd, rel=1e-5)
