@@ -46,8 +46,63 @@ def fused_stage_bytes(C, F, K, S, stage):
     return b
 
 
+def adjoint_ratio(args, torch, FL, W, dev):
+    """Adjoint configuration: 128^3 periodic box, van Albada, SSP-RK3 at CFL 0.4, 400 steps,
+    J = |theta_N - target|^2 / 2 with a seeded smooth target; gradients w.r.t. theta_0 and u_f
+    through ceil(sqrt(N))-step checkpoints.  Returns forward (with checkpoint stores) and
+    backward (recompute + reverse sweep) times and their ratio."""
+    n = args.adjoint_n
+    wl = W.workload_box(n, renumbered=False)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    th0 = mesh.cells_to_mesh(torch.from_numpy(wl.theta0).to(dev))
+    u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
+    tgt = mesh.cells_to_mesh(torch.from_numpy(
+        0.5 * W.field_smooth_random(n, 3, seed=W.SEED_TARGET) + 0.5).to(dev))
+    steps = args.adjoint_steps
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    def once(n_steps, timed):
+        t0 = th0.clone().requires_grad_(True)
+        uu = u.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        out = FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, uu, n_steps)
+        ev[1].record(stream)
+        loss = 0.5 * ((out - tgt) ** 2).sum()
+        ev[2].record(stream)
+        loss.backward()
+        ev[3].record(stream)
+        ev[3].synchronize()
+        return ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+
+    once(min(steps, 10), False)  # warm-up
+    fwd_ms, bwd_ms = once(steps, True)
+    plain = th0.clone()
+    work = FL.rk_workspace(mesh, "ssprk3", 1)
+    torch.cuda.synchronize()
+    ev[4].record(stream)
+    FL.rk_steps(mesh, "vanalbada", "ssprk3", wl.dt, plain, u, steps, work=work)
+    ev[5].record(stream)
+    ev[5].synchronize()
+    plain_ms = ev[4].elapsed_time(ev[5])
+    log(f"adjoint {n}^3 x {steps}: forward {fwd_ms:.1f} ms, backward {bwd_ms:.1f} ms, "
+        f"plain forward {plain_ms:.1f} ms")
+    mesh.close()
+    return {"workload": f"periodic hex box {n}^3, van Albada, SSP-RK3 CFL 0.4, {steps} steps, "
+                        f"L2 misfit to a seeded target, checkpoints every "
+                        f"{FL.checkpoint_interval(steps)} steps",
+            "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
+            "plain_forward_ms": round(plain_ms, 2),
+            "adjoint_forward_ratio": round(bwd_ms / fwd_ms, 3),
+            "forward_plus_backward_over_plain": round((fwd_ms + bwd_ms) / plain_ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--adjoint-steps", type=int, default=400,
+                    help="steps of the adjoint-cost measurement (0 to skip)")
+    ap.add_argument("--adjoint-n", type=int, default=128)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed SSP-RK3 steps per limiter")
     ap.add_argument("--warmup", type=int, default=3)
@@ -180,6 +235,9 @@ def main():
         r2 = run_case(False)
         v2 = updates / (r2["total_ms"] * 1e-3) / 1e9
         out["as_given_numbering_value"] = round(v2, 3)
+
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_ratio(args, torch, FL, W, dev)
 
     if args.cpu_baseline:
         from oracle import oracle as O

@@ -4,10 +4,12 @@ differences.
 Tolerances: the adjoint kernels sum a cell's contributions in another order than the oracle's
 serial scatter, so one reverse application agrees to a few ulps of the largest contribution
 (compared at 1e-12 of max|grad|); reverse sweeps over many steps at 1e-10 norm-relative, as the
-forward runs.  Finite differences (central, eps = 1e-6 relative) carry O(eps^2) truncation and
-O(1e-16/eps) rounding error, hence the 1e-6 relative bar on a smooth (van Albada) run whose
-field has no two equal neighbours (no d_u = 0 kinks) and whose velocity perturbation flips no
-face's sign.
+forward runs.  Finite differences use a smooth (van Albada) run whose field has no two equal
+neighbours (no d_u = 0 kinks) and whose velocity perturbation flips no face's sign.  Near-flat
+regions (differences of ~1e-3 from the seeded noise) make the central difference's truncation
+error grow fast with the step (1.8e-4 relative at eps = 1e-5 and 1e-6 at eps = 1e-6 on the 16^3
+case, measured with the oracle alone), so the 16^3 check uses eps = 3e-8 (1.5e-7 relative error for the oracle itself;
+the velocity direction curves more than theta), against a 1e-6 relative bar.
 """
 
 import numpy as np
@@ -156,12 +158,13 @@ def test_finite_difference_16cubed():
         FL.rk_steps(mesh, "vanalbada", "ssprk3", wl.dt, x, uu, steps)
         return float(0.5 * ((x - tgt) ** 2).sum())
 
-    eps = 1e-6
+    eps = 3e-8
     umin = float(u.detach().abs().min())
     for k in range(3):
         v = dev(rng.standard_normal(th.shape))
         dv = dev(rng.standard_normal(wl.u.shape))
-        dv *= 0.5 * umin / (eps * float(dv.abs().max()))  # no face changes sign
+        # unit-size direction, shrunk further if needed so that no face changes sign
+        dv *= min(1.0, 0.5 * umin / eps) / float(dv.abs().max())
         fd = (J(t0.detach() + eps * v, u.detach() + eps * dv)
               - J(t0.detach() - eps * v, u.detach() - eps * dv)) / (2 * eps)
         ad = float((t0.grad * v).sum() + (u.grad * dv).sum())
@@ -188,9 +191,13 @@ def test_adjoint_config_128_consistency():
     """128^3, van Albada, SSP-RK3 with sqrt(N) checkpoints: the reverse-mode directional
     derivative of the misfit matches a central difference of the GPU forward (the forward is
     itself checked against the oracle elsewhere).  60 of the configuration's 400 steps keep the
-    test short; the benchmark times the full 400."""
+    test short; the benchmark times the full 400.  The field is a smooth seeded one: van Albada's
+    face value is smooth except where both differences vanish, and plateaus or tiny noise put
+    thousands of faces at or next to that point, where no finite difference is accurate."""
     n, steps = 128, 60
-    wl, th, rng = noisy_box(n, seed=8, renumbered=False)
+    wl = W.workload_box(n, renumbered=False)
+    rng = np.random.default_rng(8)
+    th = W.field_smooth_random(n, 3, seed=11) + 1.0
     target = 0.5 * W.field_smooth_random(n, 3, seed=W.SEED_TARGET) + 0.5
     mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
     cp, fp = maps(mesh)
@@ -203,12 +210,15 @@ def test_adjoint_config_128_consistency():
     loss.backward()
     v = dev(rng.standard_normal(th.shape))
 
-    def J(tt):
+    def run(tt):
         x = tt.clone()
         FL.rk_steps(mesh, "vanalbada", "ssprk3", wl.dt, x, u, steps)
-        return float(0.5 * ((x - tgt) ** 2).sum())
+        return x
 
-    eps = 1e-5
-    fd = (J(t0.detach() + eps * v) - J(t0.detach() - eps * v)) / (2 * eps)
+    # dJ/d(eps) = sum (x - target) dx/d(eps): difference the final states (a difference of the
+    # two losses would cancel catastrophically over 2M cells)
+    eps = 1e-7
+    dx = (run(t0.detach() + eps * v) - run(t0.detach() - eps * v)) / (2 * eps)
+    fd = float(((run(t0.detach()) - tgt) * dx).sum())
     ad = float((t0.grad * v).sum())
-    assert ad == pytest.approx(fd, rel=1e-5)
+    assert ad == pytest.approx(fd, rel=1e-6)

@@ -462,9 +462,9 @@ def test_rhs_jvp_matches_finite_difference(lim):
     om = O.OracleMesh.from_arrays(wl.mesh)
     v = rng.standard_normal(th.size)
     du = rng.standard_normal(wl.u.size)
-    eps = 1e-6
+    eps = 1e-7  # truncation ~1e-8 relative, rounding ~1e-8
     umin = np.abs(wl.u).min()
-    du *= 0.5 * umin / (eps * np.abs(du).max())  # no face changes sign
+    du *= min(1.0, 0.5 * umin / eps) / np.abs(du).max()  # unit size, no face changes sign
     jv = om.rhs_jvp(lim, th, wl.u, v, du)
     fd = (om.rhs(lim, th + eps * v, wl.u + eps * du) - om.rhs(lim, th - eps * v, wl.u - eps * du)) / (2 * eps)
     np.testing.assert_allclose(jv, fd, rtol=0, atol=1e-6 * np.abs(jv).max())
@@ -515,7 +515,7 @@ def test_run_adjoint_matches_finite_difference_of_loss():
         v = rng.standard_normal(th.size)
         du = rng.standard_normal(wl.u.size)
         eps = 1e-6
-        du *= 0.5 * np.abs(wl.u).min() / (eps * np.abs(du).max())
+        du *= min(1.0, 0.5 * np.abs(wl.u).min() / eps) / np.abs(du).max()  # no sign flips
         fd = (J(th + eps * v, wl.u + eps * du) - J(th - eps * v, wl.u - eps * du)) / (2 * eps)
         ad = v @ tb + du @ ub
         assert ad == pytest.approx(fd, rel=1e-6)
