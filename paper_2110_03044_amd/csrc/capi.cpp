@@ -432,7 +432,7 @@ fl_status fl_convect_adjoint(const fl_mesh *m, int lim, int S, const double *the
 
 size_t fl_rk_adjoint_workspace_bytes(const fl_mesh *m, int scheme, int S) {
     if (!m || S < 1 || S > FL_MAX_SCALARS || (scheme != FL_EULER && scheme != FL_SSPRK3)) return 0;
-    return 2 * align256((size_t)m->h.nc * S * sizeof(double));
+    return (scheme == FL_EULER ? 1 : 3) * align256((size_t)m->h.nc * S * sizeof(double));
 }
 
 fl_status fl_rk_step_store(const fl_mesh *m, int lim, int scheme, double dt, int S,
@@ -478,25 +478,29 @@ fl_status fl_rk_step_adjoint(const fl_mesh *m, int lim, int scheme, double dt, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     const size_t cell = (size_t)m->h.nc * S;
+    const size_t slab = align256(cell * sizeof(double));
     double *w1 = (double *)work;
-    double *w2 = (double *)((char *)work + align256(cell * sizeof(double)));
+    double *w2 = (double *)((char *)work + slab);
+    double *w3 = (double *)((char *)work + 2 * slab);
     hipError_t e;
+    // Each reverse stage gathers its input cotangent, so it writes a different buffer.
     if (scheme == FL_EULER) {
         e = launch_adjoint(m, lim, S, u, stages, lambda, 0.0, 1.0, dt, ADJ_EULER, w1, nullptr,
                            u_bar, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lambda, w1, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
     } else {
-        // stage 3 reads lambda, stage 2 reads w1 and writes lambda, stage 1 reads lambda
+        // lambda -> w1 (stage 3), w1 -> w3 (stage 2), w3 -> lambda (stage 1); w2 accumulates
+        // the theta^n cotangent
         e = launch_adjoint(m, lim, S, u, stages + 2 * cell, lambda, kRk3A[2], kRk3B[2], dt,
                            ADJ_LAST, w1, w2, u_bar, st);
         if (e == hipSuccess)
             e = launch_adjoint(m, lim, S, u, stages + cell, w1, kRk3A[1], kRk3B[1], dt, ADJ_MID,
-                               lambda, w2, u_bar, st);
+                               w3, w2, u_bar, st);
         if (e == hipSuccess)
-            e = launch_adjoint(m, lim, S, u, stages, lambda, kRk3A[0], kRk3B[0], dt, ADJ_FIRST,
-                               w1, w2, u_bar, st);
+            e = launch_adjoint(m, lim, S, u, stages, w3, kRk3A[0], kRk3B[0], dt, ADJ_FIRST,
+                               lambda, w2, u_bar, st);
     }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(lambda, w1, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step_adjoint launch");
 }
 

@@ -24,83 +24,83 @@ namespace adev {
 constexpr int kBlock = 256;
 constexpr double kRBig = 1.0e18;
 
-__device__ __forceinline__ double psi_inf(int lim, bool pos) {
-    switch (lim) {
-        case FL_MINMOD: return pos ? 1.0 : 0.0;
-        case FL_VANLEER: return pos ? 2.0 : 0.0;
-        case FL_VANALBADA: return 1.0;
-        case FL_SUPERBEE: return pos ? 2.0 : 0.0;
-        case FL_SMART: return pos ? 4.0 : 0.0;
-        case FL_CENTRAL: return 1.0;
-        default: return 0.0;
-    }
+template <int LIM>
+__device__ __forceinline__ double psi_inf(bool pos) {
+    if constexpr (LIM == FL_MINMOD) return pos ? 1.0 : 0.0;
+    else if constexpr (LIM == FL_VANLEER || LIM == FL_SUPERBEE) return pos ? 2.0 : 0.0;
+    else if constexpr (LIM == FL_VANALBADA || LIM == FL_CENTRAL) return 1.0;
+    else if constexpr (LIM == FL_SMART) return pos ? 4.0 : 0.0;
+    else return 0.0;
 }
 
-__device__ __forceinline__ double psi(int lim, double r) {
-    switch (lim) {
-        case FL_MINMOD: return fmax(0.0, fmin(1.0, r));
-        case FL_VANLEER: {
-            const double ar = fabs(r);
-            return (r + ar) / (1.0 + ar);
-        }
-        case FL_VANALBADA: {
-            const double r2 = r * r;
-            return (r2 + r) / (r2 + 1.0);
-        }
-        case FL_SUPERBEE: return fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
-        case FL_SMART: return fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
-        case FL_CENTRAL: return 1.0;
-        default: return 0.0;
-    }
-}
-
-// psi'(r) on the branch the evaluation takes (left-closed pieces at break points).
-__device__ __forceinline__ double dpsi(int lim, double r) {
-    switch (lim) {
-        case FL_MINMOD: return (r > 0.0 && r < 1.0) ? 1.0 : 0.0;
-        case FL_VANLEER: {
-            const double q = 1.0 + r;
-            return r > 0.0 ? 2.0 / (q * q) : 0.0;
-        }
-        case FL_VANALBADA: {
-            const double q = r * r + 1.0;
-            return (1.0 + 2.0 * r - r * r) / (q * q);
-        }
-        case FL_SUPERBEE:
-            return r <= 0.0 ? 0.0 : r <= 0.5 ? 2.0 : r <= 1.0 ? 0.0 : r <= 2.0 ? 1.0 : 0.0;
-        case FL_SMART:
-            return r <= 0.0 ? 0.0 : r <= 0.2 ? 2.0 : r <= 5.0 ? 0.75 : 0.0;
-        default: return 0.0;
+// psi(r) and psi'(r) on the branch the evaluation takes (left-closed pieces at break points).
+template <int LIM>
+__device__ __forceinline__ void psi_dpsi(double r, double &p, double &dp) {
+    if constexpr (LIM == FL_MINMOD) {
+        p = fmax(0.0, fmin(1.0, r));
+        dp = (r > 0.0 && r < 1.0) ? 1.0 : 0.0;
+    } else if constexpr (LIM == FL_VANLEER) {
+        const double q = 1.0 / (1.0 + fabs(r));
+        p = (r + fabs(r)) * q;
+        dp = r > 0.0 ? 2.0 * q * q : 0.0;
+    } else if constexpr (LIM == FL_VANALBADA) {
+        const double q = 1.0 / (r * r + 1.0);
+        p = (r * r + r) * q;
+        dp = (1.0 + 2.0 * r - r * r) * q * q;
+    } else if constexpr (LIM == FL_SUPERBEE) {
+        p = fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
+        dp = r <= 0.0 ? 0.0 : r <= 0.5 ? 2.0 : r <= 1.0 ? 0.0 : r <= 2.0 ? 1.0 : 0.0;
+    } else if constexpr (LIM == FL_SMART) {
+        p = fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
+        dp = r <= 0.0 ? 0.0 : r <= 0.2 ? 2.0 : r <= 5.0 ? 0.75 : 0.0;
+    } else if constexpr (LIM == FL_CENTRAL) {
+        p = 1.0;
+        dp = 0.0;
+    } else {
+        p = 0.0;
+        dp = 0.0;
     }
 }
 
 // theta_f and its partials g_a = d theta_f / d d_U, g_b = d theta_f / d d_u.
-__device__ __forceinline__ double face_value_d(int lim, double tC, double tD, double tU,
-                                               double &ga, double &gb) {
-    const double du = tD - tC;
-    const double dU = tC - tU;
-    if (du == 0.0) {
-        ga = 0.0;
-        gb = (dU == 0.0) ? 0.0 : 0.5 * psi_inf(lim, dU > 0.0);
-        return tC;
-    }
-    if (lim == FL_UPWIND) {
+template <int LIM>
+__device__ __forceinline__ double face_value_d(double tC, double tD, double tU, double &ga,
+                                               double &gb) {
+    const double b = tD - tC;  // d_u
+    const double a = tC - tU;  // d_U
+    if constexpr (LIM == FL_UPWIND) {
         ga = 0.0;
         gb = 0.0;
         return tC;
     }
-    const double r = dU / du;
+    if (b == 0.0) {
+        ga = 0.0;
+        gb = (a == 0.0) ? 0.0 : 0.5 * psi_inf<LIM>(a > 0.0);
+        return tC;
+    }
+    if constexpr (LIM == FL_VANALBADA) {
+        // psi(a/b) b / 2 = a b (a + b) / (2 (a^2 + b^2)): one reciprocal for value and partials
+        const double q = a * a + b * b;
+        if (q >= 1e-280 && q <= 1e280) {
+            const double iq = 1.0 / q;
+            const double iq2 = iq * iq;
+            ga = 0.5 * (b * b) * (b * b + 2.0 * a * b - a * a) * iq2;
+            gb = 0.5 * (a * a) * (a * a + 2.0 * a * b - b * b) * iq2;
+            return tC + 0.5 * (a * b) * (a + b) * iq;
+        }
+    }
+    const double r = a / b;
     if (!(fabs(r) <= kRBig)) {
-        const double p = psi_inf(lim, r > 0.0);
+        const double p = psi_inf<LIM>(r > 0.0);
         ga = 0.0;
         gb = 0.5 * p;
-        return tC + 0.5 * p * du;
+        return tC + 0.5 * p * b;
     }
-    const double p = psi(lim, r);
-    const double dp = dpsi(lim, r);
+    double p, dp;
+    psi_dpsi<LIM>(r, p, dp);
     ga = 0.5 * dp;
     gb = 0.5 * (p - r * dp);
-    return tC + 0.5 * p * du;
+    return tC + 0.5 * p * b;
 }
 
 template <int S>
@@ -115,13 +115,13 @@ __device__ __forceinline__ void load(const double *__restrict__ a, int64_t c, do
 //       ADJ_MID      acc[x] += a lam[x]; out[x] = b (lam[x] + dt J^T lam)
 //       ADJ_FIRST    out[x] = acc[x] + b (lam[x] + dt J^T lam)
 // and u_bar += scale (dL/du)^T lam with scale = b dt (1 for ADJ_APPLY).
-template <int S, int P>
+template <int S, int P, int LIM>
 __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     int64_t nc, const uint32_t *__restrict__ sface, const int32_t *__restrict__ snbr,
     const int32_t *__restrict__ sfar, const uint32_t *__restrict__ srev,
     const double *__restrict__ u, const double *__restrict__ area, double area0,
-    const double *__restrict__ vol, double vol0, const double *__restrict__ th,
-    const double *__restrict__ lam, double a, double b, double dt, int mode, int lim,
+    const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
+    const double *__restrict__ lam, double a, double b, double dt, int mode,
     double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
     constexpr int K = 2 * P;
     const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -140,18 +140,27 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     load<S>(lam, x, lx);
 #pragma unroll
     for (int k = 0; k < K; ++k) load<S>(th, nb[k], tn[k]);
-    const double vx = vol ? vol[x] : vol0;
+    // lambda / V appears in every face term: multiply by reciprocal volumes
+    const double ivx = vol ? 1.0 / vol[x] : ivol0;
     const double scale = (mode == ADJ_APPLY) ? 1.0 : b * dt;
     double jt[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) jt[s] = 0.0;
+    // Face velocities are requested up front; the per-slot theta / lambda gathers stay next to
+    // their use (hoisting them as well raised register use and measured slower at 128^3).
+    double ufk[K], urk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        ufk[k] = u[fw[k] & 0x7fffffffu];
+        urk[k] = u[rw[k] & 0x7fffffffu];
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t f = fw[k] & 0x7fffffffu, fr = rw[k] & 0x7fffffffu;
         const int64_t n = nb[k], g = gf[k];
-        const double uf = u[f], ur = u[fr];
+        const double uf = ufk[k], ur = urk[k];
         const double af = area ? area[f] : area0, ar = area ? area[fr] : area0;
-        const double vn = vol ? vol[n] : vol0, vg = vol ? vol[g] : vol0;
+        const double ivn = vol ? 1.0 / vol[n] : ivol0, ivg = vol ? 1.0 / vol[g] : ivol0;
         double ln[S], lg[S], tg[S];
         load<S>(lam, n, ln);
         load<S>(lam, g, lg);
@@ -162,10 +171,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
         double usum = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            double ga, gb, tf;
-            if (x_up) tf = face_value_d(lim, tx[s], tn[k][s], tn[k ^ 1][s], ga, gb);
-            else tf = face_value_d(lim, tn[k][s], tx[s], tg[s], ga, gb);
-            const double mu = x_own ? (ln[s] / vn - lx[s] / vx) : (lx[s] / vx - ln[s] / vn);
+            double ga, gb;
+            // pick (theta_C, theta_D, theta_U) first: one evaluation even where lanes diverge
+            const double tC = x_up ? tx[s] : tn[k][s];
+            const double tD = x_up ? tn[k][s] : tx[s];
+            const double tU = x_up ? tn[k ^ 1][s] : tg[s];
+            const double tf = face_value_d<LIM>(tC, tD, tU, ga, gb);
+            const double mu = x_own ? (ln[s] * ivn - lx[s] * ivx) : (lx[s] * ivx - ln[s] * ivn);
             const double z = af * uf * mu;
             jt[s] += x_up ? z * (1.0 + ga - gb) : z * gb;
             usum += tf * mu;
@@ -178,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 double ga, gb;
-                (void)face_value_d(lim, tn[k][s], tg[s], tx[s], ga, gb);
-                const double mu = n_own ? (lg[s] / vg - ln[s] / vn) : (ln[s] / vn - lg[s] / vg);
+                (void)face_value_d<LIM>(tn[k][s], tg[s], tx[s], ga, gb);
+                const double mu = n_own ? (lg[s] * ivg - ln[s] * ivn) : (ln[s] * ivn - lg[s] * ivg);
                 jt[s] -= (ar * ur * mu) * ga;
             }
         }
@@ -206,31 +218,44 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
 }  // namespace adev
 
 namespace {
-template <int S>
-hipError_t launch_adjoint_s(const fl_mesh *m, int lim, const double *u, const double *th,
-                            const double *lam, double a, double b, double dt, int mode,
-                            double *out, double *acc, double *ubar, hipStream_t st) {
+template <int S, int P, int LIM>
+hipError_t launch3(const fl_mesh *m, const double *u, const double *th, const double *lam,
+                   double a, double b, double dt, int mode, double *out, double *acc,
+                   double *ubar, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nc + adev::kBlock - 1) / adev::kBlock);
-    const uint32_t *rev = reinterpret_cast<const uint32_t *>(m->d_rev);
-    switch (m->h.pairs) {
-        case 1:
-            adev::adjoint_stage_kernel<S, 1><<<nb, adev::kBlock, 0, st>>>(
-                m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, rev, u, m->d_area,
-                m->h.area0, m->d_vol, m->h.vol0, th, lam, a, b, dt, mode, lim, out, acc, ubar);
-            break;
-        case 2:
-            adev::adjoint_stage_kernel<S, 2><<<nb, adev::kBlock, 0, st>>>(
-                m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, rev, u, m->d_area,
-                m->h.area0, m->d_vol, m->h.vol0, th, lam, a, b, dt, mode, lim, out, acc, ubar);
-            break;
-        case 3:
-            adev::adjoint_stage_kernel<S, 3><<<nb, adev::kBlock, 0, st>>>(
-                m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, rev, u, m->d_area,
-                m->h.area0, m->d_vol, m->h.vol0, th, lam, a, b, dt, mode, lim, out, acc, ubar);
-            break;
+    adev::adjoint_stage_kernel<S, P, LIM><<<nb, adev::kBlock, 0, st>>>(
+        m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far,
+        reinterpret_cast<const uint32_t *>(m->d_rev), u, m->d_area, m->h.area0, m->d_vol,
+        1.0 / m->h.vol0, th, lam, a, b, dt, mode, out, acc, ubar);
+    return hipGetLastError();
+}
+
+template <int S, int P>
+hipError_t launch2(const fl_mesh *m, int lim, const double *u, const double *th,
+                   const double *lam, double a, double b, double dt, int mode, double *out,
+                   double *acc, double *ubar, hipStream_t st) {
+    switch (lim) {
+        case FL_UPWIND: return launch3<S, P, FL_UPWIND>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case FL_MINMOD: return launch3<S, P, FL_MINMOD>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case FL_VANLEER: return launch3<S, P, FL_VANLEER>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case FL_VANALBADA: return launch3<S, P, FL_VANALBADA>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case FL_SUPERBEE: return launch3<S, P, FL_SUPERBEE>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case FL_SMART: return launch3<S, P, FL_SMART>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case FL_CENTRAL: return launch3<S, P, FL_CENTRAL>(m, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch1(const fl_mesh *m, int lim, const double *u, const double *th,
+                   const double *lam, double a, double b, double dt, int mode, double *out,
+                   double *acc, double *ubar, hipStream_t st) {
+    switch (m->h.pairs) {
+        case 1: return launch2<S, 1>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 2: return launch2<S, 2>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 3: return launch2<S, 3>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 }  // namespace
 
@@ -238,14 +263,14 @@ hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, con
                           const double *lam, double a, double b, double dt, int mode, double *out,
                           double *acc, double *ubar, hipStream_t st) {
     switch (S) {
-        case 1: return launch_adjoint_s<1>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 2: return launch_adjoint_s<2>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 3: return launch_adjoint_s<3>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 4: return launch_adjoint_s<4>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 5: return launch_adjoint_s<5>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 6: return launch_adjoint_s<6>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 7: return launch_adjoint_s<7>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
-        case 8: return launch_adjoint_s<8>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 1: return launch1<1>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 2: return launch1<2>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 3: return launch1<3>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 4: return launch1<4>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 5: return launch1<5>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 6: return launch1<6>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 7: return launch1<7>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
+        case 8: return launch1<8>(m, lim, u, th, lam, a, b, dt, mode, out, acc, ubar, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -208,8 +208,11 @@ __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
         const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const double tf = c_upwind ? face_value(lim, tc[s], tnb[k][s], tnb[k ^ 1][s])
-                                       : face_value(lim, tnb[k][s], tc[s], tg[k][s]);
+            // pick (theta_C, theta_D, theta_U) first: one evaluation even where lanes diverge
+            const double tC = c_upwind ? tc[s] : tnb[k][s];
+            const double tD = c_upwind ? tnb[k][s] : tc[s];
+            const double tU = c_upwind ? tnb[k ^ 1][s] : tg[k][s];
+            const double tf = face_value(lim, tC, tD, tU);
             const double ph = au[k] * tf;
             acc[s] = c_is_own ? acc[s] - ph : acc[s] + ph;
         }

@@ -296,11 +296,17 @@ class _Advect(torch.autograd.Function):
         S = _S(theta)
         work = rk_workspace(mesh, scheme, S)
         ckpts = []
+        stages = stage_buffer(mesh, scheme, S, min(every, max(n_steps, 1)))
         for start in range(0, n_steps, every):
             ckpts.append(theta.clone())
-            rk_steps(mesh, limiter, scheme, dt, theta, u_d, min(every, n_steps - start), work=work)
+            count = min(every, n_steps - start)
+            if start + count < n_steps:
+                rk_steps(mesh, limiter, scheme, dt, theta, u_d, count, work=work)
+            else:  # the last segment keeps its stage inputs: the backward starts there
+                for j in range(count):
+                    rk_step_store(mesh, limiter, scheme, dt, theta, u_d, stages[j], work=work)
         ctx.mesh, ctx.limiter, ctx.scheme, ctx.dt = mesh, limiter, scheme, dt
-        ctx.n_steps, ctx.every, ctx.ckpts = n_steps, every, ckpts
+        ctx.n_steps, ctx.every, ctx.ckpts, ctx.stages = n_steps, every, ckpts, stages
         ctx.save_for_backward(u_d)
         return theta
 
@@ -313,16 +319,19 @@ class _Advect(torch.autograd.Function):
         u_bar = torch.zeros_like(u_d)
         work = rk_workspace(mesh, scheme, S)
         awork = rk_adjoint_workspace(mesh, scheme, S)
-        stages = stage_buffer(mesh, scheme, S, min(ctx.every, max(ctx.n_steps, 1)))
+        stages = ctx.stages
+        last = len(ctx.ckpts) - 1
         for seg in reversed(range(len(ctx.ckpts))):
             start = seg * ctx.every
             count = min(ctx.every, ctx.n_steps - start)
-            th = ctx.ckpts[seg].clone()
-            for j in range(count):  # recompute the segment, storing every stage input
-                rk_step_store(mesh, lim, scheme, dt, th, u_d, stages[j], work=work)
+            if seg != last:  # recompute the segment, storing every stage input
+                th = ctx.ckpts[seg].clone()
+                for j in range(count):
+                    rk_step_store(mesh, lim, scheme, dt, th, u_d, stages[j], work=work)
             for j in reversed(range(count)):
                 rk_step_adjoint(mesh, lim, scheme, dt, stages[j], u_d, lam, u_bar, work=awork)
         ctx.ckpts = None
+        ctx.stages = None
         return lam, u_bar, None, None, None, None, None, None
 
 
