@@ -1,0 +1,436 @@
+// Batched problems: many independent meshes, scalar counts, limiters and time steps advanced
+// by ONE kernel launch per Runge-Kutta stage, replayed from a HIP graph.
+//
+// Each problem is described once in device memory (mesh slot tables, face velocity, buffers,
+// limiter, dt).  The work table lists (problem, first cell) tiles of `tile` cells; a persistent
+// grid of workgroups strides over the table, each workgroup processing one tile at a time with
+// one thread per cell.  Tiles never span problems, so the problem descriptor and the limiter
+// branch are uniform within a workgroup.  The scalar count is a run-time loop bound: one kernel
+// serves every S.  The arithmetic per cell and face is the fused stage kernel's, in the same
+// order, so each problem's result equals its single-problem run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "fl_kernels.h"
+
+struct BatchProblem {
+    int64_t nc;
+    int32_t P, S, lim, pad;
+    double dt, area0, vol0;
+    const uint32_t *sface;
+    const int32_t *snbr, *sfar;
+    const double *u, *area, *vol;
+    double *th, *t1, *t2;
+};
+
+struct BatchTile {
+    int32_t prob, pad;
+    int64_t c0;
+};
+
+namespace fl {
+namespace bdev {
+
+constexpr int kBlock = 256;
+constexpr double kRBig = 1.0e18;
+
+__device__ __forceinline__ double psi_inf(int lim, bool pos) {
+    switch (lim) {
+        case FL_MINMOD: return pos ? 1.0 : 0.0;
+        case FL_VANLEER: return pos ? 2.0 : 0.0;
+        case FL_VANALBADA: return 1.0;
+        case FL_SUPERBEE: return pos ? 2.0 : 0.0;
+        case FL_SMART: return pos ? 4.0 : 0.0;
+        case FL_CENTRAL: return 1.0;
+        default: return 0.0;
+    }
+}
+
+__device__ __forceinline__ double psi(int lim, double r) {
+    if (!(fabs(r) <= kRBig)) return psi_inf(lim, r > 0.0);
+    switch (lim) {
+        case FL_MINMOD: return fmax(0.0, fmin(1.0, r));
+        case FL_VANLEER: {
+            const double ar = fabs(r);
+            return (r + ar) / (1.0 + ar);
+        }
+        case FL_VANALBADA: {
+            const double r2 = r * r;
+            return (r2 + r) / (r2 + 1.0);
+        }
+        case FL_SUPERBEE: return fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
+        case FL_SMART: return fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
+        case FL_CENTRAL: return 1.0;
+        default: return 0.0;
+    }
+}
+
+__device__ __forceinline__ double face_value(int lim, double tC, double tD, double tU) {
+    const double du = tD - tC;
+    if (lim == FL_UPWIND || du == 0.0) return tC;
+    const double r = (tC - tU) / du;
+    return tC + 0.5 * psi(lim, r) * du;
+}
+
+template <int P>
+__device__ __forceinline__ void cell_stage(const BatchProblem &pb, int64_t c, const double *ts,
+                                           const double *tn, double a, double b, int mode,
+                                           double *out) {
+    constexpr int K = 2 * P;
+    const int64_t nc = pb.nc;
+    const int S = pb.S, lim = pb.lim;
+    uint32_t fw[K];
+    int64_t nb[K], gf[K];
+    double au[K], uu[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        fw[k] = pb.sface[(int64_t)k * nc + c];
+        nb[k] = pb.snbr[(int64_t)k * nc + c];
+        gf[k] = pb.sfar[(int64_t)k * nc + c];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t f = fw[k] & 0x7fffffffu;
+        uu[k] = pb.u[f];
+        au[k] = (pb.area ? pb.area[f] : pb.area0) * uu[k];
+    }
+    const double V = pb.vol ? pb.vol[c] : pb.vol0;
+    for (int s = 0; s < S; ++s) {
+        const double tc = ts[c * S + s];
+        double tnb[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) tnb[k] = ts[nb[k] * S + s];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool c_is_own = (fw[k] >> 31) != 0;
+            const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
+            const double tg = (!c_upwind && lim != FL_UPWIND) ? ts[gf[k] * S + s] : 0.0;
+            const double tC = c_upwind ? tc : tnb[k];
+            const double tD = c_upwind ? tnb[k] : tc;
+            const double tU = c_upwind ? tnb[k ^ 1] : tg;
+            const double ph = au[k] * face_value(lim, tC, tD, tU);
+            acc = c_is_own ? acc - ph : acc + ph;
+        }
+        const int64_t i = c * S + s;
+        if (mode == MODE_EULER) out[i] = tc + pb.dt * (acc / V);
+        else out[i] = a * tn[i] + b * (tc + pb.dt * (acc / V));
+    }
+}
+
+// stage 0: theta -> t1 (Euler form); stage 1: (t1, theta) -> t2; stage 2: (t2, theta) -> theta.
+// Forward Euler uses stage 0 only, followed by batch_copy_kernel (t1 -> theta).
+__global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchProblem *__restrict__ probs,
+                                                             const BatchTile *__restrict__ tiles,
+                                                             int64_t ntiles, int tile, int stage) {
+    const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile T = tiles[t];
+        const BatchProblem &pb = probs[T.prob];
+        const double *ts = stage == 0 ? pb.th : stage == 1 ? pb.t1 : pb.t2;
+        double *out = stage == 0 ? pb.t1 : stage == 1 ? pb.t2 : pb.th;
+        const int mode = stage == 0 ? MODE_EULER : MODE_RK;
+        const int64_t c1 = min(T.c0 + (int64_t)tile, pb.nc);
+        for (int64_t c = T.c0 + threadIdx.x; c < c1; c += blockDim.x) {
+            switch (pb.P) {
+                case 1: cell_stage<1>(pb, c, ts, pb.th, A[stage], B[stage], mode, out); break;
+                case 2: cell_stage<2>(pb, c, ts, pb.th, A[stage], B[stage], mode, out); break;
+                default: cell_stage<3>(pb, c, ts, pb.th, A[stage], B[stage], mode, out); break;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_copy_kernel(const BatchProblem *__restrict__ probs,
+                                                            const BatchTile *__restrict__ tiles,
+                                                            int64_t ntiles, int tile) {
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile T = tiles[t];
+        const BatchProblem &pb = probs[T.prob];
+        const int64_t e0 = T.c0 * pb.S, e1 = min(T.c0 + (int64_t)tile, pb.nc) * pb.S;
+        for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) pb.th[i] = pb.t1[i];
+    }
+}
+
+}  // namespace bdev
+}  // namespace fl
+
+using namespace fl;
+
+struct fl_batch {
+    int device = -1;
+    int scheme = FL_SSPRK3;
+    int tile = 0;            // cells per tile (0 until tuned)
+    int grid = 0;            // persistent grid size
+    std::vector<BatchProblem> probs;
+    std::vector<const fl_mesh *> meshes;
+    BatchProblem *d_probs = nullptr;
+    BatchTile *d_tiles = nullptr;
+    int64_t ntiles = 0;
+    std::vector<double *> owned;  // t1/t2 buffers
+    hipStream_t cap = nullptr;    // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+fl_status hip_err(hipError_t e, const char *what) {
+    return fail(FL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Guard {
+    int prev = -1;
+    bool changed = false;
+    explicit Guard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) changed = hipSetDevice(dev) == hipSuccess;
+    }
+    ~Guard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+void drop_graph(fl_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Builds the tile table for a tile size and uploads it.
+fl_status set_tile(fl_batch *b, int tile) {
+    std::vector<BatchTile> tiles;
+    for (size_t i = 0; i < b->probs.size(); ++i)
+        for (int64_t c0 = 0; c0 < b->probs[i].nc; c0 += tile) tiles.push_back({(int32_t)i, 0, c0});
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_tiles = nullptr;
+    hipError_t e = hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(BatchTile));
+    if (e != hipSuccess) return fail(FL_E_NOMEM, "batch tile table");
+    e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_err(e, "batch tile table upload");
+    b->ntiles = (int64_t)tiles.size();
+    b->tile = tile;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    // persistent grid: a few workgroups per CU, never more than there are tiles
+    b->grid = (int)std::min<int64_t>(b->ntiles, (int64_t)cus * 8);
+    if (b->grid < 1) b->grid = 1;
+    drop_graph(b);
+    return FL_OK;
+}
+
+hipError_t enqueue_step(const fl_batch *b, hipStream_t st) {
+    const int ns = b->scheme == FL_EULER ? 1 : 3;
+    for (int s = 0; s < ns; ++s) {
+        bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
+                                                                  b->ntiles, b->tile, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (b->scheme == FL_EULER) {
+        bdev::batch_copy_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
+                                                                 b->ntiles, b->tile);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+// Times the non-destructive first stage (theta -> t1) for each candidate tile size.
+fl_status autotune(fl_batch *b, hipStream_t st) {
+    static const int cand[] = {128, 256, 512, 1024, 2048, 4096};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(FL_E_HIP, "hipEventCreate");
+    float best = 1e30f;
+    int best_tile = 256;
+    for (int tile : cand) {
+        fl_status s = set_tile(b, tile);
+        if (s != FL_OK) return s;
+        for (int rep = 0; rep < 2; ++rep)
+            bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
+                                                                      b->ntiles, b->tile, 0);
+        (void)hipEventRecord(e0, st);
+        for (int rep = 0; rep < 5; ++rep)
+            bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
+                                                                      b->ntiles, b->tile, 0);
+        (void)hipEventRecord(e1, st);
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) return hip_err(e, "autotune");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_tile = tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return set_tile(b, best_tile);
+}
+
+void destroy(fl_batch *b) {
+    Guard g(b->device);
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (double *p : b->owned) (void)hipFree(p);
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, const int *n_scalars,
+                          const double *dt, int scheme, double *const *theta,
+                          const double *const *u_f, int tile_cells, int device, fl_batch **out) {
+    if (!out) return fail(FL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !meshes || !limiter || !n_scalars || !dt || !theta || !u_f)
+        return fail(FL_E_INVALID, "n must be positive and every array non-NULL");
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (tile_cells < 0 || (tile_cells > 0 && tile_cells % 64 != 0))
+        return fail(FL_E_INVALID, "tile_cells must be 0 (autotune) or a positive multiple of 64");
+    fl_batch *b = nullptr;
+    try {
+        b = new fl_batch();
+    } catch (const std::bad_alloc &) {
+        return fail(FL_E_NOMEM, "host allocation failed");
+    }
+    b->device = device;
+    b->scheme = scheme;
+    Guard g(device);
+    for (int i = 0; i < n; ++i) {
+        const fl_mesh *m = meshes[i];
+        if (!m || m->device != device || m->path != FL_PATH_FUSED || m->h.pairs < 1) {
+            destroy(b);
+            return fail(FL_E_INVALID, "every mesh must be a fused-path mesh on the batch's device");
+        }
+        if (limiter[i] < 0 || limiter[i] >= FL_NUM_LIMITERS || n_scalars[i] < 1 ||
+            n_scalars[i] > FL_MAX_SCALARS || !theta[i] || !u_f[i] || !(dt[i] == dt[i])) {
+            destroy(b);
+            return fail(FL_E_INVALID, "bad limiter, scalar count, dt or pointer for a problem");
+        }
+        BatchProblem p{};
+        p.nc = m->h.nc;
+        p.P = m->h.pairs;
+        p.S = n_scalars[i];
+        p.lim = limiter[i];
+        p.dt = dt[i];
+        p.area0 = m->h.area0;
+        p.vol0 = m->h.vol0;
+        p.sface = m->d_slot_face;
+        p.snbr = m->d_slot_nbr;
+        p.sfar = m->d_slot_far;
+        p.u = u_f[i];
+        p.area = m->d_area;
+        p.vol = m->d_vol;
+        p.th = theta[i];
+        const size_t bytes = (size_t)p.nc * p.S * sizeof(double);
+        for (double **dst : {&p.t1, &p.t2}) {
+            if (hipMalloc((void **)dst, bytes) != hipSuccess) {
+                destroy(b);
+                return fail(FL_E_NOMEM, "batch stage buffers");
+            }
+            b->owned.push_back(*dst);
+        }
+        b->probs.push_back(p);
+        b->meshes.push_back(m);
+    }
+    hipError_t e = hipMalloc((void **)&b->d_probs, b->probs.size() * sizeof(BatchProblem));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_probs, b->probs.data(), b->probs.size() * sizeof(BatchProblem),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreate(&b->cap);
+    if (e != hipSuccess) {
+        destroy(b);
+        return hip_err(e, "batch setup");
+    }
+    if (tile_cells > 0) {
+        fl_status s = set_tile(b, tile_cells);
+        if (s != FL_OK) {
+            destroy(b);
+            return s;
+        }
+    }
+    *out = b;
+    return FL_OK;
+}
+
+fl_status fl_batch_step(fl_batch *b, int n_steps, void *stream) {
+    if (!b) return fail(FL_E_INVALID, "batch is NULL");
+    if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    Guard g(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (b->tile == 0) {
+        fl_status s = autotune(b, st);
+        if (s != FL_OK) return s;
+    }
+    if (!b->exec) {
+        // record one step on the private stream; replay the graph on the caller's stream
+        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
+        hipError_t le = enqueue_step(b, b->cap);
+        e = hipStreamEndCapture(b->cap, &b->graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            drop_graph(b);
+            return hip_err(le != hipSuccess ? le : e, "batch capture");
+        }
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return hip_err(e, "hipGraphInstantiate");
+        }
+    }
+    for (int i = 0; i < n_steps; ++i) {
+        hipError_t e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
+    }
+    return FL_OK;
+}
+
+fl_status fl_batch_step_unbatched(fl_batch *b, int n_steps, void *stream) {
+    if (!b) return fail(FL_E_INVALID, "batch is NULL");
+    if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    Guard g(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    for (int it = 0; it < n_steps; ++it)
+        for (size_t i = 0; i < b->probs.size(); ++i) {
+            const BatchProblem &p = b->probs[i];
+            const fl_mesh *m = b->meshes[i];
+            hipError_t e;
+            if (b->scheme == FL_EULER) {
+                e = launch_fused(m, p.lim, p.S, p.th, p.th, p.u, 0.0, 1.0, p.dt, MODE_EULER, p.t1, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(p.th, p.t1, (size_t)p.nc * p.S * sizeof(double),
+                                       hipMemcpyDeviceToDevice, st);
+            } else {
+                e = launch_fused(m, p.lim, p.S, p.th, p.th, p.u, 0.0, 1.0, p.dt, MODE_EULER, p.t1, st);
+                if (e == hipSuccess)
+                    e = launch_fused(m, p.lim, p.S, p.t1, p.th, p.u, 0.75, 0.25, p.dt, MODE_RK, p.t2, st);
+                if (e == hipSuccess)
+                    e = launch_fused(m, p.lim, p.S, p.t2, p.th, p.u, 1.0 / 3.0, 2.0 / 3.0, p.dt,
+                                     MODE_RK, p.th, st);
+            }
+            if (e != hipSuccess) return hip_err(e, "unbatched launch");
+        }
+    return FL_OK;
+}
+
+fl_status fl_batch_tile(const fl_batch *b, int *tile_cells) {
+    if (!b || !tile_cells) return fail(FL_E_INVALID, "NULL argument");
+    *tile_cells = b->tile;
+    return FL_OK;
+}
+
+fl_status fl_batch_destroy(fl_batch *b) {
+    if (b) destroy(b);
+    return FL_OK;
+}
+
+}  // extern "C"

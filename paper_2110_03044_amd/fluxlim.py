@@ -341,3 +341,67 @@ def advect(mesh: Mesh, limiter, scheme, dt: float, theta0: torch.Tensor, u: torc
     discrete adjoint, ceil(sqrt(n_steps))-step checkpoints recomputed in the backward pass)."""
     every = checkpoint_every or checkpoint_interval(n_steps)
     return _Advect.apply(theta0, u, mesh, limiter, scheme, float(dt), int(n_steps), int(every))
+
+
+# ---------------------------------------------------------------------------------------------
+# Batched problems
+# ---------------------------------------------------------------------------------------------
+
+class Batch:
+    """Independent problems (mesh, limiter, theta, u, dt) advanced together: one kernel launch per
+    Runge-Kutta stage for all of them, recorded once in a HIP graph and replayed.
+
+    problems: sequence of (mesh, limiter, theta, u, dt); theta is updated in place.  Meshes may
+    be shared.  tile_cells = 0 lets the library time candidate tile sizes on the first step."""
+
+    def __init__(self, problems, scheme="ssprk3", tile_cells: int = 0):
+        n = len(problems)
+        if n == 0:
+            raise ValueError("empty batch")
+        meshes = [p[0] for p in problems]
+        dev = meshes[0].device_index
+        self._keep = []
+        mh = (ctypes.c_void_p * n)(*[m.handle.value for m in meshes])
+        lim = (ctypes.c_int * n)(*[limiter_id(p[1]) for p in problems])
+        ns = (ctypes.c_int * n)()
+        th = (ctypes.c_void_p * n)()
+        uu = (ctypes.c_void_p * n)()
+        dts = (ctypes.c_double * n)()
+        for i, (m, _, theta, u, dt) in enumerate(problems):
+            m._cells(theta)
+            m._faces(u)
+            ns[i] = _S(theta)
+            th[i] = theta.data_ptr()
+            uu[i] = u.data_ptr()
+            dts[i] = float(dt)
+            self._keep += [theta, u]
+        self.meshes = meshes
+        self.n = n
+        h = ctypes.c_void_p()
+        call("fl_batch_create", n, mh, lim, ns, dts, scheme_id(scheme), th, uu, int(tile_cells),
+             dev, ctypes.byref(h))
+        self._h = h
+        self.device = meshes[0].device
+
+    def step(self, n_steps: int = 1, stream=None):
+        call("fl_batch_step", self._h, int(n_steps), _stream(self.device, stream))
+
+    def step_unbatched(self, n_steps: int = 1, stream=None):
+        call("fl_batch_step_unbatched", self._h, int(n_steps), _stream(self.device, stream))
+
+    @property
+    def tile_cells(self) -> int:
+        t = ctypes.c_int()
+        call("fl_batch_tile", self._h, ctypes.byref(t))
+        return t.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

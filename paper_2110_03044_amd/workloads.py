@@ -232,9 +232,11 @@ def field_square_gauss_1d(n: int) -> np.ndarray:
 
 
 def field_blob_step(n: int, centre=(0.35, 0.35, 0.35), sigma: float = 0.08, width: float = 0.01,
-                    step_at: float = 0.5) -> np.ndarray:
-    """Periodic Gaussian blob plus a tanh step in x (natural numbering of periodic_box(n, 3))."""
-    x = cell_centres(n, 3)
+                    step_at: float = 0.5, x: Optional[np.ndarray] = None) -> np.ndarray:
+    """Periodic Gaussian blob plus a tanh step in x (natural numbering of periodic_box(n, 3));
+    x may pass precomputed cell_centres(n, 3)."""
+    if x is None:
+        x = cell_centres(n, 3)
     d = np.abs(x - np.asarray(centre)[None, :])
     d = np.minimum(d, 1.0 - d)
     r2 = (d * d).sum(axis=1)
@@ -360,9 +362,10 @@ def batch_recipe(count: int = 512, side_min: int = 12, side_max: int = 96, s_max
 def batch_fields(p: BatchProblem) -> np.ndarray:
     """[C][S] initial fields of one batched problem: shifted blobs plus steps, seeded."""
     rng = np.random.default_rng(p.seed)
+    x = cell_centres(p.n, 3)
     fs = []
     for s in range(p.n_scalars):
         c = tuple(rng.uniform(0.2, 0.8, size=3))
         fs.append(field_blob_step(p.n, centre=c, sigma=0.08 + 0.02 * s, width=0.02,
-                                  step_at=float(rng.uniform(0.3, 0.7))))
+                                  step_at=float(rng.uniform(0.3, 0.7)), x=x))
     return multi_scalar(fs)

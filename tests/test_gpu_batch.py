@@ -1,0 +1,104 @@
+"""Batched problems on the GPU: each problem of a batch equals its single-problem run bit for
+bit (same arithmetic in the same order), on every replay of the recorded graph, for autotuned
+and fixed tile sizes, and matches the CPU oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2110_03044_amd import _lib, fluxlim as FL, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+LIMS = ["upwind", "minmod", "vanleer", "vanalbada", "superbee", "smart", "central"]
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def make_problems(count=14, seed=5, dims=(1, 2, 3)):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(count):
+        d = int(dims[i % len(dims)])
+        n = int(rng.integers(5, 15)) if d == 3 else int(rng.integers(7, 40))
+        S = int(rng.integers(1, 9))
+        lim = LIMS[i % len(LIMS)]
+        nat = W.periodic_box(n, d)
+        m = W.renumber(nat, seed=100 + i) if i % 2 else nat
+        if d == 3:
+            u = m.face_velocity_from_natural(W.velocity_curl(n, seed=i))
+        else:
+            u = W.velocity_uniform(m, (0.8, -0.6, 0.0))
+        th = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+        dt = W.cfl_dt(m, u, float(rng.uniform(0.2, 0.45)))
+        probs.append(dict(mesh=m, u=u, th=th, dt=dt, lim=lim))
+    return probs
+
+
+def to_dev(p, reorder=True):
+    mesh = FL.Mesh.from_arrays(p["mesh"], device=0, reorder=reorder)
+    th = mesh.cells_to_mesh(torch.from_numpy(p["th"]).to(DEV))
+    u = mesh.faces_to_mesh(torch.from_numpy(p["u"]).to(DEV))
+    return mesh, th, u
+
+
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+@pytest.mark.parametrize("tile", [0, 64, 1024])
+def test_batch_equals_single_runs_on_every_replay(scheme, tile):
+    probs = make_problems()
+    dev_probs = [to_dev(p) for p in probs]
+    batch_th = [th.clone() for _, th, _ in dev_probs]
+    single_th = [th.clone() for _, th, _ in dev_probs]
+    b = FL.Batch([(m, p["lim"], bt, u, p["dt"]) for (m, _, u), bt, p in zip(dev_probs, batch_th, probs)],
+                 scheme=scheme, tile_cells=tile)
+    for replay in range(3):
+        b.step(2)
+        torch.cuda.synchronize()
+        for (m, _, u), st, p in zip(dev_probs, single_th, probs):  # eager work between replays
+            FL.rk_steps(m, p["lim"], scheme, p["dt"], st, u, 2)
+        torch.cuda.synchronize()
+        for i, (bt, st) in enumerate(zip(batch_th, single_th)):
+            assert torch.equal(bt, st), (replay, i, probs[i]["lim"])
+    assert b.tile_cells > 0 and (tile == 0 or b.tile_cells == tile)
+    b.close()
+
+
+def test_batch_matches_oracle_and_unbatched():
+    probs = make_problems(count=8, seed=9)
+    dev_probs = [to_dev(p) for p in probs]
+    a = [th.clone() for _, th, _ in dev_probs]
+    c = [th.clone() for _, th, _ in dev_probs]
+    b1 = FL.Batch([(m, p["lim"], t, u, p["dt"]) for (m, _, u), t, p in zip(dev_probs, a, probs)])
+    b2 = FL.Batch([(m, p["lim"], t, u, p["dt"]) for (m, _, u), t, p in zip(dev_probs, c, probs)],
+                  tile_cells=256)
+    b1.step(4)
+    b2.step_unbatched(4)
+    torch.cuda.synchronize()
+    for i, ((m, _, _), p) in enumerate(zip(dev_probs, probs)):
+        assert torch.equal(a[i], c[i]), i
+        want = O.OracleMesh.from_arrays(p["mesh"]).run(p["lim"], "ssprk3", p["dt"], p["th"], p["u"], 4)
+        got = m.cells_from_mesh(a[i]).cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max(), (i, p["lim"])
+
+
+def test_batch_shared_mesh_and_rejections():
+    p = make_problems(count=1, seed=2, dims=(3,))[0]
+    mesh, th, u = to_dev(p)
+    t1, t2 = th.clone(), (2.0 * th).clone()
+    b = FL.Batch([(mesh, "superbee", t1, u, p["dt"]), (mesh, "vanleer", t2, u, 0.5 * p["dt"])])
+    b.step(3)
+    r1, r2 = th.clone(), (2.0 * th).clone()
+    FL.rk_steps(mesh, "superbee", "ssprk3", p["dt"], r1, u, 3)
+    FL.rk_steps(mesh, "vanleer", "ssprk3", 0.5 * p["dt"], r2, u, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(t1, r1) and torch.equal(t2, r2)
+    face = FL.Mesh.from_arrays(p["mesh"], device=0, face_path=True)
+    with pytest.raises(_lib.FluxLimError):
+        FL.Batch([(face, "minmod", face.cells_to_mesh(torch.from_numpy(p["th"]).to(DEV)),
+                   face.faces_to_mesh(torch.from_numpy(p["u"]).to(DEV)), p["dt"])])
+    with pytest.raises(_lib.FluxLimError):
+        FL.Batch([(mesh, "minmod", t1, u, p["dt"])], tile_cells=100)
