@@ -4,17 +4,17 @@
 // Each problem is described once in device memory (mesh slot tables, face velocity, buffers,
 // limiter, dt).  The work table lists (problem, first cell) tiles of `tile` cells; a persistent
 // grid of workgroups strides over the table, each workgroup processing one tile at a time with
-// one thread per cell.  Tiles never span problems, so the problem descriptor and the limiter
-// branch are uniform within a workgroup.  The scalar count is a run-time loop bound: one kernel
-// serves every S.  The arithmetic per cell and face is the fused stage kernel's, in the same
-// order, so each problem's result equals its single-problem run.
+// one thread per cell.  Tiles never span problems, so the problem descriptor, the limiter and
+// the (pairs, scalars) specialisation chosen per tile are uniform within a workgroup: one kernel
+// serves every problem.  Each cell runs the single-problem kernel's own routine (fl_device.h),
+// so each problem's result equals its single-problem run bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <new>
 #include <vector>
 
-#include "fl_kernels.h"
+#include "fl_device.h"
 
 struct BatchProblem {
     int64_t nc;
@@ -35,90 +35,32 @@ namespace fl {
 namespace bdev {
 
 constexpr int kBlock = 256;
-constexpr double kRBig = 1.0e18;
 
-__device__ __forceinline__ double psi_inf(int lim, bool pos) {
-    switch (lim) {
-        case FL_MINMOD: return pos ? 1.0 : 0.0;
-        case FL_VANLEER: return pos ? 2.0 : 0.0;
-        case FL_VANALBADA: return 1.0;
-        case FL_SUPERBEE: return pos ? 2.0 : 0.0;
-        case FL_SMART: return pos ? 4.0 : 0.0;
-        case FL_CENTRAL: return 1.0;
-        default: return 0.0;
+// One cell of one problem: the single-problem routine, specialised for the problem's pair and
+// scalar counts (a uniform branch: a tile never spans problems).
+__device__ __forceinline__ void batch_cell(const BatchProblem &pb, int64_t c, const double *ts,
+                                           double a, double b, int mode, double *out) {
+#define FL_BCELL(SS, PP)                                                                       \
+    dev::fused_cell<SS, PP>(c, pb.nc, pb.sface, pb.snbr, pb.sfar, pb.u, pb.area, pb.area0,     \
+                            pb.vol, pb.vol0, ts, pb.th, a, b, pb.dt, mode, pb.lim, out)
+#define FL_BCELL_S(PP)                      \
+    switch (pb.S) {                         \
+        case 1: FL_BCELL(1, PP); break;     \
+        case 2: FL_BCELL(2, PP); break;     \
+        case 3: FL_BCELL(3, PP); break;     \
+        case 4: FL_BCELL(4, PP); break;     \
+        case 5: FL_BCELL(5, PP); break;     \
+        case 6: FL_BCELL(6, PP); break;     \
+        case 7: FL_BCELL(7, PP); break;     \
+        default: FL_BCELL(8, PP); break;    \
     }
-}
-
-__device__ __forceinline__ double psi(int lim, double r) {
-    if (!(fabs(r) <= kRBig)) return psi_inf(lim, r > 0.0);
-    switch (lim) {
-        case FL_MINMOD: return fmax(0.0, fmin(1.0, r));
-        case FL_VANLEER: {
-            const double ar = fabs(r);
-            return (r + ar) / (1.0 + ar);
-        }
-        case FL_VANALBADA: {
-            const double r2 = r * r;
-            return (r2 + r) / (r2 + 1.0);
-        }
-        case FL_SUPERBEE: return fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
-        case FL_SMART: return fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
-        case FL_CENTRAL: return 1.0;
-        default: return 0.0;
+    switch (pb.P) {
+        case 1: FL_BCELL_S(1); break;
+        case 2: FL_BCELL_S(2); break;
+        default: FL_BCELL_S(3); break;
     }
-}
-
-__device__ __forceinline__ double face_value(int lim, double tC, double tD, double tU) {
-    const double du = tD - tC;
-    if (lim == FL_UPWIND || du == 0.0) return tC;
-    const double r = (tC - tU) / du;
-    return tC + 0.5 * psi(lim, r) * du;
-}
-
-template <int P>
-__device__ __forceinline__ void cell_stage(const BatchProblem &pb, int64_t c, const double *ts,
-                                           const double *tn, double a, double b, int mode,
-                                           double *out) {
-    constexpr int K = 2 * P;
-    const int64_t nc = pb.nc;
-    const int S = pb.S, lim = pb.lim;
-    uint32_t fw[K];
-    int64_t nb[K], gf[K];
-    double au[K], uu[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        fw[k] = pb.sface[(int64_t)k * nc + c];
-        nb[k] = pb.snbr[(int64_t)k * nc + c];
-        gf[k] = pb.sfar[(int64_t)k * nc + c];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t f = fw[k] & 0x7fffffffu;
-        uu[k] = pb.u[f];
-        au[k] = (pb.area ? pb.area[f] : pb.area0) * uu[k];
-    }
-    const double V = pb.vol ? pb.vol[c] : pb.vol0;
-    for (int s = 0; s < S; ++s) {
-        const double tc = ts[c * S + s];
-        double tnb[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) tnb[k] = ts[nb[k] * S + s];
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool c_is_own = (fw[k] >> 31) != 0;
-            const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
-            const double tg = (!c_upwind && lim != FL_UPWIND) ? ts[gf[k] * S + s] : 0.0;
-            const double tC = c_upwind ? tc : tnb[k];
-            const double tD = c_upwind ? tnb[k] : tc;
-            const double tU = c_upwind ? tnb[k ^ 1] : tg;
-            const double ph = au[k] * face_value(lim, tC, tD, tU);
-            acc = c_is_own ? acc - ph : acc + ph;
-        }
-        const int64_t i = c * S + s;
-        if (mode == MODE_EULER) out[i] = tc + pb.dt * (acc / V);
-        else out[i] = a * tn[i] + b * (tc + pb.dt * (acc / V));
-    }
+#undef FL_BCELL_S
+#undef FL_BCELL
 }
 
 // stage 0: theta -> t1 (Euler form); stage 1: (t1, theta) -> t2; stage 2: (t2, theta) -> theta.
@@ -135,13 +77,8 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchProblem 
         double *out = stage == 0 ? pb.t1 : stage == 1 ? pb.t2 : pb.th;
         const int mode = stage == 0 ? MODE_EULER : MODE_RK;
         const int64_t c1 = min(T.c0 + (int64_t)tile, pb.nc);
-        for (int64_t c = T.c0 + threadIdx.x; c < c1; c += blockDim.x) {
-            switch (pb.P) {
-                case 1: cell_stage<1>(pb, c, ts, pb.th, A[stage], B[stage], mode, out); break;
-                case 2: cell_stage<2>(pb, c, ts, pb.th, A[stage], B[stage], mode, out); break;
-                default: cell_stage<3>(pb, c, ts, pb.th, A[stage], B[stage], mode, out); break;
-            }
-        }
+        for (int64_t c = T.c0 + threadIdx.x; c < c1; c += blockDim.x)
+            batch_cell(pb, c, ts, A[stage], B[stage], mode, out);
     }
 }
 

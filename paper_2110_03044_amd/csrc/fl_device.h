@@ -1,0 +1,148 @@
+// Device routines shared by the single-problem and the batched kernels: the limiter, the
+// limited face value and the fused per-cell stage.  Both launch paths call exactly this code, so
+// a problem advanced inside a batch gives the same bits as when advanced alone.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fl_kernels.h"
+
+namespace fl {
+namespace dev {
+
+constexpr double kRBig = 1.0e18;
+
+// psi at r = +inf (pos) or -inf.
+__device__ __forceinline__ double psi_inf(int lim, bool pos) {
+    switch (lim) {
+        case FL_MINMOD: return pos ? 1.0 : 0.0;
+        case FL_VANLEER: return pos ? 2.0 : 0.0;
+        case FL_VANALBADA: return 1.0;
+        case FL_SUPERBEE: return pos ? 2.0 : 0.0;
+        case FL_SMART: return pos ? 4.0 : 0.0;
+        case FL_CENTRAL: return 1.0;
+        default: return 0.0;
+    }
+}
+
+// Limiters of Sweby's family (superbee as in Table 1 of the paper).
+__device__ __forceinline__ double psi(int lim, double r) {
+    if (!(fabs(r) <= kRBig)) return psi_inf(lim, r > 0.0);
+    switch (lim) {
+        case FL_MINMOD: return fmax(0.0, fmin(1.0, r));
+        case FL_VANLEER: {
+            const double ar = fabs(r);
+            return (r + ar) / (1.0 + ar);
+        }
+        case FL_VANALBADA: {
+            const double r2 = r * r;
+            return (r2 + r) / (r2 + 1.0);
+        }
+        case FL_SUPERBEE: return fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
+        case FL_SMART: return fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
+        case FL_CENTRAL: return 1.0;
+        default: return 0.0;
+    }
+}
+
+// Limited face value of the Sweby form from the upwind, downwind and far-upwind values:
+// theta_C + psi(r) (theta_D - theta_C) / 2, r = (theta_C - theta_U) / (theta_D - theta_C).
+__device__ __forceinline__ double face_value(int lim, double tC, double tD, double tU) {
+    const double du = tD - tC;
+    if (lim == FL_UPWIND || du == 0.0) return tC;
+    const double r = (tC - tU) / du;
+    return tC + 0.5 * psi(lim, r) * du;
+}
+
+// Scalars S0 .. S0+CS-1 of cell c (CS <= 2 keeps the gathered values in registers for any S).
+template <int S, int P, int S0>
+__device__ __forceinline__ void fused_chunks(int64_t c, const uint32_t *fw, const int64_t *nb,
+                                             const int64_t *gf, const double *uu,
+                                             const double *au, double V,
+                                             const double *__restrict__ ts,
+                                             const double *__restrict__ tn, double a, double b,
+                                             double dt, int mode, int lim,
+                                             double *__restrict__ out) {
+    if constexpr (S0 < S) {
+        constexpr int K = 2 * P;
+        constexpr int CS = (S - S0) >= 2 ? 2 : 1;
+        double tc[CS], tnb[K][CS], tg[K][CS];
+#pragma unroll
+        for (int i = 0; i < CS; ++i) tc[i] = ts[c * S + S0 + i];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = 0; i < CS; ++i) tnb[k][i] = ts[nb[k] * S + S0 + i];
+            if (lim != FL_UPWIND) {
+#pragma unroll
+                for (int i = 0; i < CS; ++i) tg[k][i] = ts[gf[k] * S + S0 + i];
+            }
+        }
+        double acc[CS];
+#pragma unroll
+        for (int i = 0; i < CS; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool c_is_own = (fw[k] >> 31) != 0;
+            // Q(u_f): C = own where u_f > 0, C = nbr otherwise
+            const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
+#pragma unroll
+            for (int i = 0; i < CS; ++i) {
+                // pick (theta_C, theta_D, theta_U) first: one evaluation where lanes diverge
+                const double tC = c_upwind ? tc[i] : tnb[k][i];
+                const double tD = c_upwind ? tnb[k][i] : tc[i];
+                const double tU = c_upwind ? tnb[k ^ 1][i] : tg[k][i];
+                const double ph = au[k] * face_value(lim, tC, tD, tU);
+                acc[i] = c_is_own ? acc[i] - ph : acc[i] + ph;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CS; ++i) {
+            const int64_t j = c * S + S0 + i;
+            if (mode == MODE_RHS) out[j] = acc[i] / V;
+            else if (mode == MODE_EULER) out[j] = tc[i] + dt * (acc[i] / V);
+            else out[j] = a * tn[j] + b * (tc[i] + dt * (acc[i] / V));
+        }
+        fused_chunks<S, P, S0 + CS>(c, fw, nb, gf, uu, au, V, ts, tn, a, b, dt, mode, lim, out);
+    }
+}
+
+// One stage for cell c with P opposite-face pairs (slots 2p and 2p+1 are opposite faces).
+// Slot k gives the face f_k (bit 31: c is its own), the other cell n_k and the far-upwind cell
+// g_k on n_k's side; the far-upwind cell on c's side of f_k is n_{k^1}.  The table entries and
+// velocities are read once for all scalars, then every gather of a chunk is issued before its
+// arithmetic (the kernel is bound by gather latency and L2 misses, not by arithmetic).
+// out = rhs (MODE_RHS), theta_s + dt rhs (MODE_EULER) or a theta_n + b (theta_s + dt rhs).
+template <int S, int P>
+__device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t *__restrict__ sface,
+                                           const int32_t *__restrict__ snbr,
+                                           const int32_t *__restrict__ sfar,
+                                           const double *__restrict__ u,
+                                           const double *__restrict__ area, double area0,
+                                           const double *__restrict__ vol, double vol0,
+                                           const double *__restrict__ ts,
+                                           const double *__restrict__ tn, double a, double b,
+                                           double dt, int mode, int lim,
+                                           double *__restrict__ out) {
+    constexpr int K = 2 * P;
+    uint32_t fw[K];
+    int64_t nb[K], gf[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        fw[k] = sface[(int64_t)k * nc + c];
+        nb[k] = snbr[(int64_t)k * nc + c];
+        gf[k] = sfar[(int64_t)k * nc + c];
+    }
+    double uu[K], au[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t f = fw[k] & 0x7fffffffu;
+        uu[k] = u[f];
+        au[k] = (area ? area[f] : area0) * uu[k];
+    }
+    const double V = vol ? vol[c] : vol0;
+    fused_chunks<S, P, 0>(c, fw, nb, gf, uu, au, V, ts, tn, a, b, dt, mode, lim, out);
+}
+
+}  // namespace dev
+}  // namespace fl

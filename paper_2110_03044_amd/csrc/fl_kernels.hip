@@ -19,58 +19,17 @@
 // near the memory roofline.
 #include <hip/hip_runtime.h>
 
-#include "fl_kernels.h"
+#include "fl_device.h"
 
 namespace fl {
 namespace dev {
 
 constexpr int kBlock = 256;
-constexpr double kRBig = 1.0e18;
 
 __device__ __forceinline__ int64_t block_id(int remap) {
     if (!remap) return blockIdx.x;
     const int per = gridDim.x >> 3;
     return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-}
-
-// psi at r = +inf (pos) or -inf.
-__device__ __forceinline__ double psi_inf(int lim, bool pos) {
-    switch (lim) {
-        case FL_MINMOD: return pos ? 1.0 : 0.0;
-        case FL_VANLEER: return pos ? 2.0 : 0.0;
-        case FL_VANALBADA: return 1.0;
-        case FL_SUPERBEE: return pos ? 2.0 : 0.0;
-        case FL_SMART: return pos ? 4.0 : 0.0;
-        case FL_CENTRAL: return 1.0;
-        default: return 0.0;
-    }
-}
-
-__device__ __forceinline__ double psi(int lim, double r) {
-    if (!(fabs(r) <= kRBig)) return psi_inf(lim, r > 0.0);
-    switch (lim) {
-        case FL_MINMOD: return fmax(0.0, fmin(1.0, r));
-        case FL_VANLEER: {
-            const double ar = fabs(r);
-            return (r + ar) / (1.0 + ar);
-        }
-        case FL_VANALBADA: {
-            const double r2 = r * r;
-            return (r2 + r) / (r2 + 1.0);
-        }
-        case FL_SUPERBEE: return fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
-        case FL_SMART: return fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
-        case FL_CENTRAL: return 1.0;
-        default: return 0.0;
-    }
-}
-
-// Limited face value of the Sweby form from the upwind, downwind and far-upwind values.
-__device__ __forceinline__ double face_value(int lim, double tC, double tD, double tU) {
-    const double du = tD - tC;
-    if (lim == FL_UPWIND || du == 0.0) return tC;
-    const double r = (tC - tU) / du;
-    return tC + 0.5 * psi(lim, r) * du;
 }
 
 template <int S>
@@ -163,13 +122,8 @@ __global__ __launch_bounds__(kBlock) void cell_update_kernel(
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused path
+// Fused path (the per-cell routine is in fl_device.h, shared with the batched kernel)
 // ------------------------------------------------------------------------------------------
-// One thread per cell c with P opposite-face pairs (slots 2p and 2p+1 are opposite faces).
-// Slot k gives the face f_k (bit 31: c is its own), the other cell n_k and the far-upwind cell
-// g_k on n_k's side; the far-upwind cell on c's side of f_k is n_{k^1}.  Every table entry and
-// gather is issued before any arithmetic so all of a thread's memory requests are in flight at
-// once (the kernel is bound by gather latency and L2 misses, not by arithmetic).
 template <int S, int P>
 __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
     int64_t nc, const uint32_t *__restrict__ sface, const int32_t *__restrict__ snbr,
@@ -177,47 +131,10 @@ __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
     const double *__restrict__ area, double area0, const double *__restrict__ vol, double vol0,
     const double *__restrict__ ts, const double *__restrict__ tn, double a, double b, double dt,
     int mode, int lim, double *__restrict__ out, int remap) {
-    constexpr int K = 2 * P;
     const int64_t c = block_id(remap) * kBlock + threadIdx.x;
     if (c >= nc) return;
-    uint32_t fw[K];
-    int64_t nb[K], gf[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        fw[k] = sface[(int64_t)k * nc + c];
-        nb[k] = snbr[(int64_t)k * nc + c];
-        gf[k] = sfar[(int64_t)k * nc + c];
-    }
-    double tc[S], tnb[K][S], tg[K][S], uu[K], au[K];
-    load_cell<S>(ts, c, tc);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t f = fw[k] & 0x7fffffffu;
-        uu[k] = u[f];
-        au[k] = (area ? area[f] : area0) * uu[k];
-        load_cell<S>(ts, nb[k], tnb[k]);
-        if (lim != FL_UPWIND) load_cell<S>(ts, gf[k], tg[k]);
-    }
-    double acc[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const bool c_is_own = (fw[k] >> 31) != 0;
-        // Q(u_f): C = own where u_f > 0, C = nbr otherwise
-        const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            // pick (theta_C, theta_D, theta_U) first: one evaluation even where lanes diverge
-            const double tC = c_upwind ? tc[s] : tnb[k][s];
-            const double tD = c_upwind ? tnb[k][s] : tc[s];
-            const double tU = c_upwind ? tnb[k ^ 1][s] : tg[k][s];
-            const double tf = face_value(lim, tC, tD, tU);
-            const double ph = au[k] * tf;
-            acc[s] = c_is_own ? acc[s] - ph : acc[s] + ph;
-        }
-    }
-    finish_cell<S>(c, acc, vol ? vol[c] : vol0, ts, tn, a, b, dt, mode, out);
+    fused_cell<S, P>(c, nc, sface, snbr, sfar, u, area, area0, vol, vol0, ts, tn, a, b, dt, mode,
+                     lim, out);
 }
 
 // ------------------------------------------------------------------------------------------
