@@ -36,6 +36,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "fused_stage_kernel_box256_traffic.txt")
+KERNEL_SOURCES = ["fl_device.h", "fl_kernels.hip"]
+
+
+def kernel_source_hash():
+    """sha256 of the sources that define the fused stage kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2110_03044_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(here, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n, xcd_remap):
+    """HBM bytes per fused-stage launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed
+    rocprofv3 counter summary, or None if it was taken on other kernel sources, sizes or launch
+    mapping."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if (kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n
+                or int(kv.get("xcd_remap", -1)) != int(xcd_remap)):
+            return None
+        return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def fused_stage_bytes(C, F, K, S, stage):
     """Compulsory bytes of one fused stage launch: slot tables (face, cell, far cell: 12 B per
     slot), face velocities once, theta_s read once, theta_n read once (stages 2, 3) and the
@@ -171,7 +206,8 @@ def main():
     ap.add_argument("--limiters", default=",".join(LIM_DEFAULT))
     ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--face-path", action="store_true")
-    ap.add_argument("--no-xcd-remap", action="store_true")
+    ap.add_argument("--xcd-remap", type=int, default=0,
+                    help="1: each XCD takes a contiguous eighth of the cells (FL_OPT_XCD_REMAP)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 to skip the oracle timing")
     ap.add_argument("--calib-copy-mib", type=int, default=1024,
                     help="size of the untimed calibration copy (0 to skip)")
@@ -191,8 +227,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     lims = [l for l in args.limiters.split(",") if l]
-    if args.no_xcd_remap:
-        _lib.lib()  # remap is a compile-time default in the library; flag kept for sweeps
+    _lib.call("fl_set_option", 1, int(args.xcd_remap))  # FL_OPT_XCD_REMAP
     t0 = time.time()
     wl = W.workload_box(args.n, renumbered=True)
     m = wl.mesh
@@ -282,7 +317,8 @@ def main():
         achieved = bytes_per_step / 3 / avg_launch_s / 1e9
         out["roofline"] = {"kernel": "fused_stage_kernel", "bound": "hbm",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                           "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": measured_traffic(args.n, args.xcd_remap),
                            "algorithmic_bytes_per_launch": int(bytes_per_step / 3),
                            "avg_launch_us": round(avg_launch_s * 1e6, 2)}
     # the two-kernel byte model (40 B/face + 60 B/cell per stage) as context

@@ -206,6 +206,15 @@ fl_status fl_batch_step_unbatched(fl_batch *batch, int n_steps, void *hip_stream
 fl_status fl_batch_tile(const fl_batch *batch, int *tile_cells);
 fl_status fl_batch_destroy(fl_batch *batch);
 
+/* Process-wide launch tuning, read by later launches of the single-problem kernels:
+ *   FL_OPT_XCD_REMAP  0 (default): workgroups take cells in launch order; 1: the grid is padded
+ *                     to a multiple of 8 and each of the 8 XCDs gets a contiguous eighth of the
+ *                     cells.
+ * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
+ * on other threads. */
+enum { FL_OPT_XCD_REMAP = 1 };
+fl_status fl_set_option(int option, int value);
+
 const char *fl_status_str(fl_status status);
 const char *fl_last_error(void);
 

@@ -68,6 +68,7 @@ SIGNATURES = {
     "fl_batch_step_unbatched": (_S, [_P, _I, _P]),
     "fl_batch_tile": (_S, [_P, _P]),
     "fl_batch_destroy": (_S, [_P]),
+    "fl_set_option": (_S, [_I, _I]),
     "fl_status_str": (ctypes.c_char_p, [_S]),
     "fl_last_error": (ctypes.c_char_p, []),
     "fl_debug_select": (_S, [_P, _P, _P, _P]),

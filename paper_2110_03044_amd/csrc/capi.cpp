@@ -142,6 +142,14 @@ const char *fl_status_str(fl_status s) {
 
 const char *fl_last_error(void) { return g_error.c_str(); }
 
+fl_status fl_set_option(int option, int value) {
+    if (option == FL_OPT_XCD_REMAP && (value == 0 || value == 1)) {
+        set_xcd_remap(value);
+        return FL_OK;
+    }
+    return fail(FL_E_INVALID, "unknown option or value");
+}
+
 fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                            const double *face_normal) {
     try {
