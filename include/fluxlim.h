@@ -164,6 +164,14 @@ fl_status fl_rk_steps(const fl_mesh *mesh, int limiter, int scheme, double dt, i
                       int64_t n_steps, double *theta, const double *u_f, void *work,
                       void *hip_stream);
 
+/* Explicit steps with a time-dependent velocity u(t) = s(t) u_f (the deformation benchmark of
+ * Section 4.1 reverses its field with s = cos(pi t / T)).  u_scale: host array, read during
+ * the call, of s at every stage: u_scale[i * stages + j] for stage j of step i (Euler: 1 stage;
+ * SSP-RK3: 3 stages, evaluated at t_i, t_i + dt, t_i + dt/2).  Otherwise as fl_rk_steps. */
+fl_status fl_rk_steps_scaled(const fl_mesh *mesh, int limiter, int scheme, double dt,
+                             int n_scalars, int64_t n_steps, double *theta, const double *u_f,
+                             const double *u_scale, void *work, void *hip_stream);
+
 /* Adjoint of fl_convect_apply (discrete reverse mode; Q(u_f) and the branch of psi taken at
  * theta are held fixed):
  *   theta_bar += (dL/dtheta)^T rhs_bar,   u_bar += (dL/du_f)^T rhs_bar (skipped if NULL).

@@ -334,6 +334,32 @@ int orc_run(const orc_mesh *m, int lim, int scheme, double dt, int S, int64_t ns
     return 0;
 }
 
+/* Time-dependent velocity u(t) = s(t) u: scales[i * stages + j] is s at stage j of step i.
+ * Each stage forms the face velocities s u and applies the same stage as orc_run. */
+int orc_run_scaled(const orc_mesh *m, int lim, int scheme, double dt, int S, int64_t nsteps,
+                   double *th, const double *u, const double *scales) {
+    if (scheme != ORC_EULER && scheme != ORC_SSPRK3) return -1;
+    int ns = scheme == ORC_EULER ? 1 : 3;
+    size_t n = (size_t)(m->nc * S);
+    double *rhs = (double *)malloc(n * sizeof(double));
+    double *t1 = (double *)malloc(n * sizeof(double));
+    double *t2 = (double *)malloc(n * sizeof(double));
+    double *us = (double *)malloc((size_t)m->nf * sizeof(double));
+    for (int64_t it = 0; it < nsteps; ++it) {
+        for (int st = 0; st < ns; ++st) {
+            double s = scales[it * ns + st];
+            for (int64_t f = 0; f < m->nf; ++f) us[f] = s * u[f];
+            if (ns == 1) stage(m, lim, S, dt, 0.0, 1.0, th, th, us, rhs, t1);
+            else if (st == 0) stage(m, lim, S, dt, RK3_A[0], RK3_B[0], th, th, us, rhs, t1);
+            else if (st == 1) stage(m, lim, S, dt, RK3_A[1], RK3_B[1], t1, th, us, rhs, t2);
+            else stage(m, lim, S, dt, RK3_A[2], RK3_B[2], t2, th, us, rhs, t1);
+        }
+        memcpy(th, t1, n * sizeof(double));
+    }
+    free(rhs); free(t1); free(t2); free(us);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------------
  * Tangent (forward mode) of L.  theta_f depends on theta_C, theta_D and the far cells through
  * d_U and d_u; the selection Q(u) is piecewise constant and contributes nothing.

@@ -77,6 +77,11 @@ void orc_rhs_cells(const orc_mesh *m, int limiter, int S, const double *theta, c
 int orc_run(const orc_mesh *m, int limiter, int scheme, double dt, int S, int64_t nsteps,
             double *theta, const double *u);
 
+/* As orc_run with the time-dependent velocity u(t) = s(t) u (Section 4.1's deformation flow):
+ * scales[i * stages + j] is s at stage j of step i (stages: Euler 1, SSP-RK3 3). */
+int orc_run_scaled(const orc_mesh *m, int limiter, int scheme, double dt, int S, int64_t nsteps,
+                   double *theta, const double *u, const double *scales);
+
 /* Tangent and adjoint of rhs = L(theta, u). */
 void orc_rhs_jvp(const orc_mesh *m, int limiter, int S, const double *theta, const double *u,
                  const double *dtheta, const double *du, double *drhs);

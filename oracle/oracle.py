@@ -71,6 +71,8 @@ def lib():
         L.orc_run_tangent.argtypes = [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P]
         L.orc_run_adjoint.restype = _I
         L.orc_run_adjoint.argtypes = [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P, _P]
+        L.orc_run_scaled.restype = _I
+        L.orc_run_scaled.argtypes = [_P, _I, _I, _D, _I, _I64, _P, _P, _P]
         L.orc_num_threads.restype = _I
         _lib = L
     return _lib
@@ -173,6 +175,20 @@ class OracleMesh:
         sc = {"euler": EULER, "ssprk3": SSPRK3}.get(scheme, scheme)
         rc = lib().orc_run(self._h, lim_id(limiter), int(sc), float(dt), self._S(th), int(nsteps),
                            _ptr(th), _ptr(u))
+        if rc != 0:
+            raise ValueError("bad scheme")
+        return th
+
+    def run_scaled(self, limiter, scheme, dt, theta0, u, scales) -> np.ndarray:
+        th = _f64(theta0).copy()
+        u = _f64(u)
+        sc = {"euler": EULER, "ssprk3": SSPRK3}.get(scheme, scheme)
+        scales = _f64(scales)
+        ns = 1 if sc == EULER else 3
+        if scales.size % ns:
+            raise ValueError("scales must hold stages * n_steps values")
+        rc = lib().orc_run_scaled(self._h, lim_id(limiter), int(sc), float(dt), self._S(th),
+                                  scales.size // ns, _ptr(th), _ptr(u), _ptr(scales))
         if rc != 0:
             raise ValueError("bad scheme")
         return th

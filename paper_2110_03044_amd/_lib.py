@@ -58,6 +58,7 @@ SIGNATURES = {
     "fl_rk_workspace_bytes": (_SZ, [_P, _I, _I]),
     "fl_rk_step": (_S, [_P, _I, _I, _D, _I, _P, _P, _P, _P]),
     "fl_rk_steps": (_S, [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P]),
+    "fl_rk_steps_scaled": (_S, [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P, _P]),
     "fl_adjoint_workspace_bytes": (_SZ, [_P, _I]),
     "fl_convect_adjoint": (_S, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
     "fl_rk_adjoint_workspace_bytes": (_SZ, [_P, _I, _I]),

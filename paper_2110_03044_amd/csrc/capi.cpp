@@ -95,9 +95,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // One stage: out = a tn + b (ts + dt L(ts)) in the given mode.
 hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b, int mode,
                  const double *ts, const double *tn, const double *u, double *out, double *phi,
-                 hipStream_t st) {
-    if (m->path == FL_PATH_FUSED) return launch_fused(m, lim, S, ts, tn, u, a, b, dt, mode, out, st);
-    hipError_t e = launch_face_flux(m, lim, S, ts, u, phi, st);
+                 hipStream_t st, double us = 1.0) {
+    if (m->path == FL_PATH_FUSED)
+        return launch_fused(m, lim, S, ts, tn, u, a, b, dt, mode, out, st, us);
+    hipError_t e = launch_face_flux(m, lim, S, ts, u, phi, st, us);
     if (e != hipSuccess) return e;
     return launch_cell_update(m, S, phi, ts, tn, a, b, dt, mode, out, st);
 }
@@ -395,6 +396,47 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
         }
     }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step launch");
+}
+
+fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, int S,
+                             int64_t n_steps, double *theta, const double *u,
+                             const double *u_scale, void *work, void *stream) {
+    fl_status s = check_compute(m, lim, S);
+    if (s != FL_OK) return s;
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (!theta || !u || !work || (n_steps > 0 && !u_scale))
+        return fail(FL_E_INVALID, "NULL pointer");
+    if (misaligned(theta) || misaligned(u) || ((uintptr_t)work & 255u))
+        return fail(FL_E_INVALID, "theta/u must be 8-byte and work 256-byte aligned");
+    if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    Work w = carve(m, S, work);
+    hipError_t e = hipSuccess;
+    const double *sc = u_scale;
+    if (scheme == FL_EULER) {
+        double *src = theta, *dst = w.t1;
+        for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
+            if (m->path == FL_PATH_FACE_CELL) {
+                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, theta, theta, u, theta, w.phi, st, sc[i]);
+            } else {
+                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, src, src, u, dst, w.phi, st, sc[i]);
+                std::swap(src, dst);
+            }
+        }
+        if (e == hipSuccess && src != theta)
+            e = hipMemcpyAsync(theta, src, m->h.nc * S * sizeof(double), hipMemcpyDeviceToDevice, st);
+    } else {
+        for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
+            const double *si = sc + 3 * i;
+            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, w.t1, w.phi, st, si[0]);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, w.t1, theta, u, w.t2, w.phi, st, si[1]);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, w.t2, theta, u, theta, w.phi, st, si[2]);
+        }
+    }
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_steps_scaled launch");
 }
 
 fl_status fl_rk_step(const fl_mesh *m, int lim, int scheme, double dt, int S, double *theta,

@@ -42,7 +42,7 @@ __device__ __forceinline__ void batch_cell(const BatchProblem &pb, int64_t c, co
                                            double a, double b, int mode, double *out) {
 #define FL_BCELL(SS, PP)                                                                       \
     dev::fused_cell<SS, PP>(c, pb.nc, pb.sface, pb.snbr, pb.sfar, pb.u, pb.area, pb.area0,     \
-                            pb.vol, pb.vol0, ts, pb.th, a, b, pb.dt, mode, pb.lim, out)
+                            pb.vol, pb.vol0, ts, pb.th, a, b, pb.dt, mode, pb.lim, out, 1.0)
 #define FL_BCELL_S(PP)                      \
     switch (pb.S) {                         \
         case 1: FL_BCELL(1, PP); break;     \

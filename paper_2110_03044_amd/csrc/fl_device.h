@@ -112,7 +112,8 @@ __device__ __forceinline__ void fused_chunks(int64_t c, const uint32_t *fw, cons
 // g_k on n_k's side; the far-upwind cell on c's side of f_k is n_{k^1}.  The table entries and
 // velocities are read once for all scalars, then every gather of a chunk is issued before its
 // arithmetic (the kernel is bound by gather latency and L2 misses, not by arithmetic).
-// out = rhs (MODE_RHS), theta_s + dt rhs (MODE_EULER) or a theta_n + b (theta_s + dt rhs).
+// out = rhs (MODE_RHS), theta_s + dt rhs (MODE_EULER) or a theta_n + b (theta_s + dt rhs);
+// the face velocities are us * u.
 template <int S, int P>
 __device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t *__restrict__ sface,
                                            const int32_t *__restrict__ snbr,
@@ -123,7 +124,7 @@ __device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t
                                            const double *__restrict__ ts,
                                            const double *__restrict__ tn, double a, double b,
                                            double dt, int mode, int lim,
-                                           double *__restrict__ out) {
+                                           double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
     uint32_t fw[K];
     int64_t nb[K], gf[K];
@@ -137,7 +138,7 @@ __device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t f = fw[k] & 0x7fffffffu;
-        uu[k] = u[f];
+        uu[k] = u[f] * us;  // time-dependent velocity u(t) = us u_f; us = 1 is exact
         au[k] = (area ? area[f] : area0) * uu[k];
     }
     const double V = vol ? vol[c] : vol0;

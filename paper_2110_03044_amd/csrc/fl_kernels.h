@@ -19,14 +19,15 @@ hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, con
                           const double *lam, double a, double b, double dt, int mode, double *out,
                           double *acc, double *ubar, hipStream_t st);
 
+// us scales the face velocities (time-dependent velocity); 1 leaves them untouched.
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
-                            const double *u, double *phi, hipStream_t st);
+                            const double *u, double *phi, hipStream_t st, double us = 1.0);
 hipError_t launch_cell_update(const fl_mesh *m, int S, const double *phi, const double *ts,
                               const double *tn, double a, double b, double dt, int mode,
                               double *out, hipStream_t st);
 hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                         const double *u, double a, double b, double dt, int mode, double *out,
-                        hipStream_t st);
+                        hipStream_t st, double us = 1.0);
 hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);

@@ -45,11 +45,11 @@ template <int S>
 __global__ __launch_bounds__(kBlock) void face_flux_kernel(
     int64_t nf, const int4 *__restrict__ fc4, const double *__restrict__ u,
     const double *__restrict__ theta, const double *__restrict__ area, double area0, int lim,
-    double *__restrict__ phi, int remap) {
+    double *__restrict__ phi, int remap, double us) {
     const int64_t f = block_id(remap) * kBlock + threadIdx.x;
     if (f >= nf) return;
     const int4 e = fc4[f];
-    const double uf = u[f];
+    const double uf = u[f] * us;  // time-dependent velocity scale; us = 1 is exact
     const bool pos = uf > 0.0;
     const int64_t C = pos ? e.x : e.y;
     const int64_t D = pos ? e.y : e.x;
@@ -130,11 +130,11 @@ __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
     const int32_t *__restrict__ sfar, const double *__restrict__ u,
     const double *__restrict__ area, double area0, const double *__restrict__ vol, double vol0,
     const double *__restrict__ ts, const double *__restrict__ tn, double a, double b, double dt,
-    int mode, int lim, double *__restrict__ out, int remap) {
+    int mode, int lim, double *__restrict__ out, int remap, double us) {
     const int64_t c = block_id(remap) * kBlock + threadIdx.x;
     if (c >= nc) return;
     fused_cell<S, P>(c, nc, sface, snbr, sfar, u, area, area0, vol, vol0, ts, tn, a, b, dt, mode,
-                     lim, out);
+                     lim, out, us);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -208,13 +208,12 @@ int g_remap = 0;
 void set_xcd_remap(int on) { g_remap = on; }
 
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
-                            const double *u, double *phi, hipStream_t st) {
+                            const double *u, double *phi, hipStream_t st, double us) {
     // Blocks beyond the face count exit at once (padding to a multiple of 8 XCDs).
     Grid g = grid_for(m->h.nf, g_remap);
-    const int64_t nf_eff = g.remap ? m->h.nf : m->h.nf;
     FL_DISPATCH_S(S, (dev::face_flux_kernel<kS><<<g.blocks, dev::kBlock, 0, st>>>(
-                         nf_eff, reinterpret_cast<const int4 *>(m->d_fc4), u, theta, m->d_area,
-                         m->h.area0, lim, phi, g.remap)));
+                         m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), u, theta, m->d_area,
+                         m->h.area0, lim, phi, g.remap, us)));
     return hipGetLastError();
 }
 
@@ -230,13 +229,13 @@ hipError_t launch_cell_update(const fl_mesh *m, int S, const double *phi, const 
 
 hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                         const double *u, double a, double b, double dt, int mode, double *out,
-                        hipStream_t st) {
+                        hipStream_t st, double us) {
     Grid g = grid_for(m->h.nc, g_remap);
 #define FL_FUSED(P)                                                                           \
     FL_DISPATCH_S(S, (dev::fused_stage_kernel<kS, P><<<g.blocks, dev::kBlock, 0, st>>>(       \
                          m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, u, m->d_area, \
                          m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out,   \
-                         g.remap)))
+                         g.remap, us)))
     switch (m->h.pairs) {
         case 1: FL_FUSED(1); break;
         case 2: FL_FUSED(2); break;

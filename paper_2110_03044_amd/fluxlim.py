@@ -215,6 +215,26 @@ def rk_steps(mesh: Mesh, limiter, scheme, dt: float, theta: torch.Tensor, u: tor
     return theta
 
 
+def rk_steps_scaled(mesh: Mesh, limiter, scheme, dt: float, theta: torch.Tensor,
+                    u: torch.Tensor, scales, work: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    """Advances theta in place with the time-dependent velocity s(t) u; scales holds s at every
+    stage (stages x steps values, e.g. workloads.deformation_scales)."""
+    theta = mesh._cells(theta)
+    u = mesh._faces(u)
+    S = _S(theta)
+    sc = np.ascontiguousarray(scales, dtype=np.float64)
+    ns = n_stages(scheme)
+    if sc.ndim != 1 or sc.size % ns:
+        raise ValueError("scales must hold stages * n_steps values")
+    if work is None:
+        work = rk_workspace(mesh, scheme, S)
+    call("fl_rk_steps_scaled", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
+         sc.size // ns, _tptr(theta), _tptr(u), _np_ptr(sc), _tptr(work),
+         _stream(mesh.device, stream))
+    return theta
+
+
 # ---------------------------------------------------------------------------------------------
 # Adjoint
 # ---------------------------------------------------------------------------------------------

@@ -209,6 +209,48 @@ def velocity_curl(n: int, seed: int = SEED_VELOCITY, kmax: int = 4) -> np.ndarra
     return u
 
 
+def velocity_deformation(n: int) -> np.ndarray:
+    """Normal face velocity of the deformation flow of Section 4.1 on periodic_box(n, 3):
+    u = 2 sin^2(pi x) sin(2 pi y) sin(2 pi z), v = -sin(2 pi x) sin^2(pi y) sin(2 pi z),
+    w = -sin(2 pi x) sin(2 pi y) sin^2(pi z) (times cos(pi t / T), applied per stage).
+
+    Each face carries the exact integral of the field over the face divided by its area, so the
+    flux balance of every cell is the integral of div u = 0 (to rounding).  The normal component
+    vanishes on the planes x, y, z in {0, 1}, so the periodic wrap carries no flux."""
+    h = 1.0 / n
+    lo = np.arange(n) * h
+    hi = lo + h
+    sin2_at = np.sin(np.pi * hi) ** 2                  # sin^2 at the +face plane of cell i
+    isin = (np.cos(2 * np.pi * lo) - np.cos(2 * np.pi * hi)) / (2 * np.pi)  # int of sin(2 pi t)
+    out = []
+    # axis 0 (x-faces at x = (i+1)h): 2 sin^2(pi x_f) * isin(y) * isin(z)
+    fx = 2.0 * sin2_at[:, None, None] * isin[None, :, None] * isin[None, None, :]
+    fy = -isin[:, None, None] * sin2_at[None, :, None] * isin[None, None, :]
+    fz = -isin[:, None, None] * isin[None, :, None] * sin2_at[None, None, :]
+    for f in (fx, fy, fz):
+        out.append((f / (h * h)).ravel(order="F"))  # index i + n j + n^2 k
+    return np.concatenate(out)
+
+
+def deformation_scales(n_steps: int, dt: float, period: float, scheme: str) -> np.ndarray:
+    """cos(pi t / period) at every stage time (Euler: t_i; SSP-RK3: t_i, t_i + dt, t_i + dt/2),
+    t_i = i dt."""
+    offs = [0.0] if scheme == "euler" else [0.0, 1.0, 0.5]
+    t = np.array([i * dt + c * dt for i in range(n_steps) for c in offs])
+    return np.cos(np.pi * t / period)
+
+
+def workload_deformation(n: int, cfl: float = 0.4, period: float = 3.0,
+                         scheme: str = "ssprk3") -> Workload:
+    """Section 4.1 benchmark: sphere of radius 0.15 at (0.35, 0.35, 0.35) in the deformation
+    flow, reversed by cos(pi t / T) so it returns to its initial shape at t = T = 3."""
+    mesh = periodic_box(n, 3)
+    u = velocity_deformation(n)
+    dt0 = cfl_dt(mesh, u, cfl)
+    steps = int(math.ceil(period / dt0))
+    return Workload(mesh, field_sphere(n), u, period / steps, steps, scheme, f"deformation{n}")
+
+
 def velocity_1d(mesh: MeshArrays, speed: float = 1.0) -> np.ndarray:
     return velocity_uniform(mesh, (1.0, 0.0, 0.0), speed)
 

@@ -200,3 +200,32 @@ def test_box128_config_van_leer():
     FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, dev(to_mesh_faces(wl.u, fp)), wl.steps)
     want = O.OracleMesh.from_arrays(wl.mesh).run("vanleer", "ssprk3", wl.dt, wl.theta0, wl.u, wl.steps)
     assert nrel(host(th)[cp], want) <= RUN_TOL
+
+
+@pytest.mark.parametrize("path", ["fused", "face"])
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+def test_deformation_time_dependent_velocity(scheme, path):
+    """Section 4.1's deformation flow, reversed by cos(pi t / T): the stage velocity s(t) u is
+    formed in the kernel; compared with the oracle forming it on the host."""
+    wl = W.workload_deformation(18, period=0.5, scheme=scheme, cfl=0.3)
+    sc = W.deformation_scales(wl.steps, wl.dt, 0.5, scheme)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True, face_path=(path == "face"))
+    th = dev(to_mesh_cells(wl.theta0, cp))
+    FL.rk_steps_scaled(mesh, "superbee", scheme, wl.dt, th, dev(to_mesh_faces(wl.u, fp)), sc)
+    want = O.OracleMesh.from_arrays(wl.mesh).run_scaled("superbee", scheme, wl.dt, wl.theta0,
+                                                         wl.u, sc)
+    got = host(th)[cp]
+    assert nrel(got, want) <= RUN_TOL
+    V = wl.mesh.cell_volume
+    assert abs((V * got).sum() - (V * wl.theta0).sum()) <= 1e-14
+
+
+def test_scaled_steps_with_unit_scale_equal_plain_steps():
+    wl = W.workload_box(10, renumbered=True, steps=6)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    a = dev(to_mesh_cells(wl.theta0, cp))
+    b = a.clone()
+    u = dev(to_mesh_faces(wl.u, fp))
+    FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, a, u, wl.steps)
+    FL.rk_steps_scaled(mesh, "smart", "ssprk3", wl.dt, b, u, np.ones(3 * wl.steps))
+    assert torch.equal(a, b)

@@ -350,6 +350,68 @@ def test_linear_schemes_match_fourier_closed_form(lim, scheme):
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("lim", ["upwind", "central"])
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+def test_time_dependent_velocity_matches_fourier_closed_form(lim, scheme):
+    """u(t) = s(t) u0 with constant u0: every stage multiplies each Fourier mode by its own
+    symbol scaled by s; SSP-RK3 composes its three stages with those factors."""
+    n, steps = 8, 9
+    m = W.periodic_box(n, 3)
+    vel = (0.6, 0.35, -0.5)
+    u = W.velocity_uniform(m, vel)
+    th0 = W.field_smooth_random(n, 3, seed=4) + W.field_blob_step(n)
+    dt = 0.15 / n
+    sc = W.deformation_scales(steps, dt, 0.05, scheme)  # crosses zero: the flow reverses
+    assert sc.min() < 0 < sc.max()
+    got = O.OracleMesh.from_arrays(m).run_scaled(lim, scheme, dt, th0, u, sc)
+    h = 1.0 / n
+    kk = 2 * np.pi * np.fft.fftfreq(n, d=1.0 / n) / n
+    K = np.meshgrid(kk, kk, kk, indexing="ij")
+    T = np.fft.fftn(th0.reshape((n, n, n), order="F"))
+
+    def symbol(s):
+        out = np.zeros((n, n, n), dtype=complex)
+        for d in range(3):
+            v = s * vel[d]
+            e = np.exp(1j * K[d])
+            if lim == "upwind":
+                out += -(v / h) * (1 - 1 / e) if v > 0 else -(v / h) * (e - 1)
+            else:
+                out += -(v / h) * (e - 1 / e) / 2
+        return dt * out
+
+    ns = 1 if scheme == "euler" else 3
+    for i in range(steps):
+        z = [symbol(sc[i * ns + j]) for j in range(ns)]
+        if scheme == "euler":
+            T = T * (1 + z[0])
+        else:
+            t1 = T * (1 + z[0])
+            t2 = 0.75 * T + 0.25 * (t1 * (1 + z[1]))
+            T = T / 3 + 2.0 / 3.0 * (t2 * (1 + z[2]))
+    want = np.real(np.fft.ifftn(T)).ravel(order="F")
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_deformation_flow_conserves_and_returns():
+    """Section 4.1: the reversed deformation flow returns the sphere towards its initial shape
+    (the error at t = T is well below the error at t = T/2) and conserves mass exactly.  A short
+    period (T = 0.5) keeps the deformation resolvable on a 20^3 mesh; at T = 3 the sphere (three
+    cells in radius) is smeared into a sheet before the reversal."""
+    wl = W.workload_deformation(20, period=0.5)
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    sc = W.deformation_scales(wl.steps, wl.dt, 0.5, wl.scheme)
+    half = wl.steps // 2
+    mid = om.run_scaled("superbee", wl.scheme, wl.dt, wl.theta0, wl.u, sc[: 3 * half])
+    end = om.run_scaled("superbee", wl.scheme, wl.dt, mid, wl.u, sc[3 * half:])
+    V = wl.mesh.cell_volume
+    l1 = lambda x: float((V * np.abs(x - wl.theta0)).sum())
+    assert l1(end) < 0.5 * l1(mid)
+    assert abs((V * end).sum() - (V * wl.theta0).sum()) <= 1e-14
+    # the normal velocity on the planes x, y, z in {0, 1} vanishes: the wrap carries no flux
+    assert np.abs(wl.u[: wl.mesh.n_cells][np.arange(wl.mesh.n_cells) % 20 == 19]).max() < 1e-28
+
+
 @pytest.mark.parametrize("lim", LIMS)
 def test_3d_with_axis_flow_reduces_to_1d(lim):
     """Orthogonal meshes recover the one-dimensional formulation (Section 3.1, Conclusions)."""
