@@ -192,8 +192,57 @@ def batch_compare(args, torch, FL, W, dev):
             "autotuned_tile_cells": tile}
 
 
+def deformation(args, torch, FL, W, dev):
+    """The paper's deformation benchmark (Section 4.1): sphere r = 0.15 at (0.35, 0.35, 0.35),
+    deformation flow reversed by cos(pi t / T), T = 3, superbee, SSP-RK3 at CFL 0.4, on the
+    requested periodic boxes.  Reports the return-to-initial L1 error, the mass error and the
+    face-update rate of each run."""
+    out = []
+    for n in [int(x) for x in args.deformation.split(",") if x]:
+        wl = W.workload_deformation(n)
+        sc = W.deformation_scales(wl.steps, wl.dt, 3.0, wl.scheme)
+        mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+        th0 = mesh.cells_to_mesh(torch.from_numpy(wl.theta0).to(dev))
+        u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
+        th = th0.clone()
+        work = FL.rk_workspace(mesh, "ssprk3", 1)
+        stream = torch.cuda.current_stream(dev)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        # in chunks so progress is printed during long runs
+        chunk = 500
+        for s0 in range(0, wl.steps, chunk):
+            s1 = min(wl.steps, s0 + chunk)
+            FL.rk_steps_scaled(mesh, "superbee", "ssprk3", wl.dt, th, u, sc[3 * s0:3 * s1],
+                               work=work)
+            torch.cuda.synchronize()
+            log(f"  deformation {n}^3: {s1}/{wl.steps} steps")
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        V = float(wl.mesh.cell_volume[0])
+        l1 = float((th - th0).abs().sum()) * V
+        mass0 = float(th0.sum()) * V
+        mass_err = abs(float(th.sum()) * V - mass0) / mass0
+        rate = wl.mesh.n_faces * 3 * wl.steps / (ms * 1e-3) / 1e9
+        out.append({"n": n, "steps": wl.steps, "l1_error": l1, "sphere_volume": mass0,
+                    "relative_mass_error": mass_err, "min": float(th.min()),
+                    "max": float(th.max()), "seconds": round(ms / 1e3, 3),
+                    "gface_updates_per_s": round(rate, 2)})
+        log(f"deformation {n}^3: {wl.steps} steps, L1 {l1:.3e}, mass error {mass_err:.1e}, "
+            f"{ms / 1e3:.2f} s, {rate:.1f} Gface-updates/s")
+        mesh.close()
+        del th, th0, u, work
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--deformation", default="",
+                    help="comma-separated box sides for the deformation benchmark (e.g. 72,144)")
     ap.add_argument("--batch-count", type=int, default=512, help="problems in the batch (0 to skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--adjoint-steps", type=int, default=400,
@@ -342,6 +391,9 @@ def main():
     if args.batch_count > 0:
         out["batch"] = batch_compare(args, torch, FL, W, dev)
         torch.cuda.empty_cache()
+
+    if args.deformation:
+        out["deformation"] = deformation(args, torch, FL, W, dev)
 
     if args.cpu_baseline:
         from oracle import oracle as O
