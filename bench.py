@@ -53,7 +53,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n, xcd_remap):
+def measured_traffic(n, xcd_remap, slot_velocity):
     """HBM bytes per fused-stage launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed
     rocprofv3 counter summary, or None if it was taken on other kernel sources, sizes or launch
     mapping."""
@@ -64,18 +64,22 @@ def measured_traffic(n, xcd_remap):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
         if (kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n
-                or int(kv.get("xcd_remap", -1)) != int(xcd_remap)):
+                or int(kv.get("xcd_remap", -1)) != int(xcd_remap)
+                or int(kv.get("slot_velocity", 0)) != int(slot_velocity)):
             return None
         return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
 
 
-def fused_stage_bytes(C, F, K, S, stage):
-    """Compulsory bytes of one fused stage launch: slot tables (face, cell, far cell: 12 B per
-    slot), face velocities once, theta_s read once, theta_n read once (stages 2, 3) and the
-    output written once."""
-    b = C * K * 12 + F * 8 + C * S * 8 * 2
+def fused_stage_bytes(C, F, K, S, stage, slot_velocity=True):
+    """Compulsory bytes of one fused stage launch: slot tables (other cell, far cell and the
+    signed face rate: 16 B per slot; or, gathering u through the face index, face, cell and far
+    cell, 12 B per slot, plus each face velocity once), theta_s read once, theta_n read once
+    (stages 2, 3) and the output written once.  On hex meshes (F = 3C, K = 6) both give
+    96 B per cell for the tables and velocities."""
+    b = C * K * 16 if slot_velocity else C * K * 12 + F * 8
+    b += C * S * 8 * 2
     if stage > 0:
         b += C * S * 8
     return b
@@ -257,6 +261,8 @@ def main():
     ap.add_argument("--face-path", action="store_true")
     ap.add_argument("--xcd-remap", type=int, default=0,
                     help="1: each XCD takes a contiguous eighth of the cells (FL_OPT_XCD_REMAP)")
+    ap.add_argument("--slot-velocity", type=int, default=1,
+                    help="0: stages gather u through the face index (FL_OPT_SLOT_VELOCITY)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 to skip the oracle timing")
     ap.add_argument("--calib-copy-mib", type=int, default=1024,
                     help="size of the untimed calibration copy (0 to skip)")
@@ -277,6 +283,7 @@ def main():
     dev = torch.device("cuda", 0)
     lims = [l for l in args.limiters.split(",") if l]
     _lib.call("fl_set_option", 1, int(args.xcd_remap))  # FL_OPT_XCD_REMAP
+    _lib.call("fl_set_option", 2, int(args.slot_velocity))  # FL_OPT_SLOT_VELOCITY
     t0 = time.time()
     wl = W.workload_box(args.n, renumbered=True)
     m = wl.mesh
@@ -361,13 +368,16 @@ def main():
     if r["path"] == "fused":
         K = r["K"]
         launches = 3 * n_steps_total
-        bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s) for s in range(3))
+        sv = bool(args.slot_velocity) and args.steps >= 2
+        bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
         avg_launch_s = r["total_ms"] * 1e-3 / launches
         achieved = bytes_per_step / 3 / avg_launch_s / 1e9
-        out["roofline"] = {"kernel": "fused_stage_kernel", "bound": "hbm",
+        # the timed region also holds one slot-rate build per call (sv), charged to the stages
+        out["roofline"] = {"kernel": "fused_stage_v_kernel" if sv else "fused_stage_kernel",
+                           "bound": "hbm",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(args.n, args.xcd_remap),
+                           "traffic": measured_traffic(args.n, args.xcd_remap, sv),
                            "algorithmic_bytes_per_launch": int(bytes_per_step / 3),
                            "avg_launch_us": round(avg_launch_s * 1e6, 2)}
     # the two-kernel byte model (40 B/face + 60 B/cell per stage) as context

@@ -195,6 +195,13 @@ fl_status fl_rk_step_adjoint(const fl_mesh *mesh, int limiter, int scheme, doubl
 fl_status fl_rk_step_store(const fl_mesh *mesh, int limiter, int scheme, double dt, int n_scalars,
                            double *theta, const double *u_f, double *stages, void *work,
                            void *hip_stream);
+/* n_steps such steps in one call (the recompute of a checkpoint segment): stages: device
+ * [n_steps][n_stage][n_cells][S], step i's stage inputs at stages[i]; theta advanced in place.
+ * Results are bit-identical to n_steps calls of fl_rk_step_store.  work: fl_rk_workspace_bytes
+ * bytes (two or more steps use its slot-rate table, see FL_OPT_SLOT_VELOCITY). */
+fl_status fl_rk_steps_store(const fl_mesh *mesh, int limiter, int scheme, double dt,
+                            int n_scalars, int64_t n_steps, double *theta, const double *u_f,
+                            double *stages, void *work, void *hip_stream);
 
 /* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
  * with one launch per Runge-Kutta stage for all of them (one fused cell-centric kernel over a
@@ -215,12 +222,20 @@ fl_status fl_batch_tile(const fl_batch *batch, int *tile_cells);
 fl_status fl_batch_destroy(fl_batch *batch);
 
 /* Process-wide launch tuning, read by later launches of the single-problem kernels:
- *   FL_OPT_XCD_REMAP  0 (default): workgroups take cells in launch order; 1: the grid is padded
- *                     to a multiple of 8 and each of the 8 XCDs gets a contiguous eighth of the
- *                     cells.
+ *   FL_OPT_XCD_REMAP  0 (default): workgroups take cells in launch order (the hardware deals
+ *                     consecutive workgroups to the 8 XCDs in turn); 1: the grid is padded to a
+ *                     multiple of 8 and each XCD gets a contiguous eighth of the cells;
+ *                     M in 2 .. 65536: each XCD takes runs of M consecutive 256-cell tiles (grid
+ *                     padded to a multiple of 8 M), so the tiles sharing one L2 are neighbours.
+ *   FL_OPT_SLOT_VELOCITY  1 (default): fl_rk_steps / fl_rk_steps_scaled calls of two or more
+ *                     steps on a mesh of the fused path first write the signed face rates
+ *                     E a_f u_f in cell-slot order into their workspace and read them there;
+ *                     0: every stage gathers u_f through the face index.  Results are
+ *                     bit-identical either way (for time-dependent velocity on meshes with face
+ *                     areas, up to the rounding of one product).
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
-enum { FL_OPT_XCD_REMAP = 1 };
+enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2 };
 fl_status fl_set_option(int option, int value);
 
 const char *fl_status_str(fl_status status);

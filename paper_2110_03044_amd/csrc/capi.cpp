@@ -92,20 +92,32 @@ constexpr double kRk3B[3] = {1.0, 0.25, 2.0 / 3.0};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.
+// Multi-step calls on fused-path meshes build the slot-major face rates once (FL_OPT_SLOT_VELOCITY).
+int g_slot_velocity = 1;
+
+// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.  vs: slot-major face rates of u
+// (fused path), or NULL to gather u through the face index.
 hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b, int mode,
                  const double *ts, const double *tn, const double *u, double *out, double *phi,
-                 hipStream_t st, double us = 1.0) {
-    if (m->path == FL_PATH_FUSED)
+                 hipStream_t st, double us = 1.0, const double *vs = nullptr) {
+    if (m->path == FL_PATH_FUSED) {
+        if (vs) return launch_fused_v(m, lim, S, ts, tn, vs, a, b, dt, mode, out, st, us);
         return launch_fused(m, lim, S, ts, tn, u, a, b, dt, mode, out, st, us);
+    }
     hipError_t e = launch_face_flux(m, lim, S, ts, u, phi, st, us);
     if (e != hipSuccess) return e;
     return launch_cell_update(m, S, phi, ts, tn, a, b, dt, mode, out, st);
 }
 
 struct Work {
-    double *phi = nullptr, *t1 = nullptr, *t2 = nullptr;
+    double *phi = nullptr, *t1 = nullptr, *t2 = nullptr, *vs = nullptr;
 };
+
+// Workspace of fl_rk_steps: [phi (face path)] t1 t2 [vs (fused path)].
+size_t slot_velocity_bytes(const fl_mesh *m) {
+    return m->path == FL_PATH_FUSED ? align256((size_t)2 * m->h.pairs * m->h.nc * sizeof(double))
+                                    : 0;
+}
 
 Work carve(const fl_mesh *m, int S, void *work) {
     Work w;
@@ -118,7 +130,20 @@ Work carve(const fl_mesh *m, int S, void *work) {
     w.t1 = (double *)p;
     p += cell;
     w.t2 = (double *)p;
+    p += cell;
+    if (m->path == FL_PATH_FUSED) w.vs = (double *)p;
     return w;
+}
+
+// The slot-major rates for a multi-step call, or NULL (single steps gather u directly: the
+// table costs about one stage's table traffic to build).
+hipError_t prepare_rates(const fl_mesh *m, const double *u, int64_t n_steps, const Work &w,
+                         hipStream_t st, const double **vs) {
+    *vs = nullptr;
+    if (m->path != FL_PATH_FUSED || !g_slot_velocity || n_steps < 2) return hipSuccess;
+    hipError_t e = launch_slot_velocity(m, u, w.vs, st);
+    if (e == hipSuccess) *vs = w.vs;
+    return e;
 }
 
 }  // namespace
@@ -144,8 +169,12 @@ const char *fl_status_str(fl_status s) {
 const char *fl_last_error(void) { return g_error.c_str(); }
 
 fl_status fl_set_option(int option, int value) {
-    if (option == FL_OPT_XCD_REMAP && (value == 0 || value == 1)) {
+    if (option == FL_OPT_XCD_REMAP && value >= 0 && value <= (1 << 16)) {
         set_xcd_remap(value);
+        return FL_OK;
+    }
+    if (option == FL_OPT_SLOT_VELOCITY && (value == 0 || value == 1)) {
+        g_slot_velocity = value;
         return FL_OK;
     }
     return fail(FL_E_INVALID, "unknown option or value");
@@ -354,7 +383,7 @@ size_t fl_rk_workspace_bytes(const fl_mesh *m, int scheme, int S) {
     if (!m || S < 1 || S > FL_MAX_SCALARS || (scheme != FL_EULER && scheme != FL_SSPRK3)) return 0;
     size_t b = 2 * align256((size_t)m->h.nc * S * sizeof(double));
     if (m->path == FL_PATH_FACE_CELL) b += align256((size_t)m->h.nf * S * sizeof(double));
-    return b;
+    return b + slot_velocity_bytes(m);
 }
 
 fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, int64_t n_steps,
@@ -370,7 +399,8 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     Work w = carve(m, S, work);
-    hipError_t e = hipSuccess;
+    const double *vs = nullptr;
+    hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
     if (scheme == FL_EULER) {
         if (m->path == FL_PATH_FACE_CELL) {
             for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i)
@@ -379,7 +409,7 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
             // the fused kernel gathers its input, so it cannot write in place: ping-pong
             double *src = theta, *dst = w.t1;
             for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
-                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, src, src, u, dst, w.phi, st);
+                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, src, src, u, dst, w.phi, st, 1.0, vs);
                 std::swap(src, dst);
             }
             if (e == hipSuccess && src != theta)
@@ -388,11 +418,11 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
         }
     } else {
         for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
-            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, w.t1, w.phi, st);
+            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, w.t1, w.phi, st, 1.0, vs);
             if (e == hipSuccess)
-                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, w.t1, theta, u, w.t2, w.phi, st);
+                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, w.t1, theta, u, w.t2, w.phi, st, 1.0, vs);
             if (e == hipSuccess)
-                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, w.t2, theta, u, theta, w.phi, st);
+                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, w.t2, theta, u, theta, w.phi, st, 1.0, vs);
         }
     }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step launch");
@@ -412,7 +442,8 @@ fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     Work w = carve(m, S, work);
-    hipError_t e = hipSuccess;
+    const double *vs = nullptr;
+    hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
     const double *sc = u_scale;
     if (scheme == FL_EULER) {
         double *src = theta, *dst = w.t1;
@@ -420,7 +451,7 @@ fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, i
             if (m->path == FL_PATH_FACE_CELL) {
                 e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, theta, theta, u, theta, w.phi, st, sc[i]);
             } else {
-                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, src, src, u, dst, w.phi, st, sc[i]);
+                e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, src, src, u, dst, w.phi, st, sc[i], vs);
                 std::swap(src, dst);
             }
         }
@@ -429,11 +460,11 @@ fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, i
     } else {
         for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
             const double *si = sc + 3 * i;
-            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, w.t1, w.phi, st, si[0]);
+            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, theta, theta, u, w.t1, w.phi, st, si[0], vs);
             if (e == hipSuccess)
-                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, w.t1, theta, u, w.t2, w.phi, st, si[1]);
+                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, w.t1, theta, u, w.t2, w.phi, st, si[1], vs);
             if (e == hipSuccess)
-                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, w.t2, theta, u, theta, w.phi, st, si[2]);
+                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, w.t2, theta, u, theta, w.phi, st, si[2], vs);
         }
     }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_steps_scaled launch");
@@ -513,6 +544,44 @@ fl_status fl_rk_step_store(const fl_mesh *m, int lim, int scheme, double dt, int
         }
     }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step_store launch");
+}
+
+fl_status fl_rk_steps_store(const fl_mesh *m, int lim, int scheme, double dt, int S,
+                            int64_t n_steps, double *theta, const double *u, double *stages,
+                            void *work, void *stream) {
+    fl_status s = check_compute(m, lim, S);
+    if (s != FL_OK) return s;
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (!theta || !u || !stages || !work) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(theta) || misaligned(u) || misaligned(stages) || ((uintptr_t)work & 255u))
+        return fail(FL_E_INVALID, "theta/u/stages must be 8-byte and work 256-byte aligned");
+    if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    if (n_steps == 0) return FL_OK;
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cell = (size_t)m->h.nc * S;
+    const size_t per_step = cell * (scheme == FL_EULER ? 1 : 3);
+    Work w = carve(m, S, work);
+    const double *vs = nullptr;
+    hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stages, theta, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
+    // each step's last stage writes the next step's stored input directly (the last: theta)
+    for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i) {
+        double *tn = stages + i * per_step;
+        double *next = (i + 1 < n_steps) ? tn + per_step : theta;
+        if (scheme == FL_EULER) {
+            e = stage(m, lim, S, dt, 0.0, 1.0, MODE_EULER, tn, tn, u, next, w.phi, st, 1.0, vs);
+        } else {
+            double *t1 = tn + cell, *t2 = tn + 2 * cell;
+            e = stage(m, lim, S, dt, kRk3A[0], kRk3B[0], MODE_EULER, tn, tn, u, t1, w.phi, st, 1.0, vs);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[1], kRk3B[1], MODE_RK, t1, tn, u, t2, w.phi, st, 1.0, vs);
+            if (e == hipSuccess)
+                e = stage(m, lim, S, dt, kRk3A[2], kRk3B[2], MODE_RK, t2, tn, u, next, w.phi, st, 1.0, vs);
+        }
+    }
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_steps_store launch");
 }
 
 fl_status fl_rk_step_adjoint(const fl_mesh *m, int lim, int scheme, double dt, int S,

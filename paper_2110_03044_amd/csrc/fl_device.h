@@ -56,9 +56,8 @@ __device__ __forceinline__ double face_value(int lim, double tC, double tD, doub
 
 // Scalars S0 .. S0+CS-1 of cell c (CS <= 2 keeps the gathered values in registers for any S).
 template <int S, int P, int S0>
-__device__ __forceinline__ void fused_chunks(int64_t c, const uint32_t *fw, const int64_t *nb,
-                                             const int64_t *gf, const double *uu,
-                                             const double *au, double V,
+__device__ __forceinline__ void fused_chunks(int64_t c, const double *w, const int64_t *nb,
+                                             const int64_t *gf, double V,
                                              const double *__restrict__ ts,
                                              const double *__restrict__ tn, double a, double b,
                                              double dt, int mode, int lim,
@@ -83,17 +82,16 @@ __device__ __forceinline__ void fused_chunks(int64_t c, const uint32_t *fw, cons
         for (int i = 0; i < CS; ++i) acc[i] = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const bool c_is_own = (fw[k] >> 31) != 0;
-            // Q(u_f): C = own where u_f > 0, C = nbr otherwise
-            const bool c_upwind = ((uu[k] > 0.0) == c_is_own);
+            // Q(u_f): c is the upwind cell C of its face k where the flow leaves c (w_k > 0);
+            // where w_k == 0 the flux vanishes whichever cell is taken
+            const bool c_upwind = w[k] > 0.0;
 #pragma unroll
             for (int i = 0; i < CS; ++i) {
                 // pick (theta_C, theta_D, theta_U) first: one evaluation where lanes diverge
                 const double tC = c_upwind ? tc[i] : tnb[k][i];
                 const double tD = c_upwind ? tnb[k][i] : tc[i];
                 const double tU = c_upwind ? tnb[k ^ 1][i] : tg[k][i];
-                const double ph = au[k] * face_value(lim, tC, tD, tU);
-                acc[i] = c_is_own ? acc[i] - ph : acc[i] + ph;
+                acc[i] -= w[k] * face_value(lim, tC, tD, tU);
             }
         }
 #pragma unroll
@@ -103,15 +101,17 @@ __device__ __forceinline__ void fused_chunks(int64_t c, const uint32_t *fw, cons
             else if (mode == MODE_EULER) out[j] = tc[i] + dt * (acc[i] / V);
             else out[j] = a * tn[j] + b * (tc[i] + dt * (acc[i] / V));
         }
-        fused_chunks<S, P, S0 + CS>(c, fw, nb, gf, uu, au, V, ts, tn, a, b, dt, mode, lim, out);
+        fused_chunks<S, P, S0 + CS>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
     }
 }
 
 // One stage for cell c with P opposite-face pairs (slots 2p and 2p+1 are opposite faces).
 // Slot k gives the face f_k (bit 31: c is its own), the other cell n_k and the far-upwind cell
-// g_k on n_k's side; the far-upwind cell on c's side of f_k is n_{k^1}.  The table entries and
-// velocities are read once for all scalars, then every gather of a chunk is issued before its
-// arithmetic (the kernel is bound by gather latency and L2 misses, not by arithmetic).
+// g_k on n_k's side; the far-upwind cell on c's side of f_k is n_{k^1}.  The face terms enter as
+// w_k = a_f u_f E, the signed rate out of c (E = +1 where c is the face's own cell, -1 where it
+// is the nbr), so rhs_c = -sum_k w_k theta_f,k / V_c.  The table entries and velocities are read
+// once for all scalars, then every gather of a chunk is issued before its arithmetic (the kernel
+// is bound by gather latency and L2 misses, not by arithmetic).
 // out = rhs (MODE_RHS), theta_s + dt rhs (MODE_EULER) or a theta_n + b (theta_s + dt rhs);
 // the face velocities are us * u.
 template <int S, int P>
@@ -134,15 +134,44 @@ __device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t
         nb[k] = snbr[(int64_t)k * nc + c];
         gf[k] = sfar[(int64_t)k * nc + c];
     }
-    double uu[K], au[K];
+    double w[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t f = fw[k] & 0x7fffffffu;
-        uu[k] = u[f] * us;  // time-dependent velocity u(t) = us u_f; us = 1 is exact
-        au[k] = (area ? area[f] : area0) * uu[k];
+        // time-dependent velocity u(t) = us u_f; us = 1 is exact
+        const double au = (area ? area[f] : area0) * (u[f] * us);
+        w[k] = (fw[k] >> 31) ? au : -au;
     }
     const double V = vol ? vol[c] : vol0;
-    fused_chunks<S, P, 0>(c, fw, nb, gf, uu, au, V, ts, tn, a, b, dt, mode, lim, out);
+    fused_chunks<S, P, 0>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
+}
+
+// The same stage with the face terms read from a slot-major table vs[k][c] built once per call
+// (slot_velocity_kernel): vs = E a_f u_f where the mesh has face areas, E u_f where all areas
+// are area0.  Every operand then streams in cell order except the theta gathers; for us = 1 the
+// rates w_k, and so the results, are bit-identical to fused_cell's.
+template <int S, int P>
+__device__ __forceinline__ void fused_cell_v(int64_t c, int64_t nc,
+                                             const int32_t *__restrict__ snbr,
+                                             const int32_t *__restrict__ sfar,
+                                             const double *__restrict__ vs, bool has_area,
+                                             double area0, const double *__restrict__ vol,
+                                             double vol0, const double *__restrict__ ts,
+                                             const double *__restrict__ tn, double a, double b,
+                                             double dt, int mode, int lim,
+                                             double *__restrict__ out, double us) {
+    constexpr int K = 2 * P;
+    int64_t nb[K], gf[K];
+    double w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        nb[k] = snbr[(int64_t)k * nc + c];
+        gf[k] = sfar[(int64_t)k * nc + c];
+        const double v = vs[(int64_t)k * nc + c] * us;
+        w[k] = has_area ? v : area0 * v;
+    }
+    const double V = vol ? vol[c] : vol0;
+    fused_chunks<S, P, 0>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
 }
 
 }  // namespace dev

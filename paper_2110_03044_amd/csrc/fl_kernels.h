@@ -13,7 +13,8 @@ enum { MODE_RHS = 0, MODE_EULER = 1, MODE_RK = 2 };
 // Adjoint-stage modes (see fl_adjoint.hip).
 enum { ADJ_APPLY = 0, ADJ_EULER = 1, ADJ_LAST = 2, ADJ_MID = 3, ADJ_FIRST = 4 };
 
-void set_xcd_remap(int on);
+// 0: launch order; 1: each XCD a contiguous eighth of the tiles; M >= 2: runs of M tiles per XCD.
+void set_xcd_remap(int value);
 
 hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, const double *th,
                           const double *lam, double a, double b, double dt, int mode, double *out,
@@ -28,6 +29,11 @@ hipError_t launch_cell_update(const fl_mesh *m, int S, const double *phi, const 
 hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                         const double *u, double a, double b, double dt, int mode, double *out,
                         hipStream_t st, double us = 1.0);
+// Slot-major signed face rates vs[2P][C] for launch_fused_v (fused-path meshes only).
+hipError_t launch_slot_velocity(const fl_mesh *m, const double *u, double *vs, hipStream_t st);
+hipError_t launch_fused_v(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                          const double *vs, double a, double b, double dt, int mode, double *out,
+                          hipStream_t st, double us = 1.0);
 hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);

@@ -26,10 +26,14 @@ namespace dev {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int64_t block_id(int remap) {
-    if (!remap) return blockIdx.x;
-    const int per = gridDim.x >> 3;
-    return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+// Workgroup -> cell tile.  Dispatch sends workgroup d to XCD d mod 8; with chunk M > 0 (the grid
+// padded to a multiple of 8 M) XCD x takes runs of M consecutive tiles, so the tiles one XCD
+// (one L2) works on at a time are neighbours on the cell curve.  M = grid / 8 gives each XCD a
+// contiguous eighth of the mesh.
+__device__ __forceinline__ int64_t block_id(int chunk) {
+    if (!chunk) return blockIdx.x;
+    const int64_t d = blockIdx.x, xcd = d & 7, local = d >> 3;
+    return (local / chunk) * (8 * (int64_t)chunk) + xcd * chunk + local % chunk;
 }
 
 template <int S>
@@ -137,6 +141,36 @@ __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
                      lim, out, us);
 }
 
+// vs[k][c] = E a_f u_f (E = +1 where c is the own cell of its slot-k face, -1 where it is the
+// nbr; a_f omitted where the mesh has no face areas).  Built once per multi-step call; its
+// gathers of u are the only ones the fused stages then avoid.
+template <int P>
+__global__ __launch_bounds__(kBlock) void slot_velocity_kernel(
+    int64_t nc, const uint32_t *__restrict__ sface, const double *__restrict__ u,
+    const double *__restrict__ area, double *__restrict__ vs) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nc) return;
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        const uint32_t fw = sface[(int64_t)k * nc + c];
+        const int64_t f = fw & 0x7fffffffu;
+        const double x = area ? area[f] * u[f] : u[f];
+        vs[(int64_t)k * nc + c] = (fw >> 31) ? x : -x;
+    }
+}
+
+template <int S, int P>
+__global__ __launch_bounds__(kBlock) void fused_stage_v_kernel(
+    int64_t nc, const int32_t *__restrict__ snbr, const int32_t *__restrict__ sfar,
+    const double *__restrict__ vs, int has_area, double area0, const double *__restrict__ vol,
+    double vol0, const double *__restrict__ ts, const double *__restrict__ tn, double a, double b,
+    double dt, int mode, int lim, double *__restrict__ out, int remap, double us) {
+    const int64_t c = block_id(remap) * kBlock + threadIdx.x;
+    if (c >= nc) return;
+    fused_cell_v<S, P>(c, nc, snbr, sfar, vs, has_area != 0, area0, vol, vol0, ts, tn, a, b, dt,
+                       mode, lim, out, us);
+}
+
 // ------------------------------------------------------------------------------------------
 // Utilities
 // ------------------------------------------------------------------------------------------
@@ -175,14 +209,17 @@ namespace {
 
 struct Grid {
     unsigned blocks;
-    int remap;
+    int remap;  // chunk M of block_id, 0 = launch order
 };
 
-Grid grid_for(int64_t n, bool remap) {
+// remap: 0 launch order; 1 contiguous eighths; M >= 2 runs of M tiles per XCD.
+Grid grid_for(int64_t n, int remap) {
     int64_t nb = (n + dev::kBlock - 1) / dev::kBlock;
     if (nb < 1) nb = 1;
-    if (remap && nb >= 64) return {(unsigned)(((nb + 7) / 8) * 8), 1};
-    return {(unsigned)nb, 0};
+    if (remap <= 0 || nb < 64) return {(unsigned)nb, 0};
+    const int64_t chunk = remap == 1 ? (nb + 7) / 8 : remap;
+    const int64_t span = 8 * chunk;
+    return {(unsigned)(((nb + span - 1) / span) * span), (int)chunk};
 }
 
 }  // namespace
@@ -200,12 +237,10 @@ Grid grid_for(int64_t n, bool remap) {
         default: return hipErrorInvalidValue;    \
     }
 
-// Block ids map to cells in launch order by default: with a locality-ordered mesh the
-// round-robin spread of consecutive blocks over the 8 XCDs measured ~7% faster at 256^3 than
-// giving each XCD a contiguous eighth of the mesh (the MALL, shared by all XCDs, serves the
-// neighbourhood reuse either way).  The remapped order stays available for tuning.
+// Block ids map to cells in launch order unless FL_OPT_XCD_REMAP selects an XCD-aware order
+// (block_id above).
 int g_remap = 0;
-void set_xcd_remap(int on) { g_remap = on; }
+void set_xcd_remap(int value) { g_remap = value; }
 
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
                             const double *u, double *phi, hipStream_t st, double us) {
@@ -243,6 +278,36 @@ hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, cons
         default: return hipErrorInvalidValue;
     }
 #undef FL_FUSED
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_velocity(const fl_mesh *m, const double *u, double *vs, hipStream_t st) {
+    const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);
+    switch (m->h.pairs) {
+        case 1: dev::slot_velocity_kernel<1><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, vs); break;
+        case 2: dev::slot_velocity_kernel<2><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, vs); break;
+        case 3: dev::slot_velocity_kernel<3><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, vs); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_v(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                          const double *vs, double a, double b, double dt, int mode, double *out,
+                          hipStream_t st, double us) {
+    Grid g = grid_for(m->h.nc, g_remap);
+    const int has_area = m->d_area != nullptr;
+#define FL_FUSED_V(P)                                                                          \
+    FL_DISPATCH_S(S, (dev::fused_stage_v_kernel<kS, P><<<g.blocks, dev::kBlock, 0, st>>>(      \
+                         m->h.nc, m->d_slot_nbr, m->d_slot_far, vs, has_area, m->h.area0,     \
+                         m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out, g.remap, us)))
+    switch (m->h.pairs) {
+        case 1: FL_FUSED_V(1); break;
+        case 2: FL_FUSED_V(2); break;
+        case 3: FL_FUSED_V(3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FL_FUSED_V
     return hipGetLastError();
 }
 

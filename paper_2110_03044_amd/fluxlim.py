@@ -35,6 +35,15 @@ def scheme_id(s) -> int:
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
 
+OPTIONS = {"xcd_remap": 1, "slot_velocity": 2}
+
+
+def set_option(name: str, value: int) -> None:
+    """Process-wide launch option (fl_set_option): "xcd_remap" (default 0) or "slot_velocity"
+    (default 1: multi-step calls read signed face rates from a cell-slot table)."""
+    call("fl_set_option", OPTIONS[name], int(value))
+
+
 def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -308,6 +317,24 @@ def checkpoint_interval(n_steps: int) -> int:
     return max(1, math.isqrt(max(n_steps - 1, 0)) + 1) if n_steps > 0 else 1
 
 
+def rk_steps_store(mesh: Mesh, limiter, scheme, dt, theta, u, stages, n_steps: int,
+                   work=None, stream=None):
+    """n_steps steps in place on theta, storing step i's stage inputs in stages[i]
+    (stages: [>= n_steps, stages per step, C(, S)])."""
+    theta = mesh._cells(theta)
+    S = _S(theta)
+    if work is None:
+        work = rk_workspace(mesh, scheme, S)
+    per = n_stages(scheme) * theta.numel()
+    if not stages.is_contiguous() or stages.dtype != torch.float64 or stages.numel() < n_steps * per \
+            or stages.device != theta.device:
+        raise ValueError("stages must be a contiguous float64 [n_steps, stages, n_cells(, S)] buffer")
+    call("fl_rk_steps_store", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
+         int(n_steps), _tptr(theta), _tptr(mesh._faces(u)), _tptr(stages), _tptr(work),
+         _stream(mesh.device, stream))
+    return theta
+
+
 class _Advect(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta0, u, mesh, limiter, scheme, dt, n_steps, every):
@@ -323,8 +350,7 @@ class _Advect(torch.autograd.Function):
             if start + count < n_steps:
                 rk_steps(mesh, limiter, scheme, dt, theta, u_d, count, work=work)
             else:  # the last segment keeps its stage inputs: the backward starts there
-                for j in range(count):
-                    rk_step_store(mesh, limiter, scheme, dt, theta, u_d, stages[j], work=work)
+                rk_steps_store(mesh, limiter, scheme, dt, theta, u_d, stages, count, work=work)
         ctx.mesh, ctx.limiter, ctx.scheme, ctx.dt = mesh, limiter, scheme, dt
         ctx.n_steps, ctx.every, ctx.ckpts, ctx.stages = n_steps, every, ckpts, stages
         ctx.save_for_backward(u_d)
@@ -346,8 +372,7 @@ class _Advect(torch.autograd.Function):
             count = min(ctx.every, ctx.n_steps - start)
             if seg != last:  # recompute the segment, storing every stage input
                 th = ctx.ckpts[seg].clone()
-                for j in range(count):
-                    rk_step_store(mesh, lim, scheme, dt, th, u_d, stages[j], work=work)
+                rk_steps_store(mesh, lim, scheme, dt, th, u_d, stages, count, work=work)
             for j in reversed(range(count)):
                 rk_step_adjoint(mesh, lim, scheme, dt, stages[j], u_d, lam, u_bar, work=awork)
         ctx.ckpts = None

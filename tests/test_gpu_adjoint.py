@@ -222,3 +222,28 @@ def test_adjoint_config_128_consistency():
     fd = float(((run(t0.detach()) - tgt) * dx).sum())
     ad = float((t0.grad * v).sum())
     assert ad == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("S", [1, 3])
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+def test_multi_step_store_equals_single_step_stores(scheme, S):
+    """fl_rk_steps_store (one call per checkpoint segment, slot-rate table) stores the same stage
+    inputs and leaves the same theta, bit for bit, as one fl_rk_step_store call per step."""
+    wl, th, rng = noisy_box(11, seed=12)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    cp, fp = maps(mesh)
+    th = np.stack([th + 0.1 * s for s in range(S)], axis=1) if S > 1 else th
+    u = mesh.faces_to_mesh(dev(wl.u))
+    steps = 7
+    a = mesh.cells_to_mesh(dev(th))
+    b = a.clone()
+    sa = FL.stage_buffer(mesh, scheme, S, steps)
+    sb = torch.full_like(sa, float("nan"))
+    for j in range(steps):
+        FL.rk_step_store(mesh, "superbee", scheme, wl.dt, a, u, sa[j])
+    FL.rk_steps_store(mesh, "superbee", scheme, wl.dt, b, u, sb, steps)
+    assert torch.equal(a, b)
+    assert torch.equal(sa, sb)
+    c = mesh.cells_to_mesh(dev(th))
+    FL.rk_steps(mesh, "superbee", scheme, wl.dt, c, u, steps)
+    assert torch.equal(c, b)

@@ -229,3 +229,88 @@ def test_scaled_steps_with_unit_scale_equal_plain_steps():
     FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, a, u, wl.steps)
     FL.rk_steps_scaled(mesh, "smart", "ssprk3", wl.dt, b, u, np.ones(3 * wl.steps))
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("S", [1, 3, 8])
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+@pytest.mark.parametrize("areas", [False, True])
+def test_slot_rate_table_gives_the_same_bits(areas, scheme, S):
+    """Multi-step calls read the signed face rates E a_f u_f from a cell-slot table built once
+    per call; single steps and FL_OPT_SLOT_VELOCITY = 0 gather u through the face index.  Both
+    must give the same bits, with uniform or per-face areas and volumes, and match the oracle."""
+    import dataclasses
+
+    m = W.renumber(W.periodic_box(13, 3), seed=8)  # 2197 cells: ragged last block
+    if areas:
+        rng = np.random.default_rng(9)
+        m = dataclasses.replace(m, face_area=m.face_area * rng.uniform(0.5, 1.5, m.n_faces),
+                                cell_volume=m.cell_volume * rng.uniform(0.5, 1.5, m.n_cells))
+    u = m.face_velocity_from_natural(W.velocity_curl(13, seed=3))
+    th = W.multi_scalar([m.cell_field_from_natural(W.field_blob_step(13)),
+                         m.cell_field_from_natural(W.field_smooth_random(13, 3, 2)),
+                         m.cell_field_from_natural(W.field_sphere(13))] * 3)[:, :S]
+    th = np.ascontiguousarray(th if S > 1 else th[:, 0])
+    dt = W.cfl_dt(m, u, 0.3)
+    mesh, cp, fp = mesh_pair(m, reorder=True)
+    ud = dev(to_mesh_faces(u, fp))
+    t0 = dev(to_mesh_cells(th, cp))
+    steps = 9
+    try:
+        runs = {}
+        for opt in (1, 0):
+            FL.set_option("slot_velocity", opt)
+            t = t0.clone()
+            FL.rk_steps(mesh, "vanleer", scheme, dt, t, ud, steps)
+            runs[opt] = t
+        one = t0.clone()
+        for _ in range(steps):
+            FL.rk_steps(mesh, "vanleer", scheme, dt, one, ud, 1)
+    finally:
+        FL.set_option("slot_velocity", 1)
+    assert torch.equal(runs[1], runs[0])
+    assert torch.equal(runs[1], one)
+    want = O.OracleMesh.from_arrays(m).run("vanleer", scheme, dt, th, u, steps)
+    assert nrel(host(runs[1])[cp], want) <= RUN_TOL
+
+
+@pytest.mark.parametrize("slot_velocity", [1, 0])
+def test_scaled_steps_with_face_areas(slot_velocity):
+    import dataclasses
+
+    wl = W.workload_deformation(12, period=0.5, cfl=0.3)
+    rng = np.random.default_rng(10)
+    m = dataclasses.replace(wl.mesh,
+                            face_area=wl.mesh.face_area * rng.uniform(0.5, 1.5, wl.mesh.n_faces),
+                            cell_volume=wl.mesh.cell_volume * rng.uniform(0.5, 1.5, wl.mesh.n_cells))
+    dt = W.cfl_dt(m, wl.u, 0.3)
+    steps = 30
+    sc = W.deformation_scales(steps, dt, 0.5, "ssprk3")
+    mesh, cp, fp = mesh_pair(m, reorder=True)
+    th = dev(to_mesh_cells(wl.theta0, cp))
+    try:
+        FL.set_option("slot_velocity", slot_velocity)
+        FL.rk_steps_scaled(mesh, "superbee", "ssprk3", dt, th, dev(to_mesh_faces(wl.u, fp)), sc)
+    finally:
+        FL.set_option("slot_velocity", 1)
+    want = O.OracleMesh.from_arrays(m).run_scaled("superbee", "ssprk3", dt, wl.theta0, wl.u, sc)
+    assert nrel(host(th)[cp], want) <= RUN_TOL
+
+
+@pytest.mark.parametrize("remap", [1, 2, 5, 64])
+def test_xcd_launch_orders_give_the_same_bits(remap):
+    """FL_OPT_XCD_REMAP only changes which workgroup takes which 256-cell tile (a bijection over
+    the padded grid; padding tiles exit): 26^3 = 17576 cells is 69 tiles, enough to engage it."""
+    wl = W.workload_box(26, renumbered=True, steps=3)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    t0 = dev(to_mesh_cells(wl.theta0, cp))
+    u = dev(to_mesh_faces(wl.u, fp))
+    runs = []
+    try:
+        for r in (0, remap):
+            FL.set_option("xcd_remap", r)
+            t = t0.clone()
+            FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, t, u, wl.steps)
+            runs.append(t)
+    finally:
+        FL.set_option("xcd_remap", 0)
+    assert torch.equal(runs[0], runs[1])

@@ -145,7 +145,12 @@ def test_create_rejects_bad_arguments_and_host_only_compute():
     st = L.fl_rk_steps(mesh.handle, 9, 3, 0.1, 1, 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
                        ctypes.c_void_p(256), None)
     assert st in (-1, -6)
-    assert L.fl_rk_workspace_bytes(mesh.handle, 3, 1) == 2 * ((m.n_cells * 8 + 255) // 256 * 256)
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    # two stage buffers + the slot-major face rates (6 slots per hex cell) of the fused path
+    assert L.fl_rk_workspace_bytes(mesh.handle, 3, 1) == (2 * a256(m.n_cells * 8)
+                                                          + a256(6 * m.n_cells * 8))
     assert L.fl_rk_workspace_bytes(mesh.handle, 2, 1) == 0
     face = FL.Mesh.from_arrays(m, device=-1, face_path=True)
     assert face.path == "face"
