@@ -11,9 +11,10 @@ steps for every limiter.  A face-update is one face's limited flux in one stage 
 value = faces * stages * steps * limiters / time.
 
 Prints one JSON line (see the keys below).  `roofline` is for the dominant kernel
-(fused_stage_kernel): its algorithmic bytes per launch (every table entry, face velocity and
-cell value it must touch, read or written once) divided by its average launch duration measured
-with HIP events on the launch stream.  `cpu_baseline` times the CPU oracle on the host cores on
+(fused_stage_rec_kernel, the stage of multi-step calls): its algorithmic bytes per launch (every
+slot record and cell value it must touch, read or written once) divided by its average launch
+duration measured with HIP events on the launch stream (the timed region also holds the one
+slot-record build of each call).  `cpu_baseline` times the CPU oracle on the host cores on
 a bounded sample of the same workload.
 """
 
@@ -73,7 +74,7 @@ def measured_traffic(n, xcd_remap, slot_velocity):
 
 
 def fused_stage_bytes(C, F, K, S, stage, slot_velocity=True):
-    """Compulsory bytes of one fused stage launch: slot tables (other cell, far cell and the
+    """Compulsory bytes of one fused stage launch: slot records (other cell, far cell and the
     signed face rate: 16 B per slot; or, gathering u through the face index, face, cell and far
     cell, 12 B per slot, plus each face velocity once), theta_s read once, theta_n read once
     (stages 2, 3) and the output written once.  On hex meshes (F = 3C, K = 6) both give
@@ -101,12 +102,12 @@ def adjoint_ratio(args, torch, FL, W, dev):
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
 
-    def once(n_steps, timed):
+    def once(n_steps, timed, every=None):
         t0 = th0.clone().requires_grad_(True)
         uu = u.clone().requires_grad_(True)
         torch.cuda.synchronize()
         ev[0].record(stream)
-        out = FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, uu, n_steps)
+        out = FL.advect(mesh, "vanalbada", "ssprk3", wl.dt, t0, uu, n_steps, checkpoint_every=every)
         ev[1].record(stream)
         loss = 0.5 * ((out - tgt) ** 2).sum()
         ev[2].record(stream)
@@ -117,6 +118,13 @@ def adjoint_ratio(args, torch, FL, W, dev):
 
     once(min(steps, 10), False)  # warm-up
     fwd_ms, bwd_ms = once(steps, True)
+    # every stage input kept in HBM (20 GB at 128^3 x 400 steps): nothing is recomputed
+    full_bytes = FL.n_stages("ssprk3") * mesh.n_cells * 8 * steps
+    full = None
+    if full_bytes < 0.5 * torch.cuda.mem_get_info(dev)[0]:
+        once(steps, False, every=steps)  # warm-up: the caching allocator keeps the stage buffer
+        full = once(steps, True, every=steps)
+        torch.cuda.empty_cache()
     plain = th0.clone()
     work = FL.rk_workspace(mesh, "ssprk3", 1)
     torch.cuda.synchronize()
@@ -126,7 +134,8 @@ def adjoint_ratio(args, torch, FL, W, dev):
     ev[5].synchronize()
     plain_ms = ev[4].elapsed_time(ev[5])
     log(f"adjoint {n}^3 x {steps}: forward {fwd_ms:.1f} ms, backward {bwd_ms:.1f} ms, "
-        f"plain forward {plain_ms:.1f} ms")
+        f"plain forward {plain_ms:.1f} ms" + ("" if full is None else
+        f"; full stage storage: forward {full[0]:.1f} ms, backward {full[1]:.1f} ms"))
     mesh.close()
     return {"workload": f"periodic hex box {n}^3, van Albada, SSP-RK3 CFL 0.4, {steps} steps, "
                         f"L2 misfit to a seeded target, checkpoints every "
@@ -134,7 +143,11 @@ def adjoint_ratio(args, torch, FL, W, dev):
             "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
             "plain_forward_ms": round(plain_ms, 2),
             "adjoint_forward_ratio": round(bwd_ms / fwd_ms, 3),
-            "forward_plus_backward_over_plain": round((fwd_ms + bwd_ms) / plain_ms, 3)}
+            "forward_plus_backward_over_plain": round((fwd_ms + bwd_ms) / plain_ms, 3),
+            "full_storage": None if full is None else {
+                "stage_storage_gb": round(full_bytes / 1e9, 2),
+                "forward_ms": round(full[0], 2), "backward_ms": round(full[1], 2),
+                "adjoint_forward_ratio": round(full[1] / full[0], 3)}}
 
 
 def batch_compare(args, torch, FL, W, dev):
@@ -243,8 +256,68 @@ def deformation(args, torch, FL, W, dev):
     return out
 
 
+def algebraic_compare(args, torch, FL, W, dev):
+    """The paper's algebraic implementation (Algorithm 3: 4 ELLPACK SpMV + 4 kbin for theta_f;
+    Algorithm 4: kbin U(u), SpMV M, stage combination) against the fused stage kernel on the
+    same periodic box (random numbering + library reorder, curl velocity, superbee, SSP-RK3 at
+    CFL 0.4).  Section 4.2 compares the two strategies on 144^3 and 288^3 meshes."""
+    out = []
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for n in [int(x) for x in args.algebraic.split(",") if x]:
+        t0 = time.time()
+        wl = W.workload_box(n, renumbered=True)
+        log(f"algebraic {n}^3: workload in {time.time() - t0:.1f}s")
+        mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+        log(f"algebraic {n}^3: mesh in {time.time() - t0:.1f}s")
+        alg = FL.Algebraic(mesh)
+        log(f"algebraic {n}^3: matrices ({alg.device_bytes / 1e9:.1f} GB) in {time.time() - t0:.1f}s")
+        th0 = mesh.cells_to_mesh(torch.from_numpy(wl.theta0).to(dev))
+        u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
+        th = th0.clone()
+        awork = alg.workspace()
+        work = FL.rk_workspace(mesh, "ssprk3", 1)
+        tf = torch.empty_like(u)
+        steps = 3
+        t_alg = timed(lambda: alg.rk_steps("superbee", "ssprk3", wl.dt, th, u, steps, work=awork),
+                      2) / steps
+        t_fused = timed(lambda: FL.rk_steps(mesh, "superbee", "ssprk3", wl.dt, th, u, steps,
+                                            work=work), 2) / steps
+        t_tf = timed(lambda: alg.face_values("superbee", th, u, out=tf, work=awork), 5)
+        C, F = wl.mesh.n_cells, wl.mesh.n_faces
+        ell = sum(alg.rows[k] * alg.width[k] * 12 for k in ("D", "UUD", "OUD", "Pi"))
+        rec = {"n": n, "cells": C, "ms_per_step_algebraic": round(t_alg, 4),
+               "ms_per_step_fused": round(t_fused, 4),
+               "speedup_fused_over_algebraic": round(t_alg / t_fused, 2),
+               "ms_theta_f_algebraic": round(t_tf, 4),
+               "ell_bytes_per_cell_theta_f": round(ell / C, 1),
+               "matrix_device_gb": round(alg.device_bytes / 1e9, 2)}
+        log(f"algebraic {n}^3: {t_alg:.3f} ms/step vs fused {t_fused:.3f} ms/step "
+            f"({t_alg / t_fused:.1f}x); theta_f chain {t_tf:.3f} ms")
+        out.append(rec)
+        alg.close()
+        mesh.close()
+        del th, th0, u, awork, work, tf
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--algebraic", default="",
+                    help="comma-separated box sides for the algebraic-vs-fused comparison")
     ap.add_argument("--deformation", default="",
                     help="comma-separated box sides for the deformation benchmark (e.g. 72,144)")
     ap.add_argument("--batch-count", type=int, default=512, help="problems in the batch (0 to skip)")
@@ -372,8 +445,8 @@ def main():
         bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
         avg_launch_s = r["total_ms"] * 1e-3 / launches
         achieved = bytes_per_step / 3 / avg_launch_s / 1e9
-        # the timed region also holds one slot-rate build per call (sv), charged to the stages
-        out["roofline"] = {"kernel": "fused_stage_v_kernel" if sv else "fused_stage_kernel",
+        # the timed region also holds one slot-record build per call (sv), charged to the stages
+        out["roofline"] = {"kernel": "fused_stage_rec_kernel" if sv else "fused_stage_kernel",
                            "bound": "hbm",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -404,6 +477,9 @@ def main():
 
     if args.deformation:
         out["deformation"] = deformation(args, torch, FL, W, dev)
+
+    if args.algebraic:
+        out["algebraic"] = algebraic_compare(args, torch, FL, W, dev)
 
     if args.cpu_baseline:
         from oracle import oracle as O

@@ -221,18 +221,64 @@ fl_status fl_batch_step_unbatched(fl_batch *batch, int n_steps, void *hip_stream
 fl_status fl_batch_tile(const fl_batch *batch, int *tile_cells);
 fl_status fl_batch_destroy(fl_batch *batch);
 
+/* The paper's algebraic form of the same operator (Algorithms 3 and 4, Section 3.4), kept as a
+ * second, literal implementation to compare with the fused path: the face differences
+ * D_{C->F} = E_{C->F}, the unoriented and oriented upstream-difference matrices
+ * UUD = T_{C->F} = N (I (x) A_FF) N^T E / 2 and OUD = -S_{C->F} = -N (I (x) A^D_FF) N^T E / 2,
+ * so that d_U = Q UUD theta + OUD theta = theta_C - theta_U (the sign reading of the
+ * upstream-difference equations that restores the one-dimensional gradient ratio), the
+ * cell-to-face interpolation Pi_{C->F} = W^-1 B, and the divergence M = Omega^-1 E^T A_F.  Every
+ * matrix is stored in ELLPACK format, 8-byte coefficient + 4-byte column per entry of its
+ * structural pattern (zero coefficients included, as the paper counts them: 2k entries per row
+ * of UUD and OUD), column-major [width][rows].  One scalar field (S = 1).
+ *
+ * fl_algebraic_create builds the matrices on the host from the mesh's tables and copies them to
+ * the mesh's device (a host-only mesh, device -1, gives host-only matrices: export works,
+ * compute returns FL_E_NODEVICE).  The mesh must outlive the object.  Errors as for
+ * fl_mesh_create. */
+typedef struct fl_algebraic fl_algebraic;
+typedef struct {
+    int64_t rows[5];      /* D, UUD, OUD, Pi, M */
+    int32_t width[5];
+    int64_t device_bytes; /* bytes of the ELLPACK arrays on the device */
+} fl_algebraic_info_t;
+enum { FL_ALG_D = 0, FL_ALG_UUD = 1, FL_ALG_OUD = 2, FL_ALG_PI = 3, FL_ALG_M = 4 };
+fl_status fl_algebraic_create(const fl_mesh *mesh, fl_algebraic **out);
+fl_status fl_algebraic_destroy(fl_algebraic *alg);
+fl_status fl_algebraic_info(const fl_algebraic *alg, fl_algebraic_info_t *info);
+/* Copies matrix `which` (FL_ALG_*) to host arrays val [width][rows] and col [width][rows]. */
+fl_status fl_algebraic_export(const fl_algebraic *alg, int which, double *val, int32_t *col);
+/* Device workspace bytes of fl_algebraic_face_values / fl_algebraic_rk_steps (256-byte aligned
+ * pointer): three face vectors and three cell vectors. */
+size_t fl_algebraic_workspace_bytes(const fl_algebraic *alg);
+/* theta_f (device [n_faces]) of theta (device [n_cells]) by Algorithm 3: d_u = D theta (SpMV),
+ * d_u = Q d_u (signxty), r = UUD theta (SpMV), r = Q r (signxty), r = r + OUD theta (SpMV),
+ * r = r / d_u (axdy), theta_f = F(r) d_u (the limiter kbin, F = (psi - 1)/2), theta_f = theta_f
+ * + Pi theta (SpMV).  Where d_u == 0 the two pointwise kernels give r = 0 and F(r) d_u = 0, so
+ * theta_f = theta_C. */
+fl_status fl_algebraic_face_values(const fl_algebraic *alg, int limiter, const double *theta,
+                                   const double *u_f, double *theta_f, void *work,
+                                   void *hip_stream);
+/* n_steps explicit steps by Algorithm 4 per stage (theta_f by Algorithm 3, phi = U(u_f) theta_f
+ * by kbin, rhs = M phi by SpMV, the stage combination by kbin): forward Euler as printed, or
+ * SSP-RK3 with the same stage combination as fl_rk_steps.  theta updated in place. */
+fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme, double dt,
+                                int64_t n_steps, double *theta, const double *u_f, void *work,
+                                void *hip_stream);
+
 /* Process-wide launch tuning, read by later launches of the single-problem kernels:
  *   FL_OPT_XCD_REMAP  0 (default): workgroups take cells in launch order (the hardware deals
  *                     consecutive workgroups to the 8 XCDs in turn); 1: the grid is padded to a
  *                     multiple of 8 and each XCD gets a contiguous eighth of the cells;
  *                     M in 2 .. 65536: each XCD takes runs of M consecutive 256-cell tiles (grid
  *                     padded to a multiple of 8 M), so the tiles sharing one L2 are neighbours.
- *   FL_OPT_SLOT_VELOCITY  1 (default): fl_rk_steps / fl_rk_steps_scaled calls of two or more
- *                     steps on a mesh of the fused path first write the signed face rates
- *                     E a_f u_f in cell-slot order into their workspace and read them there;
- *                     0: every stage gathers u_f through the face index.  Results are
- *                     bit-identical either way (for time-dependent velocity on meshes with face
- *                     areas, up to the rounding of one product).
+ *   FL_OPT_SLOT_VELOCITY  1 (default): fl_rk_steps, fl_rk_steps_scaled and fl_rk_steps_store
+ *                     calls of two or more steps on a mesh of the fused path first write one
+ *                     16-byte record per cell slot (other cell, far-upwind cell, signed face rate
+ *                     E a_f u_f) into their workspace and read only those records and theta;
+ *                     0: every stage reads the mesh's slot tables and gathers u_f through the
+ *                     face index.  Results are bit-identical either way (for time-dependent
+ *                     velocity on meshes with face areas, up to the rounding of one product).
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2 };

@@ -36,6 +36,11 @@ class MeshInfo(ctypes.Structure):
                 ("uniform_volume", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
+class AlgebraicInfo(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64 * 5), ("width", ctypes.c_int32 * 5),
+                ("device_bytes", ctypes.c_int64)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -70,6 +75,13 @@ SIGNATURES = {
     "fl_batch_step_unbatched": (_S, [_P, _I, _P]),
     "fl_batch_tile": (_S, [_P, _P]),
     "fl_batch_destroy": (_S, [_P]),
+    "fl_algebraic_create": (_S, [_P, _P]),
+    "fl_algebraic_destroy": (_S, [_P]),
+    "fl_algebraic_info": (_S, [_P, _P]),
+    "fl_algebraic_export": (_S, [_P, _I, _P, _P]),
+    "fl_algebraic_workspace_bytes": (_SZ, [_P]),
+    "fl_algebraic_face_values": (_S, [_P, _I, _P, _P, _P, _P, _P]),
+    "fl_algebraic_rk_steps": (_S, [_P, _I, _I, _D, _I64, _P, _P, _P, _P]),
     "fl_set_option": (_S, [_I, _I]),
     "fl_status_str": (ctypes.c_char_p, [_S]),
     "fl_last_error": (ctypes.c_char_p, []),

@@ -65,14 +65,14 @@ fl_status upload(T **dst, const T *src, size_t n, int64_t &bytes, const char *wh
 
 void free_device(fl_mesh *m) {
     void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
-                    m->d_slot_far, m->d_rev,     m->d_area,   m->d_vol,       m->d_cell_perm,
+                    m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
                     m->d_face_perm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
     m->d_slot_face = nullptr;
     m->d_slot_nbr = m->d_slot_far = nullptr;
-    m->d_rev = nullptr;
+    m->d_adj_rec = nullptr;
     m->d_area = m->d_vol = nullptr;
     m->d_cell_perm = m->d_face_perm = nullptr;
 }
@@ -92,16 +92,16 @@ constexpr double kRk3B[3] = {1.0, 0.25, 2.0 / 3.0};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Multi-step calls on fused-path meshes build the slot-major face rates once (FL_OPT_SLOT_VELOCITY).
+// Multi-step calls on fused-path meshes build the slot records once (FL_OPT_SLOT_VELOCITY).
 int g_slot_velocity = 1;
 
-// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.  vs: slot-major face rates of u
-// (fused path), or NULL to gather u through the face index.
+// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.  vs: the per-call slot records
+// (fused path), or NULL to read the mesh's slot tables and gather u through the face index.
 hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b, int mode,
                  const double *ts, const double *tn, const double *u, double *out, double *phi,
-                 hipStream_t st, double us = 1.0, const double *vs = nullptr) {
+                 hipStream_t st, double us = 1.0, const void *vs = nullptr) {
     if (m->path == FL_PATH_FUSED) {
-        if (vs) return launch_fused_v(m, lim, S, ts, tn, vs, a, b, dt, mode, out, st, us);
+        if (vs) return launch_fused_rec(m, lim, S, ts, tn, vs, a, b, dt, mode, out, st, us);
         return launch_fused(m, lim, S, ts, tn, u, a, b, dt, mode, out, st, us);
     }
     hipError_t e = launch_face_flux(m, lim, S, ts, u, phi, st, us);
@@ -110,12 +110,13 @@ hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b
 }
 
 struct Work {
-    double *phi = nullptr, *t1 = nullptr, *t2 = nullptr, *vs = nullptr;
+    double *phi = nullptr, *t1 = nullptr, *t2 = nullptr;
+    void *vs = nullptr;
 };
 
-// Workspace of fl_rk_steps: [phi (face path)] t1 t2 [vs (fused path)].
+// Workspace of fl_rk_steps: [phi (face path)] t1 t2 [slot records (fused path)].
 size_t slot_velocity_bytes(const fl_mesh *m) {
-    return m->path == FL_PATH_FUSED ? align256((size_t)2 * m->h.pairs * m->h.nc * sizeof(double))
+    return m->path == FL_PATH_FUSED ? align256((size_t)2 * m->h.pairs * m->h.nc * kSlotRecBytes)
                                     : 0;
 }
 
@@ -131,17 +132,17 @@ Work carve(const fl_mesh *m, int S, void *work) {
     p += cell;
     w.t2 = (double *)p;
     p += cell;
-    if (m->path == FL_PATH_FUSED) w.vs = (double *)p;
+    if (m->path == FL_PATH_FUSED) w.vs = p;
     return w;
 }
 
-// The slot-major rates for a multi-step call, or NULL (single steps gather u directly: the
-// table costs about one stage's table traffic to build).
+// The slot records for a multi-step call, or NULL (single steps gather u directly: the records
+// cost about one stage's table traffic to build).
 hipError_t prepare_rates(const fl_mesh *m, const double *u, int64_t n_steps, const Work &w,
-                         hipStream_t st, const double **vs) {
+                         hipStream_t st, const void **vs) {
     *vs = nullptr;
     if (m->path != FL_PATH_FUSED || !g_slot_velocity || n_steps < 2) return hipSuccess;
-    hipError_t e = launch_slot_velocity(m, u, w.vs, st);
+    hipError_t e = launch_slot_records(m, u, w.vs, st);
     if (e == hipSuccess) *vs = w.vs;
     return e;
 }
@@ -245,9 +246,19 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                 st = upload(&m->d_slot_face, h.slot_face.data(), h.slot_face.size(), B, "slot faces");
                 if (st == FL_OK) st = upload(&m->d_slot_nbr, h.slot_nbr.data(), h.slot_nbr.size(), B, "slot cells");
                 if (st == FL_OK) st = upload(&m->d_slot_far, h.slot_far.data(), h.slot_far.size(), B, "slot far cells");
-                if (st == FL_OK)
-                    st = upload(&m->d_rev, reinterpret_cast<const int32_t *>(h.slot_rev.data()),
-                                h.slot_rev.size(), B, "slot opposite faces");
+                if (st == FL_OK) {
+                    // adjoint records {face | own bit, opposite face of the neighbour | its own
+                    // bit, neighbour, far cell}: one 16-byte load per slot in the reverse kernel
+                    const size_t n = h.slot_face.size();
+                    std::vector<int32_t> rec(4 * n);
+                    for (size_t i = 0; i < n; ++i) {
+                        rec[4 * i] = (int32_t)h.slot_face[i];
+                        rec[4 * i + 1] = (int32_t)h.slot_rev[i];
+                        rec[4 * i + 2] = h.slot_nbr[i];
+                        rec[4 * i + 3] = h.slot_far[i];
+                    }
+                    st = upload(&m->d_adj_rec, rec.data(), rec.size(), B, "adjoint slot records");
+                }
             }
             if (st == FL_OK && !h.uni_area) st = upload(&m->d_area, h.area.data(), h.area.size(), B, "areas");
             if (st == FL_OK && !h.uni_vol) st = upload(&m->d_vol, h.vol.data(), h.vol.size(), B, "volumes");
@@ -399,7 +410,7 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     Work w = carve(m, S, work);
-    const double *vs = nullptr;
+    const void *vs = nullptr;
     hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
     if (scheme == FL_EULER) {
         if (m->path == FL_PATH_FACE_CELL) {
@@ -442,7 +453,7 @@ fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     Work w = carve(m, S, work);
-    const double *vs = nullptr;
+    const void *vs = nullptr;
     hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
     const double *sc = u_scale;
     if (scheme == FL_EULER) {
@@ -562,7 +573,7 @@ fl_status fl_rk_steps_store(const fl_mesh *m, int lim, int scheme, double dt, in
     const size_t cell = (size_t)m->h.nc * S;
     const size_t per_step = cell * (scheme == FL_EULER ? 1 : 3);
     Work w = carve(m, S, work);
-    const double *vs = nullptr;
+    const void *vs = nullptr;
     hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
     if (e == hipSuccess)
         e = hipMemcpyAsync(stages, theta, cell * sizeof(double), hipMemcpyDeviceToDevice, st);

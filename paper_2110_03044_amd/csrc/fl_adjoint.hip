@@ -115,11 +115,12 @@ __device__ __forceinline__ void load(const double *__restrict__ a, int64_t c, do
 //       ADJ_MID      acc[x] += a lam[x]; out[x] = b (lam[x] + dt J^T lam)
 //       ADJ_FIRST    out[x] = acc[x] + b (lam[x] + dt J^T lam)
 // and u_bar += scale (dL/du)^T lam with scale = b dt (1 for ADJ_APPLY).
+// rec[k][x] = {face of slot k | bit 31 if x owns it, face of the neighbour n_k opposite to it |
+// bit 31 if n_k owns that one, n_k, far-upwind cell on n_k's side}: one 16-byte load per slot
+// (the kernel is bound by the address processing of its loads, so fewer, wider loads pay).
 template <int S, int P, int LIM>
 __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
-    int64_t nc, const uint32_t *__restrict__ sface, const int32_t *__restrict__ snbr,
-    const int32_t *__restrict__ sfar, const uint32_t *__restrict__ srev,
-    const double *__restrict__ u, const double *__restrict__ area, double area0,
+    int64_t nc, const int4 *__restrict__ rec, const double *__restrict__ u, const double *__restrict__ area, double area0,
     const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
     const double *__restrict__ lam, double a, double b, double dt, int mode,
     double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
@@ -130,10 +131,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     int64_t nb[K], gf[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        fw[k] = sface[(int64_t)k * nc + x];
-        rw[k] = srev[(int64_t)k * nc + x];
-        nb[k] = snbr[(int64_t)k * nc + x];
-        gf[k] = sfar[(int64_t)k * nc + x];
+        const int4 r = rec[(int64_t)k * nc + x];
+        fw[k] = (uint32_t)r.x;
+        rw[k] = (uint32_t)r.y;
+        nb[k] = r.z;
+        gf[k] = r.w;
     }
     double tx[S], lx[S], tn[K][S];
     load<S>(th, x, tx);
@@ -146,13 +148,16 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     double jt[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) jt[s] = 0.0;
-    // Face velocities are requested up front; the per-slot theta / lambda gathers stay next to
-    // their use (hoisting them as well raised register use and measured slower at 128^3).
-    double ufk[K], urk[K];
+    // Face velocities and the u_bar entries of the faces this cell owns are requested up front;
+    // the per-slot theta / lambda gathers stay next to their use (hoisting them as well raised
+    // register use and measured slower at 128^3).  u_bar is read once and written once per face
+    // (the slot faces are distinct, so the loads need not wait for earlier slots' stores).
+    double ufk[K], urk[K], ubk[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         ufk[k] = u[fw[k] & 0x7fffffffu];
         urk[k] = u[rw[k] & 0x7fffffffu];
+        ubk[k] = (ubar != nullptr && (fw[k] >> 31)) ? ubar[fw[k] & 0x7fffffffu] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
             jt[s] += x_up ? z * (1.0 + ga - gb) : z * gb;
             usum += tf * mu;
         }
-        if (ubar != nullptr && x_own) ubar[f] += scale * (af * usum);
+        ubk[k] += scale * (af * usum);
         // face fr between n and g, opposite to f in n: x is its far-upwind cell when the flow
         // runs from n to g
         const bool n_own = (rw[k] >> 31) != 0;
@@ -195,6 +200,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
                 jt[s] -= (ar * ur * mu) * ga;
             }
         }
+    }
+    if (ubar != nullptr) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (fw[k] >> 31) ubar[fw[k] & 0x7fffffffu] = ubk[k];
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -224,8 +234,7 @@ hipError_t launch3(const fl_mesh *m, const double *u, const double *th, const do
                    double *ubar, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nc + adev::kBlock - 1) / adev::kBlock);
     adev::adjoint_stage_kernel<S, P, LIM><<<nb, adev::kBlock, 0, st>>>(
-        m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far,
-        reinterpret_cast<const uint32_t *>(m->d_rev), u, m->d_area, m->h.area0, m->d_vol,
+        m->h.nc, reinterpret_cast<const int4 *>(m->d_adj_rec), u, m->d_area, m->h.area0, m->d_vol,
         1.0 / m->h.vol0, th, lam, a, b, dt, mode, out, acc, ubar);
     return hipGetLastError();
 }

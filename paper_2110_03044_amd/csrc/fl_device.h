@@ -146,28 +146,35 @@ __device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t
     fused_chunks<S, P, 0>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
 }
 
-// The same stage with the face terms read from a slot-major table vs[k][c] built once per call
-// (slot_velocity_kernel): vs = E a_f u_f where the mesh has face areas, E u_f where all areas
-// are area0.  Every operand then streams in cell order except the theta gathers; for us = 1 the
-// rates w_k, and so the results, are bit-identical to fused_cell's.
+// One slot of the per-call record table of multi-step calls: the other cell, the far-upwind cell
+// on its side and the signed face rate E a_f u_f (E u_f where all areas are area0), 16 bytes so
+// that one load brings all three.
+struct alignas(16) SlotRec {
+    int32_t nbr, far;
+    double rate;
+};
+
+// The same stage reading the slot records rec[k][c] built once per call (slot_record_kernel):
+// every operand then streams in cell order except the theta gathers, with one 16-byte load per
+// slot (the kernel is bound by the address processing of its loads, so fewer, wider loads pay).
+// For us = 1 the rates w_k, and so the results, are bit-identical to fused_cell's.
 template <int S, int P>
-__device__ __forceinline__ void fused_cell_v(int64_t c, int64_t nc,
-                                             const int32_t *__restrict__ snbr,
-                                             const int32_t *__restrict__ sfar,
-                                             const double *__restrict__ vs, bool has_area,
-                                             double area0, const double *__restrict__ vol,
-                                             double vol0, const double *__restrict__ ts,
-                                             const double *__restrict__ tn, double a, double b,
-                                             double dt, int mode, int lim,
-                                             double *__restrict__ out, double us) {
+__device__ __forceinline__ void fused_cell_rec(int64_t c, int64_t nc,
+                                               const SlotRec *__restrict__ rec, bool has_area,
+                                               double area0, const double *__restrict__ vol,
+                                               double vol0, const double *__restrict__ ts,
+                                               const double *__restrict__ tn, double a, double b,
+                                               double dt, int mode, int lim,
+                                               double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
     int64_t nb[K], gf[K];
     double w[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        nb[k] = snbr[(int64_t)k * nc + c];
-        gf[k] = sfar[(int64_t)k * nc + c];
-        const double v = vs[(int64_t)k * nc + c] * us;
+        const int4 raw = *reinterpret_cast<const int4 *>(rec + (int64_t)k * nc + c);
+        nb[k] = raw.x;
+        gf[k] = raw.y;
+        const double v = __hiloint2double(raw.w, raw.z) * us;
         w[k] = has_area ? v : area0 * v;
     }
     const double V = vol ? vol[c] : vol0;

@@ -60,7 +60,8 @@ struct fl_mesh {
     uint32_t *d_slot_face = nullptr;
     int32_t *d_slot_nbr = nullptr;
     int32_t *d_slot_far = nullptr;
-    int32_t *d_rev = nullptr;      // [2P][C] adjoint: face of the neighbour opposite slot k
+    int32_t *d_adj_rec = nullptr;  // [2P][C][4] adjoint: slot face, the neighbour's face opposite
+                                   // it (both with own bits), neighbour, far cell
     double *d_area = nullptr;      // [F] if non-uniform
     double *d_vol = nullptr;       // [C] if non-uniform
     int32_t *d_cell_perm = nullptr, *d_face_perm = nullptr;  // user -> mesh

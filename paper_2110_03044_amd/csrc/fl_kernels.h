@@ -29,11 +29,13 @@ hipError_t launch_cell_update(const fl_mesh *m, int S, const double *phi, const 
 hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                         const double *u, double a, double b, double dt, int mode, double *out,
                         hipStream_t st, double us = 1.0);
-// Slot-major signed face rates vs[2P][C] for launch_fused_v (fused-path meshes only).
-hipError_t launch_slot_velocity(const fl_mesh *m, const double *u, double *vs, hipStream_t st);
-hipError_t launch_fused_v(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
-                          const double *vs, double a, double b, double dt, int mode, double *out,
-                          hipStream_t st, double us = 1.0);
+// Per-call slot records rec[2P][C] (16 bytes each: other cell, far cell, signed face rate) for
+// launch_fused_rec (fused-path meshes only).
+constexpr size_t kSlotRecBytes = 16;
+hipError_t launch_slot_records(const fl_mesh *m, const double *u, void *rec, hipStream_t st);
+hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                            const void *rec, double a, double b, double dt, int mode, double *out,
+                            hipStream_t st, double us = 1.0);
 hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);

@@ -141,34 +141,39 @@ __global__ __launch_bounds__(kBlock) void fused_stage_kernel(
                      lim, out, us);
 }
 
-// vs[k][c] = E a_f u_f (E = +1 where c is the own cell of its slot-k face, -1 where it is the
-// nbr; a_f omitted where the mesh has no face areas).  Built once per multi-step call; its
-// gathers of u are the only ones the fused stages then avoid.
+// rec[k][c] = {n_k, g_k, E a_f u_f} (E = +1 where c is the own cell of its slot-k face, -1 where
+// it is the nbr; a_f omitted where the mesh has no face areas).  Built once per multi-step call.
 template <int P>
-__global__ __launch_bounds__(kBlock) void slot_velocity_kernel(
-    int64_t nc, const uint32_t *__restrict__ sface, const double *__restrict__ u,
-    const double *__restrict__ area, double *__restrict__ vs) {
+__global__ __launch_bounds__(kBlock) void slot_record_kernel(
+    int64_t nc, const uint32_t *__restrict__ sface, const int32_t *__restrict__ snbr,
+    const int32_t *__restrict__ sfar, const double *__restrict__ u,
+    const double *__restrict__ area, SlotRec *__restrict__ rec) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= nc) return;
 #pragma unroll
     for (int k = 0; k < 2 * P; ++k) {
-        const uint32_t fw = sface[(int64_t)k * nc + c];
+        const int64_t at = (int64_t)k * nc + c;
+        const uint32_t fw = sface[at];
         const int64_t f = fw & 0x7fffffffu;
         const double x = area ? area[f] * u[f] : u[f];
-        vs[(int64_t)k * nc + c] = (fw >> 31) ? x : -x;
+        SlotRec r;
+        r.nbr = snbr[at];
+        r.far = sfar[at];
+        r.rate = (fw >> 31) ? x : -x;
+        rec[at] = r;
     }
 }
 
 template <int S, int P>
-__global__ __launch_bounds__(kBlock) void fused_stage_v_kernel(
-    int64_t nc, const int32_t *__restrict__ snbr, const int32_t *__restrict__ sfar,
-    const double *__restrict__ vs, int has_area, double area0, const double *__restrict__ vol,
-    double vol0, const double *__restrict__ ts, const double *__restrict__ tn, double a, double b,
-    double dt, int mode, int lim, double *__restrict__ out, int remap, double us) {
+__global__ __launch_bounds__(kBlock) void fused_stage_rec_kernel(
+    int64_t nc, const SlotRec *__restrict__ rec, int has_area, double area0,
+    const double *__restrict__ vol, double vol0, const double *__restrict__ ts,
+    const double *__restrict__ tn, double a, double b, double dt, int mode, int lim,
+    double *__restrict__ out, int remap, double us) {
     const int64_t c = block_id(remap) * kBlock + threadIdx.x;
     if (c >= nc) return;
-    fused_cell_v<S, P>(c, nc, snbr, sfar, vs, has_area != 0, area0, vol, vol0, ts, tn, a, b, dt,
-                       mode, lim, out, us);
+    fused_cell_rec<S, P>(c, nc, rec, has_area != 0, area0, vol, vol0, ts, tn, a, b, dt, mode,
+                         lim, out, us);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -281,33 +286,35 @@ hipError_t launch_fused(const fl_mesh *m, int lim, int S, const double *ts, cons
     return hipGetLastError();
 }
 
-hipError_t launch_slot_velocity(const fl_mesh *m, const double *u, double *vs, hipStream_t st) {
+hipError_t launch_slot_records(const fl_mesh *m, const double *u, void *rec, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);
+    dev::SlotRec *r = static_cast<dev::SlotRec *>(rec);
     switch (m->h.pairs) {
-        case 1: dev::slot_velocity_kernel<1><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, vs); break;
-        case 2: dev::slot_velocity_kernel<2><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, vs); break;
-        case 3: dev::slot_velocity_kernel<3><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, vs); break;
+        case 1: dev::slot_record_kernel<1><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, u, m->d_area, r); break;
+        case 2: dev::slot_record_kernel<2><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, u, m->d_area, r); break;
+        case 3: dev::slot_record_kernel<3><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, m->d_slot_nbr, m->d_slot_far, u, m->d_area, r); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fused_v(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
-                          const double *vs, double a, double b, double dt, int mode, double *out,
-                          hipStream_t st, double us) {
+hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                            const void *rec, double a, double b, double dt, int mode, double *out,
+                            hipStream_t st, double us) {
     Grid g = grid_for(m->h.nc, g_remap);
     const int has_area = m->d_area != nullptr;
-#define FL_FUSED_V(P)                                                                          \
-    FL_DISPATCH_S(S, (dev::fused_stage_v_kernel<kS, P><<<g.blocks, dev::kBlock, 0, st>>>(      \
-                         m->h.nc, m->d_slot_nbr, m->d_slot_far, vs, has_area, m->h.area0,     \
-                         m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out, g.remap, us)))
+    const dev::SlotRec *r = static_cast<const dev::SlotRec *>(rec);
+#define FL_FUSED_REC(P)                                                                        \
+    FL_DISPATCH_S(S, (dev::fused_stage_rec_kernel<kS, P><<<g.blocks, dev::kBlock, 0, st>>>(    \
+                         m->h.nc, r, has_area, m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b,   \
+                         dt, mode, lim, out, g.remap, us)))
     switch (m->h.pairs) {
-        case 1: FL_FUSED_V(1); break;
-        case 2: FL_FUSED_V(2); break;
-        case 3: FL_FUSED_V(3); break;
+        case 1: FL_FUSED_REC(1); break;
+        case 2: FL_FUSED_REC(2); break;
+        case 3: FL_FUSED_REC(3); break;
         default: return hipErrorInvalidValue;
     }
-#undef FL_FUSED_V
+#undef FL_FUSED_REC
     return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ OPTIONS = {"xcd_remap": 1, "slot_velocity": 2}
 
 def set_option(name: str, value: int) -> None:
     """Process-wide launch option (fl_set_option): "xcd_remap" (default 0) or "slot_velocity"
-    (default 1: multi-step calls read signed face rates from a cell-slot table)."""
+    (default 1: multi-step calls read per-call slot records with the signed face rates)."""
     call("fl_set_option", OPTIONS[name], int(value))
 
 
@@ -380,12 +380,98 @@ class _Advect(torch.autograd.Function):
         return lam, u_bar, None, None, None, None, None, None
 
 
+def checkpoint_interval_for_budget(mesh: Mesh, scheme, S: int, n_steps: int,
+                                   budget_bytes: int) -> int:
+    """The longest checkpoint interval whose stored stage inputs ([every, stages, C, S] doubles)
+    fit in budget_bytes, never shorter than ceil(sqrt(n_steps)); n_steps (nothing recomputed) when
+    the whole run fits."""
+    per_step = n_stages(scheme) * mesh.n_cells * S * 8
+    fit = int(budget_bytes) // max(per_step, 1)
+    return max(checkpoint_interval(n_steps), min(max(n_steps, 1), fit))
+
+
 def advect(mesh: Mesh, limiter, scheme, dt: float, theta0: torch.Tensor, u: torch.Tensor,
-           n_steps: int, checkpoint_every: Optional[int] = None) -> torch.Tensor:
+           n_steps: int, checkpoint_every: Optional[int] = None,
+           memory_budget: Optional[int] = None) -> torch.Tensor:
     """theta after n_steps explicit steps, differentiable w.r.t. theta0 and u (hand-written
-    discrete adjoint, ceil(sqrt(n_steps))-step checkpoints recomputed in the backward pass)."""
-    every = checkpoint_every or checkpoint_interval(n_steps)
-    return _Advect.apply(theta0, u, mesh, limiter, scheme, float(dt), int(n_steps), int(every))
+    discrete adjoint).  The forward keeps theta every `checkpoint_every` steps (default
+    ceil(sqrt(n_steps)), or the longest interval whose stage storage fits in memory_budget bytes)
+    and the stage inputs of the last segment; the backward recomputes each other segment once,
+    storing its stage inputs, and runs the reverse steps."""
+    if checkpoint_every is None:
+        if memory_budget is not None:
+            checkpoint_every = checkpoint_interval_for_budget(mesh, scheme, _S(theta0), n_steps,
+                                                              memory_budget)
+        else:
+            checkpoint_every = checkpoint_interval(n_steps)
+    return _Advect.apply(theta0, u, mesh, limiter, scheme, float(dt), int(n_steps),
+                         int(checkpoint_every))
+
+
+# ---------------------------------------------------------------------------------------------
+# The paper's algebraic form (SpMV + pointwise kernels), for comparison with the fused path
+# ---------------------------------------------------------------------------------------------
+
+ALG_MATRICES = ("D", "UUD", "OUD", "Pi", "M")
+
+
+class Algebraic:
+    """The matrices of Algorithms 3 and 4 (ELLPACK, on the mesh's device) and the literal
+    SpMV/kbin chain over them (one scalar).  The mesh must stay open while this object is used."""
+
+    def __init__(self, mesh: Mesh):
+        h = ctypes.c_void_p()
+        call("fl_algebraic_create", mesh.handle, ctypes.byref(h))
+        self._h = h
+        self.mesh = mesh
+        info = _lib.AlgebraicInfo()
+        call("fl_algebraic_info", h, ctypes.byref(info))
+        self.rows = {k: int(info.rows[i]) for i, k in enumerate(ALG_MATRICES)}
+        self.width = {k: int(info.width[i]) for i, k in enumerate(ALG_MATRICES)}
+        self.device_bytes = int(info.device_bytes)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fl_algebraic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self, name: str):
+        """(val, col) of one matrix, each [width, rows]."""
+        i = ALG_MATRICES.index(name)
+        val = np.empty((self.width[name], self.rows[name]), dtype=np.float64)
+        col = np.empty((self.width[name], self.rows[name]), dtype=np.int32)
+        call("fl_algebraic_export", self._h, i, _np_ptr(val), _np_ptr(col))
+        return val, col
+
+    def workspace(self) -> torch.Tensor:
+        return _workspace(int(lib().fl_algebraic_workspace_bytes(self._h)), self.mesh.device)
+
+    def face_values(self, limiter, theta, u, out=None, work=None, stream=None) -> torch.Tensor:
+        theta = self.mesh._cells(theta)
+        if _S(theta) != 1:
+            raise ValueError("the algebraic chain takes one scalar field")
+        u = self.mesh._faces(u)
+        out = torch.empty_like(u) if out is None else self.mesh._faces(out)
+        work = self.workspace() if work is None else work
+        call("fl_algebraic_face_values", self._h, limiter_id(limiter), _tptr(theta), _tptr(u),
+             _tptr(out), _tptr(work), _stream(self.mesh.device, stream))
+        return out
+
+    def rk_steps(self, limiter, scheme, dt, theta, u, n_steps=1, work=None, stream=None):
+        theta = self.mesh._cells(theta)
+        if _S(theta) != 1:
+            raise ValueError("the algebraic chain takes one scalar field")
+        work = self.workspace() if work is None else work
+        call("fl_algebraic_rk_steps", self._h, limiter_id(limiter), scheme_id(scheme), float(dt),
+             int(n_steps), _tptr(theta), _tptr(self.mesh._faces(u)), _tptr(work),
+             _stream(self.mesh.device, stream))
+        return theta
 
 
 # ---------------------------------------------------------------------------------------------

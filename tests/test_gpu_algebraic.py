@@ -1,0 +1,121 @@
+"""GPU parity of the algebraic form (Algorithm 3's SpMV + kbin chain, Algorithm 4's update) against
+the CPU oracle, and against the fused path.
+
+Tolerances: the chain forms theta_f as Pi theta + F(r) d_u with r from sums of 2k products, the
+oracle as theta_C + psi(r) d_u / 2 from the gathered differences; both are FP64 and differ by
+rounding only: 1e-13 of max|theta_f| for one evaluation, the 1e-10 max norm-relative error of the
+cell values for whole runs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2110_03044_amd import fluxlim as FL, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+LIMS = ["upwind", "minmod", "vanleer", "vanalbada", "superbee", "smart", "central"]
+RUN_TOL = 1e-10
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def nrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = [
+    ("line9", lambda: W.periodic_box(9, 1)),
+    ("quad10r", lambda: W.renumber(W.periodic_box(10, 2), seed=4)),
+    ("hex13r", lambda: W.renumber(W.periodic_box(13, 3), seed=5)),
+]
+
+
+def _fields(m):
+    n, dim = m.n, m.dim
+    th = m.cell_field_from_natural(W.field_smooth_random(n, dim, 3)) if dim > 1 else \
+        W.field_square_gauss_1d(n)
+    u = m.face_velocity_from_natural(W.velocity_curl(n, seed=2)) if dim == 3 else \
+        W.velocity_uniform(m, (1.0, 0.5, 0.0)[:3], 1.0)
+    return th, u
+
+
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("lim", LIMS)
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_face_values_match_oracle(name, make, lim, reorder):
+    m = make()
+    th, u = _fields(m)
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=reorder)
+    cp, fp = mesh.permutation()
+    alg = FL.Algebraic(mesh)
+    tf = alg.face_values(lim, mesh.cells_to_mesh(dev(th)), mesh.faces_to_mesh(dev(u)))
+    got = mesh.faces_from_mesh(tf).cpu().numpy()
+    want = O.OracleMesh.from_arrays(m).face_values(lim, th, u)
+    assert nrel(got, want) <= 1e-13
+
+
+def test_face_values_plateaus():
+    """Flat neighbourhoods (d_u == 0 and d_U == 0) take theta_C; no NaN leaves the chain."""
+    m = W.renumber(W.periodic_box(8, 3), seed=1)
+    th = np.round(m.cell_field_from_natural(W.field_blob_step(8)))  # 0/1 plateaus
+    u = m.face_velocity_from_natural(W.velocity_curl(8, seed=3))
+    mesh = FL.Mesh.from_arrays(m, device=0)
+    alg = FL.Algebraic(mesh)
+    got = alg.face_values("superbee", dev(th), dev(u)).cpu().numpy()
+    want = O.OracleMesh.from_arrays(m).face_values("superbee", th, u)
+    assert np.isfinite(got).all()
+    assert nrel(got, want) <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+@pytest.mark.parametrize("lim", ["minmod", "vanleer", "superbee", "smart"])
+def test_runs_match_oracle_and_fused_path(lim, scheme):
+    wl = W.workload_box(16, renumbered=True, steps=20)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    cp, _ = mesh.permutation()
+    th0 = mesh.cells_to_mesh(dev(wl.theta0))
+    u = mesh.faces_to_mesh(dev(wl.u))
+    alg = FL.Algebraic(mesh)
+    a = alg.rk_steps(lim, scheme, wl.dt, th0.clone(), u, wl.steps)
+    b = FL.rk_steps(mesh, lim, scheme, wl.dt, th0.clone(), u, wl.steps)
+    got = mesh.cells_from_mesh(a).cpu().numpy()
+    want = O.OracleMesh.from_arrays(wl.mesh).run(lim, scheme, wl.dt, wl.theta0, wl.u, wl.steps)
+    assert nrel(got, want) <= RUN_TOL
+    assert nrel(got, mesh.cells_from_mesh(b).cpu().numpy()) <= RUN_TOL
+    V = wl.mesh.cell_volume
+    assert abs((V * got).sum() - (V * wl.theta0).sum()) <= 1e-13 * (V * np.abs(wl.theta0)).sum()
+
+
+def test_line_config_matches_oracle():
+    """The 1-D workload (square wave + Gaussian, Euler at CFL 0.5, 400 steps = one period)."""
+    wl = W.workload_line()
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0)
+    alg = FL.Algebraic(mesh)
+    got = alg.rk_steps("superbee", "euler", wl.dt, dev(wl.theta0), dev(wl.u), wl.steps)
+    want = O.OracleMesh.from_arrays(wl.mesh).run("superbee", "euler", wl.dt, wl.theta0, wl.u,
+                                                 wl.steps)
+    assert nrel(got.cpu().numpy(), want) <= RUN_TOL
+
+
+def test_errors():
+    m = W.periodic_box(6, 3)
+    mesh = FL.Mesh.from_arrays(m, device=0)
+    alg = FL.Algebraic(mesh)
+    th = dev(np.ones(m.n_cells))
+    with pytest.raises(ValueError):
+        alg.face_values("vanleer", th.reshape(-1, 1).repeat(1, 2).contiguous(), dev(np.ones(m.n_faces)))
+    from paper_2110_03044_amd import _lib
+
+    with pytest.raises(_lib.FluxLimError):
+        _lib.call("fl_algebraic_rk_steps", alg._h, 2, 7, 0.1, 1, FL._tptr(th),
+                  FL._tptr(dev(np.ones(m.n_faces))), FL._tptr(alg.workspace()), None)

@@ -148,9 +148,9 @@ def test_create_rejects_bad_arguments_and_host_only_compute():
     def a256(x):
         return (x + 255) // 256 * 256
 
-    # two stage buffers + the slot-major face rates (6 slots per hex cell) of the fused path
+    # two stage buffers + the 16-byte slot records (6 slots per hex cell) of the fused path
     assert L.fl_rk_workspace_bytes(mesh.handle, 3, 1) == (2 * a256(m.n_cells * 8)
-                                                          + a256(6 * m.n_cells * 8))
+                                                          + a256(6 * m.n_cells * 16))
     assert L.fl_rk_workspace_bytes(mesh.handle, 2, 1) == 0
     face = FL.Mesh.from_arrays(m, device=-1, face_path=True)
     assert face.path == "face"
@@ -162,3 +162,57 @@ def test_nonuniform_area_and_volume_kept():
     area = m.face_area * (1 + 0.1 * np.arange(m.n_faces) / m.n_faces)
     mesh = FL.Mesh(m.face_cells, m.face_normal, area, m.cell_volume, device=-1)
     assert mesh.info.uniform_area == 0 and mesh.info.uniform_volume == 1
+
+
+def _ell_dense(val, col, n_cols):
+    width, rows = val.shape
+    A = np.zeros((rows, n_cols))
+    for k in range(width):
+        np.add.at(A, (np.arange(rows), col[k]), val[k])
+    return A
+
+
+@pytest.mark.parametrize("name,m,k", [
+    ("line7", W.periodic_box(7, 1), 2),
+    ("quad6r", W.renumber(W.periodic_box(6, 2), seed=3), 4),
+    ("hex5r", W.renumber(W.periodic_box(5, 3), seed=4), 6),
+])
+def test_algebraic_matrices_match_the_literal_construction(name, m, k):
+    """The library's ELLPACK matrices of Algorithms 3/4 equal the oracle's sparse-matrix
+    construction of Section 2 (D = E, UUD = T, OUD = -S, Pi, M), with 2k stored entries per row
+    of UUD and OUD (zero coefficients of the pattern included, as the paper counts them)."""
+    from oracle.mini_oracle import AlgebraicMesh
+
+    import dataclasses
+
+    rng = np.random.default_rng(1)
+    m = dataclasses.replace(m, face_area=m.face_area * rng.uniform(0.5, 1.5, m.n_faces),
+                            cell_volume=m.cell_volume * rng.uniform(0.5, 1.5, m.n_cells))
+    mesh = FL.Mesh.from_arrays(m, device=-1)
+    alg = FL.Algebraic(mesh)
+    ref = AlgebraicMesh.from_arrays(m)
+    C, F = m.n_cells, m.n_faces
+    assert alg.rows == {"D": F, "UUD": F, "OUD": F, "Pi": F, "M": C}
+    assert alg.width == {"D": 2, "UUD": 2 * k, "OUD": 2 * k, "Pi": 2, "M": k}
+    want = {"D": ref.E, "UUD": ref.T, "OUD": -ref.S, "Pi": ref.Pi, "M": ref.M}
+    for key, A in want.items():
+        val, col = alg.export(key)
+        got = _ell_dense(val, col, F if key == "M" else C)
+        np.testing.assert_allclose(got, A.toarray(), rtol=0, atol=1e-14, err_msg=key)
+    # every structural column of a UUD row is a distinct cell
+    _, col = alg.export("UUD")
+    assert all(len(set(col[:, f])) == 2 * k for f in range(F))
+    alg.close()
+    mesh.close()
+
+
+def test_checkpoint_interval_for_memory_budget():
+    m = W.periodic_box(10, 3)  # 1000 cells: one SSP-RK3 step stores 3 * 1000 * 8 = 24000 bytes
+    mesh = FL.Mesh.from_arrays(m, device=-1)
+    f = FL.checkpoint_interval_for_budget
+    assert f(mesh, "ssprk3", 1, 400, 0) == 20  # never below ceil(sqrt(N))
+    assert f(mesh, "ssprk3", 1, 400, 24000 * 57) == 57
+    assert f(mesh, "ssprk3", 1, 400, 10**12) == 400  # everything stored: nothing recomputed
+    assert f(mesh, "euler", 2, 400, 16000 * 100) == 100
+    assert [FL.checkpoint_interval(n) for n in (1, 2, 4, 5, 400, 401)] == [1, 2, 2, 3, 20, 21]
+    mesh.close()
