@@ -54,7 +54,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n, xcd_remap, slot_velocity):
+def measured_traffic(n, xcd_remap, slot_velocity, lds_stage):
     """HBM bytes per fused-stage launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed
     rocprofv3 counter summary, or None if it was taken on other kernel sources, sizes or launch
     mapping."""
@@ -66,11 +66,23 @@ def measured_traffic(n, xcd_remap, slot_velocity):
                 kv[k.strip()] = v.strip()
         if (kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n
                 or int(kv.get("xcd_remap", -1)) != int(xcd_remap)
-                or int(kv.get("slot_velocity", 0)) != int(slot_velocity)):
+                or int(kv.get("slot_velocity", 0)) != int(slot_velocity)
+                or int(kv.get("lds_stage", 0)) != int(lds_stage)):
             return None
         return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
+
+
+def lds_stage_bytes(C, K, S, stage, halo_total):
+    """Compulsory bytes of one LDS-staged stage launch: local slot indices (4 B per slot), the
+    per-call signed face rates (8 B per slot), the tile halo lists (4 B per entry), theta_s read
+    once, theta_n read once (stages 2, 3) and the output written once.  Halo values are other
+    tiles' cells: counted once, with their own tile."""
+    b = C * K * 12 + 4 * halo_total + C * S * 8 * 2
+    if stage > 0:
+        b += C * S * 8
+    return b
 
 
 def fused_stage_bytes(C, F, K, S, stage, slot_velocity=True):
@@ -334,6 +346,8 @@ def main():
     ap.add_argument("--face-path", action="store_true")
     ap.add_argument("--xcd-remap", type=int, default=0,
                     help="1: each XCD takes a contiguous eighth of the cells (FL_OPT_XCD_REMAP)")
+    ap.add_argument("--lds-stage", type=int, default=1,
+                    help="0: multi-step calls use the slot records instead of LDS staging")
     ap.add_argument("--slot-velocity", type=int, default=1,
                     help="0: stages gather u through the face index (FL_OPT_SLOT_VELOCITY)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 to skip the oracle timing")
@@ -357,6 +371,7 @@ def main():
     lims = [l for l in args.limiters.split(",") if l]
     _lib.call("fl_set_option", 1, int(args.xcd_remap))  # FL_OPT_XCD_REMAP
     _lib.call("fl_set_option", 2, int(args.slot_velocity))  # FL_OPT_SLOT_VELOCITY
+    _lib.call("fl_set_option", 3, int(args.lds_stage))  # FL_OPT_LDS_STAGE
     t0 = time.time()
     wl = W.workload_box(args.n, renumbered=True)
     m = wl.mesh
@@ -394,7 +409,8 @@ def main():
         torch.cuda.synchronize()
         info = mesh.info
         res = dict(mesh=mesh, total_ms=total_ms, per_lim=per_lim, path=mesh.path,
-                   K=int(info.max_degree), th=th, u=u)
+                   K=int(info.max_degree), th=th, u=u, max_halo=int(info.max_halo),
+                   halo_total=int(info.halo_total))
         return res
 
     # A plain device copy of known size (untimed): its FETCH_SIZE / WRITE_SIZE counters calibrate
@@ -442,15 +458,22 @@ def main():
         K = r["K"]
         launches = 3 * n_steps_total
         sv = bool(args.slot_velocity) and args.steps >= 2
-        bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
+        lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
+            (256 + r["max_halo"]) * S * 8 <= 64 * 1024
+        if lds:
+            kname = "fused_stage_lds_kernel"
+            bytes_per_step = sum(lds_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
+        else:
+            kname = "fused_stage_rec_kernel" if sv else "fused_stage_kernel"
+            bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
         avg_launch_s = r["total_ms"] * 1e-3 / launches
         achieved = bytes_per_step / 3 / avg_launch_s / 1e9
-        # the timed region also holds one slot-record build per call (sv), charged to the stages
-        out["roofline"] = {"kernel": "fused_stage_rec_kernel" if sv else "fused_stage_kernel",
+        # the timed region also holds one per-call table build per call (sv), charged to the stages
+        out["roofline"] = {"kernel": kname,
                            "bound": "hbm",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(args.n, args.xcd_remap, sv),
+                           "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds),
                            "algorithmic_bytes_per_launch": int(bytes_per_step / 3),
                            "avg_launch_us": round(avg_launch_s * 1e6, 2)}
     # the two-kernel byte model (40 B/face + 60 B/cell per stage) as context

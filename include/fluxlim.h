@@ -99,6 +99,9 @@ typedef struct fl_mesh_info_t {
     int32_t uniform_area;   /* 1 if all face areas are equal (then stored as one scalar)     */
     int32_t uniform_volume; /* 1 if all cell volumes are equal                               */
     int64_t device_bytes;   /* device memory held by the mesh                                */
+    int32_t tile_cells;     /* cells per LDS-staged tile (fused path), 0 if no tile tables   */
+    int32_t max_halo;       /* largest tile halo (cells outside a tile that it reads), -1   */
+    int64_t halo_total;     /* halo entries summed over the tiles                            */
 } fl_mesh_info_t;
 
 /* Checks an incidence against the mesh model without a GPU (Section 2).  face_cells: host
@@ -279,9 +282,14 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     0: every stage reads the mesh's slot tables and gathers u_f through the
  *                     face index.  Results are bit-identical either way (for time-dependent
  *                     velocity on meshes with face areas, up to the rounding of one product).
+ *   FL_OPT_LDS_STAGE  1 (default): those multi-step calls, on meshes with tile tables
+ *                     (fl_mesh_info_t.tile_cells > 0) and with (tile_cells + max_halo) * S * 8
+ *                     bytes of LDS per tile at most 64 KiB, stage each tile's theta and its halo
+ *                     in LDS and read the per-call rates E a_f u_f (8 bytes per slot) instead of
+ *                     the 16-byte records; 0: the records.  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
-enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2 };
+enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3 };
 fl_status fl_set_option(int option, int value);
 
 const char *fl_status_str(fl_status status);

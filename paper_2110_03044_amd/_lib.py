@@ -33,7 +33,9 @@ class MeshInfo(ctypes.Structure):
                 ("max_degree", ctypes.c_int32), ("pairs", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("reordered", ctypes.c_int32), ("uniform_area", ctypes.c_int32),
-                ("uniform_volume", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("uniform_volume", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("tile_cells", ctypes.c_int32), ("max_halo", ctypes.c_int32),
+                ("halo_total", ctypes.c_int64)]
 
 
 class AlgebraicInfo(ctypes.Structure):

@@ -66,13 +66,15 @@ fl_status upload(T **dst, const T *src, size_t n, int64_t &bytes, const char *wh
 void free_device(fl_mesh *m) {
     void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
-                    m->d_face_perm};
+                    m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
     m->d_slot_face = nullptr;
     m->d_slot_nbr = m->d_slot_far = nullptr;
     m->d_adj_rec = nullptr;
+    m->d_halo_ptr = m->d_halo = nullptr;
+    m->d_slot_local = nullptr;
     m->d_area = m->d_vol = nullptr;
     m->d_cell_perm = m->d_face_perm = nullptr;
 }
@@ -92,16 +94,31 @@ constexpr double kRk3B[3] = {1.0, 0.25, 2.0 / 3.0};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Multi-step calls on fused-path meshes build the slot records once (FL_OPT_SLOT_VELOCITY).
+// Multi-step calls on fused-path meshes build per-call slot tables once (FL_OPT_SLOT_VELOCITY)
+// and, where the mesh has tile tables and the tile fits in LDS, run the LDS-staged stage
+// (FL_OPT_LDS_STAGE).
 int g_slot_velocity = 1;
+int g_lds_stage = 1;
 
-// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.  vs: the per-call slot records
-// (fused path), or NULL to read the mesh's slot tables and gather u through the face index.
+// How the stages of one call read the face velocities: gathered through the face index
+// (PLAN_GATHER), from per-call slot records (PLAN_RECORDS), or from per-call rates with the
+// LDS-staged stage (PLAN_LDS).
+enum { PLAN_GATHER = 0, PLAN_RECORDS = 1, PLAN_LDS = 2 };
+struct Plan {
+    int kind = PLAN_GATHER;
+    void *table = nullptr;
+};
+
+// One stage: out = a tn + b (ts + dt L(ts)) in the given mode.
 hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b, int mode,
                  const double *ts, const double *tn, const double *u, double *out, double *phi,
-                 hipStream_t st, double us = 1.0, const void *vs = nullptr) {
+                 hipStream_t st, double us = 1.0, const Plan &pl = Plan()) {
     if (m->path == FL_PATH_FUSED) {
-        if (vs) return launch_fused_rec(m, lim, S, ts, tn, vs, a, b, dt, mode, out, st, us);
+        if (pl.kind == PLAN_LDS)
+            return launch_fused_lds(m, lim, S, ts, tn, static_cast<const double *>(pl.table), a,
+                                    b, dt, mode, out, st, us);
+        if (pl.kind == PLAN_RECORDS)
+            return launch_fused_rec(m, lim, S, ts, tn, pl.table, a, b, dt, mode, out, st, us);
         return launch_fused(m, lim, S, ts, tn, u, a, b, dt, mode, out, st, us);
     }
     hipError_t e = launch_face_flux(m, lim, S, ts, u, phi, st, us);
@@ -136,14 +153,20 @@ Work carve(const fl_mesh *m, int S, void *work) {
     return w;
 }
 
-// The slot records for a multi-step call, or NULL (single steps gather u directly: the records
-// cost about one stage's table traffic to build).
-hipError_t prepare_rates(const fl_mesh *m, const double *u, int64_t n_steps, const Work &w,
-                         hipStream_t st, const void **vs) {
-    *vs = nullptr;
+// The per-call tables of a multi-step call (single steps gather u directly: the tables cost
+// about one stage's table traffic to build).
+hipError_t prepare_rates(const fl_mesh *m, const double *u, int S, int64_t n_steps,
+                         const Work &w, hipStream_t st, Plan *pl) {
+    *pl = Plan();
     if (m->path != FL_PATH_FUSED || !g_slot_velocity || n_steps < 2) return hipSuccess;
+    const size_t lds = lds_stage_bytes(m, S);
+    if (g_lds_stage && lds > 0 && lds <= kMaxStageLds) {
+        hipError_t e = launch_slot_rates(m, u, static_cast<double *>(w.vs), st);
+        if (e == hipSuccess) *pl = Plan{PLAN_LDS, w.vs};
+        return e;
+    }
     hipError_t e = launch_slot_records(m, u, w.vs, st);
-    if (e == hipSuccess) *vs = w.vs;
+    if (e == hipSuccess) *pl = Plan{PLAN_RECORDS, w.vs};
     return e;
 }
 
@@ -176,6 +199,10 @@ fl_status fl_set_option(int option, int value) {
     }
     if (option == FL_OPT_SLOT_VELOCITY && (value == 0 || value == 1)) {
         g_slot_velocity = value;
+        return FL_OK;
+    }
+    if (option == FL_OPT_LDS_STAGE && (value == 0 || value == 1)) {
+        g_lds_stage = value;
         return FL_OK;
     }
     return fail(FL_E_INVALID, "unknown option or value");
@@ -259,6 +286,13 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                     }
                     st = upload(&m->d_adj_rec, rec.data(), rec.size(), B, "adjoint slot records");
                 }
+                if (st == FL_OK && h.max_halo >= 0) {
+                    st = upload(&m->d_halo_ptr, h.halo_ptr.data(), h.halo_ptr.size(), B, "tile halo pointers");
+                    if (st == FL_OK) st = upload(&m->d_halo, h.halo.data(), h.halo.size(), B, "tile halos");
+                    if (st == FL_OK)
+                        st = upload(&m->d_slot_local, h.slot_local.data(), h.slot_local.size(), B,
+                                    "local slot indices");
+                }
             }
             if (st == FL_OK && !h.uni_area) st = upload(&m->d_area, h.area.data(), h.area.size(), B, "areas");
             if (st == FL_OK && !h.uni_vol) st = upload(&m->d_vol, h.vol.data(), h.vol.size(), B, "volumes");
@@ -306,6 +340,9 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
     info->uniform_area = m->h.uni_area ? 1 : 0;
     info->uniform_volume = m->h.uni_vol ? 1 : 0;
     info->device_bytes = m->device_bytes;
+    info->tile_cells = m->h.max_halo >= 0 ? kTileCells : 0;
+    info->max_halo = m->h.max_halo;
+    info->halo_total = (int64_t)m->h.halo.size();
     return FL_OK;
 }
 
@@ -410,8 +447,8 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     Work w = carve(m, S, work);
-    const void *vs = nullptr;
-    hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
+    Plan vs;
+    hipError_t e = prepare_rates(m, u, S, n_steps, w, st, &vs);
     if (scheme == FL_EULER) {
         if (m->path == FL_PATH_FACE_CELL) {
             for (int64_t i = 0; i < n_steps && e == hipSuccess; ++i)
@@ -453,8 +490,8 @@ fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     Work w = carve(m, S, work);
-    const void *vs = nullptr;
-    hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
+    Plan vs;
+    hipError_t e = prepare_rates(m, u, S, n_steps, w, st, &vs);
     const double *sc = u_scale;
     if (scheme == FL_EULER) {
         double *src = theta, *dst = w.t1;
@@ -573,8 +610,8 @@ fl_status fl_rk_steps_store(const fl_mesh *m, int lim, int scheme, double dt, in
     const size_t cell = (size_t)m->h.nc * S;
     const size_t per_step = cell * (scheme == FL_EULER ? 1 : 3);
     Work w = carve(m, S, work);
-    const void *vs = nullptr;
-    hipError_t e = prepare_rates(m, u, n_steps, w, st, &vs);
+    Plan vs;
+    hipError_t e = prepare_rates(m, u, S, n_steps, w, st, &vs);
     if (e == hipSuccess)
         e = hipMemcpyAsync(stages, theta, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
     // each step's last stage writes the next step's stored input directly (the last: theta)

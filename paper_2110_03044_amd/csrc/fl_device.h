@@ -55,10 +55,13 @@ __device__ __forceinline__ double face_value(int lim, double tC, double tD, doub
 }
 
 // Scalars S0 .. S0+CS-1 of cell c (CS <= 2 keeps the gathered values in registers for any S).
+// theta_s is read from src at index cs (this cell) and nb[k], gf[k] (its slots' cells): src is
+// theta_s itself with global indices, or a tile's LDS copy with local indices; tn and out are
+// indexed by the global cell c.
 template <int S, int P, int S0>
-__device__ __forceinline__ void fused_chunks(int64_t c, const double *w, const int64_t *nb,
+__device__ __forceinline__ void fused_chunks(int64_t c, int64_t cs, const double *src,
+                                             const double *w, const int64_t *nb,
                                              const int64_t *gf, double V,
-                                             const double *__restrict__ ts,
                                              const double *__restrict__ tn, double a, double b,
                                              double dt, int mode, int lim,
                                              double *__restrict__ out) {
@@ -67,14 +70,14 @@ __device__ __forceinline__ void fused_chunks(int64_t c, const double *w, const i
         constexpr int CS = (S - S0) >= 2 ? 2 : 1;
         double tc[CS], tnb[K][CS], tg[K][CS];
 #pragma unroll
-        for (int i = 0; i < CS; ++i) tc[i] = ts[c * S + S0 + i];
+        for (int i = 0; i < CS; ++i) tc[i] = src[cs * S + S0 + i];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int i = 0; i < CS; ++i) tnb[k][i] = ts[nb[k] * S + S0 + i];
+            for (int i = 0; i < CS; ++i) tnb[k][i] = src[nb[k] * S + S0 + i];
             if (lim != FL_UPWIND) {
 #pragma unroll
-                for (int i = 0; i < CS; ++i) tg[k][i] = ts[gf[k] * S + S0 + i];
+                for (int i = 0; i < CS; ++i) tg[k][i] = src[gf[k] * S + S0 + i];
             }
         }
         double acc[CS];
@@ -101,7 +104,7 @@ __device__ __forceinline__ void fused_chunks(int64_t c, const double *w, const i
             else if (mode == MODE_EULER) out[j] = tc[i] + dt * (acc[i] / V);
             else out[j] = a * tn[j] + b * (tc[i] + dt * (acc[i] / V));
         }
-        fused_chunks<S, P, S0 + CS>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
+        fused_chunks<S, P, S0 + CS>(c, cs, src, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
     }
 }
 
@@ -143,7 +146,7 @@ __device__ __forceinline__ void fused_cell(int64_t c, int64_t nc, const uint32_t
         w[k] = (fw[k] >> 31) ? au : -au;
     }
     const double V = vol ? vol[c] : vol0;
-    fused_chunks<S, P, 0>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
+    fused_chunks<S, P, 0>(c, c, ts, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
 }
 
 // One slot of the per-call record table of multi-step calls: the other cell, the far-upwind cell
@@ -178,7 +181,53 @@ __device__ __forceinline__ void fused_cell_rec(int64_t c, int64_t nc,
         w[k] = has_area ? v : area0 * v;
     }
     const double V = vol ? vol[c] : vol0;
-    fused_chunks<S, P, 0>(c, w, nb, gf, V, ts, tn, a, b, dt, mode, lim, out);
+    fused_chunks<S, P, 0>(c, c, ts, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
+}
+
+// The stage for the cells of one tile (kTileCells consecutive cells, one per thread of the
+// workgroup): theta_s of the tile and of its halo is first copied to LDS (the tile's cells in
+// order, then the halo cells, each read from global memory once per tile), then every cell reads
+// its slots' cells there through 16-bit local indices (slot_local: neighbour | far << 16) and
+// the per-call signed face rates.  Call from every thread of the workgroup (it synchronises);
+// the arithmetic is fused_chunks', so results are bit-identical to fused_cell_rec's.
+template <int S, int P>
+__device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds,
+                                           const int32_t *__restrict__ halo_ptr,
+                                           const int32_t *__restrict__ halo,
+                                           const uint32_t *__restrict__ slot_local,
+                                           const double *__restrict__ rate, bool has_area,
+                                           double area0, const double *__restrict__ vol,
+                                           double vol0, const double *__restrict__ ts,
+                                           const double *__restrict__ tn, double a, double b,
+                                           double dt, int mode, int lim,
+                                           double *__restrict__ out, double us) {
+    constexpr int K = 2 * P;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t left = nc - c0;
+    const int nt = left < kTileCells ? (int)left : kTileCells;
+    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < nt * S; i += kTileCells) lds[i] = ts[c0 * S + i];
+    for (int i = tid; i < nh; i += kTileCells) {
+        const int64_t g = halo[h0 + i];
+#pragma unroll
+        for (int s = 0; s < S; ++s) lds[(kTileCells + i) * S + s] = ts[g * S + s];
+    }
+    __syncthreads();
+    if (tid >= nt) return;
+    const int64_t c = c0 + tid;
+    int64_t nb[K], gf[K];
+    double w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t l = slot_local[(int64_t)k * nc + c];
+        nb[k] = l & 0xffffu;
+        gf[k] = l >> 16;
+        const double v = rate[(int64_t)k * nc + c] * us;
+        w[k] = has_area ? v : area0 * v;
+    }
+    const double V = vol ? vol[c] : vol0;
+    fused_chunks<S, P, 0>(c, tid, lds, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
 }
 
 }  // namespace dev

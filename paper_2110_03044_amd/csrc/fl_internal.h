@@ -34,9 +34,19 @@ struct HostTables {
     std::vector<int32_t> slot_far;   // far-upwind cell of the face on the other cell's side
     std::vector<uint32_t> slot_rev;  // face of the other cell opposite to this slot's face
                                      // | (1u << 31) if the other cell is that face's own
+    // Tiles of kTileCells consecutive cells for the LDS-staged fused stage (fused path only):
+    // tile t stages its own cells and the cells its slots reference outside it (its halo,
+    // ascending) in LDS; slot_local[k][c] = local index of n_k | local index of g_k << 16
+    // (0 .. kTileCells-1: the tile's own cells; kTileCells + j: halo entry j).
+    std::vector<int32_t> halo_ptr;   // [tiles + 1]
+    std::vector<int32_t> halo;       // cell indices
+    std::vector<uint32_t> slot_local;
+    int32_t max_halo = -1;           // -1: no tile tables (local indices would not fit 16 bits)
     // Numbering maps user -> mesh (empty = identity).
     std::vector<int32_t> cell_perm, face_perm;
 };
+
+constexpr int kTileCells = 256;
 
 enum { REORDER_NONE = 0, REORDER_CURVE = 1, REORDER_BFS = 2 };
 
@@ -60,6 +70,9 @@ struct fl_mesh {
     uint32_t *d_slot_face = nullptr;
     int32_t *d_slot_nbr = nullptr;
     int32_t *d_slot_far = nullptr;
+    int32_t *d_halo_ptr = nullptr; // LDS-staged stage: tile halo lists and local slot indices
+    int32_t *d_halo = nullptr;
+    uint32_t *d_slot_local = nullptr;
     int32_t *d_adj_rec = nullptr;  // [2P][C][4] adjoint: slot face, the neighbour's face opposite
                                    // it (both with own bits), neighbour, far cell
     double *d_area = nullptr;      // [F] if non-uniform

@@ -36,6 +36,15 @@ hipError_t launch_slot_records(const fl_mesh *m, const double *u, void *rec, hip
 hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                             const void *rec, double a, double b, double dt, int mode, double *out,
                             hipStream_t st, double us = 1.0);
+// LDS-staged stage (fused path with tile tables): per-call rates rate[2P][C] (8 bytes per slot)
+// and one workgroup per tile with lds_stage_bytes(m, S) of dynamic LDS; used while that is at
+// most kMaxStageLds (0 = no tile tables).
+constexpr size_t kMaxStageLds = 64 * 1024;
+size_t lds_stage_bytes(const fl_mesh *m, int S);
+hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st);
+hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                            const double *rate, double a, double b, double dt, int mode,
+                            double *out, hipStream_t st, double us = 1.0);
 hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);

@@ -25,6 +25,7 @@ namespace fl {
 namespace dev {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kTileCells, "one thread per cell of an LDS-staged tile");
 
 // Workgroup -> cell tile.  Dispatch sends workgroup d to XCD d mod 8; with chunk M > 0 (the grid
 // padded to a multiple of 8 M) XCD x takes runs of M consecutive tiles, so the tiles one XCD
@@ -176,6 +177,37 @@ __global__ __launch_bounds__(kBlock) void fused_stage_rec_kernel(
                          lim, out, us);
 }
 
+// rate[k][c] = E a_f u_f of slot k (the rate part of the slot records), for the LDS-staged stage.
+template <int P>
+__global__ __launch_bounds__(kBlock) void slot_rate_kernel(int64_t nc,
+                                                           const uint32_t *__restrict__ sface,
+                                                           const double *__restrict__ u,
+                                                           const double *__restrict__ area,
+                                                           double *__restrict__ rate) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nc) return;
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        const uint32_t fw = sface[(int64_t)k * nc + c];
+        const int64_t f = fw & 0x7fffffffu;
+        const double x = area ? area[f] * u[f] : u[f];
+        rate[(int64_t)k * nc + c] = (fw >> 31) ? x : -x;
+    }
+}
+
+// One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo) * S doubles.
+template <int S, int P>
+__global__ __launch_bounds__(kBlock) void fused_stage_lds_kernel(
+    int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
+    const uint32_t *__restrict__ slot_local, const double *__restrict__ rate, int has_area,
+    double area0, const double *__restrict__ vol, double vol0, const double *__restrict__ ts,
+    const double *__restrict__ tn, double a, double b, double dt, int mode, int lim,
+    double *__restrict__ out, double us) {
+    extern __shared__ double lds[];
+    fused_tile<S, P>(nc, blockIdx.x, lds, halo_ptr, halo, slot_local, rate, has_area != 0, area0,
+                     vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
+}
+
 // ------------------------------------------------------------------------------------------
 // Utilities
 // ------------------------------------------------------------------------------------------
@@ -315,6 +347,43 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
         default: return hipErrorInvalidValue;
     }
 #undef FL_FUSED_REC
+    return hipGetLastError();
+}
+
+size_t lds_stage_bytes(const fl_mesh *m, int S) {
+    if (m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
+    return (size_t)(kTileCells + m->h.max_halo) * S * sizeof(double);
+}
+
+hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st) {
+    const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);
+    switch (m->h.pairs) {
+        case 1: dev::slot_rate_kernel<1><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, rate); break;
+        case 2: dev::slot_rate_kernel<2><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, rate); break;
+        case 3: dev::slot_rate_kernel<3><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, rate); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
+                            const double *rate, double a, double b, double dt, int mode,
+                            double *out, hipStream_t st, double us) {
+    const size_t lds = lds_stage_bytes(m, S);
+    if (lds == 0 || lds > kMaxStageLds) return hipErrorInvalidValue;
+    const unsigned tiles = (unsigned)((m->h.nc + kTileCells - 1) / kTileCells);
+    const int has_area = m->d_area != nullptr;
+#define FL_FUSED_LDS(P)                                                                          \
+    FL_DISPATCH_S(S, (dev::fused_stage_lds_kernel<kS, P><<<tiles, dev::kBlock, lds, st>>>(       \
+                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_slot_local, rate, has_area,      \
+                         m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out, us)))
+    switch (m->h.pairs) {
+        case 1: FL_FUSED_LDS(1); break;
+        case 2: FL_FUSED_LDS(2); break;
+        case 3: FL_FUSED_LDS(3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FL_FUSED_LDS
     return hipGetLastError();
 }
 

@@ -313,6 +313,48 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
     t.pairs = P;
 }
 
+// Tile halos for the LDS-staged fused stage: for each run of kTileCells consecutive cells, the
+// sorted list of cells outside the run that its slots name (neighbours and far-upwind cells),
+// and every slot's neighbour and far cell as local indices into [tile cells | halo].
+void build_tiles(HostTables &t) {
+    t.max_halo = -1;
+    if (t.pairs < 1) return;
+    const int64_t nc = t.nc, K = 2 * t.pairs;
+    const int64_t ntiles = (nc + kTileCells - 1) / kTileCells;
+    std::vector<int32_t> ptr(ntiles + 1, 0), halo;
+    std::vector<uint32_t> local((size_t)K * nc, 0);
+    std::vector<int32_t> refs;
+    int32_t max_halo = 0;
+    for (int64_t tile = 0; tile < ntiles; ++tile) {
+        const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
+        refs.clear();
+        for (int64_t k = 0; k < K; ++k)
+            for (int64_t c = c0; c < c1; ++c) {
+                const int32_t n = t.slot_nbr[k * nc + c], g = t.slot_far[k * nc + c];
+                if (n < c0 || n >= c1) refs.push_back(n);
+                if (g < c0 || g >= c1) refs.push_back(g);
+            }
+        std::sort(refs.begin(), refs.end());
+        refs.erase(std::unique(refs.begin(), refs.end()), refs.end());
+        if (kTileCells + refs.size() > 65535) return;  // local indices are 16-bit
+        max_halo = std::max<int32_t>(max_halo, (int32_t)refs.size());
+        auto loc = [&](int32_t cell) -> uint32_t {
+            if (cell >= c0 && cell < c1) return (uint32_t)(cell - c0);
+            return (uint32_t)(kTileCells + (std::lower_bound(refs.begin(), refs.end(), cell) - refs.begin()));
+        };
+        for (int64_t k = 0; k < K; ++k)
+            for (int64_t c = c0; c < c1; ++c)
+                local[k * nc + c] = loc(t.slot_nbr[k * nc + c]) | (loc(t.slot_far[k * nc + c]) << 16);
+        halo.insert(halo.end(), refs.begin(), refs.end());
+        if (halo.size() > (size_t)INT32_MAX) return;
+        ptr[tile + 1] = (int32_t)halo.size();
+    }
+    t.halo_ptr.swap(ptr);
+    t.halo.swap(halo);
+    t.slot_local.swap(local);
+    t.max_halo = max_halo;
+}
+
 }  // namespace
 
 fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
@@ -402,6 +444,7 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     }
     t.uniform_degree = (min_degree == t.max_degree);
     build_slots(t, cs, opp);
+    build_tiles(t);
     return FL_OK;
 }
 

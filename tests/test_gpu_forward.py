@@ -235,9 +235,11 @@ def test_scaled_steps_with_unit_scale_equal_plain_steps():
 @pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
 @pytest.mark.parametrize("areas", [False, True])
 def test_slot_rate_table_gives_the_same_bits(areas, scheme, S):
-    """Multi-step calls read the signed face rates E a_f u_f from a cell-slot table built once
-    per call; single steps and FL_OPT_SLOT_VELOCITY = 0 gather u through the face index.  Both
-    must give the same bits, with uniform or per-face areas and volumes, and match the oracle."""
+    """Multi-step calls read the signed face rates E a_f u_f from per-call slot tables, staging
+    each 256-cell tile's theta and halo in LDS where it fits (FL_OPT_LDS_STAGE; here S <= 3 on
+    this 2197-cell mesh with ragged last tile) and reading 16-byte slot records otherwise; single
+    steps and FL_OPT_SLOT_VELOCITY = 0 gather u through the face index.  All must give the same
+    bits, with uniform or per-face areas and volumes, and match the oracle."""
     import dataclasses
 
     m = W.renumber(W.periodic_box(13, 3), seed=8)  # 2197 cells: ragged last block
@@ -255,20 +257,25 @@ def test_slot_rate_table_gives_the_same_bits(areas, scheme, S):
     ud = dev(to_mesh_faces(u, fp))
     t0 = dev(to_mesh_cells(th, cp))
     steps = 9
+    assert mesh.info.tile_cells == 256 and mesh.info.max_halo > 0
     try:
         runs = {}
-        for opt in (1, 0):
+        for opt, lds in ((1, 1), (1, 0), (0, 1)):
             FL.set_option("slot_velocity", opt)
+            FL.set_option("lds_stage", lds)
             t = t0.clone()
             FL.rk_steps(mesh, "vanleer", scheme, dt, t, ud, steps)
-            runs[opt] = t
+            runs[opt, lds] = t
         one = t0.clone()
         for _ in range(steps):
             FL.rk_steps(mesh, "vanleer", scheme, dt, one, ud, 1)
     finally:
         FL.set_option("slot_velocity", 1)
-    assert torch.equal(runs[1], runs[0])
-    assert torch.equal(runs[1], one)
+        FL.set_option("lds_stage", 1)
+    assert torch.equal(runs[1, 1], runs[1, 0])
+    assert torch.equal(runs[1, 1], runs[0, 1])
+    assert torch.equal(runs[1, 1], one)
+    runs = {1: runs[1, 1]}
     want = O.OracleMesh.from_arrays(m).run("vanleer", scheme, dt, th, u, steps)
     assert nrel(host(runs[1])[cp], want) <= RUN_TOL
 
