@@ -38,7 +38,7 @@ def log(*a):
 
 
 TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "fused_stage_kernel_box256_traffic.txt")
+                               "fused_stage_lds_kernel_box256_traffic.txt")
 KERNEL_SOURCES = ["fl_device.h", "fl_kernels.hip"]
 
 

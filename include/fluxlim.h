@@ -286,7 +286,9 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     (fl_mesh_info_t.tile_cells > 0) and with (tile_cells + max_halo) * S * 8
  *                     bytes of LDS per tile at most 64 KiB, stage each tile's theta and its halo
  *                     in LDS and read the per-call rates E a_f u_f (8 bytes per slot) instead of
- *                     the 16-byte records; 0: the records.  Results are bit-identical.
+ *                     the 16-byte records; the adjoint stages (fl_convect_adjoint,
+ *                     fl_rk_step_adjoint) likewise stage theta and lambda, where twice that
+ *                     fits; 0: the records and global gathers.  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3 };

@@ -98,7 +98,6 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // and, where the mesh has tile tables and the tile fits in LDS, run the LDS-staged stage
 // (FL_OPT_LDS_STAGE).
 int g_slot_velocity = 1;
-int g_lds_stage = 1;
 
 // How the stages of one call read the face velocities: gathered through the face index
 // (PLAN_GATHER), from per-call slot records (PLAN_RECORDS), or from per-call rates with the
@@ -160,7 +159,7 @@ hipError_t prepare_rates(const fl_mesh *m, const double *u, int S, int64_t n_ste
     *pl = Plan();
     if (m->path != FL_PATH_FUSED || !g_slot_velocity || n_steps < 2) return hipSuccess;
     const size_t lds = lds_stage_bytes(m, S);
-    if (g_lds_stage && lds > 0 && lds <= kMaxStageLds) {
+    if (lds > 0 && lds <= kMaxStageLds) {
         hipError_t e = launch_slot_rates(m, u, static_cast<double *>(w.vs), st);
         if (e == hipSuccess) *pl = Plan{PLAN_LDS, w.vs};
         return e;
@@ -202,7 +201,7 @@ fl_status fl_set_option(int option, int value) {
         return FL_OK;
     }
     if (option == FL_OPT_LDS_STAGE && (value == 0 || value == 1)) {
-        g_lds_stage = value;
+        set_lds_stage(value);
         return FL_OK;
     }
     return fail(FL_E_INVALID, "unknown option or value");

@@ -109,39 +109,38 @@ __device__ __forceinline__ void load(const double *__restrict__ a, int64_t c, do
     for (int s = 0; s < S; ++s) v[s] = a[c * S + s];
 }
 
+template <int S>
+__device__ __forceinline__ void load_s(const double *src, int64_t i, int stride, double *v) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s] = src[i * stride + s];
+}
+
 // mode: ADJ_APPLY    theta_bar[x] += J^T lam, u_bar += (dL/du)^T lam            (scale 1)
 //       ADJ_EULER    out[x] = lam[x] + dt J^T lam                               (b = 1)
 //       ADJ_LAST     acc[x] = a lam[x];  out[x] = b (lam[x] + dt J^T lam)
 //       ADJ_MID      acc[x] += a lam[x]; out[x] = b (lam[x] + dt J^T lam)
 //       ADJ_FIRST    out[x] = acc[x] + b (lam[x] + dt J^T lam)
 // and u_bar += scale (dL/du)^T lam with scale = b dt (1 for ADJ_APPLY).
-// rec[k][x] = {face of slot k | bit 31 if x owns it, face of the neighbour n_k opposite to it |
-// bit 31 if n_k owns that one, n_k, far-upwind cell on n_k's side}: one 16-byte load per slot
-// (the kernel is bound by the address processing of its loads, so fewer, wider loads pay).
+//
+// One cell x.  Slot k: face fw[k] (bit 31: x owns it), the face rw[k] of the neighbour opposite
+// to it (bit 31: the neighbour owns that one), the neighbour and the far-upwind cell on its side
+// with global indices nbg/gfg (volumes) and source indices nbi/gfi.  theta and lambda of a cell
+// with source index i are tsrc[i * stride + s] and lsrc[i * stride + s]: the global arrays
+// (stride S, source index = global index) or a tile's LDS copy (interleaved, stride 2S).
 template <int S, int P, int LIM>
-__global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
-    int64_t nc, const int4 *__restrict__ rec, const double *__restrict__ u, const double *__restrict__ area, double area0,
-    const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
-    const double *__restrict__ lam, double a, double b, double dt, int mode,
-    double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
+__device__ __forceinline__ void adj_cell(
+    int64_t nc, int64_t x, int64_t xi, const uint32_t *fw, const uint32_t *rw,
+    const int64_t *nbg, const int64_t *gfg, const int64_t *nbi, const int64_t *gfi,
+    const double *tsrc, const double *lsrc, int stride, const double *__restrict__ u,
+    const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
+    double a, double b, double dt, int mode, double *__restrict__ out,
+    double *__restrict__ acc, double *__restrict__ ubar) {
     constexpr int K = 2 * P;
-    const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (x >= nc) return;
-    uint32_t fw[K], rw[K];
-    int64_t nb[K], gf[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int4 r = rec[(int64_t)k * nc + x];
-        fw[k] = (uint32_t)r.x;
-        rw[k] = (uint32_t)r.y;
-        nb[k] = r.z;
-        gf[k] = r.w;
-    }
     double tx[S], lx[S], tn[K][S];
-    load<S>(th, x, tx);
-    load<S>(lam, x, lx);
+    load_s<S>(tsrc, xi, stride, tx);
+    load_s<S>(lsrc, xi, stride, lx);
 #pragma unroll
-    for (int k = 0; k < K; ++k) load<S>(th, nb[k], tn[k]);
+    for (int k = 0; k < K; ++k) load_s<S>(tsrc, nbi[k], stride, tn[k]);
     // lambda / V appears in every face term: multiply by reciprocal volumes
     const double ivx = vol ? 1.0 / vol[x] : ivol0;
     const double scale = (mode == ADJ_APPLY) ? 1.0 : b * dt;
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
 #pragma unroll
     for (int s = 0; s < S; ++s) jt[s] = 0.0;
     // Face velocities and the u_bar entries of the faces this cell owns are requested up front;
-    // the per-slot theta / lambda gathers stay next to their use (hoisting them as well raised
+    // the per-slot theta / lambda reads stay next to their use (hoisting them as well raised
     // register use and measured slower at 128^3).  u_bar is read once and written once per face
     // (the slot faces are distinct, so the loads need not wait for earlier slots' stores).
     double ufk[K], urk[K], ubk[K];
@@ -162,14 +161,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t f = fw[k] & 0x7fffffffu, fr = rw[k] & 0x7fffffffu;
-        const int64_t n = nb[k], g = gf[k];
         const double uf = ufk[k], ur = urk[k];
         const double af = area ? area[f] : area0, ar = area ? area[fr] : area0;
-        const double ivn = vol ? 1.0 / vol[n] : ivol0, ivg = vol ? 1.0 / vol[g] : ivol0;
+        const double ivn = vol ? 1.0 / vol[nbg[k]] : ivol0, ivg = vol ? 1.0 / vol[gfg[k]] : ivol0;
         double ln[S], lg[S], tg[S];
-        load<S>(lam, n, ln);
-        load<S>(lam, g, lg);
-        load<S>(th, g, tg);
+        load_s<S>(lsrc, nbi[k], stride, ln);
+        load_s<S>(lsrc, gfi[k], stride, lg);
+        load_s<S>(tsrc, gfi[k], stride, tg);
         // face f between x and n
         const bool x_own = (fw[k] >> 31) != 0;
         const bool x_up = ((uf > 0.0) == x_own);
@@ -225,6 +223,90 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     }
 }
 
+// rec[k][x] = {face of slot k | bit 31 if x owns it, face of the neighbour n_k opposite to it |
+// bit 31 if n_k owns that one, n_k, far-upwind cell on n_k's side}: one 16-byte load per slot.
+template <int P>
+__device__ __forceinline__ void read_rec(int64_t nc, int64_t x, const int4 *__restrict__ rec,
+                                         uint32_t *fw, uint32_t *rw, int64_t *nb, int64_t *gf) {
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        const int4 r = rec[(int64_t)k * nc + x];
+        fw[k] = (uint32_t)r.x;
+        rw[k] = (uint32_t)r.y;
+        nb[k] = r.z;
+        gf[k] = r.w;
+    }
+}
+
+// One thread per cell, theta and lambda gathered from global memory.
+template <int S, int P, int LIM>
+__global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
+    int64_t nc, const int4 *__restrict__ rec, const double *__restrict__ u,
+    const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
+    const double *__restrict__ th, const double *__restrict__ lam, double a, double b, double dt,
+    int mode, double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
+    constexpr int K = 2 * P;
+    const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (x >= nc) return;
+    uint32_t fw[K], rw[K];
+    int64_t nb[K], gf[K];
+    read_rec<P>(nc, x, rec, fw, rw, nb, gf);
+    adj_cell<S, P, LIM>(nc, x, x, fw, rw, nb, gf, nb, gf, th, lam, S, u, area, area0, vol, ivol0,
+                        a, b, dt, mode, out, acc, ubar);
+}
+
+// One workgroup per tile of kTileCells cells: theta and lambda of the tile and of its halo are
+// staged in LDS (interleaved per cell, each read from global memory once per tile), then every
+// cell reads them there through the 16-bit local slot indices of the forward's tile tables.
+// Dynamic LDS of (kTileCells + max halo) * 2 S doubles.  Same arithmetic as
+// adjoint_stage_kernel, so the results are bit-identical.
+template <int S, int P, int LIM>
+__global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
+    int64_t nc, const int4 *__restrict__ rec, const int32_t *__restrict__ halo_ptr,
+    const int32_t *__restrict__ halo, const uint32_t *__restrict__ slot_local,
+    const double *__restrict__ u, const double *__restrict__ area, double area0,
+    const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
+    const double *__restrict__ lam, double a, double b, double dt, int mode,
+    double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
+    extern __shared__ double lds[];
+    constexpr int K = 2 * P;
+    const int64_t tile = blockIdx.x;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t left = nc - c0;
+    const int nt = left < kTileCells ? (int)left : kTileCells;
+    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < nt; i += kTileCells) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            lds[i * 2 * S + s] = th[(c0 + i) * S + s];
+            lds[i * 2 * S + S + s] = lam[(c0 + i) * S + s];
+        }
+    }
+    for (int i = tid; i < nh; i += kTileCells) {
+        const int64_t g = halo[h0 + i];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            lds[(kTileCells + i) * 2 * S + s] = th[g * S + s];
+            lds[(kTileCells + i) * 2 * S + S + s] = lam[g * S + s];
+        }
+    }
+    __syncthreads();
+    if (tid >= nt) return;
+    const int64_t x = c0 + tid;
+    uint32_t fw[K], rw[K];
+    int64_t nb[K], gf[K], nl[K], gl[K];
+    read_rec<P>(nc, x, rec, fw, rw, nb, gf);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t l = slot_local[(int64_t)k * nc + x];
+        nl[k] = l & 0xffffu;
+        gl[k] = l >> 16;
+    }
+    adj_cell<S, P, LIM>(nc, x, tid, fw, rw, nb, gf, nl, gl, lds, lds + S, 2 * S, u, area, area0,
+                        vol, ivol0, a, b, dt, mode, out, acc, ubar);
+}
+
 }  // namespace adev
 
 namespace {
@@ -232,10 +314,19 @@ template <int S, int P, int LIM>
 hipError_t launch3(const fl_mesh *m, const double *u, const double *th, const double *lam,
                    double a, double b, double dt, int mode, double *out, double *acc,
                    double *ubar, hipStream_t st) {
+    const size_t lds = adjoint_lds_bytes(m, S);
+    if (lds > 0 && lds <= kMaxStageLds) {
+        const unsigned tiles = (unsigned)((m->h.nc + kTileCells - 1) / kTileCells);
+        adev::adjoint_stage_lds_kernel<S, P, LIM><<<tiles, adev::kBlock, lds, st>>>(
+            m->h.nc, reinterpret_cast<const int4 *>(m->d_adj_rec), m->d_halo_ptr, m->d_halo,
+            m->d_slot_local, u, m->d_area, m->h.area0, m->d_vol, 1.0 / m->h.vol0, th, lam, a, b,
+            dt, mode, out, acc, ubar);
+        return hipGetLastError();
+    }
     const unsigned nb = (unsigned)((m->h.nc + adev::kBlock - 1) / adev::kBlock);
     adev::adjoint_stage_kernel<S, P, LIM><<<nb, adev::kBlock, 0, st>>>(
-        m->h.nc, reinterpret_cast<const int4 *>(m->d_adj_rec), u, m->d_area, m->h.area0, m->d_vol,
-        1.0 / m->h.vol0, th, lam, a, b, dt, mode, out, acc, ubar);
+        m->h.nc, reinterpret_cast<const int4 *>(m->d_adj_rec), u, m->d_area, m->h.area0,
+        m->d_vol, 1.0 / m->h.vol0, th, lam, a, b, dt, mode, out, acc, ubar);
     return hipGetLastError();
 }
 

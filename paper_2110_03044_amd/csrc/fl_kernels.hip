@@ -350,10 +350,15 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
     return hipGetLastError();
 }
 
+int g_lds_stage = 1;
+void set_lds_stage(int on) { g_lds_stage = on; }
+
 size_t lds_stage_bytes(const fl_mesh *m, int S) {
-    if (m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
+    if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
     return (size_t)(kTileCells + m->h.max_halo) * S * sizeof(double);
 }
+
+size_t adjoint_lds_bytes(const fl_mesh *m, int S) { return 2 * lds_stage_bytes(m, S); }
 
 hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);

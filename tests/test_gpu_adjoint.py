@@ -247,3 +247,37 @@ def test_multi_step_store_equals_single_step_stores(scheme, S):
     c = mesh.cells_to_mesh(dev(th))
     FL.rk_steps(mesh, "superbee", scheme, wl.dt, c, u, steps)
     assert torch.equal(c, b)
+
+
+@pytest.mark.parametrize("S", [1, 3])
+@pytest.mark.parametrize("lim", ["vanalbada", "superbee"])
+def test_lds_staged_adjoint_gives_the_same_bits(lim, S):
+    """With tile tables, the reverse stages stage theta and lambda of each tile and its halo in
+    LDS (FL_OPT_LDS_STAGE); the results must equal the global-gather kernel's bit for bit, for
+    the operator adjoint and every mode of the reverse SSP-RK3 / Euler steps.  2197 cells: ragged
+    last tile."""
+    wl, th, rng = noisy_box(13, seed=21)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    assert mesh.info.tile_cells == 256
+    th = np.stack([th + 0.1 * s for s in range(S)], axis=1) if S > 1 else th
+    t = mesh.cells_to_mesh(dev(th))
+    u = mesh.faces_to_mesh(dev(wl.u))
+    lam0 = mesh.cells_to_mesh(dev(rng.standard_normal(th.shape)))
+    res = {}
+    try:
+        for lds in (1, 0):
+            FL.set_option("lds_stage", lds)
+            tb, ub = FL.convect_adjoint(mesh, lim, t, u, lam0)
+            outs = [tb, ub]
+            for scheme in ("ssprk3", "euler"):
+                st = FL.stage_buffer(mesh, scheme, S, 1)
+                FL.rk_step_store(mesh, lim, scheme, wl.dt, t.clone(), u, st[0])
+                lam = lam0.clone()
+                ubar = torch.zeros_like(u)
+                FL.rk_step_adjoint(mesh, lim, scheme, wl.dt, st[0], u, lam, ubar)
+                outs += [lam, ubar]
+            res[lds] = outs
+    finally:
+        FL.set_option("lds_stage", 1)
+    for x, y in zip(res[1], res[0]):
+        assert torch.equal(x, y)
