@@ -14,9 +14,13 @@
  * from own into nbr (E_{C->F}[f][nbr] = +1, E_{C->F}[f][own] = -1).  u_f is the normal
  * velocity along that normal.  The velocity sign matrix Q(u_f) takes +1 where u_f > 0 and -1
  * otherwise (Table 1, signxty), so C = own where u_f > 0 and C = nbr where u_f <= 0.  The
- * far-upwind difference d_U = theta_C - theta_U uses the cell U across the face of C opposite
- * to f, found once at mesh creation by projecting the face normals (the upstream adjacency
- * A^U_FF of Section 3.1 with the velocity sign applied to the projected difference).
+ * upstream difference d_U = sum_j w_j (theta_C - theta_j) runs over the other faces j of C with
+ * weights w_j = Q_f (n_f . t_j), t_j the normal of j oriented into C (the upstream adjacency
+ * A^U_FF of Section 3.1 through the normal matrices: the rows of S_{C->F} and T_{C->F}), found
+ * once at mesh creation.  On hexahedra, quadrilaterals and lines one face has weight 1 and the
+ * rest 0, so d_U = theta_C - theta_U with U the cell across the face of C opposite to f; other
+ * cells (triangles, tetrahedra, skewed cells) keep the list of weights and run on the face/cell
+ * path (no adjoint, no batching for them).
  *
  * Conventions for every entry point:
  *   - all floating point is IEEE binary64 (double);
@@ -48,8 +52,8 @@ typedef int32_t fl_status;
 #define FL_E_INVALID -1     /* bad argument: null pointer, size, enum, alignment            */
 #define FL_E_TOPOLOGY -2    /* incidence violates the mesh model (index range, own == nbr,
                                two faces joining the same two cells, far-upwind == downwind) */
-#define FL_E_UNSUPPORTED -3 /* valid but outside this library: boundary faces (nbr = -1),
-                               cells whose upstream difference needs more than one face       */
+#define FL_E_UNSUPPORTED -3 /* valid but outside this library: boundary faces (nbr = -1);
+                               the adjoint and batching on cells without opposite face pairs */
 #define FL_E_NOMEM -4       /* host or device allocation failed                              */
 #define FL_E_HIP -5         /* a HIP runtime call failed (message in fl_last_error)          */
 #define FL_E_NODEVICE -6    /* compute call on a host-only mesh (device = -1)                */
@@ -102,6 +106,9 @@ typedef struct fl_mesh_info_t {
     int32_t tile_cells;     /* cells per LDS-staged tile (fused path), 0 if no tile tables   */
     int32_t max_halo;       /* largest tile halo (cells outside a tile that it reads), -1   */
     int64_t halo_total;     /* halo entries summed over the tiles                            */
+    int32_t general;        /* 1: some face side projects on several faces or with a weight */
+                            /* other than 1 (triangles, tetrahedra, skewed cells)            */
+    int32_t max_side;       /* most projected faces on one face side                         */
 } fl_mesh_info_t;
 
 /* Checks an incidence against the mesh model without a GPU (Section 2).  face_cells: host
@@ -110,9 +117,10 @@ typedef struct fl_mesh_info_t {
 fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                            const double *face_normal);
 
-/* Builds the mesh tables (far-upwind cell per face side, cell -> face lists, and where every
- * cell's faces form opposite pairs, the per-cell slot tables of the fused kernel) and copies
- * them to `device`.  Inputs are host arrays, read only during the call:
+/* Builds the mesh tables (far-upwind cell per face side, or its list of projected faces and
+ * weights on general cells, cell -> face lists, and where every cell's faces form opposite
+ * pairs, the per-cell slot tables and tile halos of the fused kernels) and copies them to
+ * `device`.  Inputs are host arrays, read only during the call:
  *   face_cells  int32 [n_faces][2] (own, nbr), 0 <= index < n_cells, own != nbr;
  *   face_normal double [n_faces][3], unit, own -> nbr (1-D and 2-D meshes pad with 0);
  *   face_area   double [n_faces] or NULL (= 1);   cell_volume double [n_cells] or NULL (= 1).
@@ -131,7 +139,8 @@ fl_status fl_mesh_info(const fl_mesh *mesh, fl_mesh_info_t *info);
 fl_status fl_mesh_permutation(const fl_mesh *mesh, int32_t *cell_perm, int32_t *face_perm);
 
 /* Host copies of the tables, in mesh order (any pointer may be NULL):
- *   face_far int32 [n_faces][2]: far-upwind cell when C = own, and when C = nbr;
+ *   face_far int32 [n_faces][2]: far-upwind cell when C = own, and when C = nbr (-1 on meshes
+ *            of general cells: see fl_mesh_info_t.general);
  *   cf_ptr   int32 [n_cells + 1], cf_idx int32 [cf_ptr[n_cells]]: faces of each cell in
  *            ascending face order, encoded f for faces whose nbr is the cell and ~f (-f-1)
  *            for faces whose own is the cell. */
@@ -208,8 +217,9 @@ fl_status fl_rk_steps_store(const fl_mesh *mesh, int limiter, int scheme, double
 
 /* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
  * with one launch per Runge-Kutta stage for all of them (one fused cell-centric kernel over a
- * work table of (problem, cell tile) entries).  Every mesh must support the fused path and live
- * on `device`; meshes may be shared between problems.  theta[i] / u_f[i] are device pointers the
+ * work table of (problem, cell tile) entries).  Every mesh must live on `device` (else
+ * FL_E_INVALID) and support the fused path (faces in opposite pairs, else FL_E_UNSUPPORTED);
+ * meshes may be shared between problems.  theta[i] / u_f[i] are device pointers the
  * batch keeps (not owned) until fl_batch_destroy.  tile_cells = 0 picks the tile size by timing
  * candidates on the first fl_batch_step (autotuning); a positive value fixes it. */
 fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter,

@@ -35,7 +35,8 @@ class MeshInfo(ctypes.Structure):
                 ("reordered", ctypes.c_int32), ("uniform_area", ctypes.c_int32),
                 ("uniform_volume", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("tile_cells", ctypes.c_int32), ("max_halo", ctypes.c_int32),
-                ("halo_total", ctypes.c_int64)]
+                ("halo_total", ctypes.c_int64), ("general", ctypes.c_int32),
+                ("max_side", ctypes.c_int32)]
 
 
 class AlgebraicInfo(ctypes.Structure):

@@ -66,7 +66,8 @@ fl_status upload(T **dst, const T *src, size_t n, int64_t &bytes, const char *wh
 void free_device(fl_mesh *m) {
     void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
-                    m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local};
+                    m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local, m->d_side_ptr,
+                    m->d_side_cell, m->d_side_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
@@ -75,6 +76,8 @@ void free_device(fl_mesh *m) {
     m->d_adj_rec = nullptr;
     m->d_halo_ptr = m->d_halo = nullptr;
     m->d_slot_local = nullptr;
+    m->d_side_ptr = m->d_side_cell = nullptr;
+    m->d_side_w = nullptr;
     m->d_area = m->d_vol = nullptr;
     m->d_cell_perm = m->d_face_perm = nullptr;
 }
@@ -265,6 +268,11 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
             }
             int64_t &B = m->device_bytes;
             st = upload(&m->d_fc4, fc4.data(), fc4.size(), B, "face records");
+            if (st == FL_OK && h.general) {
+                st = upload(&m->d_side_ptr, h.side_ptr.data(), h.side_ptr.size(), B, "side pointers");
+                if (st == FL_OK) st = upload(&m->d_side_cell, h.side_cell.data(), h.side_cell.size(), B, "side cells");
+                if (st == FL_OK) st = upload(&m->d_side_w, h.side_w.data(), h.side_w.size(), B, "side weights");
+            }
             if (st == FL_OK && !h.uniform_degree)
                 st = upload(&m->d_cf_ptr, h.cf_ptr.data(), h.cf_ptr.size(), B, "cell pointers");
             if (st == FL_OK) st = upload(&m->d_cf_idx, h.cf_idx.data(), h.cf_idx.size(), B, "cell faces");
@@ -342,6 +350,11 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
     info->tile_cells = m->h.max_halo >= 0 ? kTileCells : 0;
     info->max_halo = m->h.max_halo;
     info->halo_total = (int64_t)m->h.halo.size();
+    info->general = m->h.general ? 1 : 0;
+    int32_t ms = 0;
+    for (size_t i = 0; i + 1 < m->h.side_ptr.size(); ++i)
+        ms = std::max(ms, m->h.side_ptr[i + 1] - m->h.side_ptr[i]);
+    info->max_side = m->h.general ? ms : 1;
     return FL_OK;
 }
 

@@ -244,9 +244,14 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
     Guard g(device);
     for (int i = 0; i < n; ++i) {
         const fl_mesh *m = meshes[i];
-        if (!m || m->device != device || m->path != FL_PATH_FUSED || m->h.pairs < 1) {
+        if (!m || m->device != device) {
             destroy(b);
-            return fail(FL_E_INVALID, "every mesh must be a fused-path mesh on the batch's device");
+            return fail(FL_E_INVALID, "every mesh must live on the batch's device");
+        }
+        if (m->path != FL_PATH_FUSED || m->h.pairs < 1) {
+            destroy(b);
+            return fail(FL_E_UNSUPPORTED,
+                        "batched problems need fused-path meshes (faces in opposite pairs)");
         }
         if (limiter[i] < 0 || limiter[i] >= FL_NUM_LIMITERS || n_scalars[i] < 1 ||
             n_scalars[i] > FL_MAX_SCALARS || !theta[i] || !u_f[i] || !(dt[i] == dt[i])) {

@@ -54,6 +54,13 @@ __device__ __forceinline__ double face_value(int lim, double tC, double tD, doub
     return tC + 0.5 * psi(lim, r) * du;
 }
 
+// The same from the differences themselves, for cells whose upstream difference projects on
+// several faces: d_U = sum_j w_j (theta_C - theta_j), d_u = theta_D - theta_C.
+__device__ __forceinline__ double face_value_d(int lim, double tC, double du, double dU) {
+    if (lim == FL_UPWIND || du == 0.0) return tC;
+    return tC + 0.5 * psi(lim, dU / du) * du;
+}
+
 // Scalars S0 .. S0+CS-1 of cell c (CS <= 2 keeps the gathered values in registers for any S).
 // theta_s is read from src at index cs (this cell) and nb[k], gf[k] (its slots' cells): src is
 // theta_s itself with global indices, or a tile's LDS copy with local indices; tn and out are

@@ -22,7 +22,13 @@ struct HostTables {
     std::vector<double> vol;        // [C] (empty if uniform)
     double area0 = 1.0, vol0 = 1.0; // the uniform values
     bool uni_area = true, uni_vol = true;
-    std::vector<int32_t> far;       // [F][2] far-upwind cell for C = own, C = nbr
+    std::vector<int32_t> far;       // [F][2] far-upwind cell for C = own, C = nbr (-1: general)
+    // General cells (general = true): per face side (2f + side), the far cells and weights of
+    // the upstream difference d_U = sum_j w_j (theta_C - theta_j), CSR over 2F sides.
+    bool general = false;
+    std::vector<int32_t> side_ptr;   // [2F + 1]
+    std::vector<int32_t> side_cell;
+    std::vector<double> side_w;
     std::vector<int32_t> cf_ptr;    // [C+1]
     std::vector<int32_t> cf_idx;    // signed: f (cell is nbr) or ~f (cell is own), ascending f
     int32_t max_degree = 0;
@@ -70,6 +76,9 @@ struct fl_mesh {
     uint32_t *d_slot_face = nullptr;
     int32_t *d_slot_nbr = nullptr;
     int32_t *d_slot_far = nullptr;
+    int32_t *d_side_ptr = nullptr; // general cells: per-side far cells and weights
+    int32_t *d_side_cell = nullptr;
+    double *d_side_w = nullptr;
     int32_t *d_halo_ptr = nullptr; // LDS-staged stage: tile halo lists and local slot indices
     int32_t *d_halo = nullptr;
     uint32_t *d_slot_local = nullptr;

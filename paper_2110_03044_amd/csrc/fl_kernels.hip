@@ -74,6 +74,43 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(
     for (int k = 0; k < S; ++k) phi[f * S + k] = au * face_value(lim, tC[k], tD[k], tU[k]);
 }
 
+// General cells: the upstream difference of the upwind side sums its projected faces
+// (side lists: far cells and weights, built at mesh creation).
+template <int S>
+__global__ __launch_bounds__(kBlock) void face_flux_general_kernel(
+    int64_t nf, const int4 *__restrict__ fc4, const int32_t *__restrict__ side_ptr,
+    const int32_t *__restrict__ side_cell, const double *__restrict__ side_w,
+    const double *__restrict__ u, const double *__restrict__ theta,
+    const double *__restrict__ area, double area0, int lim, double *__restrict__ phi, double us) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= nf) return;
+    const int4 e = fc4[f];
+    const double uf = u[f] * us;
+    const bool pos = uf > 0.0;
+    const int64_t C = pos ? e.x : e.y;
+    const int64_t D = pos ? e.y : e.x;
+    const double au = (area ? area[f] : area0) * uf;
+    double tC[S], tD[S], dU[S];
+    load_cell<S>(theta, C, tC);
+    load_cell<S>(theta, D, tD);
+    if (lim == FL_UPWIND) {
+#pragma unroll
+        for (int k = 0; k < S; ++k) phi[f * S + k] = au * tC[k];
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) dU[k] = 0.0;
+    const int64_t side = 2 * f + (pos ? 0 : 1);
+    for (int64_t p = side_ptr[side]; p < side_ptr[side + 1]; ++p) {
+        const int64_t j = side_cell[p];
+        const double w = side_w[p];
+#pragma unroll
+        for (int k = 0; k < S; ++k) dU[k] += w * (tC[k] - theta[j * S + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) phi[f * S + k] = au * face_value_d(lim, tC[k], tD[k] - tC[k], dU[k]);
+}
+
 // out = rhs (MODE_RHS), theta_s + dt rhs (MODE_EULER) or a theta_n + b (theta_s + dt rhs).
 template <int S>
 __device__ __forceinline__ void finish_cell(int64_t c, const double *acc, double V,
@@ -225,7 +262,11 @@ __global__ __launch_bounds__(kBlock) void permute_kernel(int64_t n, int S,
     }
 }
 
+// (C, D, U) per face; U = -2 where the upwind side projects on more than one face (general
+// cells, side lists given).
 __global__ __launch_bounds__(kBlock) void select_kernel(int64_t nf, const int4 *__restrict__ fc4,
+                                                        const int32_t *__restrict__ side_ptr,
+                                                        const int32_t *__restrict__ side_cell,
                                                         const double *__restrict__ u,
                                                         int32_t *__restrict__ cdu) {
     const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -234,7 +275,13 @@ __global__ __launch_bounds__(kBlock) void select_kernel(int64_t nf, const int4 *
     const bool pos = u[f] > 0.0;
     cdu[3 * f] = pos ? e.x : e.y;
     cdu[3 * f + 1] = pos ? e.y : e.x;
-    cdu[3 * f + 2] = pos ? e.z : e.w;
+    if (side_ptr) {
+        const int64_t side = 2 * f + (pos ? 0 : 1);
+        const int32_t p0 = side_ptr[side], n = side_ptr[side + 1] - p0;
+        cdu[3 * f + 2] = n == 1 ? side_cell[p0] : -2;
+    } else {
+        cdu[3 * f + 2] = pos ? e.z : e.w;
+    }
 }
 
 }  // namespace dev
@@ -282,6 +329,14 @@ void set_xcd_remap(int value) { g_remap = value; }
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
                             const double *u, double *phi, hipStream_t st, double us) {
     // Blocks beyond the face count exit at once (padding to a multiple of 8 XCDs).
+    if (m->h.general) {
+        const unsigned nb = (unsigned)((m->h.nf + dev::kBlock - 1) / dev::kBlock);
+        FL_DISPATCH_S(S, (dev::face_flux_general_kernel<kS><<<nb, dev::kBlock, 0, st>>>(
+                             m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), m->d_side_ptr,
+                             m->d_side_cell, m->d_side_w, u, theta, m->d_area, m->h.area0, lim,
+                             phi, us)));
+        return hipGetLastError();
+    }
     Grid g = grid_for(m->h.nf, g_remap);
     FL_DISPATCH_S(S, (dev::face_flux_kernel<kS><<<g.blocks, dev::kBlock, 0, st>>>(
                          m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), u, theta, m->d_area,
@@ -402,7 +457,8 @@ hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, co
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nf + dev::kBlock - 1) / dev::kBlock);
     dev::select_kernel<<<nb, dev::kBlock, 0, st>>>(
-        m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), u, cdu);
+        m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), m->h.general ? m->d_side_ptr : nullptr,
+        m->d_side_cell, u, cdu);
     return hipGetLastError();
 }
 

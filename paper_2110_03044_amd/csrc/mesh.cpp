@@ -9,8 +9,10 @@
 //     weight w_j = s (n_f . t_j), t_j the normal of j oriented into C.  This is the upstream
 //     adjacency A^U_FF = (A_FF - Q A^D_FF)/2 of Section 3.1 applied through the normal matrices
 //     (d_U = Q N (I (x) A^U) N^T E theta), precomputed once as the paper precomputes S_{C->F} and
-//     T_{C->F}.  Exactly one face with weight 1 (the rest 0) is supported: hexahedra,
-//     quadrilaterals and lines, in any numbering; d_U is then theta_C - theta_U;
+//     T_{C->F}.  Where every side has exactly one face with weight 1 (hexahedra,
+//     quadrilaterals and lines, in any numbering) d_U is theta_C - theta_U and one far cell per
+//     side is kept; otherwise (triangles, tetrahedra, skewed cells) every side keeps its list of
+//     (far cell, weight) pairs;
 //   * where every cell's faces form opposite pairs, the per-cell slot tables of the fused kernel;
 //   * optionally a renumbering for gather locality (space-filling curve or breadth-first).
 #include <algorithm>
@@ -107,25 +109,32 @@ fl_status check_duplicates(int64_t nc, const int32_t *fc, const Csr &cs) {
     return FL_OK;
 }
 
-// far[2f + side], opp[2f + side]: side 0 is C = own, side 1 is C = nbr.
-fl_status far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
-                     std::vector<int32_t> &far, std::vector<int32_t> &opp) {
+// Weight of face j of cell C for face f with flow sign s: s (n_f . t_j), t_j = n_j oriented into C.
+inline double projection(const int32_t *fc, const double *nrm, int64_t f, int64_t j, int64_t C,
+                         double s) {
+    const double *a = nrm + 3 * f, *b = nrm + 3 * j;
+    const double t = fc[2 * j + 1] == C ? 1.0 : -1.0;
+    return s * (t * (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]));
+}
+
+// far[2f + side], opp[2f + side]: side 0 is C = own, side 1 is C = nbr.  Returns true when every
+// side has exactly one projected face, with weight 1 (hexahedra, quadrilaterals, lines in any
+// numbering: d_U = theta_C - theta_U); otherwise far and opp are left at -1.
+bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
+                std::vector<int32_t> &far, std::vector<int32_t> &opp) {
     far.assign(2 * nf, -1);
     opp.assign(2 * nf, -1);
     for (int64_t f = 0; f < nf; ++f) {
-        const double *nf_ = nrm + 3 * f;
         for (int side = 0; side < 2; ++side) {
-            int64_t C = fc[2 * f + side];
-            double s = side == 0 ? 1.0 : -1.0;
+            const int64_t C = fc[2 * f + side];
+            const double s = side == 0 ? 1.0 : -1.0;
             int count = 0;
             int64_t jj = -1;
             double ww = 0.0;
             for (int64_t p = cs.ptr[C]; p < cs.ptr[C + 1]; ++p) {
-                int64_t j = cs.idx[p];
+                const int64_t j = cs.idx[p];
                 if (j == f) continue;
-                const double *nj = nrm + 3 * j;
-                double t = fc[2 * j + 1] == C ? 1.0 : -1.0;
-                double w = s * t * (nf_[0] * nj[0] + nf_[1] * nj[1] + nf_[2] * nj[2]);
+                const double w = projection(fc, nrm, f, j, C, s);
                 if (std::fabs(w) > kWeightTol) {
                     ++count;
                     jj = j;
@@ -133,17 +142,41 @@ fl_status far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr
                 }
             }
             if (count != 1 || std::fabs(ww - 1.0) > kWeightTol) {
-                std::ostringstream os;
-                os << "face " << f << ", cell " << C << ": the upstream difference needs "
-                   << count << " projected faces (exactly one with weight 1 is supported: "
-                      "hexahedral, quadrilateral or line cells)";
-                return fail(FL_E_UNSUPPORTED, os.str());
+                far.assign(2 * nf, -1);
+                opp.assign(2 * nf, -1);
+                return false;
             }
             far[2 * f + side] = other(fc, jj, C);
             opp[2 * f + side] = (int32_t)jj;
         }
     }
-    return FL_OK;
+    return true;
+}
+
+// General cells: for every face side, the cells beyond the other faces of C with their nonzero
+// weights (the nonzeros of row f of S_{C->F}, T_{C->F} on that side), in C's face order:
+// d_U = sum_j w_j (theta_C - theta_j).
+bool side_lists(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs, HostTables &t) {
+    t.side_ptr.assign(2 * nf + 1, 0);
+    t.side_cell.clear();
+    t.side_w.clear();
+    for (int64_t f = 0; f < nf; ++f)
+        for (int side = 0; side < 2; ++side) {
+            const int64_t C = fc[2 * f + side];
+            const double s = side == 0 ? 1.0 : -1.0;
+            for (int64_t p = cs.ptr[C]; p < cs.ptr[C + 1]; ++p) {
+                const int64_t j = cs.idx[p];
+                if (j == f) continue;
+                const double w = projection(fc, nrm, f, j, C, s);
+                if (w != 0.0) {
+                    t.side_cell.push_back(other(fc, j, C));
+                    t.side_w.push_back(w);
+                }
+            }
+            if (t.side_cell.size() > (size_t)INT32_MAX) return false;
+            t.side_ptr[2 * f + side + 1] = (int32_t)t.side_cell.size();
+        }
+    return true;
 }
 
 // Breadth-first order of the cells (from a pseudo-peripheral start), one component after the
@@ -425,8 +458,9 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     if (!t.uni_vol) t.vol.swap(vol);
 
     std::vector<int32_t> opp;
-    st = far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
-    if (st != FL_OK) return st;
+    t.general = !far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
+    if (t.general && !side_lists(nf, t.fc.data(), t.nrm.data(), cs, t))
+        return fail(FL_E_UNSUPPORTED, "too many projected faces for 32-bit side lists");
 
     t.cf_ptr.resize(nc + 1);
     t.cf_idx.resize(2 * nf);
@@ -443,7 +477,7 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
         }
     }
     t.uniform_degree = (min_degree == t.max_degree);
-    build_slots(t, cs, opp);
+    if (!t.general) build_slots(t, cs, opp);
     build_tiles(t);
     return FL_OK;
 }

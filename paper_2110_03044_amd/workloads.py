@@ -109,6 +109,99 @@ def periodic_box(n: int, dim: int = 3) -> MeshArrays:
     return MeshArrays(face_cells, nrm, area, vol, n=n, dim=dim)
 
 
+def periodic_triangles(n: int) -> MeshArrays:
+    """Periodic square [0,1)^2 cut into n x n squares, each split by its diagonal from (i, j) to
+    (i+1, j+1) into a lower triangle (cell 2 (i + n j)) and an upper one (cell 2 (i + n j) + 1).
+
+    Faces (3 n^2, each block in square order i + n j): horizontal edges (own = the upper triangle
+    below, nbr = the lower triangle above, normal +y), vertical edges (own = the lower triangle
+    to the left, nbr = the upper triangle to the right, normal +x), diagonals (own = lower,
+    nbr = upper, normal (-1, 1)/sqrt(2)).  Face areas are edge lengths, cell volumes h^2 / 2.
+    The faces of a triangle do not come in opposite pairs, and each face side projects on one or
+    two faces with weights +-1/sqrt(2): the general cells of the upstream difference.
+    """
+    if n < 3:
+        raise ValueError("n must be at least 3")
+    C2 = n * n
+    sq = np.arange(C2, dtype=np.int64)
+    i, j = sq % n, sq // n
+    lower = lambda ii, jj: 2 * ((ii % n) + n * (jj % n))
+    upper = lambda ii, jj: 2 * ((ii % n) + n * (jj % n)) + 1
+    own = np.concatenate([upper(i, j - 1), lower(i - 1, j), lower(i, j)]).astype(np.int32)
+    nbr = np.concatenate([lower(i, j), upper(i, j), upper(i, j)]).astype(np.int32)
+    nrm = np.zeros((3 * C2, 3))
+    nrm[:C2, 1] = 1.0
+    nrm[C2:2 * C2, 0] = 1.0
+    r2 = 1.0 / math.sqrt(2.0)
+    nrm[2 * C2:, 0] = -r2
+    nrm[2 * C2:, 1] = r2
+    h = 1.0 / n
+    area = np.concatenate([np.full(2 * C2, h), np.full(C2, h * math.sqrt(2.0))])
+    vol = np.full(2 * C2, 0.5 * h * h)
+    return MeshArrays(np.stack([own, nbr], axis=1), nrm, area, vol, n=n, dim=2)
+
+
+def triangle_centroids(n: int) -> np.ndarray:
+    """Centroids [2 n^2, 2] of periodic_triangles(n)."""
+    sq = np.arange(n * n)
+    i, j = sq % n, sq // n
+    h = 1.0 / n
+    out = np.empty((2 * n * n, 2))
+    out[0::2, 0], out[0::2, 1] = (i + 2.0 / 3.0) * h, (j + 1.0 / 3.0) * h
+    out[1::2, 0], out[1::2, 1] = (i + 1.0 / 3.0) * h, (j + 2.0 / 3.0) * h
+    return out
+
+
+def velocity_stream_triangles(n: int, seed: int = SEED_VELOCITY, kmax: int = 3) -> np.ndarray:
+    """Solenoidal face velocity of periodic_triangles(n): a seeded periodic stream function psi
+    sampled at the vertices (rounded to multiples of 2^-40), the flux through an edge from A to B
+    with normal (t_y, -t_x) is psi(B) - psi(A), and u_f is that flux over the edge length.  The
+    fluxes of every triangle sum to zero exactly; scaled so that max |u_f| is about 1."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="ij")  # X[i, j] = i h
+    psi = np.zeros((n, n))
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(0, kmax + 1):
+            if (kx, ky) == (0, 0):
+                continue
+            a, b = rng.standard_normal(2) / (kx * kx + ky * ky)
+            ph = 2 * np.pi * (kx * X + ky * Y)
+            psi += a * np.cos(ph) + b * np.sin(ph)
+    P = lambda ii, jj: psi[ii % n, jj % n]
+    sq = np.arange(n * n)
+    i, j = sq % n, sq // n
+    q = np.concatenate([P(i, j) - P(i + 1, j), P(i, j + 1) - P(i, j), P(i, j) - P(i + 1, j + 1)])
+    ln = np.concatenate([np.full(2 * n * n, h), np.full(n * n, h * math.sqrt(2.0))])
+    scale = 1.0 / float(np.abs(q / ln).max())
+    psi = np.round(psi * scale * 2.0**40) / 2.0**40
+    q = np.concatenate([P(i, j) - P(i + 1, j), P(i, j + 1) - P(i, j), P(i, j) - P(i + 1, j + 1)])
+    return q / ln
+
+
+def periodic_skewed_box(n: int, shear: float = 0.3) -> MeshArrays:
+    """periodic_box(n, 3)'s incidence on a sheared lattice: cell (i, j, k) spans
+    i a1 + j a2 + k a3 with a1 = (h, 0, 0), a2 = (shear h, h, 0), a3 = (0, shear h, h).  Faces
+    are parallelograms with unit normals a2 x a3, a3 x a1, a1 x a2 (normalised, pointing to the
+    + neighbour), areas |a2 x a3| etc., volumes a1 . (a2 x a3).  Opposite faces still pair up, but
+    neighbouring faces are no longer orthogonal: every face side projects on five faces."""
+    m = periodic_box(n, 3)
+    h = 1.0 / n
+    a = [np.array([h, 0.0, 0.0]), np.array([shear * h, h, 0.0]), np.array([0.0, shear * h, h])]
+    C = n**3
+    nrm = np.empty((3 * C, 3))
+    area = np.empty(3 * C)
+    for d in range(3):
+        cr = np.cross(a[(d + 1) % 3], a[(d + 2) % 3])
+        if cr @ a[d] < 0:
+            cr = -cr
+        nrm[d * C:(d + 1) * C] = cr / np.linalg.norm(cr)
+        area[d * C:(d + 1) * C] = np.linalg.norm(cr)
+    vol = np.full(C, abs(a[0] @ np.cross(a[1], a[2])))
+    return MeshArrays(m.face_cells, nrm, area, vol, n=n, dim=3)
+
+
 def renumber(mesh: MeshArrays, seed: int = SEED_RENUMBER, flip: bool = True) -> MeshArrays:
     """Randomly renumber cells and faces (and flip each face's orientation with probability 1/2).
 

@@ -37,10 +37,16 @@ CASES = [
     ("line9", lambda: W.periodic_box(9, 1)),
     ("quad10r", lambda: W.renumber(W.periodic_box(10, 2), seed=4)),
     ("hex13r", lambda: W.renumber(W.periodic_box(13, 3), seed=5)),
+    ("tri8r", lambda: W.renumber(W.periodic_triangles(8), seed=6)),
+    ("skew5r", lambda: W.renumber(W.periodic_skewed_box(5), seed=7)),
 ]
 
 
 def _fields(m):
+    rng = np.random.default_rng(m.n_cells)
+    if m.n_cells == 2 * m.n * m.n and m.dim == 2:  # triangles
+        th = rng.standard_normal(m.n_cells)
+        return th, m.face_velocity_from_natural(W.velocity_stream_triangles(m.n, seed=2))
     n, dim = m.n, m.dim
     th = m.cell_field_from_natural(W.field_smooth_random(n, dim, 3)) if dim > 1 else \
         W.field_square_gauss_1d(n)

@@ -321,3 +321,84 @@ def test_xcd_launch_orders_give_the_same_bits(remap):
     finally:
         FL.set_option("xcd_remap", 0)
     assert torch.equal(runs[0], runs[1])
+
+
+GENERAL = [
+    ("tri9r", lambda: W.renumber(W.periodic_triangles(9), seed=13)),
+    ("skew6r", lambda: W.renumber(W.periodic_skewed_box(6), seed=14)),
+]
+
+
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("name,make", GENERAL, ids=[c[0] for c in GENERAL])
+def test_general_cells_selection(name, make, reorder):
+    """(C, D, U) per face on general cells: U is the one projected face's far cell, or -2 where
+    the upwind side projects on several faces (the oracle's convention)."""
+    m = make()
+    mesh, cp, fp = mesh_pair(m, reorder=reorder)
+    assert mesh.info.general == 1 and mesh.path == "face"
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(m.n_faces)
+    u[::5] = 0.0
+    got = mesh.debug_select(dev(to_mesh_faces(u, fp)))
+    want = O.OracleMesh.from_arrays(m).select(u)
+    cpm = np.append(cp, [-2, -2])  # maps -2 (and -1) to themselves
+    assert np.array_equal(got[fp], cpm[want])
+
+
+@pytest.mark.parametrize("S", [1, 3, 8])
+@pytest.mark.parametrize("name,make", GENERAL, ids=[c[0] for c in GENERAL])
+def test_general_cells_apply_matches_oracle(name, make, S):
+    m = make()
+    mesh, cp, fp = mesh_pair(m, reorder=True)
+    rng = np.random.default_rng(S + 20)
+    th = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+    th[::3] = np.round(th[::3])
+    u = rng.standard_normal(m.n_faces)
+    om = O.OracleMesh.from_arrays(m)
+    thd, ud = dev(to_mesh_cells(th, cp)), dev(to_mesh_faces(u, fp))
+    for lim in LIMS:
+        want = om.rhs(lim, th, u)
+        got = host(FL.convect_apply(mesh, lim, thd, ud))[cp]
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), lim
+
+
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+@pytest.mark.parametrize("lim", ["minmod", "vanleer", "superbee", "smart"])
+def test_general_cells_runs(lim, scheme):
+    """Triangles with the stream-function velocity and the sheared hexahedral lattice with a
+    uniform velocity, 30 steps, against the oracle; conservation."""
+    n = 16
+    tri = W.renumber(W.periodic_triangles(n), seed=15)
+    xy = W.triangle_centroids(n)
+    th_tri = tri.cell_field_from_natural(
+        np.exp(-((xy[:, 0] - 0.4) ** 2 + (xy[:, 1] - 0.6) ** 2) / 0.02) + (xy[:, 0] > 0.5))
+    u_tri = tri.face_velocity_from_natural(W.velocity_stream_triangles(n, seed=4))
+    sk = W.periodic_skewed_box(8)
+    th_sk = W.field_blob_step(8)
+    u_sk = W.velocity_uniform(sk, (0.6, -0.3, 0.8), 1.0)
+    for m, th, u in ((tri, th_tri, u_tri), (sk, th_sk, u_sk)):
+        dt = W.cfl_dt(m, u, 0.3)
+        mesh, cp, fp = mesh_pair(m, reorder=True)
+        t = dev(to_mesh_cells(th, cp))
+        FL.rk_steps(mesh, lim, scheme, dt, t, dev(to_mesh_faces(u, fp)), 30)
+        want = O.OracleMesh.from_arrays(m).run(lim, scheme, dt, th, u, 30)
+        got = host(t)[cp]
+        assert nrel(got, want) <= RUN_TOL
+        V = m.cell_volume
+        assert abs((V * got).sum() - (V * th).sum()) <= 1e-13 * (V * np.abs(th)).sum()
+
+
+def test_general_cells_without_adjoint_or_batch():
+    from paper_2110_03044_amd import _lib
+
+    m = W.periodic_triangles(6)
+    mesh = FL.Mesh.from_arrays(m, device=0)
+    th = dev(np.ones(m.n_cells))
+    u = dev(W.velocity_stream_triangles(6))
+    with pytest.raises(_lib.FluxLimError) as e:
+        FL.convect_adjoint(mesh, "vanalbada", th, u, th.clone())
+    assert e.value.status == -3
+    with pytest.raises(_lib.FluxLimError) as e:
+        FL.Batch([(mesh, "vanleer", th.clone(), u, 1e-3)])
+    assert e.value.status == -3

@@ -126,10 +126,14 @@ def test_validate_rejections():
     m2 = W.periodic_box(2, 3)
     st, msg = _err(m2.face_cells, m2.face_normal, m2.n_cells)
     assert st == -2 and "both join" in msg
-    # a tilted normal makes the upstream difference need two faces
+    # a tilted normal makes the upstream difference project on several faces: a general mesh,
+    # accepted (face/cell path with per-side weight lists)
     badn = nrm.copy(); badn[0] = [np.sqrt(0.5), np.sqrt(0.5), 0.0]
     st, msg = _err(fc, badn, C)
-    assert st == -3 and "projected faces" in msg
+    assert st == 0
+    mesh = FL.Mesh(fc, badn, n_cells=C, device=-1)
+    assert mesh.info.general == 1 and mesh.info.max_side >= 2 and mesh.path == "face"
+    mesh.close()
 
 
 def test_create_rejects_bad_arguments_and_host_only_compute():

@@ -254,6 +254,11 @@ def _tiny_meshes():
         nat = W.periodic_box(n, d)
         out.append((f"{d}d{n}", nat))
         out.append((f"{d}d{n}r", W.renumber(nat, seed=n + d)))
+    # general cells: triangles (one or two projected faces per side, weights +-1/sqrt 2) and a
+    # sheared hexahedral lattice (five projected faces per side)
+    for name, nat in [("tri5", W.periodic_triangles(5)), ("skew4", W.periodic_skewed_box(4))]:
+        out.append((name, nat))
+        out.append((name + "r", W.renumber(nat, seed=11)))
     return out
 
 
@@ -581,3 +586,39 @@ def test_run_adjoint_matches_finite_difference_of_loss():
         fd = (J(th + eps * v, wl.u + eps * du) - J(th - eps * v, wl.u - eps * du)) / (2 * eps)
         ad = v @ tb + du @ ub
         assert ad == pytest.approx(fd, rel=1e-6)
+
+
+def test_general_cells_conservation_and_free_stream():
+    """On triangles with the exactly solenoidal stream-function velocity: a constant field is
+    steady (d_u = d_U = 0, so theta_f = theta_C and rhs = theta div u = 0 up to rounding), and
+    every run conserves sum V theta."""
+    n = 12
+    m = W.periodic_triangles(n)
+    u = W.velocity_stream_triangles(n, seed=4)
+    om = O.OracleMesh.from_arrays(m)
+    const = np.full(m.n_cells, 2.5)
+    assert np.abs(om.rhs("superbee", const, u)).max() <= 1e-12
+    xy = W.triangle_centroids(n)
+    th = np.exp(-((xy[:, 0] - 0.4) ** 2 + (xy[:, 1] - 0.6) ** 2) / 0.02)
+    dt = W.cfl_dt(m, u, 0.4)
+    out = om.run("vanleer", "ssprk3", dt, th, u, 30)
+    V = m.cell_volume
+    assert abs((V * out).sum() - (V * th).sum()) <= 1e-14 * (V * th).sum()
+    assert out.min() >= -1e-12 and out.max() <= 1.0 + 1e-12  # van Leer keeps the bounds here
+
+
+def test_general_cell_weights_by_hand():
+    """Triangle faces: the horizontal face of the upper triangle below it projects only on that
+    triangle's diagonal, with weight 1/sqrt 2; a diagonal face projects on two faces."""
+    m = W.periodic_triangles(4)
+    om = O.OracleMesh.from_arrays(m)
+    C2 = 16
+    f = 0  # horizontal edge of square (0, 0): own = upper(0, -1) = cell 2*(0 + 4*3) + 1 = 25
+    faces, w = om.side_weights(f, side_nbr=False)
+    nz = [(int(j), float(x)) for j, x in zip(faces, w) if x != 0.0]
+    assert m.face_cells[f, 0] == 25
+    # the diagonal of square (0, 3) is face 2*C2 + 12; t_j points into the upper triangle (its nbr)
+    assert len(nz) == 1 and nz[0][0] == 2 * C2 + 12
+    assert nz[0][1] == pytest.approx(1.0 / np.sqrt(2.0), abs=1e-15)
+    faces, w = om.side_weights(2 * C2 + 5, side_nbr=False)
+    assert sum(1 for x in w if x != 0.0) == 2
