@@ -410,6 +410,7 @@ def main():
         info = mesh.info
         res = dict(mesh=mesh, total_ms=total_ms, per_lim=per_lim, path=mesh.path,
                    K=int(info.max_degree), th=th, u=u, max_halo=int(info.max_halo),
+                   tile_cells=int(info.tile_cells),
                    halo_total=int(info.halo_total))
         return res
 
@@ -459,7 +460,7 @@ def main():
         launches = 3 * n_steps_total
         sv = bool(args.slot_velocity) and args.steps >= 2
         lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
-            (256 + r["max_halo"]) * S * 8 <= 64 * 1024
+            (r["tile_cells"] + r["max_halo"]) * S * 8 <= 64 * 1024
         if lds:
             kname = "fused_stage_lds_kernel"
             bytes_per_step = sum(lds_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
