@@ -231,7 +231,12 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter,
 fl_status fl_batch_step(fl_batch *batch, int n_steps, void *hip_stream);
 /* The same work as separate per-problem launches (no graph), for comparison. */
 fl_status fl_batch_step_unbatched(fl_batch *batch, int n_steps, void *hip_stream);
+/* The tile size in use (0 before the first fl_batch_step autotunes it), and whether the tiles
+ * are staged in LDS: the autotuner also times the LDS-staged kernel (256-cell tiles, each tile's
+ * theta and halo in LDS, the mesh's tile tables; FL_OPT_LDS_STAGE and every mesh's LDS need
+ * permitting); then fl_batch_step_unbatched runs the same staged kernel per problem. */
 fl_status fl_batch_tile(const fl_batch *batch, int *tile_cells);
+fl_status fl_batch_lds(const fl_batch *batch, int *lds_staged);
 fl_status fl_batch_destroy(fl_batch *batch);
 
 /* The paper's algebraic form of the same operator (Algorithms 3 and 4, Section 3.4), kept as a
@@ -293,12 +298,13 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     face index.  Results are bit-identical either way (for time-dependent
  *                     velocity on meshes with face areas, up to the rounding of one product).
  *   FL_OPT_LDS_STAGE  1 (default): those multi-step calls, on meshes with tile tables
- *                     (fl_mesh_info_t.tile_cells > 0) and with (tile_cells + max_halo) * S * 8
- *                     bytes of LDS per tile at most 64 KiB, stage each tile's theta and its halo
- *                     in LDS and read the per-call rates E a_f u_f (8 bytes per slot) instead of
- *                     the 16-byte records; the adjoint stages (fl_convect_adjoint,
- *                     fl_rk_step_adjoint) likewise stage theta and lambda, where twice that
- *                     fits; 0: the records and global gathers.  Results are bit-identical.
+ *                     (fl_mesh_info_t.tile_cells > 0) and with (tile_cells + max_halo) *
+ *                     min(S, 2) * 8 bytes of LDS per tile at most 64 KiB, stage each tile's
+ *                     theta and its halo in LDS (two scalars at a time) and read the per-call
+ *                     rates E a_f u_f (8 bytes per slot) instead of the 16-byte records; the
+ *                     adjoint stages (fl_convect_adjoint, fl_rk_step_adjoint) likewise stage theta
+ *                     and lambda of all S scalars where (tile_cells + max_halo) * 2 S * 8 bytes
+ *                     fit; 0: the records and global gathers.  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3 };

@@ -77,6 +77,7 @@ SIGNATURES = {
     "fl_batch_step": (_S, [_P, _I, _P]),
     "fl_batch_step_unbatched": (_S, [_P, _I, _P]),
     "fl_batch_tile": (_S, [_P, _P]),
+    "fl_batch_lds": (_S, [_P, _P]),
     "fl_batch_destroy": (_S, [_P]),
     "fl_algebraic_create": (_S, [_P, _P]),
     "fl_algebraic_destroy": (_S, [_P]),

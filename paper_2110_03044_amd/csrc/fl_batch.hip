@@ -24,6 +24,8 @@ struct BatchProblem {
     const int32_t *snbr, *sfar;
     const double *u, *area, *vol;
     double *th, *t1, *t2;
+    const int32_t *halo_ptr, *halo;  // tile tables (LDS staging)
+    const uint32_t *slot_local;
 };
 
 struct BatchTile {
@@ -82,6 +84,57 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const BatchProblem 
     }
 }
 
+// One tile of one problem, staged in LDS (tile index = first cell / kTileCells): the
+// single-problem tile routine with the face terms read through the face index.
+template <int S, int P>
+__device__ __forceinline__ void batch_tile(const BatchProblem &pb, int64_t tile, double *lds,
+                                           const double *ts, double a, double b, int mode,
+                                           double *out) {
+    dev::fused_tile<S, P, false>(pb.nc, tile, lds, pb.halo_ptr, pb.halo, pb.slot_local, nullptr,
+                          pb.sface, pb.u, pb.area, pb.area0, pb.vol, pb.vol0, ts, pb.th, a, b,
+                          pb.dt, mode, pb.lim, out, 1.0);
+}
+
+// As batch_stage_kernel, with every tile's theta and halo staged in LDS (tiles of kTileCells
+// cells, one thread per cell).  The barrier at the top of each tile keeps the previous tile's
+// LDS reads ahead of the next staging; every thread of a workgroup walks the same tiles and takes
+// the same (P, S) branch, so all reach every barrier.
+__global__ __launch_bounds__(kBlock) void batch_stage_lds_kernel(
+    const BatchProblem *__restrict__ probs, const BatchTile *__restrict__ tiles, int64_t ntiles,
+    int stage) {
+    extern __shared__ double lds[];
+    const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        __syncthreads();
+        const BatchTile T = tiles[t];
+        const BatchProblem &pb = probs[T.prob];
+        const double *ts = stage == 0 ? pb.th : stage == 1 ? pb.t1 : pb.t2;
+        double *out = stage == 0 ? pb.t1 : stage == 1 ? pb.t2 : pb.th;
+        const int mode = stage == 0 ? MODE_EULER : MODE_RK;
+        const int64_t tile = T.c0 / kTileCells;
+#define FL_BTILE(SS, PP) batch_tile<SS, PP>(pb, tile, lds, ts, A[stage], B[stage], mode, out)
+#define FL_BTILE_S(PP)                     \
+    switch (pb.S) {                        \
+        case 1: FL_BTILE(1, PP); break;    \
+        case 2: FL_BTILE(2, PP); break;    \
+        case 3: FL_BTILE(3, PP); break;    \
+        case 4: FL_BTILE(4, PP); break;    \
+        case 5: FL_BTILE(5, PP); break;    \
+        case 6: FL_BTILE(6, PP); break;    \
+        case 7: FL_BTILE(7, PP); break;    \
+        default: FL_BTILE(8, PP); break;   \
+    }
+        switch (pb.P) {
+            case 1: FL_BTILE_S(1); break;
+            case 2: FL_BTILE_S(2); break;
+            default: FL_BTILE_S(3); break;
+        }
+#undef FL_BTILE_S
+#undef FL_BTILE
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void batch_copy_kernel(const BatchProblem *__restrict__ probs,
                                                             const BatchTile *__restrict__ tiles,
                                                             int64_t ntiles, int tile) {
@@ -102,6 +155,8 @@ struct fl_batch {
     int device = -1;
     int scheme = FL_SSPRK3;
     int tile = 0;            // cells per tile (0 until tuned)
+    bool lds = false;        // tiles staged in LDS (tile == kTileCells)
+    size_t lds_bytes = 0;    // dynamic LDS of the staged kernel, 0 if not every mesh allows it
     int grid = 0;            // persistent grid size
     std::vector<BatchProblem> probs;
     std::vector<const fl_mesh *> meshes;
@@ -160,12 +215,20 @@ fl_status set_tile(fl_batch *b, int tile) {
     return FL_OK;
 }
 
+hipError_t launch_stage(const fl_batch *b, int s, hipStream_t st) {
+    if (b->lds)
+        bdev::batch_stage_lds_kernel<<<b->grid, bdev::kBlock, b->lds_bytes, st>>>(
+            b->d_probs, b->d_tiles, b->ntiles, s);
+    else
+        bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
+                                                                  b->ntiles, b->tile, s);
+    return hipGetLastError();
+}
+
 hipError_t enqueue_step(const fl_batch *b, hipStream_t st) {
     const int ns = b->scheme == FL_EULER ? 1 : 3;
     for (int s = 0; s < ns; ++s) {
-        bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
-                                                                  b->ntiles, b->tile, s);
-        hipError_t e = hipGetLastError();
+        hipError_t e = launch_stage(b, s, st);
         if (e != hipSuccess) return e;
     }
     if (b->scheme == FL_EULER) {
@@ -176,37 +239,39 @@ hipError_t enqueue_step(const fl_batch *b, hipStream_t st) {
     return hipSuccess;
 }
 
-// Times the non-destructive first stage (theta -> t1) for each candidate tile size.
+// Times the non-destructive first stage (theta -> t1) for each candidate: the LDS-staged kernel
+// (tiles of kTileCells, where every mesh allows it), then the gather kernel at each tile size.
 fl_status autotune(fl_batch *b, hipStream_t st) {
-    static const int cand[] = {128, 256, 512, 1024, 2048, 4096};
+    static const int cand[] = {-1, 128, 256, 512, 1024, 2048, 4096};  // -1: LDS-staged
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(FL_E_HIP, "hipEventCreate");
     float best = 1e30f;
     int best_tile = 256;
-    for (int tile : cand) {
-        fl_status s = set_tile(b, tile);
+    for (int c : cand) {
+        if (c < 0 && b->lds_bytes == 0) continue;
+        fl_status s = set_tile(b, c < 0 ? kTileCells : c);
         if (s != FL_OK) return s;
-        for (int rep = 0; rep < 2; ++rep)
-            bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
-                                                                      b->ntiles, b->tile, 0);
+        b->lds = c < 0;
+        for (int rep = 0; rep < 2; ++rep) (void)launch_stage(b, 0, st);
         (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 5; ++rep)
-            bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
-                                                                      b->ntiles, b->tile, 0);
+        for (int rep = 0; rep < 5; ++rep) (void)launch_stage(b, 0, st);
         (void)hipEventRecord(e1, st);
         hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return hip_err(e, "autotune");
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
             best = ms;
-            best_tile = tile;
+            best_tile = c;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return set_tile(b, best_tile);
+    fl_status s = set_tile(b, best_tile < 0 ? kTileCells : best_tile);
+    b->lds = best_tile < 0;
+    return s;
 }
 
 void destroy(fl_batch *b) {
@@ -241,6 +306,8 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
     }
     b->device = device;
     b->scheme = scheme;
+    bool lds_all = true;
+    size_t lds_max = 0;
     Guard g(device);
     for (int i = 0; i < n; ++i) {
         const fl_mesh *m = meshes[i];
@@ -273,6 +340,12 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         p.area = m->d_area;
         p.vol = m->d_vol;
         p.th = theta[i];
+        p.halo_ptr = m->d_halo_ptr;
+        p.halo = m->d_halo;
+        p.slot_local = m->d_slot_local;
+        const size_t lds = lds_stage_bytes(m, p.S);
+        lds_all = lds_all && lds > 0 && lds <= kMaxStageLds;
+        lds_max = std::max(lds_max, lds);
         const size_t bytes = (size_t)p.nc * p.S * sizeof(double);
         for (double **dst : {&p.t1, &p.t2}) {
             if (hipMalloc((void **)dst, bytes) != hipSuccess) {
@@ -284,6 +357,7 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         b->probs.push_back(p);
         b->meshes.push_back(m);
     }
+    b->lds_bytes = lds_all ? lds_max : 0;
     hipError_t e = hipMalloc((void **)&b->d_probs, b->probs.size() * sizeof(BatchProblem));
     if (e == hipSuccess)
         e = hipMemcpy(b->d_probs, b->probs.data(), b->probs.size() * sizeof(BatchProblem),
@@ -294,6 +368,8 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         return hip_err(e, "batch setup");
     }
     if (tile_cells > 0) {
+        // a fixed tile of kTileCells cells runs staged in LDS where every mesh allows it
+        b->lds = tile_cells == kTileCells && b->lds_bytes > 0;
         fl_status s = set_tile(b, tile_cells);
         if (s != FL_OK) {
             destroy(b);
@@ -345,19 +421,24 @@ fl_status fl_batch_step_unbatched(fl_batch *b, int n_steps, void *stream) {
         for (size_t i = 0; i < b->probs.size(); ++i) {
             const BatchProblem &p = b->probs[i];
             const fl_mesh *m = b->meshes[i];
+            // the batch's per-cell work, one problem per launch: LDS-staged tiles when the
+            // batch runs staged, the gather kernel otherwise
+            auto one = [&](const double *ts, double a, double bb, int mode, double *out) {
+                return b->lds ? launch_fused_lds(m, p.lim, p.S, ts, p.th, nullptr, a, bb, p.dt,
+                                                 mode, out, st, 1.0, p.u)
+                              : launch_fused(m, p.lim, p.S, ts, p.th, p.u, a, bb, p.dt, mode,
+                                             out, st);
+            };
             hipError_t e;
             if (b->scheme == FL_EULER) {
-                e = launch_fused(m, p.lim, p.S, p.th, p.th, p.u, 0.0, 1.0, p.dt, MODE_EULER, p.t1, st);
+                e = one(p.th, 0.0, 1.0, MODE_EULER, p.t1);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(p.th, p.t1, (size_t)p.nc * p.S * sizeof(double),
                                        hipMemcpyDeviceToDevice, st);
             } else {
-                e = launch_fused(m, p.lim, p.S, p.th, p.th, p.u, 0.0, 1.0, p.dt, MODE_EULER, p.t1, st);
-                if (e == hipSuccess)
-                    e = launch_fused(m, p.lim, p.S, p.t1, p.th, p.u, 0.75, 0.25, p.dt, MODE_RK, p.t2, st);
-                if (e == hipSuccess)
-                    e = launch_fused(m, p.lim, p.S, p.t2, p.th, p.u, 1.0 / 3.0, 2.0 / 3.0, p.dt,
-                                     MODE_RK, p.th, st);
+                e = one(p.th, 0.0, 1.0, MODE_EULER, p.t1);
+                if (e == hipSuccess) e = one(p.t1, 0.75, 0.25, MODE_RK, p.t2);
+                if (e == hipSuccess) e = one(p.t2, 1.0 / 3.0, 2.0 / 3.0, MODE_RK, p.th);
             }
             if (e != hipSuccess) return hip_err(e, "unbatched launch");
         }
@@ -367,6 +448,12 @@ fl_status fl_batch_step_unbatched(fl_batch *b, int n_steps, void *stream) {
 fl_status fl_batch_tile(const fl_batch *b, int *tile_cells) {
     if (!b || !tile_cells) return fail(FL_E_INVALID, "NULL argument");
     *tile_cells = b->tile;
+    return FL_OK;
+}
+
+fl_status fl_batch_lds(const fl_batch *b, int *lds_staged) {
+    if (!b || !lds_staged) return fail(FL_E_INVALID, "NULL argument");
+    *lds_staged = b->lds ? 1 : 0;
     return FL_OK;
 }
 

@@ -61,10 +61,57 @@ __device__ __forceinline__ double face_value_d(int lim, double tC, double du, do
     return tC + 0.5 * psi(lim, dU / du) * du;
 }
 
-// Scalars S0 .. S0+CS-1 of cell c (CS <= 2 keeps the gathered values in registers for any S).
-// theta_s is read from src at index cs (this cell) and nb[k], gf[k] (its slots' cells): src is
-// theta_s itself with global indices, or a tile's LDS copy with local indices; tn and out are
-// indexed by the global cell c.
+// Scalars S0 .. S0+CS-1 of cell c.  theta_s of a cell with source index i is
+// src[i * SST + SOFF + s] for s < CS: src is theta_s itself (SST = S, SOFF = S0, global indices)
+// or a tile's LDS copy of this chunk (SST = CS, SOFF = 0, local indices); tn and out are indexed
+// by the global cell c.
+template <int S, int P, int S0, int CS, int SST, int SOFF>
+__device__ __forceinline__ void fused_chunk(int64_t c, int64_t cs, const double *src,
+                                            const double *w, const int64_t *nb, const int64_t *gf,
+                                            double V, const double *__restrict__ tn, double a,
+                                            double b, double dt, int mode, int lim,
+                                            double *__restrict__ out) {
+    constexpr int K = 2 * P;
+    double tc[CS], tnb[K][CS], tg[K][CS];
+#pragma unroll
+    for (int i = 0; i < CS; ++i) tc[i] = src[cs * SST + SOFF + i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int i = 0; i < CS; ++i) tnb[k][i] = src[nb[k] * SST + SOFF + i];
+        if (lim != FL_UPWIND) {
+#pragma unroll
+            for (int i = 0; i < CS; ++i) tg[k][i] = src[gf[k] * SST + SOFF + i];
+        }
+    }
+    double acc[CS];
+#pragma unroll
+    for (int i = 0; i < CS; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        // Q(u_f): c is the upwind cell C of its face k where the flow leaves c (w_k > 0);
+        // where w_k == 0 the flux vanishes whichever cell is taken
+        const bool c_upwind = w[k] > 0.0;
+#pragma unroll
+        for (int i = 0; i < CS; ++i) {
+            // pick (theta_C, theta_D, theta_U) first: one evaluation where lanes diverge
+            const double tC = c_upwind ? tc[i] : tnb[k][i];
+            const double tD = c_upwind ? tnb[k][i] : tc[i];
+            const double tU = c_upwind ? tnb[k ^ 1][i] : tg[k][i];
+            acc[i] -= w[k] * face_value(lim, tC, tD, tU);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < CS; ++i) {
+        const int64_t j = c * S + S0 + i;
+        if (mode == MODE_RHS) out[j] = acc[i] / V;
+        else if (mode == MODE_EULER) out[j] = tc[i] + dt * (acc[i] / V);
+        else out[j] = a * tn[j] + b * (tc[i] + dt * (acc[i] / V));
+    }
+}
+
+// All scalars of cell c from global memory, in chunks of at most two (the gathered values of a
+// chunk stay in registers for any S).
 template <int S, int P, int S0>
 __device__ __forceinline__ void fused_chunks(int64_t c, int64_t cs, const double *src,
                                              const double *w, const int64_t *nb,
@@ -73,44 +120,8 @@ __device__ __forceinline__ void fused_chunks(int64_t c, int64_t cs, const double
                                              double dt, int mode, int lim,
                                              double *__restrict__ out) {
     if constexpr (S0 < S) {
-        constexpr int K = 2 * P;
         constexpr int CS = (S - S0) >= 2 ? 2 : 1;
-        double tc[CS], tnb[K][CS], tg[K][CS];
-#pragma unroll
-        for (int i = 0; i < CS; ++i) tc[i] = src[cs * S + S0 + i];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-#pragma unroll
-            for (int i = 0; i < CS; ++i) tnb[k][i] = src[nb[k] * S + S0 + i];
-            if (lim != FL_UPWIND) {
-#pragma unroll
-                for (int i = 0; i < CS; ++i) tg[k][i] = src[gf[k] * S + S0 + i];
-            }
-        }
-        double acc[CS];
-#pragma unroll
-        for (int i = 0; i < CS; ++i) acc[i] = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            // Q(u_f): c is the upwind cell C of its face k where the flow leaves c (w_k > 0);
-            // where w_k == 0 the flux vanishes whichever cell is taken
-            const bool c_upwind = w[k] > 0.0;
-#pragma unroll
-            for (int i = 0; i < CS; ++i) {
-                // pick (theta_C, theta_D, theta_U) first: one evaluation where lanes diverge
-                const double tC = c_upwind ? tc[i] : tnb[k][i];
-                const double tD = c_upwind ? tnb[k][i] : tc[i];
-                const double tU = c_upwind ? tnb[k ^ 1][i] : tg[k][i];
-                acc[i] -= w[k] * face_value(lim, tC, tD, tU);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < CS; ++i) {
-            const int64_t j = c * S + S0 + i;
-            if (mode == MODE_RHS) out[j] = acc[i] / V;
-            else if (mode == MODE_EULER) out[j] = tc[i] + dt * (acc[i] / V);
-            else out[j] = a * tn[j] + b * (tc[i] + dt * (acc[i] / V));
-        }
+        fused_chunk<S, P, S0, CS, S, S0>(c, cs, src, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
         fused_chunks<S, P, S0 + CS>(c, cs, src, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
     }
 }
@@ -191,50 +202,122 @@ __device__ __forceinline__ void fused_cell_rec(int64_t c, int64_t nc,
     fused_chunks<S, P, 0>(c, c, ts, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
 }
 
-// The stage for the cells of one tile (kTileCells consecutive cells, one per thread of the
-// workgroup): theta_s of the tile and of its halo is first copied to LDS (the tile's cells in
-// order, then the halo cells, each read from global memory once per tile), then every cell reads
-// its slots' cells there through 16-bit local indices (slot_local: neighbour | far << 16) and
-// the per-call signed face rates.  Call from every thread of the workgroup (it synchronises);
-// the arithmetic is fused_chunks', so results are bit-identical to fused_cell_rec's.
-template <int S, int P>
-__device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds,
-                                           const int32_t *__restrict__ halo_ptr,
-                                           const int32_t *__restrict__ halo,
-                                           const uint32_t *__restrict__ slot_local,
-                                           const double *__restrict__ rate, bool has_area,
-                                           double area0, const double *__restrict__ vol,
-                                           double vol0, const double *__restrict__ ts,
-                                           const double *__restrict__ tn, double a, double b,
-                                           double dt, int mode, int lim,
-                                           double *__restrict__ out, double us) {
-    constexpr int K = 2 * P;
+// Copies scalars S0 .. S0+CS-1 of theta_s of tile `tile` (kTileCells consecutive cells) and of
+// its halo (the cells outside it that its slots name, ascending) to LDS: [tile cells | halo], CS
+// values per cell, each read from global memory once per tile.  Every thread of the workgroup
+// takes part; the caller puts a barrier between this and the reads.  Returns the number of cells
+// in the tile.
+template <int S, int S0, int CS>
+__device__ __forceinline__ int tile_stage(int64_t nc, int64_t tile, double *lds,
+                                          const int32_t *__restrict__ halo_ptr,
+                                          const int32_t *__restrict__ halo,
+                                          const double *__restrict__ ts) {
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
     const int nt = left < kTileCells ? (int)left : kTileCells;
     const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < nt * S; i += kTileCells) lds[i] = ts[c0 * S + i];
-    for (int i = tid; i < nh; i += kTileCells) {
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+#pragma unroll
+        for (int s = 0; s < CS; ++s) lds[i * CS + s] = ts[(c0 + i) * S + S0 + s];
+    }
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) {
         const int64_t g = halo[h0 + i];
 #pragma unroll
-        for (int s = 0; s < S; ++s) lds[(kTileCells + i) * S + s] = ts[g * S + s];
+        for (int s = 0; s < CS; ++s) lds[(kTileCells + i) * CS + s] = ts[g * S + S0 + s];
     }
-    __syncthreads();
-    if (tid >= nt) return;
-    const int64_t c = c0 + tid;
-    int64_t nb[K], gf[K];
-    double w[K];
+    return nt;
+}
+
+// Local slot indices and signed face rates of cell c of a tile.  The face terms come from the
+// per-call rates (RATES) or, as in fused_cell, from u through the face index; either way the
+// rates w_k, and so the results, are bit-identical to fused_cell's for us = 1.
+template <int P, bool RATES>
+__device__ __forceinline__ void tile_slots(int64_t nc, int64_t c,
+                                           const uint32_t *__restrict__ slot_local,
+                                           const double *__restrict__ rate,
+                                           const uint32_t *__restrict__ sface,
+                                           const double *__restrict__ u,
+                                           const double *__restrict__ area, bool has_area,
+                                           double area0, double us, int64_t *nb, int64_t *gf,
+                                           double *w) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < 2 * P; ++k) {
         const uint32_t l = slot_local[(int64_t)k * nc + c];
         nb[k] = l & 0xffffu;
         gf[k] = l >> 16;
-        const double v = rate[(int64_t)k * nc + c] * us;
-        w[k] = has_area ? v : area0 * v;
+        if constexpr (RATES) {
+            const double v = rate[(int64_t)k * nc + c] * us;
+            w[k] = has_area ? v : area0 * v;
+        } else {
+            const uint32_t fw = sface[(int64_t)k * nc + c];
+            const int64_t f = fw & 0x7fffffffu;
+            const double au = (area ? area[f] : area0) * (u[f] * us);
+            w[k] = (fw >> 31) ? au : -au;
+        }
     }
-    const double V = vol ? vol[c] : vol0;
-    fused_chunks<S, P, 0>(c, tid, lds, w, nb, gf, V, tn, a, b, dt, mode, lim, out);
+}
+
+// Chunks S0.. (S0 > 0) of one tile: barrier (the previous chunk's LDS reads are done), stage the
+// chunk (all threads), barrier, each cell of the tile computes it from LDS.
+template <int S, int P, int S0>
+__device__ __forceinline__ void tile_chunks(int64_t nc, int64_t tile, double *lds,
+                                            const int32_t *__restrict__ halo_ptr,
+                                            const int32_t *__restrict__ halo,
+                                            const double *__restrict__ ts, bool active, int64_t c,
+                                            const double *w, const int64_t *nb, const int64_t *gf,
+                                            double V, const double *__restrict__ tn, double a,
+                                            double b, double dt, int mode, int lim,
+                                            double *__restrict__ out) {
+    if constexpr (S0 < S) {
+        constexpr int CS = (S - S0) >= 2 ? 2 : 1;
+        __syncthreads();
+        tile_stage<S, S0, CS>(nc, tile, lds, halo_ptr, halo, ts);
+        __syncthreads();
+        if (active)
+            fused_chunk<S, P, S0, CS, CS, 0>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt, mode,
+                                             lim, out);
+        tile_chunks<S, P, S0 + CS>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf, V, tn,
+                                   a, b, dt, mode, lim, out);
+    }
+}
+
+// The whole stage of one tile, one thread per cell (kTileCells threads).  Face terms from
+// `rate` (RATES), or from u through the face index.  LDS: (kTileCells + halo) * min(S,
+// 2) doubles.  Every thread of the workgroup must call it (barriers).  The first chunk is staged
+// before the slots are read, so that the slot loads overlap the LDS reads rather than the
+// staging (a barrier waits for every outstanding load).
+template <int S, int P, bool RATES>
+__device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds,
+                                           const int32_t *__restrict__ halo_ptr,
+                                           const int32_t *__restrict__ halo,
+                                           const uint32_t *__restrict__ slot_local,
+                                           const double *__restrict__ rate,
+                                           const uint32_t *__restrict__ sface,
+                                           const double *__restrict__ u,
+                                           const double *__restrict__ area, double area0,
+                                           const double *__restrict__ vol, double vol0,
+                                           const double *__restrict__ ts,
+                                           const double *__restrict__ tn, double a, double b,
+                                           double dt, int mode, int lim,
+                                           double *__restrict__ out, double us) {
+    constexpr int K = 2 * P;
+    constexpr int CS0 = S >= 2 ? 2 : 1;
+    const int nt = tile_stage<S, 0, CS0>(nc, tile, lds, halo_ptr, halo, ts);
+    __syncthreads();
+    const bool active = (int)threadIdx.x < nt;
+    const int64_t c = tile * kTileCells + threadIdx.x;
+    int64_t nb[K], gf[K];
+    double w[K];
+    double V = vol0;
+    if (active) {
+        tile_slots<P, RATES>(nc, c, slot_local, rate, sface, u, area, area != nullptr, area0, us,
+                             nb, gf, w);
+        if (vol) V = vol[c];
+        fused_chunk<S, P, 0, CS0, CS0, 0>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt, mode,
+                                          lim, out);
+    }
+    tile_chunks<S, P, CS0>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf, V, tn, a, b,
+                           dt, mode, lim, out);
 }
 
 }  // namespace dev

@@ -37,8 +37,9 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
                             const void *rec, double a, double b, double dt, int mode, double *out,
                             hipStream_t st, double us = 1.0);
 // LDS-staged stage (fused path with tile tables): per-call rates rate[2P][C] (8 bytes per slot)
-// and one workgroup per tile with lds_stage_bytes(m, S) of dynamic LDS; used while that is at
-// most kMaxStageLds (0 = no tile tables).
+// and one workgroup per tile with lds_stage_bytes(m, S) = (tile + max halo) * min(S, 2) doubles
+// of dynamic LDS (scalars staged two at a time); used while that is at most kMaxStageLds (0 = no
+// tile tables).
 // The adjoint stage stages theta and lambda: adjoint_lds_bytes(m, S).  Both are 0 while
 // FL_OPT_LDS_STAGE is off (set_lds_stage).
 constexpr size_t kMaxStageLds = 64 * 1024;
@@ -46,9 +47,11 @@ void set_lds_stage(int on);
 size_t lds_stage_bytes(const fl_mesh *m, int S);
 size_t adjoint_lds_bytes(const fl_mesh *m, int S);
 hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st);
+// rate: the per-call signed face rates, or NULL to read u (then non-NULL) through the face index.
 hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                             const double *rate, double a, double b, double dt, int mode,
-                            double *out, hipStream_t st, double us = 1.0);
+                            double *out, hipStream_t st, double us = 1.0,
+                            const double *u = nullptr);
 hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);

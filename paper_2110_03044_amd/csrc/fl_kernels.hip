@@ -232,17 +232,19 @@ __global__ __launch_bounds__(kBlock) void slot_rate_kernel(int64_t nc,
     }
 }
 
-// One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo) * S doubles.
-template <int S, int P>
+// One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo) * min(S, 2)
+// doubles.
+template <int S, int P, bool RATES>
 __global__ __launch_bounds__(kBlock) void fused_stage_lds_kernel(
     int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
-    const uint32_t *__restrict__ slot_local, const double *__restrict__ rate, int has_area,
-    double area0, const double *__restrict__ vol, double vol0, const double *__restrict__ ts,
-    const double *__restrict__ tn, double a, double b, double dt, int mode, int lim,
-    double *__restrict__ out, double us) {
+    const uint32_t *__restrict__ slot_local, const double *__restrict__ rate,
+    const uint32_t *__restrict__ sface, const double *__restrict__ u,
+    const double *__restrict__ area, double area0, const double *__restrict__ vol, double vol0,
+    const double *__restrict__ ts, const double *__restrict__ tn, double a, double b, double dt,
+    int mode, int lim, double *__restrict__ out, double us) {
     extern __shared__ double lds[];
-    fused_tile<S, P>(nc, blockIdx.x, lds, halo_ptr, halo, slot_local, rate, has_area != 0, area0,
-                     vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
+    fused_tile<S, P, RATES>(nc, blockIdx.x, lds, halo_ptr, halo, slot_local, rate, sface, u, area,
+                            area0, vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -408,12 +410,17 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
 int g_lds_stage = 1;
 void set_lds_stage(int on) { g_lds_stage = on; }
 
+// The forward stage stages at most two scalars at a time; the adjoint stages theta and lambda of
+// every scalar at once.
 size_t lds_stage_bytes(const fl_mesh *m, int S) {
     if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
-    return (size_t)(kTileCells + m->h.max_halo) * S * sizeof(double);
+    return (size_t)(kTileCells + m->h.max_halo) * (S < 2 ? S : 2) * sizeof(double);
 }
 
-size_t adjoint_lds_bytes(const fl_mesh *m, int S) { return 2 * lds_stage_bytes(m, S); }
+size_t adjoint_lds_bytes(const fl_mesh *m, int S) {
+    if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
+    return (size_t)(kTileCells + m->h.max_halo) * 2 * S * sizeof(double);
+}
 
 hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);
@@ -428,15 +435,21 @@ hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hi
 
 hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, const double *tn,
                             const double *rate, double a, double b, double dt, int mode,
-                            double *out, hipStream_t st, double us) {
+                            double *out, hipStream_t st, double us, const double *u) {
     const size_t lds = lds_stage_bytes(m, S);
-    if (lds == 0 || lds > kMaxStageLds) return hipErrorInvalidValue;
+    if (lds == 0 || lds > kMaxStageLds || (!rate && !u)) return hipErrorInvalidValue;
     const unsigned tiles = (unsigned)((m->h.nc + kTileCells - 1) / kTileCells);
-    const int has_area = m->d_area != nullptr;
-#define FL_FUSED_LDS(P)                                                                          \
-    FL_DISPATCH_S(S, (dev::fused_stage_lds_kernel<kS, P><<<tiles, dev::kBlock, lds, st>>>(       \
-                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_slot_local, rate, has_area,      \
-                         m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out, us)))
+#define FL_FUSED_LDS_R(P, R)                                                                     \
+    FL_DISPATCH_S(S, (dev::fused_stage_lds_kernel<kS, P, R><<<tiles, dev::kBlock, lds, st>>>(    \
+                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_slot_local, rate,                \
+                         m->d_slot_face, u, m->d_area, m->h.area0, m->d_vol, m->h.vol0, ts, tn,   \
+                         a, b, dt, mode, lim, out, us)))
+#define FL_FUSED_LDS(P)            \
+    if (rate) {                    \
+        FL_FUSED_LDS_R(P, true);   \
+    } else {                       \
+        FL_FUSED_LDS_R(P, false);  \
+    }
     switch (m->h.pairs) {
         case 1: FL_FUSED_LDS(1); break;
         case 2: FL_FUSED_LDS(2); break;
@@ -444,6 +457,7 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
         default: return hipErrorInvalidValue;
     }
 #undef FL_FUSED_LDS
+#undef FL_FUSED_LDS_R
     return hipGetLastError();
 }
 

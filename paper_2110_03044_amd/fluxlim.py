@@ -527,6 +527,12 @@ class Batch:
         call("fl_batch_tile", self._h, ctypes.byref(t))
         return t.value
 
+    @property
+    def lds_staged(self) -> bool:
+        t = ctypes.c_int()
+        call("fl_batch_lds", self._h, ctypes.byref(t))
+        return bool(t.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             lib().fl_batch_destroy(self._h)

@@ -47,7 +47,7 @@ def to_dev(p, reorder=True):
 
 
 @pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
-@pytest.mark.parametrize("tile", [0, 64, 1024])
+@pytest.mark.parametrize("tile", [0, 64, 256, 1024])
 def test_batch_equals_single_runs_on_every_replay(scheme, tile):
     probs = make_problems()
     dev_probs = [to_dev(p) for p in probs]
@@ -64,7 +64,39 @@ def test_batch_equals_single_runs_on_every_replay(scheme, tile):
         for i, (bt, st) in enumerate(zip(batch_th, single_th)):
             assert torch.equal(bt, st), (replay, i, probs[i]["lim"])
     assert b.tile_cells > 0 and (tile == 0 or b.tile_cells == tile)
+    assert b.lds_staged == (tile == 256 or (tile == 0 and b.tile_cells == 256 and b.lds_staged))
     b.close()
+
+
+@pytest.mark.parametrize("S", [1, 4, 8])
+def test_lds_staged_batch_and_per_problem_launches(S):
+    """Tiles of 256 cells run staged in LDS (two scalars at a time, so any S fits); the batch,
+    its per-problem launches and the gather kernel give the same bits."""
+    probs = make_problems(count=6, seed=31)
+    for p in probs:
+        rng = np.random.default_rng(p["mesh"].n_cells)
+        p["th"] = rng.standard_normal((p["mesh"].n_cells, S)) if S > 1 else \
+            rng.standard_normal(p["mesh"].n_cells)
+    dev_probs = [to_dev(p) for p in probs]
+    outs = {}
+    try:
+        for lds in (1, 0):
+            FL.set_option("lds_stage", lds)
+            for kind in ("batch", "unbatched"):
+                ths = [th.clone() for _, th, _ in dev_probs]
+                b = FL.Batch([(m, p["lim"], t, u, p["dt"])
+                              for (m, _, u), t, p in zip(dev_probs, ths, probs)], tile_cells=256)
+                assert b.lds_staged == bool(lds)
+                (b.step if kind == "batch" else b.step_unbatched)(3)
+                torch.cuda.synchronize()
+                outs[lds, kind] = ths
+                b.close()
+    finally:
+        FL.set_option("lds_stage", 1)
+    ref = outs[0, "batch"]
+    for key, ths in outs.items():
+        for i, (x, y) in enumerate(zip(ths, ref)):
+            assert torch.equal(x, y), (key, i)
 
 
 def test_batch_matches_oracle_and_unbatched():
