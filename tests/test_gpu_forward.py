@@ -402,3 +402,31 @@ def test_general_cells_without_adjoint_or_batch():
     with pytest.raises(_lib.FluxLimError) as e:
         FL.Batch([(mesh, "vanleer", th.clone(), u, 1e-3)])
     assert e.value.status == -3
+
+
+def test_full_size_box256_sampled_first_stage_and_conservation():
+    """The 256^3 random mesh of the benchmark, library reorder, in the launch configuration the
+    benchmark times (multi-step call: per-call rates, LDS-staged stages).  The first stage output
+    t1 = theta0 + dt rhs(theta0), stored by the two-step store call, is compared with the oracle's
+    rhs at 20000 sampled cells (computed from theta0 alone); the two-step result conserves
+    sum V theta and equals the plain two-step call bit for bit."""
+    wl = W.workload_box(256, renumbered=True)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    assert mesh.info.tile_cells > 0
+    t0 = dev(to_mesh_cells(wl.theta0, cp))
+    u = dev(to_mesh_faces(wl.u, fp))
+    stages = FL.stage_buffer(mesh, "ssprk3", 1, 2)
+    a = t0.clone()
+    FL.rk_steps_store(mesh, "vanleer", "ssprk3", wl.dt, a, u, stages, 2)
+    b = t0.clone()
+    FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, b, u, 2)
+    assert torch.equal(a, b)
+    rng = np.random.default_rng(17)
+    cells = np.sort(rng.choice(wl.mesh.n_cells, 20000, replace=False))
+    rhs = O.OracleMesh.from_arrays(wl.mesh).rhs_cells("vanleer", wl.theta0, wl.u, cells)
+    want = wl.theta0[cells] + wl.dt * rhs
+    got = host(stages[0, 1])[cp[cells]]
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(wl.theta0).max()
+    V = wl.mesh.cell_volume[0]
+    total0 = float(t0.sum()) * V
+    assert abs(float(a.sum()) * V - total0) <= 1e-12 * abs(total0)
