@@ -220,3 +220,14 @@ def test_checkpoint_interval_for_memory_budget():
     assert f(mesh, "euler", 2, 400, 16000 * 100) == 100
     assert [FL.checkpoint_interval(n) for n in (1, 2, 4, 5, 400, 401)] == [1, 2, 2, 3, 20, 21]
     mesh.close()
+
+
+def test_empty_and_oversized_meshes_are_rejected_before_reading():
+    """n_cells or n_faces of 0, and sizes beyond the 32-bit index range, are FL_E_INVALID; the
+    size check comes before any array is read (the arrays passed here are one face long)."""
+    L = _lib.lib()
+    fc = np.zeros((1, 2), dtype=np.int32)
+    nrm = np.zeros((1, 3))
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for nc, nf in [(0, 1), (1, 0), (0, 0), (2**31, 1), (4, 2**30)]:
+        assert L.fl_mesh_validate(nc, nf, P(fc), P(nrm)) == -1, (nc, nf)
