@@ -67,13 +67,14 @@ void free_device(fl_mesh *m) {
     void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
                     m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local, m->d_side_ptr,
-                    m->d_side_cell, m->d_side_w};
+                    m->d_side_cell, m->d_side_w, m->d_adj_fr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
     m->d_slot_face = nullptr;
     m->d_slot_nbr = m->d_slot_far = nullptr;
     m->d_adj_rec = nullptr;
+    m->d_adj_fr = nullptr;
     m->d_halo_ptr = m->d_halo = nullptr;
     m->d_slot_local = nullptr;
     m->d_side_ptr = m->d_side_cell = nullptr;
@@ -292,6 +293,15 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                         rec[4 * i + 3] = h.slot_far[i];
                     }
                     st = upload(&m->d_adj_rec, rec.data(), rec.size(), B, "adjoint slot records");
+                }
+                if (st == FL_OK && h.max_halo >= 0) {
+                    const size_t n = h.slot_face.size();
+                    std::vector<int32_t> fr(2 * n);
+                    for (size_t i = 0; i < n; ++i) {
+                        fr[2 * i] = (int32_t)h.slot_face[i];
+                        fr[2 * i + 1] = (int32_t)h.slot_rev[i];
+                    }
+                    st = upload(&m->d_adj_fr, fr.data(), fr.size(), B, "adjoint face pairs");
                 }
                 if (st == FL_OK && h.max_halo >= 0) {
                     st = upload(&m->d_halo_ptr, h.halo_ptr.data(), h.halo_ptr.size(), B, "tile halo pointers");

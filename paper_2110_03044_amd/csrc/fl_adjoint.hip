@@ -124,17 +124,17 @@ __device__ __forceinline__ void load_s(const double *src, int64_t i, int stride,
 //
 // One cell x.  Slot k: face fw[k] (bit 31: x owns it), the face rw[k] of the neighbour opposite
 // to it (bit 31: the neighbour owns that one), the neighbour and the far-upwind cell on its side
-// with global indices nbg/gfg (volumes) and source indices nbi/gfi.  theta and lambda of a cell
-// with source index i are tsrc[i * stride + s] and lsrc[i * stride + s]: the global arrays
-// (stride S, source index = global index) or a tile's LDS copy (interleaved, stride 2S).
+// with source indices nbi/gfi.  theta, lambda and the volume of a cell with source index i are
+// tsrc[i * stride + s], lsrc[i * stride + s] and vsrc[i * vstride] (vsrc NULL: all volumes are
+// 1 / ivol0): the global arrays (stride S, vstride 1, source index = global index) or a tile's
+// LDS copy (interleaved per cell).
 template <int S, int P, int LIM>
 __device__ __forceinline__ void adj_cell(
     int64_t nc, int64_t x, int64_t xi, const uint32_t *fw, const uint32_t *rw,
-    const int64_t *nbg, const int64_t *gfg, const int64_t *nbi, const int64_t *gfi,
-    const double *tsrc, const double *lsrc, int stride, const double *__restrict__ u,
-    const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
-    double a, double b, double dt, int mode, double *__restrict__ out,
-    double *__restrict__ acc, double *__restrict__ ubar) {
+    const int64_t *nbi, const int64_t *gfi, const double *tsrc, const double *lsrc,
+    const double *vsrc, int stride, int vstride, const double *__restrict__ u,
+    const double *__restrict__ area, double area0, double ivol0, double a, double b, double dt,
+    int mode, double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
     constexpr int K = 2 * P;
     double tx[S], lx[S], tn[K][S];
     load_s<S>(tsrc, xi, stride, tx);
@@ -142,7 +142,7 @@ __device__ __forceinline__ void adj_cell(
 #pragma unroll
     for (int k = 0; k < K; ++k) load_s<S>(tsrc, nbi[k], stride, tn[k]);
     // lambda / V appears in every face term: multiply by reciprocal volumes
-    const double ivx = vol ? 1.0 / vol[x] : ivol0;
+    const double ivx = vsrc ? 1.0 / vsrc[xi * vstride] : ivol0;
     const double scale = (mode == ADJ_APPLY) ? 1.0 : b * dt;
     double jt[S];
 #pragma unroll
@@ -163,7 +163,8 @@ __device__ __forceinline__ void adj_cell(
         const int64_t f = fw[k] & 0x7fffffffu, fr = rw[k] & 0x7fffffffu;
         const double uf = ufk[k], ur = urk[k];
         const double af = area ? area[f] : area0, ar = area ? area[fr] : area0;
-        const double ivn = vol ? 1.0 / vol[nbg[k]] : ivol0, ivg = vol ? 1.0 / vol[gfg[k]] : ivol0;
+        const double ivn = vsrc ? 1.0 / vsrc[nbi[k] * vstride] : ivol0;
+        const double ivg = vsrc ? 1.0 / vsrc[gfi[k] * vstride] : ivol0;
         double ln[S], lg[S], tg[S];
         load_s<S>(lsrc, nbi[k], stride, ln);
         load_s<S>(lsrc, gfi[k], stride, lg);
@@ -251,18 +252,19 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     uint32_t fw[K], rw[K];
     int64_t nb[K], gf[K];
     read_rec<P>(nc, x, rec, fw, rw, nb, gf);
-    adj_cell<S, P, LIM>(nc, x, x, fw, rw, nb, gf, nb, gf, th, lam, S, u, area, area0, vol, ivol0,
-                        a, b, dt, mode, out, acc, ubar);
+    adj_cell<S, P, LIM>(nc, x, x, fw, rw, nb, gf, th, lam, vol, S, 1, u, area, area0, ivol0, a, b,
+                        dt, mode, out, acc, ubar);
 }
 
-// One workgroup per tile of kTileCells cells: theta and lambda of the tile and of its halo are
-// staged in LDS (interleaved per cell, each read from global memory once per tile), then every
-// cell reads them there through the 16-bit local slot indices of the forward's tile tables.
-// Dynamic LDS of (kTileCells + max halo) * 2 S doubles.  Same arithmetic as
+// One workgroup per tile of kTileCells cells: theta, lambda (and the volume, where volumes
+// differ) of the tile and of its halo are staged in LDS, interleaved per cell, each read from
+// global memory once per tile; then every cell reads them there through the 16-bit local slot
+// indices of the forward's tile tables, and its faces from 8-byte {face, opposite face} records.
+// Dynamic LDS of (kTileCells + max halo) * (2 S + [1]) doubles.  Same arithmetic as
 // adjoint_stage_kernel, so the results are bit-identical.
 template <int S, int P, int LIM>
 __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
-    int64_t nc, const int4 *__restrict__ rec, const int32_t *__restrict__ halo_ptr,
+    int64_t nc, const int2 *__restrict__ fr, const int32_t *__restrict__ halo_ptr,
     const int32_t *__restrict__ halo, const uint32_t *__restrict__ slot_local,
     const double *__restrict__ u, const double *__restrict__ area, double area0,
     const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
@@ -270,6 +272,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
     double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
     extern __shared__ double lds[];
     constexpr int K = 2 * P;
+    const int st = 2 * S + (vol ? 1 : 0);
     const int64_t tile = blockIdx.x;
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
@@ -279,32 +282,36 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
     for (int i = tid; i < nt; i += kTileCells) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            lds[i * 2 * S + s] = th[(c0 + i) * S + s];
-            lds[i * 2 * S + S + s] = lam[(c0 + i) * S + s];
+            lds[i * st + s] = th[(c0 + i) * S + s];
+            lds[i * st + S + s] = lam[(c0 + i) * S + s];
         }
+        if (vol) lds[i * st + 2 * S] = vol[c0 + i];
     }
     for (int i = tid; i < nh; i += kTileCells) {
         const int64_t g = halo[h0 + i];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            lds[(kTileCells + i) * 2 * S + s] = th[g * S + s];
-            lds[(kTileCells + i) * 2 * S + S + s] = lam[g * S + s];
+            lds[(kTileCells + i) * st + s] = th[g * S + s];
+            lds[(kTileCells + i) * st + S + s] = lam[g * S + s];
         }
+        if (vol) lds[(kTileCells + i) * st + 2 * S] = vol[g];
     }
     __syncthreads();
     if (tid >= nt) return;
     const int64_t x = c0 + tid;
     uint32_t fw[K], rw[K];
-    int64_t nb[K], gf[K], nl[K], gl[K];
-    read_rec<P>(nc, x, rec, fw, rw, nb, gf);
+    int64_t nl[K], gl[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+        const int2 r = fr[(int64_t)k * nc + x];
+        fw[k] = (uint32_t)r.x;
+        rw[k] = (uint32_t)r.y;
         const uint32_t l = slot_local[(int64_t)k * nc + x];
         nl[k] = l & 0xffffu;
         gl[k] = l >> 16;
     }
-    adj_cell<S, P, LIM>(nc, x, tid, fw, rw, nb, gf, nl, gl, lds, lds + S, 2 * S, u, area, area0,
-                        vol, ivol0, a, b, dt, mode, out, acc, ubar);
+    adj_cell<S, P, LIM>(nc, x, tid, fw, rw, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr, st,
+                        st, u, area, area0, ivol0, a, b, dt, mode, out, acc, ubar);
 }
 
 }  // namespace adev
@@ -318,7 +325,7 @@ hipError_t launch3(const fl_mesh *m, const double *u, const double *th, const do
     if (lds > 0 && lds <= kMaxStageLds) {
         const unsigned tiles = (unsigned)((m->h.nc + kTileCells - 1) / kTileCells);
         adev::adjoint_stage_lds_kernel<S, P, LIM><<<tiles, adev::kBlock, lds, st>>>(
-            m->h.nc, reinterpret_cast<const int4 *>(m->d_adj_rec), m->d_halo_ptr, m->d_halo,
+            m->h.nc, reinterpret_cast<const int2 *>(m->d_adj_fr), m->d_halo_ptr, m->d_halo,
             m->d_slot_local, u, m->d_area, m->h.area0, m->d_vol, 1.0 / m->h.vol0, th, lam, a, b,
             dt, mode, out, acc, ubar);
         return hipGetLastError();

@@ -82,6 +82,8 @@ struct fl_mesh {
     int32_t *d_halo_ptr = nullptr; // LDS-staged stage: tile halo lists and local slot indices
     int32_t *d_halo = nullptr;
     uint32_t *d_slot_local = nullptr;
+    int32_t *d_adj_fr = nullptr;   // [2P][C][2] LDS adjoint: slot face, the neighbour's face
+                                   // opposite it (both with own bits)
     int32_t *d_adj_rec = nullptr;  // [2P][C][4] adjoint: slot face, the neighbour's face opposite
                                    // it (both with own bits), neighbour, far cell
     double *d_area = nullptr;      // [F] if non-uniform

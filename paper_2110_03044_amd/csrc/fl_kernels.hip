@@ -418,8 +418,10 @@ size_t lds_stage_bytes(const fl_mesh *m, int S) {
 }
 
 size_t adjoint_lds_bytes(const fl_mesh *m, int S) {
-    if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
-    return (size_t)(kTileCells + m->h.max_halo) * 2 * S * sizeof(double);
+    if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local ||
+        !m->d_adj_fr)
+        return 0;
+    return (size_t)(kTileCells + m->h.max_halo) * (2 * S + (m->d_vol ? 1 : 0)) * sizeof(double);
 }
 
 hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st) {
