@@ -298,13 +298,14 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     face index.  Results are bit-identical either way (for time-dependent
  *                     velocity on meshes with face areas, up to the rounding of one product).
  *   FL_OPT_LDS_STAGE  1 (default): those multi-step calls, on meshes with tile tables
- *                     (fl_mesh_info_t.tile_cells > 0) and with (tile_cells + max_halo) *
+ *                     (fl_mesh_info_t.tile_cells > 0) and with (tile_cells + max_halo + 1) *
  *                     min(S, 2) * 8 bytes of LDS per tile at most 64 KiB, stage each tile's
  *                     theta and its halo in LDS (two scalars at a time) and read the per-call
  *                     rates E a_f u_f (8 bytes per slot) instead of the 16-byte records; the
  *                     adjoint stages (fl_convect_adjoint, fl_rk_step_adjoint) likewise stage theta
- *                     and lambda of all S scalars where (tile_cells + max_halo) * 2 S * 8 bytes
- *                     fit; 0: the records and global gathers.  Results are bit-identical.
+ *                     and lambda of all S scalars (and the cell volumes, where they differ)
+ *                     where (tile_cells + max_halo) * (2 S [+ 1]) * 8 bytes fit; 0: the records
+ *                     and global gathers.  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3 };

@@ -305,7 +305,13 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                 }
                 if (st == FL_OK && h.max_halo >= 0) {
                     st = upload(&m->d_halo_ptr, h.halo_ptr.data(), h.halo_ptr.size(), B, "tile halo pointers");
-                    if (st == FL_OK) st = upload(&m->d_halo, h.halo.data(), h.halo.size(), B, "tile halos");
+                    if (st == FL_OK) {
+                        // padded: the staging reads each tile's first entry, also where its
+                        // halo is empty
+                        std::vector<int32_t> hp(h.halo);
+                        hp.resize(h.halo.size() + kHaloPad, 0);
+                        st = upload(&m->d_halo, hp.data(), hp.size(), B, "tile halos");
+                    }
                     if (st == FL_OK)
                         st = upload(&m->d_slot_local, h.slot_local.data(), h.slot_local.size(), B,
                                     "local slot indices");

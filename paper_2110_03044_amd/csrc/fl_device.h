@@ -257,6 +257,100 @@ __device__ __forceinline__ void tile_slots(int64_t nc, int64_t c,
     }
 }
 
+// The first chunk (CS scalars) of one tile staged as tile_stage does, with the cell's raw slot
+// words loaded after the theta gathers of the tile cell and of its first kHaloAhead halo
+// entries and before their LDS stores.  Loads complete in issue order, so the stores wait for
+// the gathers only and the slot words stay in flight across the barrier that follows
+// (tile_slots_finish decodes them after it).  No load sits in a branch, so that the compiler's
+// count of outstanding loads stays exact: a lane past the tile's cells reads the tile's first
+// cell, one past its halo the halo's first entry (the device array is padded by kHaloPad
+// entries, so that entry exists even for an empty halo at the end).
+template <int P, bool RATES>
+struct SlotRaw {
+    uint32_t l[2 * P];                 // local indices: neighbour | far cell << 16
+    double r[RATES ? 2 * P : 1];       // per-call rates (RATES)
+    uint32_t fw[RATES ? 1 : 2 * P];    // face | own bit (face-index form)
+};
+
+template <int S, int CS, int P, bool RATES>
+__device__ __forceinline__ int tile_stage_slots(int64_t nc, int64_t tile, double *lds,
+                                                const int32_t *__restrict__ halo_ptr,
+                                                const int32_t *__restrict__ halo,
+                                                const double *__restrict__ ts,
+                                                const uint32_t *__restrict__ slot_local,
+                                                const double *__restrict__ rate,
+                                                const uint32_t *__restrict__ sface,
+                                                SlotRaw<P, RATES> &raw) {
+    const int64_t c0 = tile * kTileCells;
+    const int64_t left = nc - c0;
+    const int nt = left < kTileCells ? (int)left : kTileCells;
+    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int64_t c = c0 + (tid < nt ? tid : 0);
+    double tv[CS], hv[kHaloAhead][CS];
+#pragma unroll
+    for (int s = 0; s < CS; ++s) tv[s] = ts[c * S + s];
+    // a lane past the halo re-reads the halo's first entry and gathers its own cell: lines the
+    // tile reads anyway
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * nthr;
+        const int64_t h = halo[h0 + (i < nh ? i : 0)];
+        const int64_t g = i < nh ? h : c;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) hv[j][s] = ts[g * S + s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        raw.l[k] = slot_local[(int64_t)k * nc + c];
+        if constexpr (RATES) raw.r[k] = rate[(int64_t)k * nc + c];
+        else raw.fw[k] = sface[(int64_t)k * nc + c];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // every lane stores (tid < kTileCells): entries past nt are never read
+#pragma unroll
+    for (int s = 0; s < CS; ++s) lds[tid * CS + s] = tv[s];
+    // lanes past the halo store to the spare entry just after it (never read; the LDS holds
+    // kTileCells + max halo + 1 entries), so that no gather is sunk into a branch
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * nthr;
+        const int e = kTileCells + (i < nh ? i : nh);
+#pragma unroll
+        for (int s = 0; s < CS; ++s) lds[e * CS + s] = hv[j][s];
+    }
+    for (int i = tid + kHaloAhead * nthr; i < nh; i += nthr) {
+        const int64_t g = halo[h0 + i];
+#pragma unroll
+        for (int s = 0; s < CS; ++s) lds[(kTileCells + i) * CS + s] = ts[g * S + s];
+    }
+    return nt;
+}
+
+// Decodes the raw slot words as tile_slots does (same arithmetic, so the same bits).
+template <int P, bool RATES>
+__device__ __forceinline__ void tile_slots_finish(const SlotRaw<P, RATES> &raw,
+                                                  const double *__restrict__ u,
+                                                  const double *__restrict__ area, bool has_area,
+                                                  double area0, double us, int64_t *nb,
+                                                  int64_t *gf, double *w) {
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        nb[k] = raw.l[k] & 0xffffu;
+        gf[k] = raw.l[k] >> 16;
+        if constexpr (RATES) {
+            const double v = raw.r[k] * us;
+            w[k] = has_area ? v : area0 * v;
+        } else {
+            const uint32_t fw = raw.fw[k];
+            const int64_t f = fw & 0x7fffffffu;
+            const double au = (area ? area[f] : area0) * (u[f] * us);
+            w[k] = (fw >> 31) ? au : -au;
+        }
+    }
+}
+
 // Chunks S0.. (S0 > 0) of one tile: barrier (the previous chunk's LDS reads are done), stage the
 // chunk (all threads), barrier, each cell of the tile computes it from LDS.
 template <int S, int P, int S0>
@@ -282,10 +376,9 @@ __device__ __forceinline__ void tile_chunks(int64_t nc, int64_t tile, double *ld
 }
 
 // The whole stage of one tile, one thread per cell (kTileCells threads).  Face terms from
-// `rate` (RATES), or from u through the face index.  LDS: (kTileCells + halo) * min(S,
-// 2) doubles.  Every thread of the workgroup must call it (barriers).  The first chunk is staged
-// before the slots are read, so that the slot loads overlap the LDS reads rather than the
-// staging (a barrier waits for every outstanding load).
+// `rate` (RATES), or from u through the face index.  LDS: (kTileCells + max halo + 1) * min(S,
+// 2) doubles.  Every thread of the workgroup must call it (barriers).  The slot loads are
+// issued while the first chunk is being staged (tile_stage_slots).
 template <int S, int P, bool RATES>
 __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds,
                                            const int32_t *__restrict__ halo_ptr,
@@ -302,16 +395,17 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
                                            double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
     constexpr int CS0 = S >= 2 ? 2 : 1;
-    const int nt = tile_stage<S, 0, CS0>(nc, tile, lds, halo_ptr, halo, ts);
+    int64_t nb[K], gf[K];
+    double w[K];
+    SlotRaw<P, RATES> raw;
+    const int nt = tile_stage_slots<S, CS0, P, RATES>(nc, tile, lds, halo_ptr, halo, ts,
+                                                      slot_local, rate, sface, raw);
     __syncthreads();
     const bool active = (int)threadIdx.x < nt;
     const int64_t c = tile * kTileCells + threadIdx.x;
-    int64_t nb[K], gf[K];
-    double w[K];
     double V = vol0;
     if (active) {
-        tile_slots<P, RATES>(nc, c, slot_local, rate, sface, u, area, area != nullptr, area0, us,
-                             nb, gf, w);
+        tile_slots_finish<P, RATES>(raw, u, area, area != nullptr, area0, us, nb, gf, w);
         if (vol) V = vol[c];
         fused_chunk<S, P, 0, CS0, CS0, 0>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt, mode,
                                           lim, out);

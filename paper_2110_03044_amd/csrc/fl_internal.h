@@ -53,6 +53,11 @@ struct HostTables {
 };
 
 constexpr int kTileCells = 256;
+// Halo entries per thread whose theta is gathered before the slot loads are issued.  The device
+// halo array carries kHaloPad extra zeros (cell 0), so that every tile, also one with an empty
+// halo at the end, has a first entry to read.
+constexpr int kHaloAhead = 3;
+constexpr int kHaloPad = 1;
 
 enum { REORDER_NONE = 0, REORDER_CURVE = 1, REORDER_BFS = 2 };
 

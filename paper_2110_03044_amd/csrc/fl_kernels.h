@@ -37,7 +37,7 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
                             const void *rec, double a, double b, double dt, int mode, double *out,
                             hipStream_t st, double us = 1.0);
 // LDS-staged stage (fused path with tile tables): per-call rates rate[2P][C] (8 bytes per slot)
-// and one workgroup per tile with lds_stage_bytes(m, S) = (tile + max halo) * min(S, 2) doubles
+// and one workgroup per tile with lds_stage_bytes(m, S) = (tile + max halo + 1) * min(S, 2) doubles
 // of dynamic LDS (scalars staged two at a time); used while that is at most kMaxStageLds (0 = no
 // tile tables).
 // The adjoint stage stages theta and lambda: adjoint_lds_bytes(m, S).  Both are 0 while

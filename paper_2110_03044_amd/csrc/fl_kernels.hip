@@ -232,8 +232,8 @@ __global__ __launch_bounds__(kBlock) void slot_rate_kernel(int64_t nc,
     }
 }
 
-// One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo) * min(S, 2)
-// doubles.
+// One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
+// min(S, 2) doubles.
 template <int S, int P, bool RATES>
 __global__ __launch_bounds__(kBlock) void fused_stage_lds_kernel(
     int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
@@ -414,7 +414,7 @@ void set_lds_stage(int on) { g_lds_stage = on; }
 // every scalar at once.
 size_t lds_stage_bytes(const fl_mesh *m, int S) {
     if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
-    return (size_t)(kTileCells + m->h.max_halo) * (S < 2 ? S : 2) * sizeof(double);
+    return (size_t)(kTileCells + m->h.max_halo + 1) * (S < 2 ? S : 2) * sizeof(double);
 }
 
 size_t adjoint_lds_bytes(const fl_mesh *m, int S) {

@@ -12,6 +12,8 @@ case, measured with the oracle alone), so the 16^3 check uses eps = 3e-8 (1.5e-7
 the velocity direction curves more than theta), against a 1e-6 relative bar.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -249,14 +251,22 @@ def test_multi_step_store_equals_single_step_stores(scheme, S):
     assert torch.equal(c, b)
 
 
+@pytest.mark.parametrize("varied", [False, True], ids=["uniform", "varied_volumes"])
 @pytest.mark.parametrize("S", [1, 3])
 @pytest.mark.parametrize("lim", ["vanalbada", "superbee"])
-def test_lds_staged_adjoint_gives_the_same_bits(lim, S):
+def test_lds_staged_adjoint_gives_the_same_bits(lim, S, varied):
     """With tile tables, the reverse stages stage theta and lambda of each tile and its halo in
-    LDS (FL_OPT_LDS_STAGE); the results must equal the global-gather kernel's bit for bit, for
-    the operator adjoint and every mode of the reverse SSP-RK3 / Euler steps.  2197 cells: ragged
-    last tile."""
+    LDS (FL_OPT_LDS_STAGE), and the cell volumes beside them where they differ; the results must
+    equal the global-gather kernel's bit for bit, for the operator adjoint and every mode of the
+    reverse SSP-RK3 / Euler steps.  2197 cells: ragged last tile.  The varied case scales every
+    cell volume and face area by a seeded factor in [0.7, 1.3] (the operator is defined for any
+    positive V_c and a_f) and also checks the operator adjoint against the oracle."""
     wl, th, rng = noisy_box(13, seed=21)
+    if varied:
+        m = wl.mesh
+        wl.mesh = dataclasses.replace(
+            m, cell_volume=m.cell_volume * rng.uniform(0.7, 1.3, m.n_cells),
+            face_area=m.face_area * rng.uniform(0.7, 1.3, m.n_faces))
     mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
     assert mesh.info.tile_cells == 256
     th = np.stack([th + 0.1 * s for s in range(S)], axis=1) if S > 1 else th
@@ -281,3 +291,10 @@ def test_lds_staged_adjoint_gives_the_same_bits(lim, S):
         FL.set_option("lds_stage", 1)
     for x, y in zip(res[1], res[0]):
         assert torch.equal(x, y)
+    if varied:
+        lam_n = host(mesh.cells_from_mesh(lam0))
+        tb_o, ub_o = O.OracleMesh.from_arrays(wl.mesh).rhs_vjp(lim, th, wl.u, lam_n)
+        got_t = host(mesh.cells_from_mesh(res[1][0]))
+        got_u = host(mesh.faces_from_mesh(res[1][1]))
+        assert np.abs(got_t - tb_o).max() <= 1e-12 * np.abs(tb_o).max()
+        assert np.abs(got_u - ub_o).max() <= 1e-12 * np.abs(ub_o).max()
