@@ -304,7 +304,7 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     rates E a_f u_f (8 bytes per slot) instead of the 16-byte records; the
  *                     adjoint stages (fl_convect_adjoint, fl_rk_step_adjoint) likewise stage theta
  *                     and lambda of all S scalars (and the cell volumes, where they differ)
- *                     where (tile_cells + max_halo) * (2 S [+ 1]) * 8 bytes fit; 0: the records
+ *                     where (tile_cells + max_halo + 1) * (2 S [+ 1]) * 8 bytes fit; 0: the records
  *                     and global gathers.  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
 // differ) of the tile and of its halo are staged in LDS, interleaved per cell, each read from
 // global memory once per tile; then every cell reads them there through the 16-bit local slot
 // indices of the forward's tile tables, and its faces from 8-byte {face, opposite face} records.
-// Dynamic LDS of (kTileCells + max halo) * (2 S + [1]) doubles.  Same arithmetic as
+// Dynamic LDS of (kTileCells + max halo + 1) * (2 S + [1]) doubles.  Same arithmetic as
 // adjoint_stage_kernel, so the results are bit-identical.
 template <int S, int P, int LIM>
 __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
@@ -279,22 +279,65 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
     const int nt = left < kTileCells ? (int)left : kTileCells;
     const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
     const int tid = threadIdx.x;
-    for (int i = tid; i < nt; i += kTileCells) {
+    // As the forward's first chunk: theta and lambda of the tile cell and of the first
+    // kHaloAhead halo entries are gathered, then the slot records are loaded, then the gathered
+    // values are stored.  No load sits in a branch, so the records stay in flight across the
+    // barrier: a lane past the tile reads its first cell, one past the halo the halo's first
+    // entry (the array is padded) and its own cell, and stores to the spare entry after the halo.
+    const int64_t xc = c0 + (tid < nt ? tid : 0);
+    double tv[S], lv[S], ht[kHaloAhead][S], hl[kHaloAhead][S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        tv[s] = th[xc * S + s];
+        lv[s] = lam[xc * S + s];
+    }
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * kTileCells;
+        const int64_t h = halo[h0 + (i < nh ? i : 0)];
+        const int64_t g = i < nh ? h : xc;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            lds[i * st + s] = th[(c0 + i) * S + s];
-            lds[i * st + S + s] = lam[(c0 + i) * S + s];
+            ht[j][s] = th[g * S + s];
+            hl[j][s] = lam[g * S + s];
         }
-        if (vol) lds[i * st + 2 * S] = vol[c0 + i];
     }
-    for (int i = tid; i < nh; i += kTileCells) {
+    __builtin_amdgcn_sched_barrier(0);
+    int2 rr[K];
+    uint32_t ll[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        rr[k] = fr[(int64_t)k * nc + xc];
+        ll[k] = slot_local[(int64_t)k * nc + xc];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        lds[tid * st + s] = tv[s];
+        lds[tid * st + S + s] = lv[s];
+    }
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * kTileCells;
+        const int e = kTileCells + (i < nh ? i : nh);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            lds[e * st + s] = ht[j][s];
+            lds[e * st + S + s] = hl[j][s];
+        }
+    }
+    for (int i = tid + kHaloAhead * kTileCells; i < nh; i += kTileCells) {
         const int64_t g = halo[h0 + i];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             lds[(kTileCells + i) * st + s] = th[g * S + s];
             lds[(kTileCells + i) * st + S + s] = lam[g * S + s];
         }
-        if (vol) lds[(kTileCells + i) * st + 2 * S] = vol[g];
+    }
+    if (vol) {
+        if (tid < nt) lds[tid * st + 2 * S] = vol[c0 + tid];
+        for (int i = tid; i < nh; i += kTileCells)
+            lds[(kTileCells + i) * st + 2 * S] = vol[halo[h0 + i]];
     }
     __syncthreads();
     if (tid >= nt) return;
@@ -303,12 +346,10 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
     int64_t nl[K], gl[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int2 r = fr[(int64_t)k * nc + x];
-        fw[k] = (uint32_t)r.x;
-        rw[k] = (uint32_t)r.y;
-        const uint32_t l = slot_local[(int64_t)k * nc + x];
-        nl[k] = l & 0xffffu;
-        gl[k] = l >> 16;
+        fw[k] = (uint32_t)rr[k].x;
+        rw[k] = (uint32_t)rr[k].y;
+        nl[k] = ll[k] & 0xffffu;
+        gl[k] = ll[k] >> 16;
     }
     adj_cell<S, P, LIM>(nc, x, tid, fw, rw, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr, st,
                         st, u, area, area0, ivol0, a, b, dt, mode, out, acc, ubar);

@@ -421,7 +421,7 @@ size_t adjoint_lds_bytes(const fl_mesh *m, int S) {
     if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local ||
         !m->d_adj_fr)
         return 0;
-    return (size_t)(kTileCells + m->h.max_halo) * (2 * S + (m->d_vol ? 1 : 0)) * sizeof(double);
+    return (size_t)(kTileCells + m->h.max_halo + 1) * (2 * S + (m->d_vol ? 1 : 0)) * sizeof(double);
 }
 
 hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st) {
