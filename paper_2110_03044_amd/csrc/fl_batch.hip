@@ -90,9 +90,10 @@ template <int S, int P>
 __device__ __forceinline__ void batch_tile(const BatchProblem &pb, int64_t tile, double *lds,
                                            const double *ts, double a, double b, int mode,
                                            double *out) {
-    dev::fused_tile<S, P, false>(pb.nc, tile, lds, pb.halo_ptr, pb.halo, pb.slot_local, nullptr,
-                          pb.sface, pb.u, pb.area, pb.area0, pb.vol, pb.vol0, ts, pb.th, a, b,
-                          pb.dt, mode, pb.lim, out, 1.0);
+    // theta_n is not loaded ahead: the 4 VGPRs it needs would cost this kernel a wave per SIMD
+    dev::fused_tile<S, P, false, false>(pb.nc, tile, lds, pb.halo_ptr, pb.halo, pb.slot_local,
+                                        nullptr, pb.sface, pb.u, pb.area, pb.area0, pb.vol,
+                                        pb.vol0, ts, pb.th, a, b, pb.dt, mode, pb.lim, out, 1.0);
 }
 
 // As batch_stage_kernel, with every tile's theta and halo staged in LDS (tiles of kTileCells

@@ -65,12 +65,14 @@ __device__ __forceinline__ double face_value_d(int lim, double tC, double du, do
 // src[i * SST + SOFF + s] for s < CS: src is theta_s itself (SST = S, SOFF = S0, global indices)
 // or a tile's LDS copy of this chunk (SST = CS, SOFF = 0, local indices); tn and out are indexed
 // by the global cell c.
-template <int S, int P, int S0, int CS, int SST, int SOFF>
+// PRE: theta_n of the chunk was loaded ahead into tnv (stage-combination mode only).
+template <int S, int P, int S0, int CS, int SST, int SOFF, bool PRE = false>
 __device__ __forceinline__ void fused_chunk(int64_t c, int64_t cs, const double *src,
                                             const double *w, const int64_t *nb, const int64_t *gf,
                                             double V, const double *__restrict__ tn, double a,
                                             double b, double dt, int mode, int lim,
-                                            double *__restrict__ out) {
+                                            double *__restrict__ out,
+                                            const double *tnv = nullptr) {
     constexpr int K = 2 * P;
     double tc[CS], tnb[K][CS], tg[K][CS];
 #pragma unroll
@@ -101,12 +103,15 @@ __device__ __forceinline__ void fused_chunk(int64_t c, int64_t cs, const double 
             acc[i] -= w[k] * face_value(lim, tC, tD, tU);
         }
     }
+    // The stage combination with its roundings written out (explicit fma), so that every kernel
+    // built on this routine rounds it alike whatever the compiler would contract.
 #pragma unroll
     for (int i = 0; i < CS; ++i) {
         const int64_t j = c * S + S0 + i;
-        if (mode == MODE_RHS) out[j] = acc[i] / V;
-        else if (mode == MODE_EULER) out[j] = tc[i] + dt * (acc[i] / V);
-        else out[j] = a * tn[j] + b * (tc[i] + dt * (acc[i] / V));
+        const double rhs = acc[i] / V;
+        if (mode == MODE_RHS) out[j] = rhs;
+        else if (mode == MODE_EULER) out[j] = fma(dt, rhs, tc[i]);
+        else out[j] = fma(b, fma(dt, rhs, tc[i]), a * (PRE ? tnv[i] : tn[j]));
     }
 }
 
@@ -272,7 +277,7 @@ struct SlotRaw {
     uint32_t fw[RATES ? 1 : 2 * P];    // face | own bit (face-index form)
 };
 
-template <int S, int CS, int P, bool RATES>
+template <int S, int CS, int P, bool RATES, bool PRE>
 __device__ __forceinline__ int tile_stage_slots(int64_t nc, int64_t tile, double *lds,
                                                 const int32_t *__restrict__ halo_ptr,
                                                 const int32_t *__restrict__ halo,
@@ -280,6 +285,7 @@ __device__ __forceinline__ int tile_stage_slots(int64_t nc, int64_t tile, double
                                                 const uint32_t *__restrict__ slot_local,
                                                 const double *__restrict__ rate,
                                                 const uint32_t *__restrict__ sface,
+                                                const double *__restrict__ tn, double *tnv,
                                                 SlotRaw<P, RATES> &raw) {
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
@@ -306,6 +312,12 @@ __device__ __forceinline__ int tile_stage_slots(int64_t nc, int64_t tile, double
         raw.l[k] = slot_local[(int64_t)k * nc + c];
         if constexpr (RATES) raw.r[k] = rate[(int64_t)k * nc + c];
         else raw.fw[k] = sface[(int64_t)k * nc + c];
+    }
+    // PRE: theta_n of the chunk (used by the stage combination only; Euler stages pass tn == ts)
+    if constexpr (PRE) {
+        const double *tnp = tn ? tn : ts;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) tnv[s] = tnp[c * S + s];
     }
     __builtin_amdgcn_sched_barrier(0);
     // every lane stores (tid < kTileCells): entries past nt are never read
@@ -378,8 +390,10 @@ __device__ __forceinline__ void tile_chunks(int64_t nc, int64_t tile, double *ld
 // The whole stage of one tile, one thread per cell (kTileCells threads).  Face terms from
 // `rate` (RATES), or from u through the face index.  LDS: (kTileCells + max halo + 1) * min(S,
 // 2) doubles.  Every thread of the workgroup must call it (barriers).  The slot loads are
-// issued while the first chunk is being staged (tile_stage_slots).
-template <int S, int P, bool RATES>
+// issued while the first chunk is being staged (tile_stage_slots), and with PRE the first
+// chunk's theta_n too (4 more VGPRs at most: kernels whose occupancy they would lower pass
+// false).
+template <int S, int P, bool RATES, bool PRE = true>
 __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds,
                                            const int32_t *__restrict__ halo_ptr,
                                            const int32_t *__restrict__ halo,
@@ -398,8 +412,9 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
     int64_t nb[K], gf[K];
     double w[K];
     SlotRaw<P, RATES> raw;
-    const int nt = tile_stage_slots<S, CS0, P, RATES>(nc, tile, lds, halo_ptr, halo, ts,
-                                                      slot_local, rate, sface, raw);
+    double tnv[CS0];
+    const int nt = tile_stage_slots<S, CS0, P, RATES, PRE>(nc, tile, lds, halo_ptr, halo, ts,
+                                                           slot_local, rate, sface, tn, tnv, raw);
     __syncthreads();
     const bool active = (int)threadIdx.x < nt;
     const int64_t c = tile * kTileCells + threadIdx.x;
@@ -407,8 +422,8 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
     if (active) {
         tile_slots_finish<P, RATES>(raw, u, area, area != nullptr, area0, us, nb, gf, w);
         if (vol) V = vol[c];
-        fused_chunk<S, P, 0, CS0, CS0, 0>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt, mode,
-                                          lim, out);
+        fused_chunk<S, P, 0, CS0, CS0, 0, PRE>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt,
+                                               mode, lim, out, tnv);
     }
     tile_chunks<S, P, CS0>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf, V, tn, a, b,
                            dt, mode, lim, out);

@@ -122,11 +122,12 @@ __device__ __forceinline__ void finish_cell(int64_t c, const double *acc, double
         for (int k = 0; k < S; ++k) out[c * S + k] = acc[k] / V;
     } else if (mode == MODE_EULER) {
 #pragma unroll
-        for (int k = 0; k < S; ++k) out[c * S + k] = ts[c * S + k] + dt * (acc[k] / V);
+        for (int k = 0; k < S; ++k) out[c * S + k] = fma(dt, acc[k] / V, ts[c * S + k]);
     } else {
+        // rounded as the fused stage rounds it (explicit fma)
 #pragma unroll
         for (int k = 0; k < S; ++k)
-            out[c * S + k] = a * tn[c * S + k] + b * (ts[c * S + k] + dt * (acc[k] / V));
+            out[c * S + k] = fma(b, fma(dt, acc[k] / V, ts[c * S + k]), a * tn[c * S + k]);
     }
 }
 
