@@ -436,13 +436,24 @@ def main():
                    halo_total=int(info.halo_total))
         return res
 
-    # A plain device copy of known size (untimed): its FETCH_SIZE / WRITE_SIZE counters calibrate
-    # the fused kernel's counters in profiled runs.
+    # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the fused
+    # kernel's counters in profiled runs, and five more copies, timed, give the bandwidth a plain
+    # copy reaches on this GPU (read + write bytes / time): context for the roofline fraction.
+    copy_gbs = None
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream(dev)
+        c0.record(stream)
+        for _ in range(5):
+            dst.copy_(src)
+        c1.record(stream)
+        c1.synchronize()
+        copy_gbs = 5 * 2 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        log(f"device copy of {args.calib_copy_mib} MiB: {copy_gbs:.0f} GB/s (read + write)")
         del src, dst
 
     reorder = not args.no_reorder
@@ -498,7 +509,10 @@ def main():
                            "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds),
                            "algorithmic_bytes_per_launch": int(bytes_per_step / 3),
-                           "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+                           "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                           "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+                           "frac_of_copy": None if copy_gbs is None else
+                           round(achieved / copy_gbs, 4)}
     # context: the face-kernel + cell-kernel byte model (40 B/face + 60 B/cell per stage, with a
     # flux array written and gathered back); the fused stage never forms that array, so the
     # model's effective bandwidth can exceed the HBM peak
