@@ -115,6 +115,23 @@ __device__ __forceinline__ void load_s(const double *src, int64_t i, int stride,
     for (int s = 0; s < S; ++s) v[s] = src[i * stride + s];
 }
 
+// Face velocities and the u_bar entries of the faces the cell owns, requested before the slot
+// loop (the per-slot theta / lambda reads stay next to their use: hoisting them as well raised
+// register use and measured slower at 128^3).  u_bar is read once and written once per face
+// (the slot faces are distinct, so the loads need not wait for earlier slots' stores).
+template <int P>
+__device__ __forceinline__ void adj_velocities(const uint32_t *fw, const uint32_t *rw,
+                                               const double *__restrict__ u,
+                                               const double *__restrict__ ubar, double *ufk,
+                                               double *urk, double *ubk) {
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        ufk[k] = u[fw[k] & 0x7fffffffu];
+        urk[k] = u[rw[k] & 0x7fffffffu];
+        ubk[k] = (ubar != nullptr && (fw[k] >> 31)) ? ubar[fw[k] & 0x7fffffffu] : 0.0;
+    }
+}
+
 // mode: ADJ_APPLY    theta_bar[x] += J^T lam, u_bar += (dL/du)^T lam            (scale 1)
 //       ADJ_EULER    out[x] = lam[x] + dt J^T lam                               (b = 1)
 //       ADJ_LAST     acc[x] = a lam[x];  out[x] = b (lam[x] + dt J^T lam)
@@ -128,13 +145,16 @@ __device__ __forceinline__ void load_s(const double *src, int64_t i, int stride,
 // tsrc[i * stride + s], lsrc[i * stride + s] and vsrc[i * vstride] (vsrc NULL: all volumes are
 // 1 / ivol0): the global arrays (stride S, vstride 1, source index = global index) or a tile's
 // LDS copy (interleaved per cell).
+// ufk, urk, ubk0: slot k's face velocity, the opposite face's velocity and the face's u_bar
+// entry (0 where x does not own it), loaded by adj_velocities.
 template <int S, int P, int LIM>
 __device__ __forceinline__ void adj_cell(
     int64_t nc, int64_t x, int64_t xi, const uint32_t *fw, const uint32_t *rw,
     const int64_t *nbi, const int64_t *gfi, const double *tsrc, const double *lsrc,
-    const double *vsrc, int stride, int vstride, const double *__restrict__ u,
-    const double *__restrict__ area, double area0, double ivol0, double a, double b, double dt,
-    int mode, double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
+    const double *vsrc, int stride, int vstride, const double *ufk, const double *urk,
+    const double *ubk0, const double *__restrict__ area, double area0, double ivol0, double a,
+    double b, double dt, int mode, double *__restrict__ out, double *__restrict__ acc,
+    double *__restrict__ ubar) {
     constexpr int K = 2 * P;
     double tx[S], lx[S], tn[K][S];
     load_s<S>(tsrc, xi, stride, tx);
@@ -147,17 +167,9 @@ __device__ __forceinline__ void adj_cell(
     double jt[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) jt[s] = 0.0;
-    // Face velocities and the u_bar entries of the faces this cell owns are requested up front;
-    // the per-slot theta / lambda reads stay next to their use (hoisting them as well raised
-    // register use and measured slower at 128^3).  u_bar is read once and written once per face
-    // (the slot faces are distinct, so the loads need not wait for earlier slots' stores).
-    double ufk[K], urk[K], ubk[K];
+    double ubk[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        ufk[k] = u[fw[k] & 0x7fffffffu];
-        urk[k] = u[rw[k] & 0x7fffffffu];
-        ubk[k] = (ubar != nullptr && (fw[k] >> 31)) ? ubar[fw[k] & 0x7fffffffu] : 0.0;
-    }
+    for (int k = 0; k < K; ++k) ubk[k] = ubk0[k];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t f = fw[k] & 0x7fffffffu, fr = rw[k] & 0x7fffffffu;
@@ -252,8 +264,10 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     uint32_t fw[K], rw[K];
     int64_t nb[K], gf[K];
     read_rec<P>(nc, x, rec, fw, rw, nb, gf);
-    adj_cell<S, P, LIM>(nc, x, x, fw, rw, nb, gf, th, lam, vol, S, 1, u, area, area0, ivol0, a, b,
-                        dt, mode, out, acc, ubar);
+    double ufk[K], urk[K], ubk[K];
+    adj_velocities<P>(fw, rw, u, ubar, ufk, urk, ubk);
+    adj_cell<S, P, LIM>(nc, x, x, fw, rw, nb, gf, th, lam, vol, S, 1, ufk, urk, ubk, area, area0,
+                        ivol0, a, b, dt, mode, out, acc, ubar);
 }
 
 // One workgroup per tile of kTileCells cells: theta, lambda (and the volume, where volumes
@@ -310,6 +324,16 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
         rr[k] = fr[(int64_t)k * nc + xc];
         ll[k] = slot_local[(int64_t)k * nc + xc];
     }
+    // the records are needed now: their velocity and u_bar gathers then stay in flight across
+    // the barrier as well (the records arrive right behind the theta / lambda gathers)
+    uint32_t fw[K], rw[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        fw[k] = (uint32_t)rr[k].x;
+        rw[k] = (uint32_t)rr[k].y;
+    }
+    double ufk[K], urk[K], ubk[K];
+    adj_velocities<P>(fw, rw, u, ubar, ufk, urk, ubk);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -342,17 +366,14 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
     __syncthreads();
     if (tid >= nt) return;
     const int64_t x = c0 + tid;
-    uint32_t fw[K], rw[K];
     int64_t nl[K], gl[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        fw[k] = (uint32_t)rr[k].x;
-        rw[k] = (uint32_t)rr[k].y;
         nl[k] = ll[k] & 0xffffu;
         gl[k] = ll[k] >> 16;
     }
     adj_cell<S, P, LIM>(nc, x, tid, fw, rw, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr, st,
-                        st, u, area, area0, ivol0, a, b, dt, mode, out, acc, ubar);
+                        st, ufk, urk, ubk, area, area0, ivol0, a, b, dt, mode, out, acc, ubar);
 }
 
 }  // namespace adev
