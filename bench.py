@@ -250,9 +250,13 @@ def deformation(args, torch, FL, W, dev):
     face-update rate of each run."""
     out = []
     for n in [int(x) for x in args.deformation.split(",") if x]:
+        t0 = time.time()
         wl = W.workload_deformation(n)
         sc = W.deformation_scales(wl.steps, wl.dt, 3.0, wl.scheme)
+        log(f"  deformation {n}^3: workload built in {time.time() - t0:.1f} s")
+        t0 = time.time()
         mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+        log(f"  deformation {n}^3: mesh tables built and uploaded in {time.time() - t0:.1f} s")
         th0 = mesh.cells_to_mesh(torch.from_numpy(wl.theta0).to(dev))
         u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
         th = th0.clone()

@@ -126,7 +126,10 @@ fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face
  *   face_area   double [n_faces] or NULL (= 1);   cell_volume double [n_cells] or NULL (= 1).
  * device = -1 builds a host-only mesh (tables, validation and export work; compute calls
  * return FL_E_NODEVICE).  On success *out owns device memory until fl_mesh_destroy; the mesh is
- * immutable and may be used from several streams at once. */
+ * immutable and may be used from several streams at once.  The host loops run on the OpenMP
+ * threads of the calling process (OMP_NUM_THREADS); the tables do not depend on their number.
+ * With the environment variable FL_MESH_PROGRESS set, each phase reports its wall time on
+ * stderr. */
 fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                          const double *face_normal, const double *face_area,
                          const double *cell_volume, int device, uint32_t flags, fl_mesh **out);

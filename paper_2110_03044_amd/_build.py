@@ -28,7 +28,8 @@ def sources():
 
 
 CXX = os.environ.get("CXX", "g++")
-HOST = ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
+# host code (mesh preprocessing) runs its loops on the host's cores with GCC's OpenMP runtime
+HOST = ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-fopenmp"]
 
 
 def _compile(src: str) -> str:
@@ -49,7 +50,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lgomp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -261,6 +261,7 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
             }
             const HostTables &h = m->h;
             std::vector<int32_t> fc4((size_t)h.nf * 4);
+#pragma omp parallel for schedule(static)
             for (int64_t f = 0; f < h.nf; ++f) {
                 fc4[4 * f] = h.fc[2 * f];
                 fc4[4 * f + 1] = h.fc[2 * f + 1];
@@ -286,6 +287,7 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                     // bit, neighbour, far cell}: one 16-byte load per slot in the reverse kernel
                     const size_t n = h.slot_face.size();
                     std::vector<int32_t> rec(4 * n);
+#pragma omp parallel for schedule(static)
                     for (size_t i = 0; i < n; ++i) {
                         rec[4 * i] = (int32_t)h.slot_face[i];
                         rec[4 * i + 1] = (int32_t)h.slot_rev[i];
@@ -297,6 +299,7 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                 if (st == FL_OK && h.max_halo >= 0) {
                     const size_t n = h.slot_face.size();
                     std::vector<int32_t> fr(2 * n);
+#pragma omp parallel for schedule(static)
                     for (size_t i = 0; i < n; ++i) {
                         fr[2 * i] = (int32_t)h.slot_face[i];
                         fr[2 * i + 1] = (int32_t)h.slot_rev[i];

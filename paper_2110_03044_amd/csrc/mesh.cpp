@@ -15,17 +15,52 @@
 //     (far cell, weight) pairs;
 //   * where every cell's faces form opposite pairs, the per-cell slot tables of the fused kernel;
 //   * optionally a renumbering for gather locality (space-filling curve or breadth-first).
+//
+// The loops over faces, cells and tiles run on the host's cores (OpenMP).  Every parallel loop
+// writes disjoint outputs or reduces with min / max / and, and every sort has unique keys, so
+// the tables (and the first error reported) are the same for any thread count.
+//
+// With the environment variable FL_MESH_PROGRESS set, each phase reports its wall time on
+// stderr (a mesh of 10^8 cells takes minutes).
+#include <omp.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <parallel/algorithm>
 #include <sstream>
 
 #include "fl_internal.h"
 
 namespace fl {
 namespace {
+
+// Phase timing on stderr when FL_MESH_PROGRESS is set.
+class Progress {
+  public:
+    Progress() : on_(std::getenv("FL_MESH_PROGRESS") != nullptr), t_(now()) {}
+    void operator()(const char *phase, int64_t nc) {
+        if (!on_) return;
+        const double t = now();
+        std::fprintf(stderr, "fl_mesh_create: %s (%lld cells) %.1f s\n", phase, (long long)nc,
+                     t - t_);
+        std::fflush(stderr);
+        t_ = t;
+    }
+
+  private:
+    static double now() {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+            .count();
+    }
+    bool on_;
+    double t_;
+};
 
 constexpr double kWeightTol = 1e-9;
 constexpr double kNormTol = 1e-12;
@@ -39,16 +74,29 @@ Csr cell_faces(int64_t nc, int64_t nf, const int32_t *fc) {
     Csr c;
     c.ptr.assign(nc + 1, 0);
     c.idx.resize(2 * nf);
+    int64_t *ptr = c.ptr.data();
+#pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; ++f) {
-        c.ptr[fc[2 * f] + 1]++;
-        c.ptr[fc[2 * f + 1] + 1]++;
+#pragma omp atomic
+        ptr[fc[2 * f] + 1]++;
+#pragma omp atomic
+        ptr[fc[2 * f + 1] + 1]++;
     }
-    for (int64_t i = 0; i < nc; ++i) c.ptr[i + 1] += c.ptr[i];
+    for (int64_t i = 0; i < nc; ++i) ptr[i + 1] += ptr[i];
     std::vector<int64_t> fill(c.ptr.begin(), c.ptr.end() - 1);
-    for (int64_t f = 0; f < nf; ++f) {
-        c.idx[fill[fc[2 * f]]++] = (int32_t)f;
-        c.idx[fill[fc[2 * f + 1]]++] = (int32_t)f;
-    }
+    int64_t *fl = fill.data();
+    int32_t *idx = c.idx.data();
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < nf; ++f)
+        for (int side = 0; side < 2; ++side) {
+            int64_t at;
+#pragma omp atomic capture
+            at = fl[fc[2 * f + side]]++;
+            idx[at] = (int32_t)f;
+        }
+    // each list in ascending face order, whatever order the threads filled it in
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nc; ++i) std::sort(idx + ptr[i], idx + ptr[i + 1]);
     return c;
 }
 
@@ -56,57 +104,79 @@ inline int32_t other(const int32_t *fc, int64_t f, int64_t c) {
     return fc[2 * f] == c ? fc[2 * f + 1] : fc[2 * f];
 }
 
+// FL_OK, or the status for invalid face f (reported through fail() when `report`).
+fl_status check_face(int64_t nc, const int32_t *fc, const double *nrm, int64_t f, bool report);
+
 fl_status check_basic(int64_t nc, int64_t nf, const int32_t *fc, const double *nrm) {
     if (!fc || !nrm) return fail(FL_E_INVALID, "face_cells and face_normal must not be NULL");
     if (nc < 1 || nf < 1) return fail(FL_E_INVALID, "n_cells and n_faces must be positive");
     if (nc > (int64_t)std::numeric_limits<int32_t>::max() - 1 || nf > (int64_t)(1 << 30) - 1)
         return fail(FL_E_INVALID, "mesh too large for 32-bit cell and face indices");
-    for (int64_t f = 0; f < nf; ++f) {
-        int64_t a = fc[2 * f], b = fc[2 * f + 1];
-        if (b == -1 || a == -1) {
-            std::ostringstream os;
-            os << "face " << f << " is a boundary face (one cell); only closed (periodic) meshes "
-                  "are supported";
-            return fail(FL_E_UNSUPPORTED, os.str());
-        }
-        if (a < 0 || a >= nc || b < 0 || b >= nc) {
-            std::ostringstream os;
-            os << "face " << f << " references a cell outside [0, " << nc << ")";
-            return fail(FL_E_TOPOLOGY, os.str());
-        }
-        if (a == b) {
-            std::ostringstream os;
-            os << "face " << f << " joins cell " << a << " to itself";
-            return fail(FL_E_TOPOLOGY, os.str());
-        }
-        const double *n = nrm + 3 * f;
-        double n2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
-        if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > kNormTol) {
-            std::ostringstream os;
-            os << "face " << f << " normal is not a finite unit vector";
-            return fail(FL_E_INVALID, os.str());
-        }
+    int64_t bad = nf;  // the lowest invalid face
+#pragma omp parallel for schedule(static) reduction(min : bad)
+    for (int64_t f = 0; f < nf; ++f)
+        if (check_face(nc, fc, nrm, f, false) != FL_OK) bad = std::min(bad, f);
+    return bad < nf ? check_face(nc, fc, nrm, bad, true) : FL_OK;
+}
+
+fl_status check_face(int64_t nc, const int32_t *fc, const double *nrm, int64_t f, bool report) {
+    auto err = [&](fl_status st, const std::string &m) { return report ? fail(st, m) : st; };
+    const int64_t a = fc[2 * f], b = fc[2 * f + 1];
+    if (b == -1 || a == -1) {
+        std::ostringstream os;
+        os << "face " << f << " is a boundary face (one cell); only closed (periodic) meshes "
+              "are supported";
+        return err(FL_E_UNSUPPORTED, os.str());
+    }
+    if (a < 0 || a >= nc || b < 0 || b >= nc) {
+        std::ostringstream os;
+        os << "face " << f << " references a cell outside [0, " << nc << ")";
+        return err(FL_E_TOPOLOGY, os.str());
+    }
+    if (a == b) {
+        std::ostringstream os;
+        os << "face " << f << " joins cell " << a << " to itself";
+        return err(FL_E_TOPOLOGY, os.str());
+    }
+    const double *n = nrm + 3 * f;
+    const double n2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > kNormTol) {
+        std::ostringstream os;
+        os << "face " << f << " normal is not a finite unit vector";
+        return err(FL_E_INVALID, os.str());
     }
     return FL_OK;
 }
 
+// Cell c's faces sorted by the cell beyond them; returns the index i > 0 of the first pair of
+// faces (i - 1, i) that join c to the same cell, or 0.
+size_t duplicate_at(const int32_t *fc, const Csr &cs, int64_t c,
+                    std::vector<std::pair<int32_t, int32_t>> &nb) {
+    nb.clear();
+    for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p)
+        nb.emplace_back(other(fc, cs.idx[p], c), cs.idx[p]);
+    std::sort(nb.begin(), nb.end());
+    for (size_t i = 1; i < nb.size(); ++i)
+        if (nb[i].first == nb[i - 1].first) return i;
+    return 0;
+}
+
 fl_status check_duplicates(int64_t nc, const int32_t *fc, const Csr &cs) {
-    std::vector<std::pair<int32_t, int32_t>> nb;
-    for (int64_t c = 0; c < nc; ++c) {
-        nb.clear();
-        for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p)
-            nb.emplace_back(other(fc, cs.idx[p], c), cs.idx[p]);
-        std::sort(nb.begin(), nb.end());
-        for (size_t i = 1; i < nb.size(); ++i)
-            if (nb[i].first == nb[i - 1].first) {
-                std::ostringstream os;
-                os << "faces " << nb[i - 1].second << " and " << nb[i].second
-                   << " both join cells " << c << " and " << nb[i].first
-                   << " (a periodic side shorter than 3 cells?)";
-                return fail(FL_E_TOPOLOGY, os.str());
-            }
+    int64_t bad = nc;  // the lowest cell with two faces to one neighbour
+#pragma omp parallel reduction(min : bad)
+    {
+        std::vector<std::pair<int32_t, int32_t>> nb;
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < nc; ++c)
+            if (duplicate_at(fc, cs, c, nb)) bad = std::min(bad, c);
     }
-    return FL_OK;
+    if (bad == nc) return FL_OK;
+    std::vector<std::pair<int32_t, int32_t>> nb;
+    const size_t i = duplicate_at(fc, cs, bad, nb);
+    std::ostringstream os;
+    os << "faces " << nb[i - 1].second << " and " << nb[i].second << " both join cells " << bad
+       << " and " << nb[i].first << " (a periodic side shorter than 3 cells?)";
+    return fail(FL_E_TOPOLOGY, os.str());
 }
 
 // Weight of face j of cell C for face f with flow sign s: s (n_f . t_j), t_j = n_j oriented into C.
@@ -124,8 +194,10 @@ bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
                 std::vector<int32_t> &far, std::vector<int32_t> &opp) {
     far.assign(2 * nf, -1);
     opp.assign(2 * nf, -1);
+    bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
     for (int64_t f = 0; f < nf; ++f) {
-        for (int side = 0; side < 2; ++side) {
+        for (int side = 0; side < 2 && ok; ++side) {
             const int64_t C = fc[2 * f + side];
             const double s = side == 0 ? 1.0 : -1.0;
             int count = 0;
@@ -142,15 +214,18 @@ bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
                 }
             }
             if (count != 1 || std::fabs(ww - 1.0) > kWeightTol) {
-                far.assign(2 * nf, -1);
-                opp.assign(2 * nf, -1);
-                return false;
+                ok = false;
+                continue;
             }
             far[2 * f + side] = other(fc, jj, C);
             opp[2 * f + side] = (int32_t)jj;
         }
     }
-    return true;
+    if (!ok) {
+        far.assign(2 * nf, -1);
+        opp.assign(2 * nf, -1);
+    }
+    return ok;
 }
 
 // General cells: for every face side, the cells beyond the other faces of C with their nonzero
@@ -225,37 +300,86 @@ std::vector<int32_t> bfs_numbering(int64_t nc, const int32_t *fc, const Csr &cs)
 // cells a workgroup gathers from lie in it or in the blocks next to it.  Returns new_of_old.
 std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double *nrm,
                                      const Csr &cs) {
+    // The walk runs level by level on all cores and visits the cells in exactly the order of a
+    // serial first-in-first-out walk: a cell's parent is its neighbour of the previous level
+    // that comes first in that order (smallest (queue position, face position) claim), and each
+    // cell of a level emits the children it won in its face order.
+    constexpr uint64_t kUnseen = ~0ULL, kDone = 0;  // claims are 1 + q * D + p
+    int64_t D = 1;
+    for (int64_t c = 0; c < nc; ++c) D = std::max<int64_t>(D, cs.ptr[c + 1] - cs.ptr[c] + 1);
     std::vector<double> pos(3 * nc, 0.0);
-    std::vector<char> seen(nc, 0);
-    std::vector<int32_t> queue;
-    queue.reserve(nc);
+    std::vector<uint64_t> claim(nc, kUnseen);
+    std::vector<int32_t> frontier, next;
+    std::vector<int64_t> cnt;
     double lo[3] = {0, 0, 0};
-    int64_t next_unseen = 0;
+    int64_t next_unseen = 0, found = 0;
     double comp_shift = 0.0;  // separate components along x
-    while ((int64_t)queue.size() < nc) {
-        while (seen[next_unseen]) ++next_unseen;
-        size_t head = queue.size();
-        queue.push_back((int32_t)next_unseen);
-        seen[next_unseen] = 1;
-        pos[3 * next_unseen] = comp_shift;
+    while (found < nc) {
+        while (claim[next_unseen] != kUnseen) ++next_unseen;
+        const int64_t root = next_unseen;
+        claim[root] = kDone;
+        pos[3 * root] = comp_shift;
+        ++found;
         double hi_x = comp_shift;
-        while (head < queue.size()) {
-            int64_t c = queue[head++];
-            for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
-                int64_t f = cs.idx[p];
-                int64_t o = other(fc, f, c);
-                if (seen[o]) continue;
-                seen[o] = 1;
-                double s = fc[2 * f] == c ? 1.0 : -1.0;
-                for (int d = 0; d < 3; ++d) pos[3 * o + d] = pos[3 * c + d] + s * nrm[3 * f + d];
-                hi_x = std::max(hi_x, pos[3 * o]);
-                queue.push_back((int32_t)o);
+        frontier.assign(1, (int32_t)root);
+        while (!frontier.empty()) {
+            const int64_t nq = (int64_t)frontier.size();
+#pragma omp parallel for schedule(static)
+            for (int64_t q = 0; q < nq; ++q) {
+                const int64_t c = frontier[q];
+                for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+                    const int64_t o = other(fc, cs.idx[p], c);
+                    const uint64_t key = 1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c]);
+                    uint64_t cur = __atomic_load_n(&claim[o], __ATOMIC_RELAXED);
+                    while (key < cur && !__atomic_compare_exchange_n(&claim[o], &cur, key, true,
+                                                                     __ATOMIC_RELAXED,
+                                                                     __ATOMIC_RELAXED)) {
+                    }
+                }
             }
+            cnt.assign(nq + 1, 0);
+#pragma omp parallel for schedule(static)
+            for (int64_t q = 0; q < nq; ++q) {
+                const int64_t c = frontier[q];
+                int64_t k = 0;
+                for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p)
+                    k += claim[other(fc, cs.idx[p], c)] ==
+                         1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c]);
+                cnt[q + 1] = k;
+            }
+            for (int64_t q = 0; q < nq; ++q) cnt[q + 1] += cnt[q];
+            next.resize(cnt[nq]);
+#pragma omp parallel for schedule(static) reduction(max : hi_x)
+            for (int64_t q = 0; q < nq; ++q) {
+                const int64_t c = frontier[q];
+                int64_t at = cnt[q];
+                for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+                    const int64_t f = cs.idx[p];
+                    const int64_t o = other(fc, f, c);
+                    if (claim[o] != 1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c])) continue;
+                    const double s = fc[2 * f] == c ? 1.0 : -1.0;
+                    for (int d = 0; d < 3; ++d) pos[3 * o + d] = pos[3 * c + d] + s * nrm[3 * f + d];
+                    hi_x = std::max(hi_x, pos[3 * o]);
+                    next[at++] = (int32_t)o;
+                }
+            }
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < (int64_t)next.size(); ++i) claim[next[i]] = kDone;
+            found += (int64_t)next.size();
+            frontier.swap(next);
         }
         comp_shift = hi_x + 2.0;
     }
-    for (int64_t c = 0; c < nc; ++c)
-        for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], pos[3 * c + d]);
+    double lo0 = 0.0, lo1 = 0.0, lo2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(min : lo0, lo1, lo2)
+    for (int64_t c = 0; c < nc; ++c) {
+        lo0 = std::min(lo0, pos[3 * c]);
+        lo1 = std::min(lo1, pos[3 * c + 1]);
+        lo2 = std::min(lo2, pos[3 * c + 2]);
+    }
+    lo[0] = lo0;
+    lo[1] = lo1;
+    lo[2] = lo2;
     auto spread = [](uint64_t v) {  // 21 bits -> every third bit
         v &= 0x1fffff;
         v = (v | v << 32) & 0x1f00000000ffffULL;
@@ -266,13 +390,15 @@ std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double
         return v;
     };
     std::vector<std::pair<uint64_t, int32_t>> key(nc);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
         uint64_t q[3];
         for (int d = 0; d < 3; ++d) q[d] = (uint64_t)std::llround(pos[3 * c + d] - lo[d]);
         key[c] = {spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2, (int32_t)c};
     }
-    std::sort(key.begin(), key.end());
+    __gnu_parallel::sort(key.begin(), key.end());  // keys unique (cell index)
     std::vector<int32_t> new_of_old(nc);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nc; ++i) new_of_old[key[i].second] = (int32_t)i;
     return new_of_old;
 }
@@ -282,20 +408,33 @@ std::vector<int32_t> face_numbering(int64_t nc, int64_t nf, const int32_t *fc,
                                     const std::vector<int32_t> &cnew) {
     std::vector<int64_t> cnt(nc + 1, 0);
     std::vector<int32_t> lo(nf), hi(nf);
+    int64_t *cp = cnt.data();
+#pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; ++f) {
         int32_t a = cnew[fc[2 * f]], b = cnew[fc[2 * f + 1]];
         lo[f] = std::min(a, b);
         hi[f] = std::max(a, b);
-        cnt[lo[f] + 1]++;
+#pragma omp atomic
+        cp[lo[f] + 1]++;
     }
     for (int64_t i = 0; i < nc; ++i) cnt[i + 1] += cnt[i];
     std::vector<int32_t> bucket(nf);
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t f = 0; f < nf; ++f) bucket[fill[lo[f]]++] = (int32_t)f;
+    int64_t *fp = fill.data();
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t at;
+#pragma omp atomic capture
+        at = fp[lo[f]]++;
+        bucket[at] = (int32_t)f;
+    }
+    // (hi, f) is unique within a bucket: the order does not depend on how it was filled
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c)
         std::sort(bucket.begin() + cnt[c], bucket.begin() + cnt[c + 1],
                   [&](int32_t x, int32_t y) { return hi[x] < hi[y] || (hi[x] == hi[y] && x < y); });
     std::vector<int32_t> fnew(nf);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nf; ++i) fnew[bucket[i]] = (int32_t)i;
     return fnew;
 }
@@ -308,19 +447,23 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
     const int32_t *fc = t.fc.data();
     auto side_of = [&](int64_t f, int64_t c) { return fc[2 * f] == c ? 0 : 1; };
     // opposite faces must pair up: opp(c, opp(c, f)) == f
+    bool paired = true;
+#pragma omp parallel for schedule(static) reduction(&& : paired)
     for (int64_t c = 0; c < nc; ++c)
         for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
             int64_t f = cs.idx[p];
             int64_t j = opp[2 * f + side_of(f, c)];
-            if (opp[2 * j + side_of(j, c)] != f) return;
+            if (opp[2 * j + side_of(j, c)] != f) paired = false;
         }
+    if (!paired) return;
     const int K = t.max_degree, P = K / 2;
     t.slot_face.assign((size_t)K * nc, 0);
     t.slot_nbr.assign((size_t)K * nc, 0);
     t.slot_far.assign((size_t)K * nc, 0);
     t.slot_rev.assign((size_t)K * nc, 0);
-    std::vector<int32_t> slots(K);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
+        int32_t slots[6];
         int q = 0;
         for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
             int32_t f = cs.idx[p];
@@ -356,11 +499,13 @@ void build_tiles(HostTables &t) {
     const int64_t ntiles = (nc + kTileCells - 1) / kTileCells;
     std::vector<int32_t> ptr(ntiles + 1, 0), halo;
     std::vector<uint32_t> local((size_t)K * nc, 0);
-    std::vector<int32_t> refs;
+    std::vector<std::vector<int32_t>> tile_refs(ntiles);
     int32_t max_halo = 0;
+    bool fits = true;
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo) reduction(&& : fits)
     for (int64_t tile = 0; tile < ntiles; ++tile) {
         const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
-        refs.clear();
+        std::vector<int32_t> &refs = tile_refs[tile];
         for (int64_t k = 0; k < K; ++k)
             for (int64_t c = c0; c < c1; ++c) {
                 const int32_t n = t.slot_nbr[k * nc + c], g = t.slot_far[k * nc + c];
@@ -369,7 +514,10 @@ void build_tiles(HostTables &t) {
             }
         std::sort(refs.begin(), refs.end());
         refs.erase(std::unique(refs.begin(), refs.end()), refs.end());
-        if (kTileCells + refs.size() > 65535) return;  // local indices are 16-bit
+        if (kTileCells + refs.size() > 65535) {  // local indices are 16-bit
+            fits = false;
+            continue;
+        }
         max_halo = std::max<int32_t>(max_halo, (int32_t)refs.size());
         auto loc = [&](int32_t cell) -> uint32_t {
             if (cell >= c0 && cell < c1) return (uint32_t)(cell - c0);
@@ -378,10 +526,19 @@ void build_tiles(HostTables &t) {
         for (int64_t k = 0; k < K; ++k)
             for (int64_t c = c0; c < c1; ++c)
                 local[k * nc + c] = loc(t.slot_nbr[k * nc + c]) | (loc(t.slot_far[k * nc + c]) << 16);
-        halo.insert(halo.end(), refs.begin(), refs.end());
-        if (halo.size() > (size_t)INT32_MAX) return;
-        ptr[tile + 1] = (int32_t)halo.size();
     }
+    if (!fits) return;
+    // the halos one after the other, in tile order
+    size_t total = 0;
+    for (int64_t tile = 0; tile < ntiles; ++tile) {
+        total += tile_refs[tile].size();
+        if (total > (size_t)INT32_MAX) return;
+        ptr[tile + 1] = (int32_t)total;
+    }
+    halo.resize(total);
+#pragma omp parallel for schedule(static)
+    for (int64_t tile = 0; tile < ntiles; ++tile)
+        std::copy(tile_refs[tile].begin(), tile_refs[tile].end(), halo.begin() + ptr[tile]);
     t.halo_ptr.swap(ptr);
     t.halo.swap(halo);
     t.slot_local.swap(local);
@@ -393,6 +550,7 @@ void build_tiles(HostTables &t) {
 fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
                             const double *face_normal, const double *face_area,
                             const double *cell_volume, int reorder, HostTables &t) {
+    Progress progress;
     fl_status st = check_basic(nc, nf, face_cells, face_normal);
     if (st != FL_OK) return st;
     if (face_area)
@@ -416,14 +574,17 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     Csr cs = cell_faces(nc, nf, t.fc.data());
     st = check_duplicates(nc, t.fc.data(), cs);
     if (st != FL_OK) return st;
+    progress("validated", nc);
 
     if (reorder) {
         std::vector<int32_t> cnew = reorder == REORDER_BFS
                                         ? bfs_numbering(nc, t.fc.data(), cs)
                                         : curve_numbering(nc, t.fc.data(), t.nrm.data(), cs);
+        progress("cells renumbered", nc);
         std::vector<int32_t> fnew = face_numbering(nc, nf, t.fc.data(), cnew);
         std::vector<int32_t> fc2(2 * nf);
         std::vector<double> nrm2(3 * nf);
+#pragma omp parallel for schedule(static)
         for (int64_t f = 0; f < nf; ++f) {
             int64_t g = fnew[f];
             fc2[2 * g] = cnew[t.fc[2 * f]];
@@ -432,11 +593,13 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
         }
         if (!area.empty()) {
             std::vector<double> a2(nf);
+#pragma omp parallel for schedule(static)
             for (int64_t f = 0; f < nf; ++f) a2[fnew[f]] = area[f];
             area.swap(a2);
         }
         if (!vol.empty()) {
             std::vector<double> v2(nc);
+#pragma omp parallel for schedule(static)
             for (int64_t c = 0; c < nc; ++c) v2[cnew[c]] = vol[c];
             vol.swap(v2);
         }
@@ -445,6 +608,7 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
         t.cell_perm.swap(cnew);
         t.face_perm.swap(fnew);
         cs = cell_faces(nc, nf, t.fc.data());
+        progress("faces renumbered", nc);
     }
 
     // uniform area / volume are kept as one scalar
@@ -461,24 +625,29 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     t.general = !far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
     if (t.general && !side_lists(nf, t.fc.data(), t.nrm.data(), cs, t))
         return fail(FL_E_UNSUPPORTED, "too many projected faces for 32-bit side lists");
+    progress("far-upwind cells", nc);
 
     t.cf_ptr.resize(nc + 1);
     t.cf_idx.resize(2 * nf);
-    t.max_degree = 0;
+    int32_t max_degree = 0;
     int32_t min_degree = std::numeric_limits<int32_t>::max();
     for (int64_t c = 0; c <= nc; ++c) t.cf_ptr[c] = (int32_t)cs.ptr[c];
+#pragma omp parallel for schedule(static) reduction(max : max_degree) reduction(min : min_degree)
     for (int64_t c = 0; c < nc; ++c) {
         int32_t d = (int32_t)(cs.ptr[c + 1] - cs.ptr[c]);
-        t.max_degree = std::max(t.max_degree, d);
+        max_degree = std::max(max_degree, d);
         min_degree = std::min(min_degree, d);
         for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
             int32_t f = cs.idx[p];
             t.cf_idx[p] = (t.fc[2 * f + 1] == c) ? f : ~f;
         }
     }
+    t.max_degree = max_degree;
     t.uniform_degree = (min_degree == t.max_degree);
     if (!t.general) build_slots(t, cs, opp);
+    progress("slot tables", nc);
     build_tiles(t);
+    progress("tile tables", nc);
     return FL_OK;
 }
 

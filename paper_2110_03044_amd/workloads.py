@@ -411,9 +411,10 @@ def cfl_dt(mesh: MeshArrays, u: np.ndarray, cfl: float) -> float:
     own = mesh.face_cells[:, 0].astype(np.int64)
     nbr = mesh.face_cells[:, 1].astype(np.int64)
     q = mesh.face_area * u
-    out = np.zeros(mesh.n_cells)
-    np.add.at(out, own, np.maximum(q, 0.0))
-    np.add.at(out, nbr, np.maximum(-q, 0.0))
+    # one pass in the order of a loop over the own sides, then the nbr sides of the faces
+    out = np.bincount(np.concatenate([own, nbr]),
+                      weights=np.concatenate([np.maximum(q, 0.0), np.maximum(-q, 0.0)]),
+                      minlength=mesh.n_cells)
     rate = float((out / mesh.cell_volume).max())
     if rate <= 0.0:
         raise ValueError("velocity is zero everywhere")

@@ -280,6 +280,43 @@ def test_slot_rate_table_gives_the_same_bits(areas, scheme, S):
     assert nrel(host(runs[1])[cp], want) <= RUN_TOL
 
 
+@pytest.mark.parametrize("S", [1, 3])
+@pytest.mark.parametrize("name", ["hex6r", "line200"])
+def test_lds_stage_single_tile_with_empty_halo(name, S):
+    """A mesh of at most 256 cells is one tile whose halo is empty: the LDS stage then reads the
+    halo array's padding entry and stores every lane's halo value to the spare LDS entry.  The
+    multi-step run (LDS-staged forward) and the reverse step (LDS-staged adjoint) must equal the
+    global-gather kernels bit for bit, and the run must match the oracle."""
+    m = W.renumber(W.periodic_box(6, 3), seed=3) if name == "hex6r" else W.periodic_box(200, 1)
+    rng = np.random.default_rng(4)
+    th = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+    u = rng.standard_normal(m.n_faces)
+    dt = W.cfl_dt(m, u, 0.3)
+    mesh, cp, fp = mesh_pair(m, reorder=True)
+    assert mesh.info.tile_cells == 256 and mesh.info.max_halo == 0
+    ud = dev(to_mesh_faces(u, fp))
+    t0 = dev(to_mesh_cells(th, cp))
+    lam0 = dev(to_mesh_cells(rng.standard_normal(th.shape), cp))
+    res = {}
+    try:
+        for lds in (1, 0):
+            FL.set_option("lds_stage", lds)
+            t = t0.clone()
+            FL.rk_steps(mesh, "superbee", "ssprk3", dt, t, ud, 7)
+            st = FL.stage_buffer(mesh, "ssprk3", S, 1)
+            FL.rk_step_store(mesh, "vanalbada", "ssprk3", dt, t0.clone(), ud, st[0])
+            lam = lam0.clone()
+            ubar = torch.zeros_like(ud)
+            FL.rk_step_adjoint(mesh, "vanalbada", "ssprk3", dt, st[0], ud, lam, ubar)
+            res[lds] = (t, lam, ubar)
+    finally:
+        FL.set_option("lds_stage", 1)
+    for x, y in zip(res[1], res[0]):
+        assert torch.equal(x, y)
+    want = O.OracleMesh.from_arrays(m).run("superbee", "ssprk3", dt, th, u, 7)
+    assert nrel(host(res[1][0])[cp], want) <= RUN_TOL
+
+
 @pytest.mark.parametrize("slot_velocity", [1, 0])
 def test_scaled_steps_with_face_areas(slot_velocity):
     import dataclasses

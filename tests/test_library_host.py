@@ -231,3 +231,43 @@ def test_empty_and_oversized_meshes_are_rejected_before_reading():
     P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     for nc, nf in [(0, 1), (1, 0), (0, 0), (2**31, 1), (4, 2**30)]:
         assert L.fl_mesh_validate(nc, nf, P(fc), P(nrm)) == -1, (nc, nf)
+
+
+_TABLES_SCRIPT = r"""
+import hashlib, sys
+import numpy as np
+sys.path.insert(0, {root!r})
+from paper_2110_03044_amd import fluxlim as FL, workloads as W
+meshes = [W.renumber(W.periodic_box(24, 3), seed=11), W.renumber(W.periodic_box(40, 2), seed=12),
+          W.renumber(W.periodic_box(300, 1), seed=13), W.renumber(W.periodic_triangles(20), seed=14),
+          W.periodic_box(17, 3)]
+for m in meshes:
+    for reorder in (False, True):
+        mesh = FL.Mesh.from_arrays(m, device=-1, reorder=reorder)
+        h = hashlib.sha256()
+        for a in mesh.permutation() + mesh.export_tables():
+            h.update(np.ascontiguousarray(a).tobytes())
+        i = mesh.info
+        print(h.hexdigest(), i.pairs, i.tile_cells, i.max_halo, i.halo_total, i.general)
+        mesh.close()
+"""
+
+
+def test_tables_do_not_depend_on_thread_count():
+    """The mesh builder's loops run on OpenMP threads; the numbering, the exported tables and
+    the tile halo figures must be the same for any thread count (1 and 4 here, each in a fresh
+    process so the runtime reads OMP_NUM_THREADS)."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = _TABLES_SCRIPT.format(root=root)
+    outs = []
+    for threads in ("1", "4"):
+        env = dict(os.environ, OMP_NUM_THREADS=threads)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr
+        outs.append(r.stdout)
+    assert outs[0] == outs[1]
+    assert len(outs[0].splitlines()) == 10
