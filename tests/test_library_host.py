@@ -271,3 +271,31 @@ def test_tables_do_not_depend_on_thread_count():
         outs.append(r.stdout)
     assert outs[0] == outs[1]
     assert len(outs[0].splitlines()) == 10
+
+
+def test_mesh_progress_report():
+    """With FL_MESH_PROGRESS set, fl_mesh_create reports each preprocessing phase on stderr;
+    without it, nothing."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2110_03044_amd import fluxlim as FL, workloads as W\n"
+            "FL.Mesh.from_arrays(W.periodic_box(10, 3), device=-1, reorder=True).close()\n" % root)
+    phases = ["validated", "cells renumbered", "faces renumbered", "far-upwind cells",
+              "slot tables", "tile tables"]
+    for on in (True, False):
+        env = dict(os.environ)
+        env.pop("FL_MESH_PROGRESS", None)
+        if on:
+            env["FL_MESH_PROGRESS"] = "1"
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr
+        lines = [l for l in r.stderr.splitlines() if l.startswith("fl_mesh_create:")]
+        if on:
+            assert [l.split(": ", 1)[1].split(" (")[0] for l in lines] == phases
+            assert all("(1000 cells)" in l for l in lines)
+        else:
+            assert lines == []
