@@ -370,8 +370,9 @@ def main():
     ap.add_argument("--limiters", default=",".join(LIM_DEFAULT))
     ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--face-path", action="store_true")
-    ap.add_argument("--xcd-remap", type=int, default=0,
-                    help="1: each XCD takes a contiguous eighth of the cells (FL_OPT_XCD_REMAP)")
+    ap.add_argument("--xcd-remap", type=int, default=8,
+                    help="FL_OPT_XCD_REMAP: M >= 2 runs of M tiles per XCD (default 8), 0 launch "
+                         "order, 1 each XCD a contiguous eighth of the cells")
     ap.add_argument("--lds-stage", type=int, default=1,
                     help="0: multi-step calls use the slot records instead of LDS staging")
     ap.add_argument("--slot-velocity", type=int, default=1,

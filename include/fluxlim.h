@@ -288,11 +288,12 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
                                 void *hip_stream);
 
 /* Process-wide launch tuning, read by later launches of the single-problem kernels:
- *   FL_OPT_XCD_REMAP  0 (default): workgroups take cells in launch order (the hardware deals
- *                     consecutive workgroups to the 8 XCDs in turn); 1: the grid is padded to a
- *                     multiple of 8 and each XCD gets a contiguous eighth of the cells;
- *                     M in 2 .. 65536: each XCD takes runs of M consecutive 256-cell tiles (grid
- *                     padded to a multiple of 8 M), so the tiles sharing one L2 are neighbours.
+ *   FL_OPT_XCD_REMAP  M in 2 .. 65536 (default 8): each XCD takes runs of M consecutive
+ *                     256-cell tiles (grid padded to a multiple of 8 M), so the tiles sharing one
+ *                     L2 are neighbours; 0: workgroups take cells in launch order (the hardware
+ *                     deals consecutive workgroups to the 8 XCDs in turn); 1: the grid is padded
+ *                     to a multiple of 8 and each XCD gets a contiguous eighth of the cells.
+ *                     Results are bit-identical for every value.
  *   FL_OPT_SLOT_VELOCITY  1 (default): fl_rk_steps, fl_rk_steps_scaled and fl_rk_steps_store
  *                     calls of two or more steps on a mesh of the fused path first write one
  *                     16-byte record per cell slot (other cell, far-upwind cell, signed face rate

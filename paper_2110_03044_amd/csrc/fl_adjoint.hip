@@ -16,6 +16,7 @@
 // u_bar of a face is written only by the thread of the face's own cell.
 #include <hip/hip_runtime.h>
 
+#include "fl_device.h"
 #include "fl_kernels.h"
 
 namespace fl {
@@ -283,11 +284,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
     const double *__restrict__ u, const double *__restrict__ area, double area0,
     const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
     const double *__restrict__ lam, double a, double b, double dt, int mode,
-    double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar) {
+    double *__restrict__ out, double *__restrict__ acc, double *__restrict__ ubar, int remap) {
     extern __shared__ double lds[];
     constexpr int K = 2 * P;
     const int st = 2 * S + (vol ? 1 : 0);
-    const int64_t tile = blockIdx.x;
+    // the tile is the same for the whole workgroup: padding workgroups leave before the barrier
+    const int64_t tile = dev::block_id(remap);
+    if (tile * kTileCells >= nc) return;
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
     const int nt = left < kTileCells ? (int)left : kTileCells;
@@ -385,11 +388,11 @@ hipError_t launch3(const fl_mesh *m, const double *u, const double *th, const do
                    double *ubar, hipStream_t st) {
     const size_t lds = adjoint_lds_bytes(m, S);
     if (lds > 0 && lds <= kMaxStageLds) {
-        const unsigned tiles = (unsigned)((m->h.nc + kTileCells - 1) / kTileCells);
-        adev::adjoint_stage_lds_kernel<S, P, LIM><<<tiles, adev::kBlock, lds, st>>>(
+        const Grid g = launch_grid(m->h.nc);  // one workgroup per tile (kBlock == kTileCells)
+        adev::adjoint_stage_lds_kernel<S, P, LIM><<<g.blocks, adev::kBlock, lds, st>>>(
             m->h.nc, reinterpret_cast<const int2 *>(m->d_adj_fr), m->d_halo_ptr, m->d_halo,
             m->d_slot_local, u, m->d_area, m->h.area0, m->d_vol, 1.0 / m->h.vol0, th, lam, a, b,
-            dt, mode, out, acc, ubar);
+            dt, mode, out, acc, ubar, g.remap);
         return hipGetLastError();
     }
     const unsigned nb = (unsigned)((m->h.nc + adev::kBlock - 1) / adev::kBlock);

@@ -100,13 +100,15 @@ __device__ __forceinline__ void batch_tile(const BatchProblem &pb, int64_t tile,
 // cells, one thread per cell).  The barrier at the top of each tile keeps the previous tile's
 // LDS reads ahead of the next staging; every thread of a workgroup walks the same tiles and takes
 // the same (P, S) branch, so all reach every barrier.
+// remap > 0 (the grid a multiple of 8 remap): the workgroups of one XCD take runs of remap
+// consecutive tiles in every round (dev::block_id is a bijection of the workgroup index).
 __global__ __launch_bounds__(kBlock) void batch_stage_lds_kernel(
     const BatchProblem *__restrict__ probs, const BatchTile *__restrict__ tiles, int64_t ntiles,
-    int stage) {
+    int stage, int remap) {
     extern __shared__ double lds[];
     const double A[3] = {0.0, 0.75, 1.0 / 3.0};
     const double B[3] = {1.0, 0.25, 2.0 / 3.0};
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = dev::block_id(remap); t < ntiles; t += gridDim.x) {
         __syncthreads();
         const BatchTile T = tiles[t];
         const BatchProblem &pb = probs[T.prob];
@@ -159,6 +161,7 @@ struct fl_batch {
     bool lds = false;        // tiles staged in LDS (tile == kTileCells)
     size_t lds_bytes = 0;    // dynamic LDS of the staged kernel, 0 if not every mesh allows it
     int grid = 0;            // persistent grid size
+    int remap = 0;           // XCD run length of the LDS-staged kernel's tile order (0: none)
     std::vector<BatchProblem> probs;
     std::vector<const fl_mesh *> meshes;
     BatchProblem *d_probs = nullptr;
@@ -212,6 +215,9 @@ fl_status set_tile(fl_batch *b, int tile) {
     // persistent grid: a few workgroups per CU, never more than there are tiles
     b->grid = (int)std::min<int64_t>(b->ntiles, (int64_t)cus * 8);
     if (b->grid < 1) b->grid = 1;
+    // XCD-aware tile order of the LDS-staged kernel, where the grid allows it
+    const int m = xcd_remap();
+    b->remap = (m >= 2 && b->grid % (8 * m) == 0) ? m : 0;
     drop_graph(b);
     return FL_OK;
 }
@@ -219,7 +225,7 @@ fl_status set_tile(fl_batch *b, int tile) {
 hipError_t launch_stage(const fl_batch *b, int s, hipStream_t st) {
     if (b->lds)
         bdev::batch_stage_lds_kernel<<<b->grid, bdev::kBlock, b->lds_bytes, st>>>(
-            b->d_probs, b->d_tiles, b->ntiles, s);
+            b->d_probs, b->d_tiles, b->ntiles, s, b->remap);
     else
         bdev::batch_stage_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
                                                                   b->ntiles, b->tile, s);

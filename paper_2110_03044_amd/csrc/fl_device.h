@@ -10,6 +10,16 @@
 namespace fl {
 namespace dev {
 
+// Workgroup -> cell tile.  Dispatch sends workgroup d to XCD d mod 8; with chunk M > 0 (the grid
+// padded to a multiple of 8 M) XCD x takes runs of M consecutive tiles, so the tiles one XCD
+// (one L2) works on at a time are neighbours on the cell curve.  M = grid / 8 gives each XCD a
+// contiguous eighth of the mesh.
+__device__ __forceinline__ int64_t block_id(int chunk) {
+    if (!chunk) return blockIdx.x;
+    const int64_t d = blockIdx.x, xcd = d & 7, local = d >> 3;
+    return (local / chunk) * (8 * (int64_t)chunk) + xcd * chunk + local % chunk;
+}
+
 constexpr double kRBig = 1.0e18;
 
 // psi at r = +inf (pos) or -inf.

@@ -13,8 +13,18 @@ enum { MODE_RHS = 0, MODE_EULER = 1, MODE_RK = 2 };
 // Adjoint-stage modes (see fl_adjoint.hip).
 enum { ADJ_APPLY = 0, ADJ_EULER = 1, ADJ_LAST = 2, ADJ_MID = 3, ADJ_FIRST = 4 };
 
-// 0: launch order; 1: each XCD a contiguous eighth of the tiles; M >= 2: runs of M tiles per XCD.
+// 0: launch order; 1: each XCD a contiguous eighth of the tiles; M >= 2: runs of M tiles per XCD
+// (default 8).
 void set_xcd_remap(int value);
+
+// Grid of 256-thread workgroups for n cells or faces in the current XCD order: `blocks`
+// workgroups (padded to a multiple of 8 remap when remapping), decoded by dev::block_id(remap).
+struct Grid {
+    unsigned blocks;
+    int remap;  // chunk M of block_id, 0 = launch order
+};
+Grid launch_grid(int64_t n);
+int xcd_remap();  // the current FL_OPT_XCD_REMAP value
 
 hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, const double *th,
                           const double *lam, double a, double b, double dt, int mode, double *out,

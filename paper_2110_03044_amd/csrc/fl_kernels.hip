@@ -27,15 +27,6 @@ namespace dev {
 constexpr int kBlock = 256;
 static_assert(kBlock == kTileCells, "one thread per cell of an LDS-staged tile");
 
-// Workgroup -> cell tile.  Dispatch sends workgroup d to XCD d mod 8; with chunk M > 0 (the grid
-// padded to a multiple of 8 M) XCD x takes runs of M consecutive tiles, so the tiles one XCD
-// (one L2) works on at a time are neighbours on the cell curve.  M = grid / 8 gives each XCD a
-// contiguous eighth of the mesh.
-__device__ __forceinline__ int64_t block_id(int chunk) {
-    if (!chunk) return blockIdx.x;
-    const int64_t d = blockIdx.x, xcd = d & 7, local = d >> 3;
-    return (local / chunk) * (8 * (int64_t)chunk) + xcd * chunk + local % chunk;
-}
 
 template <int S>
 __device__ __forceinline__ void load_cell(const double *__restrict__ th, int64_t c, double *v) {
@@ -242,10 +233,13 @@ __global__ __launch_bounds__(kBlock) void fused_stage_lds_kernel(
     const uint32_t *__restrict__ sface, const double *__restrict__ u,
     const double *__restrict__ area, double area0, const double *__restrict__ vol, double vol0,
     const double *__restrict__ ts, const double *__restrict__ tn, double a, double b, double dt,
-    int mode, int lim, double *__restrict__ out, double us) {
+    int mode, int lim, double *__restrict__ out, double us, int remap) {
     extern __shared__ double lds[];
-    fused_tile<S, P, RATES>(nc, blockIdx.x, lds, halo_ptr, halo, slot_local, rate, sface, u, area,
-                            area0, vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
+    // the tile is the same for the whole workgroup: padding workgroups leave before any barrier
+    const int64_t tile = block_id(remap);
+    if (tile * kTileCells >= nc) return;
+    fused_tile<S, P, RATES>(nc, tile, lds, halo_ptr, halo, slot_local, rate, sface, u, area, area0,
+                            vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -294,11 +288,6 @@ __global__ __launch_bounds__(kBlock) void select_kernel(int64_t nf, const int4 *
 // ------------------------------------------------------------------------------------------
 namespace {
 
-struct Grid {
-    unsigned blocks;
-    int remap;  // chunk M of block_id, 0 = launch order
-};
-
 // remap: 0 launch order; 1 contiguous eighths; M >= 2 runs of M tiles per XCD.
 Grid grid_for(int64_t n, int remap) {
     int64_t nb = (n + dev::kBlock - 1) / dev::kBlock;
@@ -324,10 +313,12 @@ Grid grid_for(int64_t n, int remap) {
         default: return hipErrorInvalidValue;    \
     }
 
-// Block ids map to cells in launch order unless FL_OPT_XCD_REMAP selects an XCD-aware order
-// (block_id above).
-int g_remap = 0;
+// Block ids map to cells through dev::block_id: runs of 8 consecutive tiles per XCD by default
+// (the tiles sharing one L2 are then neighbours), launch order with FL_OPT_XCD_REMAP = 0.
+int g_remap = 8;
 void set_xcd_remap(int value) { g_remap = value; }
+Grid launch_grid(int64_t n) { return grid_for(n, g_remap); }
+int xcd_remap() { return g_remap; }
 
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
                             const double *u, double *phi, hipStream_t st, double us) {
@@ -441,12 +432,12 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
                             double *out, hipStream_t st, double us, const double *u) {
     const size_t lds = lds_stage_bytes(m, S);
     if (lds == 0 || lds > kMaxStageLds || (!rate && !u)) return hipErrorInvalidValue;
-    const unsigned tiles = (unsigned)((m->h.nc + kTileCells - 1) / kTileCells);
+    const Grid g = grid_for(m->h.nc, g_remap);  // one workgroup per tile (kBlock == kTileCells)
 #define FL_FUSED_LDS_R(P, R)                                                                     \
-    FL_DISPATCH_S(S, (dev::fused_stage_lds_kernel<kS, P, R><<<tiles, dev::kBlock, lds, st>>>(    \
+    FL_DISPATCH_S(S, (dev::fused_stage_lds_kernel<kS, P, R><<<g.blocks, dev::kBlock, lds, st>>>( \
                          m->h.nc, m->d_halo_ptr, m->d_halo, m->d_slot_local, rate,                \
                          m->d_slot_face, u, m->d_area, m->h.area0, m->d_vol, m->h.vol0, ts, tn,   \
-                         a, b, dt, mode, lim, out, us)))
+                         a, b, dt, mode, lim, out, us, g.remap)))
 #define FL_FUSED_LDS(P)            \
     if (rate) {                    \
         FL_FUSED_LDS_R(P, true);   \

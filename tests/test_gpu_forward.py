@@ -340,24 +340,32 @@ def test_scaled_steps_with_face_areas(slot_velocity):
     assert nrel(host(th)[cp], want) <= RUN_TOL
 
 
-@pytest.mark.parametrize("remap", [1, 2, 5, 64])
+@pytest.mark.parametrize("remap", [1, 2, 5, 8, 64])
 def test_xcd_launch_orders_give_the_same_bits(remap):
     """FL_OPT_XCD_REMAP only changes which workgroup takes which 256-cell tile (a bijection over
-    the padded grid; padding tiles exit): 26^3 = 17576 cells is 69 tiles, enough to engage it."""
+    the padded grid; padding workgroups exit): 26^3 = 17576 cells is 69 tiles, enough to engage
+    it.  Forward runs and the LDS-staged reverse step must give the same bits as launch order."""
     wl = W.workload_box(26, renumbered=True, steps=3)
     mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
     t0 = dev(to_mesh_cells(wl.theta0, cp))
     u = dev(to_mesh_faces(wl.u, fp))
+    lam0 = dev(to_mesh_cells(np.random.default_rng(3).standard_normal(wl.mesh.n_cells), cp))
     runs = []
     try:
         for r in (0, remap):
             FL.set_option("xcd_remap", r)
             t = t0.clone()
             FL.rk_steps(mesh, "smart", "ssprk3", wl.dt, t, u, wl.steps)
-            runs.append(t)
+            st = FL.stage_buffer(mesh, "ssprk3", 1, 1)
+            FL.rk_step_store(mesh, "vanalbada", "ssprk3", wl.dt, t0.clone(), u, st[0])
+            lam = lam0.clone()
+            ubar = torch.zeros_like(u)
+            FL.rk_step_adjoint(mesh, "vanalbada", "ssprk3", wl.dt, st[0], u, lam, ubar)
+            runs.append((t, lam, ubar))
     finally:
-        FL.set_option("xcd_remap", 0)
-    assert torch.equal(runs[0], runs[1])
+        FL.set_option("xcd_remap", 8)
+    for x, y in zip(runs[0], runs[1]):
+        assert torch.equal(x, y)
 
 
 GENERAL = [
