@@ -148,7 +148,10 @@ __device__ __forceinline__ void adj_velocities(const uint32_t *fw, const uint32_
 // LDS copy (interleaved per cell).
 // ufk, urk, ubk0: slot k's face velocity, the opposite face's velocity and the face's u_bar
 // entry (0 where x does not own it), loaded by adj_velocities.
-template <int S, int P, int LIM>
+// TNLDS: theta of the slot neighbours is read where it is used (cheap LDS reads in the staged
+// kernel; keeping all 2P of them in registers would cost that kernel a wave per SIMD), else
+// gathered once up front.
+template <int S, int P, int LIM, bool TNLDS>
 __device__ __forceinline__ void adj_cell(
     int64_t nc, int64_t x, int64_t xi, const uint32_t *fw, const uint32_t *rw,
     const int64_t *nbi, const int64_t *gfi, const double *tsrc, const double *lsrc,
@@ -157,11 +160,13 @@ __device__ __forceinline__ void adj_cell(
     double b, double dt, int mode, double *__restrict__ out, double *__restrict__ acc,
     double *__restrict__ ubar) {
     constexpr int K = 2 * P;
-    double tx[S], lx[S], tn[K][S];
+    double tx[S], lx[S], tn[TNLDS ? 1 : K][S];
     load_s<S>(tsrc, xi, stride, tx);
     load_s<S>(lsrc, xi, stride, lx);
+    if constexpr (!TNLDS) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) load_s<S>(tsrc, nbi[k], stride, tn[k]);
+        for (int k = 0; k < K; ++k) load_s<S>(tsrc, nbi[k], stride, tn[k]);
+    }
     // lambda / V appears in every face term: multiply by reciprocal volumes
     const double ivx = vsrc ? 1.0 / vsrc[xi * vstride] : ivol0;
     const double scale = (mode == ADJ_APPLY) ? 1.0 : b * dt;
@@ -178,6 +183,18 @@ __device__ __forceinline__ void adj_cell(
         const double af = area ? area[f] : area0, ar = area ? area[fr] : area0;
         const double ivn = vsrc ? 1.0 / vsrc[nbi[k] * vstride] : ivol0;
         const double ivg = vsrc ? 1.0 / vsrc[gfi[k] * vstride] : ivol0;
+        // theta of the neighbour across slot k and of the one across the opposite slot
+        double tnk[S], tno[S];
+        if constexpr (TNLDS) {
+            load_s<S>(tsrc, nbi[k], stride, tnk);
+            load_s<S>(tsrc, nbi[k ^ 1], stride, tno);
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                tnk[s] = tn[k][s];
+                tno[s] = tn[k ^ 1][s];
+            }
+        }
         double ln[S], lg[S], tg[S];
         load_s<S>(lsrc, nbi[k], stride, ln);
         load_s<S>(lsrc, gfi[k], stride, lg);
@@ -190,9 +207,9 @@ __device__ __forceinline__ void adj_cell(
         for (int s = 0; s < S; ++s) {
             double ga, gb;
             // pick (theta_C, theta_D, theta_U) first: one evaluation even where lanes diverge
-            const double tC = x_up ? tx[s] : tn[k][s];
-            const double tD = x_up ? tn[k][s] : tx[s];
-            const double tU = x_up ? tn[k ^ 1][s] : tg[s];
+            const double tC = x_up ? tx[s] : tnk[s];
+            const double tD = x_up ? tnk[s] : tx[s];
+            const double tU = x_up ? tno[s] : tg[s];
             const double tf = face_value_d<LIM>(tC, tD, tU, ga, gb);
             const double mu = x_own ? (ln[s] * ivn - lx[s] * ivx) : (lx[s] * ivx - ln[s] * ivn);
             const double z = af * uf * mu;
@@ -207,7 +224,7 @@ __device__ __forceinline__ void adj_cell(
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 double ga, gb;
-                (void)face_value_d<LIM>(tn[k][s], tg[s], tx[s], ga, gb);
+                (void)face_value_d<LIM>(tnk[s], tg[s], tx[s], ga, gb);
                 const double mu = n_own ? (lg[s] * ivg - ln[s] * ivn) : (ln[s] * ivn - lg[s] * ivg);
                 jt[s] -= (ar * ur * mu) * ga;
             }
@@ -267,8 +284,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_kernel(
     read_rec<P>(nc, x, rec, fw, rw, nb, gf);
     double ufk[K], urk[K], ubk[K];
     adj_velocities<P>(fw, rw, u, ubar, ufk, urk, ubk);
-    adj_cell<S, P, LIM>(nc, x, x, fw, rw, nb, gf, th, lam, vol, S, 1, ufk, urk, ubk, area, area0,
-                        ivol0, a, b, dt, mode, out, acc, ubar);
+    adj_cell<S, P, LIM, false>(nc, x, x, fw, rw, nb, gf, th, lam, vol, S, 1, ufk, urk, ubk, area,
+                               area0, ivol0, a, b, dt, mode, out, acc, ubar);
 }
 
 // One workgroup per tile of kTileCells cells: theta, lambda (and the volume, where volumes
@@ -375,8 +392,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_stage_lds_kernel(
         nl[k] = ll[k] & 0xffffu;
         gl[k] = ll[k] >> 16;
     }
-    adj_cell<S, P, LIM>(nc, x, tid, fw, rw, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr, st,
-                        st, ufk, urk, ubk, area, area0, ivol0, a, b, dt, mode, out, acc, ubar);
+    adj_cell<S, P, LIM, true>(nc, x, tid, fw, rw, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr,
+                              st, st, ufk, urk, ubk, area, area0, ivol0, a, b, dt, mode, out, acc,
+                              ubar);
 }
 
 }  // namespace adev
