@@ -243,35 +243,6 @@ __device__ __forceinline__ int tile_stage(int64_t nc, int64_t tile, double *lds,
     return nt;
 }
 
-// Local slot indices and signed face rates of cell c of a tile.  The face terms come from the
-// per-call rates (RATES) or, as in fused_cell, from u through the face index; either way the
-// rates w_k, and so the results, are bit-identical to fused_cell's for us = 1.
-template <int P, bool RATES>
-__device__ __forceinline__ void tile_slots(int64_t nc, int64_t c,
-                                           const uint32_t *__restrict__ slot_local,
-                                           const double *__restrict__ rate,
-                                           const uint32_t *__restrict__ sface,
-                                           const double *__restrict__ u,
-                                           const double *__restrict__ area, bool has_area,
-                                           double area0, double us, int64_t *nb, int64_t *gf,
-                                           double *w) {
-#pragma unroll
-    for (int k = 0; k < 2 * P; ++k) {
-        const uint32_t l = slot_local[(int64_t)k * nc + c];
-        nb[k] = l & 0xffffu;
-        gf[k] = l >> 16;
-        if constexpr (RATES) {
-            const double v = rate[(int64_t)k * nc + c] * us;
-            w[k] = has_area ? v : area0 * v;
-        } else {
-            const uint32_t fw = sface[(int64_t)k * nc + c];
-            const int64_t f = fw & 0x7fffffffu;
-            const double au = (area ? area[f] : area0) * (u[f] * us);
-            w[k] = (fw >> 31) ? au : -au;
-        }
-    }
-}
-
 // The first chunk (CS scalars) of one tile staged as tile_stage does, with the cell's raw slot
 // words loaded after the theta gathers of the tile cell and of its first kHaloAhead halo
 // entries and before their LDS stores.  Loads complete in issue order, so the stores wait for
@@ -350,7 +321,9 @@ __device__ __forceinline__ int tile_stage_slots(int64_t nc, int64_t tile, double
     return nt;
 }
 
-// Decodes the raw slot words as tile_slots does (same arithmetic, so the same bits).
+// Local slot indices and signed face rates of the cell from its raw slot words.  The face terms
+// come from the per-call rates (RATES) or, as in fused_cell, from u through the face index;
+// either way the rates w_k, and so the results, are bit-identical to fused_cell's for us = 1.
 template <int P, bool RATES>
 __device__ __forceinline__ void tile_slots_finish(const SlotRaw<P, RATES> &raw,
                                                   const double *__restrict__ u,
