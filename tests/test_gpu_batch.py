@@ -134,3 +134,51 @@ def test_batch_shared_mesh_and_rejections():
                    face.faces_to_mesh(torch.from_numpy(p["u"]).to(DEV)), p["dt"])])
     with pytest.raises(_lib.FluxLimError):
         FL.Batch([(mesh, "minmod", t1, u, p["dt"])], tile_cells=100)
+
+
+def test_full_size_batch_of_512_problems():
+    """The benchmark's batch in the launch configuration it times (512 periodic boxes, sides
+    12-96, 1-8 scalars, per-problem limiter and CFL, SSP-RK3; autotuned tile, LDS staging, the
+    default XCD order): two batched steps equal two steps of per-problem launches bit for bit on
+    every problem, and the three smallest problems match the oracle."""
+    recipe = W.batch_recipe(count=512)
+    smallest = sorted(range(len(recipe)), key=lambda i: recipe[i].n)[:3]
+    meshes, nat = {}, {}
+    batched, single, start = [], [], {}
+    try:
+        for p in recipe:
+            if p.n not in meshes:
+                m = W.box_shared_cache(p.n)
+                meshes[p.n] = FL.Mesh.from_arrays(m, device=0, reorder=True)
+                nat[p.n] = (m, W.velocity_curl(p.n, seed=p.n))
+            mesh = meshes[p.n]
+            m, u = nat[p.n]
+            th0 = W.batch_fields(p)
+            t = mesh.cells_to_mesh(torch.from_numpy(th0).to(DEV))
+            ud = mesh.faces_to_mesh(torch.from_numpy(u).to(DEV))
+            dt = W.cfl_dt(m, u, p.cfl)
+            batched.append((mesh, p.limiter, t, ud, dt))
+            single.append((mesh, p.limiter, t.clone(), ud, dt))
+            if len(batched) - 1 in smallest:
+                start[len(batched) - 1] = th0
+    finally:
+        W._BOX_CACHE.clear()
+    b1 = FL.Batch(batched)
+    b2 = FL.Batch(single)
+    try:
+        b1.step(2)
+        b2.step_unbatched(2)
+        torch.cuda.synchronize()
+        assert b1.lds_staged
+    finally:
+        b1.close()
+        b2.close()
+    for x, y in zip(batched, single):
+        assert torch.equal(x[2], y[2])
+    for i in smallest:
+        p = recipe[i]
+        m, u = nat[p.n]
+        mesh, lim, t, _, dt = batched[i]
+        got = mesh.cells_from_mesh(t).cpu().numpy()
+        want = O.OracleMesh.from_arrays(m).run(LIMS[lim], "ssprk3", dt, start[i], u, 2)
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
