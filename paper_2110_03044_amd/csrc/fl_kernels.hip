@@ -207,7 +207,9 @@ __global__ __launch_bounds__(kBlock) void fused_stage_rec_kernel(
 }
 
 // rate[k][c] = E a_f u_f of slot k (the rate part of the slot records), for the LDS-staged stage.
-template <int P>
+// All face words first, then all gathers, then the stores: one dependent round trip per cell
+// rather than one per slot.  AREA: per-face areas (uniform areas enter later, as one scalar).
+template <int P, bool AREA>
 __global__ __launch_bounds__(kBlock) void slot_rate_kernel(int64_t nc,
                                                            const uint32_t *__restrict__ sface,
                                                            const double *__restrict__ u,
@@ -215,13 +217,19 @@ __global__ __launch_bounds__(kBlock) void slot_rate_kernel(int64_t nc,
                                                            double *__restrict__ rate) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= nc) return;
+    constexpr int K = 2 * P;
+    uint32_t fw[K];
+    double x[K];
 #pragma unroll
-    for (int k = 0; k < 2 * P; ++k) {
-        const uint32_t fw = sface[(int64_t)k * nc + c];
-        const int64_t f = fw & 0x7fffffffu;
-        const double x = area ? area[f] * u[f] : u[f];
-        rate[(int64_t)k * nc + c] = (fw >> 31) ? x : -x;
+    for (int k = 0; k < K; ++k) fw[k] = sface[(int64_t)k * nc + c];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t f = fw[k] & 0x7fffffffu;
+        if constexpr (AREA) x[k] = area[f] * u[f];
+        else x[k] = u[f];
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) rate[(int64_t)k * nc + c] = (fw[k] >> 31) ? x[k] : -x[k];
 }
 
 // One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
@@ -418,12 +426,18 @@ size_t adjoint_lds_bytes(const fl_mesh *m, int S) {
 
 hipError_t launch_slot_rates(const fl_mesh *m, const double *u, double *rate, hipStream_t st) {
     const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);
+#define FL_RATES(P)                                                                            \
+    (m->d_area ? dev::slot_rate_kernel<P, true><<<nb, dev::kBlock, 0, st>>>(                   \
+                     m->h.nc, m->d_slot_face, u, m->d_area, rate)                              \
+               : dev::slot_rate_kernel<P, false><<<nb, dev::kBlock, 0, st>>>(                  \
+                     m->h.nc, m->d_slot_face, u, nullptr, rate))
     switch (m->h.pairs) {
-        case 1: dev::slot_rate_kernel<1><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, rate); break;
-        case 2: dev::slot_rate_kernel<2><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, rate); break;
-        case 3: dev::slot_rate_kernel<3><<<nb, dev::kBlock, 0, st>>>(m->h.nc, m->d_slot_face, u, m->d_area, rate); break;
+        case 1: FL_RATES(1); break;
+        case 2: FL_RATES(2); break;
+        case 3: FL_RATES(3); break;
         default: return hipErrorInvalidValue;
     }
+#undef FL_RATES
     return hipGetLastError();
 }
 
