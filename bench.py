@@ -39,11 +39,12 @@ def log(*a):
 
 TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                "fused_stage_lds_kernel_box256_traffic.txt")
-KERNEL_SOURCES = ["fl_device.h", "fl_kernels.hip"]
+KERNEL_SOURCES = ["fl_device.h", "fl_kernels.hip", "mesh.cpp"]
 
 
 def kernel_source_hash():
-    """sha256 of the sources that define the fused stage kernel."""
+    """sha256 of the sources that define the fused stage kernel and the tables it reads (the
+    mesh builder decides the tile halos, and so the traffic)."""
     import hashlib
 
     h = hashlib.sha256()

@@ -389,11 +389,37 @@ std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double
         v = (v | v << 2) & 0x1249249249249249ULL;
         return v;
     };
+    // On a periodic lattice the walk reaches the cells half a period from the root from both
+    // sides, so that plane is split between the two ends of the coordinate range (which cell
+    // lands where depends on the face order), and the tiles along it are ragged.  A face whose
+    // step disagrees with its cells' positions crosses that cut; where every such face spans
+    // the same whole number P of cells along axis d, the coordinates are folded modulo P.
+    const int64_t nf = (int64_t)cs.idx.size() / 2;
+    int64_t pmn[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, pmx[3] = {0, 0, 0};
+    int odd[3] = {0, 0, 0};
+#pragma omp parallel for schedule(static) reduction(min : pmn[:3]) reduction(max : pmx[:3], odd[:3])
+    for (int64_t f = 0; f < nf; ++f) {
+        const int64_t a = fc[2 * f], b = fc[2 * f + 1];
+        for (int d = 0; d < 3; ++d) {
+            const double gap = std::fabs(pos[3 * a + d] + nrm[3 * f + d] - pos[3 * b + d]);
+            if (gap <= 0.5) continue;
+            const int64_t p = std::llround(gap);
+            pmn[d] = std::min(pmn[d], p);
+            pmx[d] = std::max(pmx[d], p);
+            odd[d] = std::max(odd[d], std::fabs(gap - (double)p) > 1e-6 ? 1 : 0);
+        }
+    }
+    int64_t period[3];
+    for (int d = 0; d < 3; ++d)
+        period[d] = (!odd[d] && pmn[d] == pmx[d] && pmn[d] >= 3) ? pmn[d] : 0;
     std::vector<std::pair<uint64_t, int32_t>> key(nc);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
         uint64_t q[3];
-        for (int d = 0; d < 3; ++d) q[d] = (uint64_t)std::llround(pos[3 * c + d] - lo[d]);
+        for (int d = 0; d < 3; ++d) {
+            const int64_t v = std::llround(pos[3 * c + d] - lo[d]);
+            q[d] = (uint64_t)(period[d] ? v % period[d] : v);
+        }
         key[c] = {spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2, (int32_t)c};
     }
     __gnu_parallel::sort(key.begin(), key.end());  // keys unique (cell index)
