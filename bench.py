@@ -39,7 +39,7 @@ def log(*a):
 
 TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                "fused_stage_lds_kernel_box256_traffic.txt")
-KERNEL_SOURCES = ["fl_device.h", "fl_kernels.hip", "mesh.cpp"]
+KERNEL_SOURCES = ["fl_internal.h", "fl_kernels.h", "fl_device.h", "fl_kernels.hip", "mesh.cpp"]
 
 
 def kernel_source_hash():

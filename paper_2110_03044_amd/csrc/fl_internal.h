@@ -53,10 +53,11 @@ struct HostTables {
 };
 
 constexpr int kTileCells = 256;
-// Halo entries per thread whose theta is gathered before the slot loads are issued.  The device
+// Halo entries per thread whose theta is gathered before the slot loads are issued (two: the
+// 512-cell halo of a whole 8x8x4 brick; larger halos take a loop for the rest).  The device
 // halo array carries kHaloPad extra zeros (cell 0), so that every tile, also one with an empty
 // halo at the end, has a first entry to read.
-constexpr int kHaloAhead = 3;
+constexpr int kHaloAhead = 2;
 constexpr int kHaloPad = 1;
 
 enum { REORDER_NONE = 0, REORDER_CURVE = 1, REORDER_BFS = 2 };
