@@ -506,15 +506,23 @@ def main():
         else:
             kname = "fused_stage_rec_kernel" if sv else "fused_stage_kernel"
             bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
+        # The timed region also holds the per-call table build of each call (one rk_steps call
+        # per limiter): its time and its compulsory bytes (slot face words and each face
+        # velocity read, rates or records written) are charged to the call's stage launches.
+        table_bytes = 0
+        if sv and args.steps >= 2:
+            table_bytes = C * K * 12 + F * 8 if lds else C * K * 28 + F * 8
+        total_bytes = bytes_per_step * n_steps_total + table_bytes * len(lims)
         avg_launch_s = r["total_ms"] * 1e-3 / launches
-        achieved = bytes_per_step / 3 / avg_launch_s / 1e9
-        # the timed region also holds one per-call table build per call (sv), charged to the stages
+        achieved = total_bytes / launches / avg_launch_s / 1e9
         out["roofline"] = {"kernel": kname,
                            "bound": "hbm",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds),
-                           "algorithmic_bytes_per_launch": int(bytes_per_step / 3),
+                           "algorithmic_bytes_per_launch": int(total_bytes / launches),
+                           "stage_bytes_per_launch": int(bytes_per_step / 3),
+                           "table_bytes_per_call": int(table_bytes),
                            "avg_launch_us": round(avg_launch_s * 1e6, 2),
                            "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
                            "frac_of_copy": None if copy_gbs is None else
