@@ -299,3 +299,17 @@ def test_mesh_progress_report():
             assert all("(1000 cells)" in l for l in lines)
         else:
             assert lines == []
+
+
+def test_periodic_lattice_tiles_are_whole_bricks_whatever_the_input_order():
+    """On a periodic box whose sides are multiples of the 8x8x4 brick, the Morton numbering gives
+    every 256-cell tile the 512-cell halo of a whole brick, also when cells and faces come in
+    random order with random orientations (the walk's cut plane is folded back)."""
+    for n in (16, 32):
+        for m in (W.periodic_box(n, 3), W.renumber(W.periodic_box(n, 3), seed=7)):
+            mesh = FL.Mesh.from_arrays(m, device=-1, reorder=True)
+            info = mesh.info
+            tiles = (mesh.n_cells + 255) // 256
+            assert info.tile_cells == 256
+            assert info.max_halo == 512 and info.halo_total == 512 * tiles
+            mesh.close()
