@@ -574,6 +574,22 @@ def main():
                                          f"{args.n}^3 mesh in its given numbering, van Leer, "
                                          f"{cpu_s:.1f} s"}
         log(f"oracle setup {t2 - t1:.1f}s, step {cpu_s:.1f}s")
+        # the same oracle on one thread, over one stage (one forward-Euler step)
+        import ctypes
+
+        gomp = ctypes.CDLL("libgomp.so.1")
+        threads = O.num_threads()
+        gomp.omp_set_num_threads(1)
+        try:
+            t3 = time.time()
+            om.run(lim, "euler", wl.dt, wl.theta0, wl.u, 1)
+            one_s = time.time() - t3
+        finally:
+            gomp.omp_set_num_threads(threads)
+        out["cpu_baseline"]["single_thread_value"] = round(F / one_s / 1e9, 5)
+        out["cpu_baseline"]["single_thread_sample"] = (
+            f"1 forward-Euler stage (all {F} faces) of the same mesh on 1 thread, {one_s:.1f} s")
+        log(f"oracle on 1 thread: one stage {one_s:.1f}s")
 
     print(json.dumps(out), flush=True)
 
