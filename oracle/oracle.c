@@ -219,10 +219,16 @@ static double upstream_difference(const orc_mesh *m, int S, const double *th, in
     return dU;
 }
 
+/* theta_f = theta_C + g(d_U, d_u), g(a, b) = psi(a/b) b / 2, and its partials ga = dg/da,
+ * gb = dg/db.  Where d_u == 0, g vanishes for every d_U, so ga = 0; gb is the derivative along
+ * d_u > 0, the limit of g(a, b)/b as b -> 0+: psi(+-inf)/2 with the sign of d_U, and psi(0)/2
+ * where d_U is also 0 (g(0, b) = psi(0) b / 2: 0 for every limiter but central differencing).
+ * Where |r| is taken as infinite, psi is constant, so ga = 0 and gb = psi(+-inf)/2. */
 static double limited_value(int lim, double tC, double dU, double du, double *ga, double *gb) {
     if (du == 0.0) {
         if (ga) *ga = 0.0;
-        if (gb) *gb = (dU == 0.0) ? 0.0 : 0.5 * orc_psi_inf(lim, dU > 0 ? 1 : -1);
+        if (gb) *gb = (dU == 0.0) ? 0.5 * orc_psi(lim, 0.0)
+                                  : 0.5 * orc_psi_inf(lim, dU > 0 ? 1 : -1);
         return tC;
     }
     double r = dU / du;
@@ -384,6 +390,14 @@ static double face_value_tangent(const orc_mesh *m, int lim, int S, const double
     double tf = limited_value(lim, tC, dU, du, &ga, &gb);
     *dtf = dC + ga * ddU + gb * ddu;
     return tf;
+}
+
+void orc_face_values_jvp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
+                         const double *dth, double *tf, double *dtf) {
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < m->nf; ++f)
+        for (int k = 0; k < S; ++k)
+            tf[f * S + k] = face_value_tangent(m, lim, S, th, dth, u, f, k, &dtf[f * S + k]);
 }
 
 void orc_rhs_jvp(const orc_mesh *m, int lim, int S, const double *th, const double *u,

@@ -82,6 +82,10 @@ int orc_run(const orc_mesh *m, int limiter, int scheme, double dt, int S, int64_
 int orc_run_scaled(const orc_mesh *m, int limiter, int scheme, double dt, int S, int64_t nsteps,
                    double *theta, const double *u, const double *scales);
 
+/* Face values theta_f and their tangent along dtheta (u held fixed), [F][S] each. */
+void orc_face_values_jvp(const orc_mesh *m, int limiter, int S, const double *theta,
+                         const double *u, const double *dtheta, double *theta_f,
+                         double *dtheta_f);
 /* Tangent and adjoint of rhs = L(theta, u). */
 void orc_rhs_jvp(const orc_mesh *m, int limiter, int S, const double *theta, const double *u,
                  const double *dtheta, const double *du, double *drhs);

@@ -66,6 +66,7 @@ def lib():
         L.orc_run.restype = _I
         L.orc_run.argtypes = [_P, _I, _I, _D, _I, _I64, _P, _P]
         L.orc_rhs_jvp.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P]
+        L.orc_face_values_jvp.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P]
         L.orc_rhs_vjp.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P]
         L.orc_run_tangent.restype = _I
         L.orc_run_tangent.argtypes = [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P]
@@ -154,6 +155,15 @@ class OracleMesh:
         lib().orc_face_values(self._h, lim_id(limiter), self._S(theta), _ptr(theta), _ptr(u),
                               _ptr(out))
         return out
+
+    def face_values_jvp(self, limiter, theta, u, dtheta):
+        """(theta_f, its tangent along dtheta), u held fixed."""
+        theta, u, dtheta = _f64(theta), _f64(u), _f64(dtheta)
+        tf = np.empty((self.n_faces,) + theta.shape[1:])
+        dtf = np.empty_like(tf)
+        lib().orc_face_values_jvp(self._h, lim_id(limiter), self._S(theta), _ptr(theta), _ptr(u),
+                                  _ptr(dtheta), _ptr(tf), _ptr(dtf))
+        return tf, dtf
 
     def rhs(self, limiter, theta, u) -> np.ndarray:
         theta, u = _f64(theta), _f64(u)

@@ -622,3 +622,126 @@ def test_general_cell_weights_by_hand():
     assert nz[0][1] == pytest.approx(1.0 / np.sqrt(2.0), abs=1e-15)
     faces, w = om.side_weights(2 * C2 + 5, side_nbr=False)
     assert sum(1 for x in w if x != 0.0) == 2
+
+
+# ------------------------------------------------------------------------------------------
+# Derivatives at the special points of the gradient ratio (Section 3's Sweby form and ratio):
+# theta_f = theta_C + g(d_U, d_u), g(a, b) = psi(a / b) b / 2.  Where d_u = 0, g vanishes for
+# every d_U, and its derivative along d_u > 0 is the limit of g(a, b) / b = psi(a / b) / 2 as
+# b -> 0+, i.e. psi(+-inf) / 2 with the sign of d_U (psi(0) / 2 where d_U = 0 too).  Where
+# |r| is evaluated as infinite, psi is constant.  The pins below take one-sided difference
+# quotients of the oracle's own face values, on the side where d_u > 0, at steps small enough
+# that the quotient is exactly psi(+-inf) / 2 in binary arithmetic, and compare them with the
+# tangent that the jvp / vjp use.
+# ------------------------------------------------------------------------------------------
+
+def _line(n=5):
+    fc = np.array([[i, (i + 1) % n] for i in range(n)], dtype=np.int32)
+    nrm = np.tile([1.0, 0.0, 0.0], (n, 1))
+    return O.OracleMesh(fc, nrm, n_cells=n)
+
+
+LINE_F, LINE_U, LINE_C, LINE_D = 2, 1, 2, 3  # with u > 0: face 2 joins C = 2 to D = 3, U = 1
+
+
+def _tangent_of_face(om, lim, th, cell, f=LINE_F):
+    u = np.ones(om.n_faces)
+    e = np.zeros_like(th)
+    e[cell] = 1.0
+    _, dtf = om.face_values_jvp(lim, th, u, e)
+    return dtf[f]
+
+
+def _quotient(om, lim, th, cell, step, f=LINE_F):
+    """(theta_f(theta + step e_cell) - theta_f(theta)) / step, exactly as the oracle rounds."""
+    u = np.ones(om.n_faces)
+    t1 = th.copy()
+    t1[cell] += step
+    return (om.face_values(lim, t1, u)[f] - om.face_values(lim, th, u)[f]) / step
+
+
+@pytest.mark.parametrize("dU_sign", [1.0, -1.0])
+@pytest.mark.parametrize("lim", LIMS)
+def test_derivative_where_face_difference_vanishes(lim, dU_sign):
+    om = _line()
+    th = np.array([0.37, -dU_sign, 0.0, 0.0, 0.61])  # d_u = 0, d_U = dU_sign
+    half_inf = 0.5 * O.lib().orc_psi_inf(O.lim_id(lim), int(dU_sign))
+    tiny = 2.0 ** -70  # d_U / tiny = 2^70 > 1e18: the ratio is evaluated as infinite
+    # theta_D up (d_u > 0): the quotient is exactly psi(+-inf) / 2 ...
+    q = _quotient(om, lim, th, LINE_D, tiny)
+    assert q == half_inf
+    assert _tangent_of_face(om, lim, th, LINE_D) == q
+    # ... and at a step in the finite range it tends to it (van Leer / van Albada: 1/r terms)
+    assert abs(_quotient(om, lim, th, LINE_D, 1e-7) - q) <= 1e-6
+    # theta_C down is also d_u > 0: theta_f = theta_C + g, so the quotient is 1 - psi(+-inf)/2
+    q = _quotient(om, lim, th, LINE_C, -tiny)
+    assert q == 1.0 - half_inf
+    assert _tangent_of_face(om, lim, th, LINE_C) == q
+    # theta_U moves d_U only, and g(., 0) = 0
+    assert _quotient(om, lim, th, LINE_U, 1e-3) == 0.0
+    assert _tangent_of_face(om, lim, th, LINE_U) == 0.0
+
+
+@pytest.mark.parametrize("lim", LIMS)
+def test_derivative_where_both_differences_vanish(lim):
+    """d_u = d_U = 0: along d_u with d_U = 0 held, g(0, b) = psi(0) b / 2 (central: b / 2)."""
+    om = _line()
+    th = np.array([0.37, 0.0, 0.0, 0.0, 0.61])
+    for step in (2.0 ** -70, 1e-3):
+        q = _quotient(om, lim, th, LINE_D, step)
+        assert q == 0.5 * O.psi(lim, 0.0)
+        assert _tangent_of_face(om, lim, th, LINE_D) == q
+    assert _tangent_of_face(om, lim, th, LINE_U) == 0.0
+
+
+@pytest.mark.parametrize("lim", LIMS)
+def test_derivative_where_ratio_is_infinite(lim):
+    """0 < d_u with |r| > 1e18: psi is its value at infinity, constant in d_U and d_u."""
+    om = _line()
+    for sgn in (1.0, -1.0):
+        th = np.array([0.37, -sgn, 0.0, 2.0 ** -70, 0.61])  # r = sgn 2^70
+        half_inf = 0.5 * O.lib().orc_psi_inf(O.lim_id(lim), int(sgn))
+        for step in (2.0 ** -72, -(2.0 ** -72)):  # r stays beyond 1e18 either way
+            assert _quotient(om, lim, th, LINE_D, step) == half_inf
+        assert _tangent_of_face(om, lim, th, LINE_D) == half_inf
+        assert _quotient(om, lim, th, LINE_U, 1e-3) == 0.0
+        assert _tangent_of_face(om, lim, th, LINE_U) == 0.0
+
+
+def test_vjp_uses_the_same_special_point_derivatives():
+    """The reverse sweep's partials at d_u = 0 and in the infinite-ratio band equal the one-sided
+    quotients above: <vjp(e_c), e_D> over the cells of face 2's two neighbours."""
+    om = _line()
+    u = np.ones(om.n_faces)
+    for lim in LIMS:
+        for th in (np.array([0.37, -1.0, 0.0, 0.0, 0.61]),
+                   np.array([0.37, -1.0, 0.0, 2.0 ** -70, 0.61])):
+            jv = om.rhs_jvp(lim, th, u, np.eye(5)[LINE_D])
+            for c in range(5):
+                tb, _ = om.rhs_vjp(lim, th, u, np.eye(5)[c])
+                assert tb[LINE_D] == pytest.approx(jv[c], abs=1e-15)
+            # rhs_3 - rhs_2 picks up face 2's flux twice (own 2, nbr 3): its tangent is the
+            # quotient of the face value, plus those of faces 1 and 3 through theta_3
+            _, dtf = om.face_values_jvp(lim, th, u, np.eye(5)[LINE_D])
+            assert dtf[LINE_F] == 0.5 * O.lib().orc_psi_inf(O.lim_id(lim), 1)
+            assert jv[3] - jv[2] == pytest.approx(2 * dtf[2] - dtf[1] - dtf[3], abs=1e-15)
+
+
+@pytest.mark.parametrize("a,b", [(0.3, 0.7), (-1.1, 0.4), (2.5, -0.2), (1e-9, 1.0), (1.0, 1e-12),
+                                 (-3.0, -1e-5), (0.5, 0.5), (1.0, -1.0)])
+def test_van_albada_partials_match_symbolic(a, b):
+    """psi_vA(a/b) b / 2 = a b (a + b) / (2 (a^2 + b^2)); its partials in exact rationals.  The
+    oracle forms g_b = (psi - r psi') / 2, which cancels for small |r|: compared at 1e-15
+    absolute (the partials are O(1) quantities) or 1e-13 relative."""
+    om = _line()
+    th = np.array([0.37, -a, 0.0, b, 0.61])  # d_U = 0 - (-a) = a, d_u = b
+    A, B = Fraction(a), Fraction(b)
+    D = (A * A + B * B) ** 2
+    ga = B * B * (B * B + 2 * A * B - A * A) / D / 2
+    gb = A * A * (A * A + 2 * A * B - B * B) / D / 2
+    assert _tangent_of_face(om, "vanalbada", th, LINE_U) == pytest.approx(-float(ga), rel=1e-13, abs=1e-15)
+    assert _tangent_of_face(om, "vanalbada", th, LINE_D) == pytest.approx(float(gb), rel=1e-13, abs=1e-15)
+    # the limits at b -> 0 are psi_vA(+-inf) / 2 = 1/2 and 0
+    th0 = np.array([0.37, -a, 0.0, 0.0, 0.61])
+    assert _tangent_of_face(om, "vanalbada", th0, LINE_D) == 0.5
+    assert _tangent_of_face(om, "vanalbada", th0, LINE_U) == 0.0
