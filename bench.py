@@ -189,11 +189,13 @@ def batch_compare(args, torch, FL, W, dev):
     W._BOX_CACHE.clear()
     log(f"batch of {len(problems)} problems ({len(meshes)} distinct meshes) built in "
         f"{_t.time() - t0:.1f}s")
-    b = FL.Batch(problems)
+    t1 = _t.time()
+    b = FL.Batch(problems)  # picks the tile (timing, or the tuning cache) and records the graph
+    create_s = _t.time() - t1
     stream = torch.cuda.current_stream(dev)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    b.step(1)  # autotune + graph capture
+    b.step(1)
     b.step_unbatched(1)
     torch.cuda.synchronize()
     K = args.batch_steps
@@ -209,6 +211,7 @@ def batch_compare(args, torch, FL, W, dev):
     unbatched_ms = ev0.elapsed_time(ev1) / K
     tile = b.tile_cells
     staged = b.lds_staged
+    from_cache = b.tuned_from_cache
     b.close()
     # per-problem launches of the other kernel too (LDS staging off: the gather kernel), so that
     # the batch is compared with the faster per-problem form
@@ -241,7 +244,8 @@ def batch_compare(args, torch, FL, W, dev):
             "speedup": round(best_ms / batched_ms, 3),
             "batched_gface_updates_per_s": round(face_updates / (batched_ms * 1e-3) / 1e9, 2),
             "lds_staged": staged,
-            "autotuned_tile_cells": tile}
+            "autotuned_tile_cells": tile,
+            "create_s": round(create_s, 3), "tile_from_tuning_cache": from_cache}
 
 
 def deformation(args, torch, FL, W, dev):
@@ -381,8 +385,12 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 to skip the oracle timing")
     ap.add_argument("--calib-copy-mib", type=int, default=1024,
                     help="size of the untimed calibration copy (0 to skip)")
-    ap.add_argument("--compare-order", action="store_true",
-                    help="also time the as-given random numbering (no library reorder)")
+    ap.add_argument("--compare-order", type=int, default=1,
+                    help="1 (default): also time the as-given random numbering (no library "
+                         "reorder); 0 to skip")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="times the whole timed region is run (the first gives value; all "
+                         "give the median reported beside it)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -405,7 +413,7 @@ def main():
     m = wl.mesh
     log(f"workload generated in {time.time() - t0:.1f}s: C={m.n_cells} F={m.n_faces} dt={wl.dt:.6g}")
 
-    def run_case(reorder: bool):
+    def run_case(reorder: bool, reps: int = 1):
         t1 = time.time()
         mesh = FL.Mesh.from_arrays(m, device=0, reorder=reorder, face_path=args.face_path)
         log(f"mesh created (reorder={reorder}, path={mesh.path}) in {time.time() - t1:.1f}s, "
@@ -419,24 +427,32 @@ def main():
             th.copy_(th0)
             FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, u, args.warmup, work=work)
         torch.cuda.synchronize()
-        per_lim = {}
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        total_ms = 0.0
-        for lim in lims:
-            th.copy_(th0)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, u, args.steps, work=work)
-            ev1.record(stream)
-            ev1.synchronize()
-            ms = ev0.elapsed_time(ev1)
-            total_ms += ms
-            per_lim[lim] = ms
+
+        def timed_region():
+            per_lim, total_ms = {}, 0.0
+            for lim in lims:
+                th.copy_(th0)
+                torch.cuda.synchronize()
+                ev0.record(stream)
+                FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, u, args.steps, work=work)
+                ev1.record(stream)
+                ev1.synchronize()
+                ms = ev0.elapsed_time(ev1)
+                total_ms += ms
+                per_lim[lim] = ms
+            return total_ms, per_lim
+
+        total_ms, per_lim = timed_region()
+        for lim, ms in per_lim.items():
             log(f"  {lim}: {ms / args.steps:.3f} ms/step")
+        # the same region again (not part of value): run-to-run spread and its median
+        repeats = [total_ms] + [timed_region()[0] for _ in range(max(0, reps - 1))]
         torch.cuda.synchronize()
         info = mesh.info
         res = dict(mesh=mesh, total_ms=total_ms, per_lim=per_lim, path=mesh.path,
+                   repeats=repeats,
                    K=int(info.max_degree), th=th, u=u, max_halo=int(info.max_halo),
                    tile_cells=int(info.tile_cells),
                    halo_total=int(info.halo_total))
@@ -463,7 +479,7 @@ def main():
         del src, dst
 
     reorder = not args.no_reorder
-    r = run_case(reorder)
+    r = run_case(reorder, args.repeats)
     C, F, S = m.n_cells, m.n_faces, 1
     n_steps_total = args.steps * len(lims)
     updates = F * S * 3 * n_steps_total
@@ -491,6 +507,9 @@ def main():
             "library_reorder": reorder, "path": r["path"],
         },
         "per_limiter_ms_per_step": {k: round(v / args.steps, 4) for k, v in r["per_lim"].items()},
+        "repeats": {"ms_per_step": [round(t / n_steps_total, 4) for t in r["repeats"]],
+                    "median_ms_per_step": round(float(np.median(r["repeats"])) / n_steps_total, 4),
+                    "median_value": round(updates / (float(np.median(r["repeats"])) * 1e-3) / 1e9, 3)},
     }
 
     # roofline of the dominant kernel
@@ -540,7 +559,11 @@ def main():
     if args.compare_order and reorder:
         r2 = run_case(False)
         v2 = updates / (r2["total_ms"] * 1e-3) / 1e9
-        out["as_given_numbering_value"] = round(v2, 3)
+        out["as_given_numbering"] = {"value": round(v2, 3), "unit": "Gface-updates/s",
+                                     "ms_per_step": round(r2["total_ms"] / n_steps_total, 4),
+                                     "note": "same mesh and launch sequence without the "
+                                             "library's locality renumbering"}
+        log(f"as-given numbering: {v2:.2f} Gface-updates/s")
         r2["mesh"].close()
         del r2
         torch.cuda.empty_cache()
@@ -561,19 +584,48 @@ def main():
     if args.cpu_baseline:
         from oracle import oracle as O
 
-        t1 = time.time()
-        om = O.OracleMesh.from_arrays(m)
         lim = "vanleer"
+        # the oracle on the numbering the GPU runs on (the library's renumbering, applied on
+        # the host from fl_mesh_permutation), then on the given random numbering
+        mm, th_m, u_m = m, wl.theta0, wl.u
+        if reorder:
+            pm = FL.Mesh.from_arrays(m, device=-1, reorder=True)
+            cp, fp = pm.permutation()
+            pm.close()
+            fc = np.empty_like(m.face_cells)
+            fc[fp] = cp[m.face_cells]
+            nrm = np.empty_like(m.face_normal)
+            nrm[fp] = m.face_normal
+            area = np.empty_like(m.face_area)
+            area[fp] = m.face_area
+            vol = np.empty_like(m.cell_volume)
+            vol[cp] = m.cell_volume
+            th_m = np.empty_like(wl.theta0)
+            th_m[cp] = wl.theta0
+            u_m = np.empty_like(wl.u)
+            u_m[fp] = wl.u
+            mm = (fc, nrm, area, vol)
+        t1 = time.time()
+        om = O.OracleMesh(*mm, n_cells=C) if reorder else O.OracleMesh.from_arrays(m)
         t2 = time.time()
-        om.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, 1)
+        om.run(lim, "ssprk3", wl.dt, th_m, u_m, 1)
         cpu_s = time.time() - t2
         cpu_rate = F * 3 / cpu_s / 1e9
         out["cpu_baseline"] = {"value": round(cpu_rate, 4), "unit": "Gface-updates/s",
                                "cores": O.num_threads(), "kind": "oracle",
                                "sample": f"1 SSP-RK3 step (3 stages, all {F} faces) of the same "
-                                         f"{args.n}^3 mesh in its given numbering, van Leer, "
-                                         f"{cpu_s:.1f} s"}
+                                         f"{args.n}^3 mesh in the numbering the GPU runs on "
+                                         f"({'library renumbering' if reorder else 'as given'}), "
+                                         f"van Leer, {cpu_s:.1f} s"}
         log(f"oracle setup {t2 - t1:.1f}s, step {cpu_s:.1f}s")
+        if reorder:
+            og = O.OracleMesh.from_arrays(m)
+            t2 = time.time()
+            og.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, 1)
+            given_s = time.time() - t2
+            del og
+            out["cpu_baseline"]["as_given_numbering_value"] = round(F * 3 / given_s / 1e9, 4)
+            log(f"oracle on the given numbering: step {given_s:.1f}s")
         # the same oracle on one thread, over one stage (one forward-Euler step)
         import ctypes
 
@@ -582,13 +634,14 @@ def main():
         gomp.omp_set_num_threads(1)
         try:
             t3 = time.time()
-            om.run(lim, "euler", wl.dt, wl.theta0, wl.u, 1)
+            om.run(lim, "euler", wl.dt, th_m, u_m, 1)
             one_s = time.time() - t3
         finally:
             gomp.omp_set_num_threads(threads)
         out["cpu_baseline"]["single_thread_value"] = round(F / one_s / 1e9, 5)
         out["cpu_baseline"]["single_thread_sample"] = (
-            f"1 forward-Euler stage (all {F} faces) of the same mesh on 1 thread, {one_s:.1f} s")
+            f"1 forward-Euler stage (all {F} faces) of the same mesh and numbering on 1 thread, "
+            f"{one_s:.1f} s")
         log(f"oracle on 1 thread: one stage {one_s:.1f}s")
 
     print(json.dumps(out), flush=True)

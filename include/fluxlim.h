@@ -32,7 +32,8 @@
  *   - hot-path calls (fl_convect_apply, fl_rk_step, fl_rk_steps, fl_convect_adjoint,
  *     fl_rk_step_adjoint, fl_batch_step) only enqueue work on the given HIP stream
  *     (hipStream_t passed as void*, NULL = the null stream): no host synchronisation, no
- *     allocation, O(1) argument checks;
+ *     allocation, O(1) argument checks (unless the opt-in finite check FL_OPT_CHECK_FINITE is
+ *     on: it scans the inputs and synchronises the stream);
  *   - errors are returned as status codes (never abort, never throw); fl_last_error() gives a
  *     thread-local message for the last failing call of the calling thread;
  *   - results are bitwise deterministic from run to run (no atomics, fixed summation order).
@@ -56,7 +57,9 @@ typedef int32_t fl_status;
                                the adjoint and batching on cells without opposite face pairs */
 #define FL_E_NOMEM -4       /* host or device allocation failed                              */
 #define FL_E_HIP -5         /* a HIP runtime call failed (message in fl_last_error)          */
-#define FL_E_NODEVICE -6    /* compute call on a host-only mesh (device = -1)                */
+#define FL_E_NONFINITE -6   /* an input holds a NaN or an infinity (only reported while the
+                               opt-in check FL_OPT_CHECK_FINITE is on)                        */
+#define FL_E_NODEVICE -7    /* compute call on a host-only mesh (device = -1)                */
 
 /* Limiters psi(r) (Sweby's family; superbee is the paper's, Table 1):
  *   FL_UPWIND    psi = 0 (first order upwind; the paper's F = -1/2)
@@ -220,26 +223,35 @@ fl_status fl_rk_steps_store(const fl_mesh *mesh, int limiter, int scheme, double
 
 /* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
  * with one launch per Runge-Kutta stage for all of them (one fused cell-centric kernel over a
- * work table of (problem, cell tile) entries).  Every mesh must live on `device` (else
- * FL_E_INVALID) and support the fused path (faces in opposite pairs, else FL_E_UNSUPPORTED);
- * meshes may be shared between problems.  theta[i] / u_f[i] are device pointers the
- * batch keeps (not owned) until fl_batch_destroy.  tile_cells = 0 picks the tile size by timing
- * candidates on the first fl_batch_step (autotuning); a positive value fixes it. */
+ * work table of (problem, cell tile) entries).  device >= 0 and every mesh created on it (a
+ * host-only mesh or device: FL_E_NODEVICE; a mesh on another device: FL_E_INVALID); every
+ * mesh must support the fused path (faces in opposite pairs, else FL_E_UNSUPPORTED); meshes may
+ * be shared between problems.  theta[i] / u_f[i] are device pointers the batch keeps (not
+ * owned) until fl_batch_destroy.  tile_cells > 0 fixes the tile size; 0 picks it here, at
+ * creation, by timing the candidates (the first stage, which writes only the batch's own stage
+ * buffers) after a device synchronisation, or reads the choice from the on-disk tuning cache:
+ * the file named by the environment variable FL_TUNE_CACHE ("" or "0": no cache), by default
+ * $XDG_CACHE_HOME/fluxlim/batch_tune.txt or $HOME/.cache/fluxlim/batch_tune.txt, one line per
+ * batch shape (GPU architecture and CU count, scheme, tile order, every problem's cells, pairs,
+ * scalars and limiter).  Creation then records one step's launches in a HIP graph.  Every tile
+ * size gives the same bits. */
 fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter,
                           const int *n_scalars, const double *dt, int scheme,
                           double *const *theta, const double *const *u_f, int tile_cells,
                           int device, fl_batch **out);
-/* Advances every problem by n_steps steps; the first call records the launch sequence of one
- * step in a HIP graph, later calls replay it. */
+/* Advances every problem by n_steps steps by replaying the graph recorded at creation on the
+ * given stream: no synchronisation, no allocation. */
 fl_status fl_batch_step(fl_batch *batch, int n_steps, void *hip_stream);
 /* The same work as separate per-problem launches (no graph), for comparison. */
 fl_status fl_batch_step_unbatched(fl_batch *batch, int n_steps, void *hip_stream);
-/* The tile size in use (0 before the first fl_batch_step autotunes it), and whether the tiles
- * are staged in LDS: the autotuner also times the LDS-staged kernel (256-cell tiles, each tile's
- * theta and halo in LDS, the mesh's tile tables; FL_OPT_LDS_STAGE and every mesh's LDS need
- * permitting); then fl_batch_step_unbatched runs the same staged kernel per problem. */
+/* The tile size in use, and whether the tiles are staged in LDS: the autotuner also times the
+ * LDS-staged kernel (256-cell tiles, each tile's theta and halo in LDS, the mesh's tile tables;
+ * FL_OPT_LDS_STAGE and every mesh's LDS need permitting); then fl_batch_step_unbatched runs the
+ * same staged kernel per problem.  fl_batch_tuned_from_cache: 1 if the autotuner's choice was
+ * read from the tuning cache instead of timed. */
 fl_status fl_batch_tile(const fl_batch *batch, int *tile_cells);
 fl_status fl_batch_lds(const fl_batch *batch, int *lds_staged);
+fl_status fl_batch_tuned_from_cache(const fl_batch *batch, int *from_cache);
 fl_status fl_batch_destroy(fl_batch *batch);
 
 /* The paper's algebraic form of the same operator (Algorithms 3 and 4, Section 3.4), kept as a
@@ -310,9 +322,18 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     and lambda of all S scalars (and the cell volumes, where they differ)
  *                     where (tile_cells + max_halo + 1) * (2 S [+ 1]) * 8 bytes fit; 0: the records
  *                     and global gathers.  Results are bit-identical.
+ *   FL_OPT_CHECK_FINITE  0 (default) or 1: the compute entry points (fl_convect_apply,
+ *                     fl_rk_step(s), fl_rk_steps_scaled, fl_rk_step(s)_store, fl_convect_adjoint,
+ *                     fl_rk_step_adjoint) first scan their floating-point inputs (theta or the
+ *                     stage states, u_f, rhs_bar or lambda on the device; dt and u_scale on the
+ *                     host) and return FL_E_NONFINITE, with nothing enqueued, if one holds a NaN
+ *                     or an infinity.  The scan synchronises the caller's stream, so calls made
+ *                     with the check on cannot be captured into a graph.  Batches and the
+ *                     algebraic path are not checked.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
-enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3 };
+enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3,
+       FL_OPT_CHECK_FINITE = 4 };
 fl_status fl_set_option(int option, int value);
 
 const char *fl_status_str(fl_status status);

@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(HERE, "libfluxlim.so")
 
 FL_OK = 0
 STATUS = {0: "FL_OK", -1: "FL_E_INVALID", -2: "FL_E_TOPOLOGY", -3: "FL_E_UNSUPPORTED",
-          -4: "FL_E_NOMEM", -5: "FL_E_HIP", -6: "FL_E_NODEVICE"}
+          -4: "FL_E_NOMEM", -5: "FL_E_HIP", -6: "FL_E_NONFINITE",
+          -7: "FL_E_NODEVICE"}
 
 FL_MESH_REORDER = 1
 FL_MESH_FACE_PATH = 2
@@ -78,6 +79,7 @@ SIGNATURES = {
     "fl_batch_step_unbatched": (_S, [_P, _I, _P]),
     "fl_batch_tile": (_S, [_P, _P]),
     "fl_batch_lds": (_S, [_P, _P]),
+    "fl_batch_tuned_from_cache": (_S, [_P, _P]),
     "fl_batch_destroy": (_S, [_P]),
     "fl_algebraic_create": (_S, [_P, _P]),
     "fl_algebraic_destroy": (_S, [_P]),

@@ -1,7 +1,9 @@
 // C ABI entry points: mesh lifetime, forward operator and explicit time steps.
 #include <hip/hip_runtime_api.h>
 
+#include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <sstream>
 
@@ -92,6 +94,14 @@ fl_status check_compute(const fl_mesh *m, int lim, int S) {
 }
 
 bool misaligned(const void *p) { return ((uintptr_t)p & 7u) != 0; }
+
+// The opt-in finite check of a call's inputs (nothing runs while FL_OPT_CHECK_FINITE is off).
+fl_status finite_inputs(const fl_mesh *m, std::initializer_list<FiniteSpan> spans, double dt,
+                        hipStream_t st) {
+    if (!check_finite_enabled()) return FL_OK;
+    if (!std::isfinite(dt)) return fail(FL_E_NONFINITE, "dt is not finite");
+    return check_finite(m->device, spans.begin(), (int)spans.size(), st);
+}
 
 constexpr double kRk3A[3] = {0.0, 0.75, 1.0 / 3.0};
 constexpr double kRk3B[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -188,6 +198,7 @@ const char *fl_status_str(fl_status s) {
         case FL_E_UNSUPPORTED: return "FL_E_UNSUPPORTED";
         case FL_E_NOMEM: return "FL_E_NOMEM";
         case FL_E_HIP: return "FL_E_HIP";
+        case FL_E_NONFINITE: return "FL_E_NONFINITE";
         case FL_E_NODEVICE: return "FL_E_NODEVICE";
         default: return "FL_E_UNKNOWN";
     }
@@ -206,6 +217,10 @@ fl_status fl_set_option(int option, int value) {
     }
     if (option == FL_OPT_LDS_STAGE && (value == 0 || value == 1)) {
         set_lds_stage(value);
+        return FL_OK;
+    }
+    if (option == FL_OPT_CHECK_FINITE && (value == 0 || value == 1)) {
+        set_check_finite(value);
         return FL_OK;
     }
     return fail(FL_E_INVALID, "unknown option or value");
@@ -444,6 +459,8 @@ fl_status fl_convect_apply(const fl_mesh *m, int lim, int S, const double *theta
     if (rhs == theta) return fail(FL_E_INVALID, "rhs must not alias theta");
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
+    s = finite_inputs(m, {{theta, m->h.nc * S}, {u, m->h.nf}}, 0.0, st);
+    if (s != FL_OK) return s;
     hipError_t e;
     if (m->path == FL_PATH_FUSED) {
         e = launch_fused(m, lim, S, theta, theta, u, 0.0, 1.0, 0.0, MODE_RHS, rhs, st);
@@ -477,6 +494,8 @@ fl_status fl_rk_steps(const fl_mesh *m, int lim, int scheme, double dt, int S, i
     if (!(dt == dt)) return fail(FL_E_INVALID, "dt is NaN");
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
+    s = finite_inputs(m, {{theta, m->h.nc * S}, {u, m->h.nf}}, dt, st);
+    if (s != FL_OK) return s;
     Work w = carve(m, S, work);
     Plan vs;
     hipError_t e = prepare_rates(m, u, S, n_steps, w, st, &vs);
@@ -520,6 +539,13 @@ fl_status fl_rk_steps_scaled(const fl_mesh *m, int lim, int scheme, double dt, i
     if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
+    if (check_finite_enabled()) {
+        const int64_t ns = n_steps * (scheme == FL_EULER ? 1 : 3);
+        for (int64_t i = 0; i < ns; ++i)
+            if (!std::isfinite(u_scale[i])) return fail(FL_E_NONFINITE, "u_scale is not finite");
+    }
+    s = finite_inputs(m, {{theta, m->h.nc * S}, {u, m->h.nf}}, dt, st);
+    if (s != FL_OK) return s;
     Work w = carve(m, S, work);
     Plan vs;
     hipError_t e = prepare_rates(m, u, S, n_steps, w, st, &vs);
@@ -585,6 +611,9 @@ fl_status fl_convect_adjoint(const fl_mesh *m, int lim, int S, const double *the
     if (theta_bar == rhs_bar || theta_bar == theta)
         return fail(FL_E_INVALID, "theta_bar must not alias theta or rhs_bar");
     DeviceGuard g(m->device);
+    s = finite_inputs(m, {{theta, m->h.nc * S}, {u, m->h.nf}, {rhs_bar, m->h.nc * S}}, 0.0,
+                      (hipStream_t)stream);
+    if (s != FL_OK) return s;
     hipError_t e = launch_adjoint(m, lim, S, u, theta, rhs_bar, 0.0, 1.0, 0.0, ADJ_APPLY,
                                   theta_bar, nullptr, u_bar, (hipStream_t)stream);
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_convect_adjoint launch");
@@ -607,6 +636,8 @@ fl_status fl_rk_step_store(const fl_mesh *m, int lim, int scheme, double dt, int
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     const size_t cell = (size_t)m->h.nc * S;
+    s = finite_inputs(m, {{theta, (int64_t)cell}, {u, m->h.nf}}, dt, st);
+    if (s != FL_OK) return s;
     Work w = carve(m, S, work);
     hipError_t e = hipMemcpyAsync(stages, theta, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) {
@@ -640,6 +671,8 @@ fl_status fl_rk_steps_store(const fl_mesh *m, int lim, int scheme, double dt, in
     hipStream_t st = (hipStream_t)stream;
     const size_t cell = (size_t)m->h.nc * S;
     const size_t per_step = cell * (scheme == FL_EULER ? 1 : 3);
+    s = finite_inputs(m, {{theta, (int64_t)cell}, {u, m->h.nf}}, dt, st);
+    if (s != FL_OK) return s;
     Work w = carve(m, S, work);
     Plan vs;
     hipError_t e = prepare_rates(m, u, S, n_steps, w, st, &vs);
@@ -676,6 +709,9 @@ fl_status fl_rk_step_adjoint(const fl_mesh *m, int lim, int scheme, double dt, i
     DeviceGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
     const size_t cell = (size_t)m->h.nc * S;
+    s = finite_inputs(m, {{stages, (int64_t)cell * (scheme == FL_EULER ? 1 : 3)}, {u, m->h.nf},
+                          {lambda, (int64_t)cell}}, dt, st);
+    if (s != FL_OK) return s;
     const size_t slab = align256(cell * sizeof(double));
     double *w1 = (double *)work;
     double *w2 = (double *)((char *)work + slab);

@@ -7,8 +7,9 @@
 // zeta_f = a_f u_f mu_f; then
 //   theta_bar_C += zeta (1 + g_a - g_b),  theta_bar_D += zeta g_b,  theta_bar_U -= zeta g_a,
 //   u_bar_f += a_f theta_f mu_f,
-// with g_a = psi'(r)/2 and g_b = (psi(r) - r psi'(r))/2 (the limit values where d_u == 0 or
-// |r| is beyond the range evaluated as infinity).  Q(u_f) and the limiter branch are held fixed.
+// with g_a = psi'(r)/2 and g_b = (psi(r) - r psi'(r))/2 (where d_u == 0: g_a = 0 and g_b the
+// derivative along d_u > 0; where |r| is beyond the range evaluated as infinity, psi is
+// constant: g_a = 0, g_b = psi(+-inf)/2).  Q(u_f) and the limiter branch are held fixed.
 //
 // No atomics: one thread per cell x gathers every contribution it receives -- from its own
 // faces (x is C or D there) and from the faces for which it is the far-upwind cell U (the face
@@ -75,8 +76,10 @@ __device__ __forceinline__ double face_value_d(double tC, double tD, double tU, 
         return tC;
     }
     if (b == 0.0) {
+        // g(., 0) = 0; along d_u > 0, g(a, b) / b -> psi(+-inf) / 2, and psi(0) / 2 where a = 0
+        // (g(0, b) = psi(0) b / 2: 1/2 for central differencing, 0 for the others)
         ga = 0.0;
-        gb = (a == 0.0) ? 0.0 : 0.5 * psi_inf<LIM>(a > 0.0);
+        gb = (a == 0.0) ? (LIM == FL_CENTRAL ? 0.5 : 0.0) : 0.5 * psi_inf<LIM>(a > 0.0);
         return tC;
     }
     if constexpr (LIM == FL_VANALBADA) {

@@ -10,8 +10,14 @@
 // so each problem's result equals its single-problem run bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fl_device.h"
@@ -171,6 +177,7 @@ struct fl_batch {
     hipStream_t cap = nullptr;    // capture stream (default priority)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool tuned_from_cache = false;  // the tile choice came from the on-disk cache
 };
 
 namespace {
@@ -248,6 +255,7 @@ hipError_t enqueue_step(const fl_batch *b, hipStream_t st) {
 
 // Times the non-destructive first stage (theta -> t1) for each candidate: the LDS-staged kernel
 // (tiles of kTileCells, where every mesh allows it), then the gather kernel at each tile size.
+// Each candidate: 2 untimed launches, then the best of 3 timed runs of 3 launches each.
 fl_status autotune(fl_batch *b, hipStream_t st) {
     static const int cand[] = {-1, 128, 256, 512, 1024, 2048, 4096};  // -1: LDS-staged
     hipEvent_t e0, e1;
@@ -261,16 +269,24 @@ fl_status autotune(fl_batch *b, hipStream_t st) {
         if (s != FL_OK) return s;
         b->lds = c < 0;
         for (int rep = 0; rep < 2; ++rep) (void)launch_stage(b, 0, st);
-        (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 5; ++rep) (void)launch_stage(b, 0, st);
-        (void)hipEventRecord(e1, st);
-        hipError_t e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipGetLastError();
-        if (e != hipSuccess) return hip_err(e, "autotune");
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-            best = ms;
+        float cand_ms = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+            (void)hipEventRecord(e0, st);
+            for (int rep = 0; rep < 3; ++rep) (void)launch_stage(b, 0, st);
+            (void)hipEventRecord(e1, st);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipGetLastError();
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return hip_err(e, "autotune");
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            cand_ms = std::min(cand_ms, ms);
+        }
+        if (cand_ms < best) {
+            best = cand_ms;
             best_tile = c;
         }
     }
@@ -279,6 +295,100 @@ fl_status autotune(fl_batch *b, hipStream_t st) {
     fl_status s = set_tile(b, best_tile < 0 ? kTileCells : best_tile);
     b->lds = best_tile < 0;
     return s;
+}
+
+// On-disk cache of the autotuner's choice, so that a batch of the same shape on the same kind of
+// GPU is not timed again: FL_TUNE_CACHE names the file ("" or "0": no cache); unset, the file is
+// $XDG_CACHE_HOME/fluxlim/batch_tune.txt or $HOME/.cache/fluxlim/batch_tune.txt.  One line per
+// shape: a 64-bit key (FNV-1a over the GPU's architecture name and CU count, the scheme, the
+// XCD tile order, the LDS bytes and every problem's cell count, pairs, scalars and limiter), the
+// tile size, and 1 if the tiles are staged in LDS.  A missing or unreadable file just means
+// tuning; the choice never changes results (every tile size gives the same bits).
+std::string tune_cache_path() {
+    const char *env = std::getenv("FL_TUNE_CACHE");
+    if (env) return (env[0] == 0 || std::strcmp(env, "0") == 0) ? std::string() : std::string(env);
+    const char *xdg = std::getenv("XDG_CACHE_HOME");
+    if (xdg && xdg[0]) return std::string(xdg) + "/fluxlim/batch_tune.txt";
+    const char *home = std::getenv("HOME");
+    if (home && home[0]) return std::string(home) + "/.cache/fluxlim/batch_tune.txt";
+    return std::string();
+}
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ULL;
+    void bytes(const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ULL;
+    }
+    template <class T>
+    void add(T v) { bytes(&v, sizeof v); }
+};
+
+uint64_t tune_key(const fl_batch *b) {
+    Fnv k;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) {
+        k.bytes(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+        k.add<int32_t>(prop.multiProcessorCount);
+    }
+    k.add<int32_t>(b->scheme);
+    k.add<int32_t>(xcd_remap());
+    k.add<uint64_t>(b->lds_bytes);
+    k.add<uint64_t>(b->probs.size());
+    for (const BatchProblem &p : b->probs) {
+        k.add<int64_t>(p.nc);
+        k.add<int32_t>(p.P);
+        k.add<int32_t>(p.S);
+        k.add<int32_t>(p.lim);
+    }
+    return k.h;
+}
+
+bool tune_cache_read(const std::string &path, uint64_t key, int *tile, int *lds) {
+    if (path.empty()) return false;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    unsigned long long k;
+    int t, l;
+    bool hit = false;
+    // the last line for a key wins
+    while (std::fscanf(f, "%llx %d %d", &k, &t, &l) == 3)
+        if (k == key && t > 0 && t % 64 == 0 && (l == 0 || (l == 1 && t == kTileCells))) {
+            *tile = t;
+            *lds = l;
+            hit = true;
+        }
+    std::fclose(f);
+    return hit;
+}
+
+void tune_cache_write(const std::string &path, uint64_t key, int tile, int lds) {
+    if (path.empty()) return;
+    // create the parent directories (errors surface as fopen failing)
+    for (size_t i = 1; i < path.size(); ++i)
+        if (path[i] == '/') (void)mkdir(path.substr(0, i).c_str(), 0755);
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%016llx %d %d\n", (unsigned long long)key, tile, lds);
+    std::fclose(f);
+}
+
+// Records one step on the private stream into a graph that fl_batch_step replays.
+fl_status capture(fl_batch *b) {
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
+    hipError_t le = enqueue_step(b, b->cap);
+    e = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        drop_graph(b);
+        return hip_err(le != hipSuccess ? le : e, "batch capture");
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(b);
+        return hip_err(e, "hipGraphInstantiate");
+    }
+    return FL_OK;
 }
 
 void destroy(fl_batch *b) {
@@ -305,6 +415,11 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
     if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
     if (tile_cells < 0 || (tile_cells > 0 && tile_cells % 64 != 0))
         return fail(FL_E_INVALID, "tile_cells must be 0 (autotune) or a positive multiple of 64");
+    // host-only meshes have no device tables: reject them before anything is allocated
+    if (device < 0) return fail(FL_E_NODEVICE, "a batch needs a device (device >= 0)");
+    for (int i = 0; i < n; ++i)
+        if (meshes[i] && meshes[i]->device < 0)
+            return fail(FL_E_NODEVICE, "a batched problem's mesh is host-only (device = -1)");
     fl_batch *b = nullptr;
     try {
         b = new fl_batch();
@@ -374,14 +489,34 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         destroy(b);
         return hip_err(e, "batch setup");
     }
+    fl_status s = FL_OK;
     if (tile_cells > 0) {
         // a fixed tile of kTileCells cells runs staged in LDS where every mesh allows it
+        s = set_tile(b, tile_cells);
         b->lds = tile_cells == kTileCells && b->lds_bytes > 0;
-        fl_status s = set_tile(b, tile_cells);
-        if (s != FL_OK) {
-            destroy(b);
-            return s;
+    } else {
+        const std::string path = tune_cache_path();
+        const uint64_t key = tune_key(b);
+        int t = 0, l = 0;
+        if (tune_cache_read(path, key, &t, &l) && (l == 0 || b->lds_bytes > 0)) {
+            s = set_tile(b, t);
+            b->lds = l == 1;
+            b->tuned_from_cache = true;
+        } else {
+            // the candidates read theta: order them after the caller's earlier work
+            hipError_t e = hipDeviceSynchronize();
+            s = e == hipSuccess ? autotune(b, b->cap) : hip_err(e, "hipDeviceSynchronize");
+            if (s == FL_OK) tune_cache_write(path, key, b->tile, b->lds ? 1 : 0);
         }
+    }
+    if (s == FL_OK) s = capture(b);
+    if (s == FL_OK) {
+        hipError_t e = hipStreamSynchronize(b->cap);
+        if (e != hipSuccess) s = hip_err(e, "batch setup");
+    }
+    if (s != FL_OK) {
+        destroy(b);
+        return s;
     }
     *out = b;
     return FL_OK;
@@ -390,28 +525,10 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
 fl_status fl_batch_step(fl_batch *b, int n_steps, void *stream) {
     if (!b) return fail(FL_E_INVALID, "batch is NULL");
     if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    if (!b->exec) return fail(FL_E_INVALID, "batch has no recorded step");
     Guard g(b->device);
     hipStream_t st = (hipStream_t)stream;
-    if (b->tile == 0) {
-        fl_status s = autotune(b, st);
-        if (s != FL_OK) return s;
-    }
-    if (!b->exec) {
-        // record one step on the private stream; replay the graph on the caller's stream
-        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
-        hipError_t le = enqueue_step(b, b->cap);
-        e = hipStreamEndCapture(b->cap, &b->graph);
-        if (le != hipSuccess || e != hipSuccess) {
-            drop_graph(b);
-            return hip_err(le != hipSuccess ? le : e, "batch capture");
-        }
-        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            drop_graph(b);
-            return hip_err(e, "hipGraphInstantiate");
-        }
-    }
+    // replay the step recorded at creation on the caller's stream: no sync, no allocation
     for (int i = 0; i < n_steps; ++i) {
         hipError_t e = hipGraphLaunch(b->exec, st);
         if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
@@ -461,6 +578,12 @@ fl_status fl_batch_tile(const fl_batch *b, int *tile_cells) {
 fl_status fl_batch_lds(const fl_batch *b, int *lds_staged) {
     if (!b || !lds_staged) return fail(FL_E_INVALID, "NULL argument");
     *lds_staged = b->lds ? 1 : 0;
+    return FL_OK;
+}
+
+fl_status fl_batch_tuned_from_cache(const fl_batch *b, int *from_cache) {
+    if (!b || !from_cache) return fail(FL_E_INVALID, "NULL argument");
+    *from_cache = b->tuned_from_cache ? 1 : 0;
     return FL_OK;
 }
 

@@ -66,4 +66,14 @@ hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, co
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);
 
+// Opt-in finite check of a call's device inputs (FL_OPT_CHECK_FINITE): FL_OK, FL_E_NONFINITE or
+// FL_E_HIP.  The device must be current; synchronises st.
+struct FiniteSpan {
+    const double *p;
+    int64_t n;
+};
+void set_check_finite(int on);
+bool check_finite_enabled();
+fl_status check_finite(int device, const FiniteSpan *spans, int n_spans, hipStream_t st);
+
 }  // namespace fl

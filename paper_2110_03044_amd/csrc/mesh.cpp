@@ -62,7 +62,6 @@ class Progress {
     double t_;
 };
 
-constexpr double kWeightTol = 1e-9;
 constexpr double kNormTol = 1e-12;
 
 struct Csr {
@@ -188,8 +187,11 @@ inline double projection(const int32_t *fc, const double *nrm, int64_t f, int64_
 }
 
 // far[2f + side], opp[2f + side]: side 0 is C = own, side 1 is C = nbr.  Returns true when every
-// side has exactly one projected face, with weight 1 (hexahedra, quadrilaterals, lines in any
-// numbering: d_U = theta_C - theta_U); otherwise far and opp are left at -1.
+// side has exactly one projected face, with weight exactly 1 and every other weight exactly 0
+// (axis-aligned hexahedra, quadrilaterals, lines in any numbering and orientation:
+// d_U = theta_C - theta_U); otherwise far and opp are left at -1.  No tolerance: a mesh whose
+// normals are off the axes by any amount keeps all its nonzero weights (side_lists), as the
+// upstream difference sums them.
 bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
                 std::vector<int32_t> &far, std::vector<int32_t> &opp) {
     far.assign(2 * nf, -1);
@@ -207,13 +209,13 @@ bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
                 const int64_t j = cs.idx[p];
                 if (j == f) continue;
                 const double w = projection(fc, nrm, f, j, C, s);
-                if (std::fabs(w) > kWeightTol) {
+                if (w != 0.0) {
                     ++count;
                     jj = j;
                     ww = w;
                 }
             }
-            if (count != 1 || std::fabs(ww - 1.0) > kWeightTol) {
+            if (count != 1 || ww != 1.0) {
                 ok = false;
                 continue;
             }

@@ -35,13 +35,15 @@ def scheme_id(s) -> int:
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
 
-OPTIONS = {"xcd_remap": 1, "slot_velocity": 2, "lds_stage": 3}
+OPTIONS = {"xcd_remap": 1, "slot_velocity": 2, "lds_stage": 3, "check_finite": 4}
 
 
 def set_option(name: str, value: int) -> None:
     """Process-wide launch option (fl_set_option): "xcd_remap" (default 8), "slot_velocity"
-    (default 1: multi-step calls read per-call slot tables with the signed face rates) or
-    "lds_stage" (default 1: those calls stage each tile's theta and halo in LDS)."""
+    (default 1: multi-step calls read per-call slot tables with the signed face rates),
+    "lds_stage" (default 1: those calls stage each tile's theta and halo in LDS) or
+    "check_finite" (default 0: 1 makes the compute calls reject non-finite inputs with
+    FL_E_NONFINITE, at the cost of a scan and a stream synchronisation per call)."""
     call("fl_set_option", OPTIONS[name], int(value))
 
 
@@ -484,7 +486,9 @@ class Batch:
     Runge-Kutta stage for all of them, recorded once in a HIP graph and replayed.
 
     problems: sequence of (mesh, limiter, theta, u, dt); theta is updated in place.  Meshes may
-    be shared.  tile_cells = 0 lets the library time candidate tile sizes on the first step."""
+    be shared.  tile_cells = 0 lets the library pick the tile size at creation (timing the
+    candidates, or from its on-disk tuning cache); creation also records the step's graph, so
+    step() only replays it."""
 
     def __init__(self, problems, scheme="ssprk3", tile_cells: int = 0):
         n = len(problems)
@@ -531,6 +535,12 @@ class Batch:
     def lds_staged(self) -> bool:
         t = ctypes.c_int()
         call("fl_batch_lds", self._h, ctypes.byref(t))
+        return bool(t.value)
+
+    @property
+    def tuned_from_cache(self) -> bool:
+        t = ctypes.c_int()
+        call("fl_batch_tuned_from_cache", self._h, ctypes.byref(t))
         return bool(t.value)
 
     def close(self):

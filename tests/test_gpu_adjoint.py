@@ -298,3 +298,32 @@ def test_lds_staged_adjoint_gives_the_same_bits(lim, S, varied):
         got_u = host(mesh.faces_from_mesh(res[1][1]))
         assert np.abs(got_t - tb_o).max() <= 1e-12 * np.abs(tb_o).max()
         assert np.abs(got_u - ub_o).max() <= 1e-12 * np.abs(ub_o).max()
+
+
+@pytest.mark.parametrize("lds", [1, 0])
+@pytest.mark.parametrize("lim", LIMS)
+def test_operator_adjoint_on_flat_fields(lim, lds):
+    """Flat regions put faces at d_u = d_U = 0 (every face of a constant field) and at d_u = 0
+    with d_U != 0 (the edges of a plateau).  The reverse stage must use the same derivative there
+    as the oracle: the derivative along d_u > 0 (psi(0)/2 where d_U = 0 too: 1/2 for central
+    differencing, whose face value is linear)."""
+    wl = W.workload_box(9, renumbered=True)
+    rng = np.random.default_rng(31)
+    m = wl.mesh
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=True)
+    cp, fp = maps(mesh)
+    uf = np.empty_like(wl.u)
+    uf[fp] = wl.u
+    om = O.OracleMesh.from_arrays(m)
+    try:
+        FL.set_option("lds_stage", lds)
+        for th in (np.full(m.n_cells, 0.25), np.where(rng.random(m.n_cells) < 0.3, 1.0, 0.0)):
+            lam = rng.standard_normal(m.n_cells)
+            tb, ub = FL.convect_adjoint(mesh, lim, dev(cells_in(th, cp)), dev(uf), dev(cells_in(lam, cp)))
+            tb_o, ub_o = om.rhs_vjp(lim, th, wl.u, lam)
+            scale = max(np.abs(tb_o).max(), 1e-300)
+            assert np.abs(host(tb)[cp] - tb_o).max() <= 1e-12 * scale
+            assert np.abs(host(ub)[fp] - ub_o).max() <= 1e-12 * max(np.abs(ub_o).max(), 1e-300)
+    finally:
+        FL.set_option("lds_stage", 1)
+    mesh.close()

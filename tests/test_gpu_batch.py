@@ -182,3 +182,33 @@ def test_full_size_batch_of_512_problems():
         got = mesh.cells_from_mesh(t).cpu().numpy()
         want = O.OracleMesh.from_arrays(m).run(LIMS[lim], "ssprk3", dt, start[i], u, 2)
         assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def test_tuning_at_creation_and_on_disk_cache(tmp_path, monkeypatch):
+    """With tile_cells = 0 the tile is chosen when the batch is created (fl_batch_step only
+    replays the graph); the choice is written to the tuning cache, a second batch of the same
+    shape reads it instead of timing, and both give the same bits.  "0" disables the cache."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("FL_TUNE_CACHE", str(path))
+    probs = make_problems(count=6, seed=9)
+    runs = []
+    for k in range(2):
+        dev_probs = [to_dev(p) for p in probs]
+        ths = [th.clone() for _, th, _ in dev_probs]
+        b = FL.Batch([(m, p["lim"], t, u, p["dt"]) for (m, _, u), t, p in zip(dev_probs, ths, probs)])
+        assert b.tile_cells > 0  # chosen before any step
+        assert b.tuned_from_cache == (k == 1)
+        lines = path.read_text().split("\n")
+        assert len([x for x in lines if x.strip()]) == 1
+        b.step(3)
+        torch.cuda.synchronize()
+        runs.append((b.tile_cells, b.lds_staged, [t.clone() for t in ths]))
+        b.close()
+    assert runs[0][:2] == runs[1][:2]
+    for x, y in zip(runs[0][2], runs[1][2]):
+        assert torch.equal(x, y)
+    monkeypatch.setenv("FL_TUNE_CACHE", "0")
+    dev_probs = [to_dev(p) for p in probs]
+    b = FL.Batch([(m, p["lim"], th, u, p["dt"]) for (m, th, u), p in zip(dev_probs, probs)])
+    assert not b.tuned_from_cache
+    b.close()

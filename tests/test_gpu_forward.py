@@ -193,8 +193,8 @@ def test_permute_roundtrip():
 
 def test_box128_config_van_leer():
     """3-D periodic hex box 128^3 in generic incidence, curl velocity, blob + step, van Leer,
-    SSP-RK3 at CFL 0.4 (the first 12 of the 100 steps; the oracle bounds the test time)."""
-    wl = W.workload_box(128, steps=12)
+    SSP-RK3 at CFL 0.4, all 100 steps (library reorder, one multi-step call)."""
+    wl = W.workload_box(128, steps=100)
     mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
     th = dev(to_mesh_cells(wl.theta0, cp))
     FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, dev(to_mesh_faces(wl.u, fp)), wl.steps)
@@ -475,3 +475,111 @@ def test_full_size_box256_sampled_first_stage_and_conservation():
     V = wl.mesh.cell_volume[0]
     total0 = float(t0.sum()) * V
     assert abs(float(a.sum()) * V - total0) <= 1e-12 * abs(total0)
+
+
+@pytest.fixture(scope="module")
+def box256():
+    """The 256^3 random mesh of the benchmark with its oracle view and the library mesh in the
+    benchmark's launch configuration (library reorder, fused LDS-staged path)."""
+    wl = W.workload_box(256, renumbered=True)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    assert mesh.path == "fused" and mesh.info.tile_cells > 0
+    om = O.OracleMesh.from_arrays(wl.mesh)
+    yield wl, mesh, cp, fp, om
+    mesh.close()
+
+
+@pytest.mark.parametrize("lim", ["minmod", "vanleer", "superbee", "smart"])
+def test_full_size_box256_all_cells_two_steps(box256, lim):
+    """Every one of the 16.8 M cells after a two-step SSP-RK3 call (per-call rate table, six
+    LDS-staged stage launches) against the oracle's two steps, for each limiter the benchmark
+    times at this size."""
+    wl, mesh, cp, fp, om = box256
+    th = dev(to_mesh_cells(wl.theta0, cp))
+    FL.rk_steps(mesh, lim, "ssprk3", wl.dt, th, dev(to_mesh_faces(wl.u, fp)), 2)
+    got = host(th)[cp]
+    want = om.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, 2)
+    err = nrel(got, want)
+    print(f"256^3 {lim}: max norm-relative error {err:.2e}")
+    assert err <= RUN_TOL
+
+
+def _rotated_box(n, angle, seed):
+    """Periodic box with each face normal turned by `angle` about a random axis (renormalised)."""
+    import dataclasses
+
+    m = W.periodic_box(n, 3)
+    rng = np.random.default_rng(seed)
+    nrm = m.face_normal.copy()
+    ax = rng.standard_normal(nrm.shape)
+    ax -= (ax * nrm).sum(1, keepdims=True) * nrm
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    nrm = nrm * np.cos(angle) + ax * np.sin(angle)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return dataclasses.replace(m, face_normal=nrm)
+
+
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("lim", ["vanleer", "superbee", "smart"])
+def test_nearly_orthogonal_mesh_keeps_every_weight(lim, reorder):
+    """Normals off the axes by ~1e-10 rad: every nonzero projection weight is kept (general cells
+    on the face path), as in the oracle; one application at 1e-13 of max|rhs| and a 20-step run
+    at the run tolerance."""
+    n = 12
+    m = _rotated_box(n, 1e-10, seed=3)
+    mesh, cp, fp = mesh_pair(m, reorder=reorder)
+    assert mesh.info.general == 1 and mesh.path == "face"
+    u = W.velocity_curl(n)
+    th0 = W.field_blob_step(n) + 1e-3 * np.random.default_rng(1).standard_normal(m.n_cells)
+    om = O.OracleMesh.from_arrays(m)
+    rhs = FL.convect_apply(mesh, lim, dev(to_mesh_cells(th0, cp)), dev(to_mesh_faces(u, fp)))
+    want = om.rhs(lim, th0, u)
+    assert np.abs(host(rhs)[cp] - want).max() <= 1e-13 * np.abs(want).max()
+    dt = W.cfl_dt(m, u, 0.4)
+    th = dev(to_mesh_cells(th0, cp))
+    FL.rk_steps(mesh, lim, "ssprk3", dt, th, dev(to_mesh_faces(u, fp)), 20)
+    assert nrel(host(th)[cp], om.run(lim, "ssprk3", dt, th0, u, 20)) <= RUN_TOL
+    mesh.close()
+
+
+def test_opt_in_finite_check():
+    """FL_OPT_CHECK_FINITE: a NaN or an infinity in theta, u_f or dt gives FL_E_NONFINITE with
+    nothing enqueued (theta unchanged); finite inputs run as without the check, bit for bit."""
+    from paper_2110_03044_amd import _lib
+
+    wl = W.workload_box(10, renumbered=True, steps=3)
+    mesh, cp, fp = mesh_pair(wl.mesh, reorder=True)
+    u = dev(to_mesh_faces(wl.u, fp))
+    t0 = dev(to_mesh_cells(wl.theta0, cp))
+    ref = t0.clone()
+    FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, ref, u, 3)
+    FL.set_option("check_finite", 1)
+    try:
+        t = t0.clone()
+        FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, u, 3)
+        assert torch.equal(t, ref)
+        for bad_cell, bad_face, bad_dt in [(5, None, None), (None, 7, None), (None, None, np.inf)]:
+            t = t0.clone()
+            uu = u.clone()
+            if bad_cell is not None:
+                t[bad_cell] = float("nan")
+            if bad_face is not None:
+                uu[bad_face] = float("inf")
+            before = t.clone()
+            with pytest.raises(_lib.FluxLimError) as e:
+                FL.rk_steps(mesh, "vanleer", "ssprk3", bad_dt if bad_dt else wl.dt, t, uu, 3)
+            assert e.value.status == -6
+            assert torch.equal(t.isnan(), before.isnan()) and torch.equal(
+                torch.nan_to_num(t), torch.nan_to_num(before))
+        t = t0.clone()
+        t[3] = float("-inf")
+        with pytest.raises(_lib.FluxLimError) as e:
+            FL.convect_apply(mesh, "vanleer", t, u)
+        assert e.value.status == -6
+    finally:
+        FL.set_option("check_finite", 0)
+    t = t0.clone()
+    t[5] = float("nan")
+    FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, u, 1)  # unchecked: runs
+    torch.cuda.synchronize()
+    mesh.close()

@@ -2,6 +2,7 @@
 tables the kernels read, compared bit for bit with the oracle's face selection."""
 
 import ctypes
+import dataclasses
 import os
 import re
 
@@ -38,6 +39,73 @@ def test_status_strings():
     L = _lib.lib()
     assert L.fl_status_str(0) == b"FL_OK"
     assert L.fl_status_str(-3) == b"FL_E_UNSUPPORTED"
+    assert L.fl_status_str(-6) == b"FL_E_NONFINITE"
+    assert L.fl_status_str(-7) == b"FL_E_NODEVICE"
+    for code, name in _lib.STATUS.items():
+        assert L.fl_status_str(code).decode() == name
+
+
+def test_finite_check_option():
+    L = _lib.lib()
+    assert L.fl_set_option(4, 1) == 0  # FL_OPT_CHECK_FINITE on
+    assert L.fl_set_option(4, 0) == 0
+    assert L.fl_set_option(4, 2) == -1
+
+
+def test_batch_rejects_host_only_meshes_before_allocating():
+    """A host-only mesh has no device tables: fl_batch_create must refuse it (FL_E_NODEVICE)
+    before any allocation or launch, whatever device the batch names."""
+    m = W.periodic_box(6, 3)
+    mesh = FL.Mesh.from_arrays(m, device=-1)
+    L = _lib.lib()
+    mh = (ctypes.c_void_p * 1)(mesh.handle.value)
+    lim = (ctypes.c_int * 1)(2)
+    ns = (ctypes.c_int * 1)(1)
+    dts = (ctypes.c_double * 1)(1e-3)
+    th = (ctypes.c_void_p * 1)(256)
+    uu = (ctypes.c_void_p * 1)(512)
+    for device in (-1, 0):
+        out = ctypes.c_void_p(1)
+        st = L.fl_batch_create(1, mh, lim, ns, dts, 3, th, uu, 0, device, ctypes.byref(out))
+        assert st == -7, (device, st)
+        assert out.value is None
+    mesh.close()
+
+
+def _rotated_box(n, angle, seed):
+    """A periodic box whose face normals are each turned by `angle` radians about a random axis
+    and renormalised: geometrically a hexahedral mesh, but the projection weights are no longer
+    exactly 0 and 1."""
+    m = W.periodic_box(n, 3)
+    rng = np.random.default_rng(seed)
+    nrm = m.face_normal.copy()
+    ax = rng.standard_normal(nrm.shape)
+    ax -= (ax * nrm).sum(1, keepdims=True) * nrm  # axis orthogonal to the normal
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    nrm = nrm * np.cos(angle) + ax * np.sin(angle)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return dataclasses.replace(m, face_normal=nrm)
+
+
+def test_nearly_orthogonal_normals_keep_every_weight():
+    """No tolerance in the far-upwind selection: normals off the axes by 1e-10 rad give weights
+    like 1e-10 on the side faces, which the upstream difference sums (the oracle does), so the
+    mesh is built as general cells with the oracle's exact weights, not as hexahedra."""
+    m = _rotated_box(5, 1e-10, seed=1)
+    mesh = FL.Mesh.from_arrays(m, device=-1)
+    assert mesh.info.general == 1 and mesh.path == "face" and mesh.info.pairs == 0
+    far, _, _ = mesh.export_tables()
+    assert (far == -1).all()
+    om = O.OracleMesh.from_arrays(m)
+    f = 7
+    faces, w = om.side_weights(f, side_nbr=False)
+    nz = w[w != 0.0]
+    assert len(nz) >= 3 and np.abs(nz).min() < 1e-9 and np.abs(nz).max() == pytest.approx(1.0, abs=1e-15)
+    mesh.close()
+    # the exact box stays on the fused path
+    exact = FL.Mesh.from_arrays(W.periodic_box(5, 3), device=-1)
+    assert exact.info.general == 0 and exact.path == "fused"
+    exact.close()
 
 
 def _meshes():
@@ -145,10 +213,10 @@ def test_create_rejects_bad_arguments_and_host_only_compute():
     L = _lib.lib()
     st = L.fl_convect_apply(mesh.handle, 2, 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
                             ctypes.c_void_p(16), None, None)
-    assert st == -6  # FL_E_NODEVICE
+    assert st == -7  # FL_E_NODEVICE
     st = L.fl_rk_steps(mesh.handle, 9, 3, 0.1, 1, 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
                        ctypes.c_void_p(256), None)
-    assert st in (-1, -6)
+    assert st in (-1, -7)
     def a256(x):
         return (x + 255) // 256 * 256
 
