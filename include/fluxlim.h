@@ -339,6 +339,20 @@ fl_status fl_set_option(int option, int value);
 const char *fl_status_str(fl_status status);
 const char *fl_last_error(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fl_rk_steps with its workspace in a fixed device
+ * array of FL_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs on until
+ * the process ends, instead of a caller-provided buffer.  The caller still passes theta and u_f.
+ * Returns FL_E_INVALID, with nothing enqueued, when fl_rk_workspace_bytes(mesh, scheme,
+ * n_scalars) exceeds that size (about 1.2 M hexahedral cells at one scalar), and allocates
+ * nothing.  All calls on one GPU share its array, so calls that may overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  Results are bit-identical to
+ * fl_rk_steps. */
+#define FL_NOALLOC_SCRATCH_BYTES (128u << 20)
+fl_status fl_rk_steps_noalloc(const fl_mesh *mesh, int limiter, int scheme, double dt,
+                              int n_scalars, int64_t n_steps, double *theta, const double *u_f,
+                              void *hip_stream);
+
 /* Test hook: runs the device face selection for u_f (device [n_faces]) and copies, per face,
  * (C, D, U) to cdu (host int32 [n_faces][3]).  Synchronises the stream. */
 fl_status fl_debug_select(const fl_mesh *mesh, const double *u_f, int32_t *cdu, void *hip_stream);
