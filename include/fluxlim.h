@@ -221,6 +221,30 @@ fl_status fl_rk_steps_store(const fl_mesh *mesh, int limiter, int scheme, double
                             int n_scalars, int64_t n_steps, double *theta, const double *u_f,
                             double *stages, void *work, void *hip_stream);
 
+/* Reverse of n_steps steps of fl_rk_steps_store (the backward pass of a checkpoint segment):
+ * stages: device [n_steps][n_stage][n_cells][S] as fl_rk_steps_store wrote them; lambda: device
+ * [n_cells][S], on entry the cotangent of theta after the last step, on exit that of theta before
+ * the first.  Identical arithmetic to n_steps calls of fl_rk_step_adjoint (same bits for lambda).
+ * rates: the face velocities as a table of signed rates in cell-slot order, written once per
+ * velocity field by fl_adjoint_rates (fl_adjoint_rates_bytes bytes, 16-byte aligned device
+ * memory; a backward pass writes it once and passes it to every segment).  The face-velocity
+ * cotangent is accumulated (+=) in u_acc, a device buffer of fl_adjoint_uacc_bytes bytes in the
+ * mesh's cell-slot layout (each face is kept by exactly one of its cells), or skipped if u_acc
+ * is NULL: zero it once, pass it to every call of a backward pass, then add it to a face-ordered
+ * u_bar with fl_adjoint_uacc_scatter (u_bar += its entries; starting from u_bar = 0 this gives
+ * the same bits as fl_rk_step_adjoint's u_bar).  work: fl_rk_steps_adjoint_workspace_bytes
+ * bytes.  Needs a fused-path mesh (FL_E_UNSUPPORTED otherwise). */
+size_t fl_adjoint_rates_bytes(const fl_mesh *mesh);
+fl_status fl_adjoint_rates(const fl_mesh *mesh, const double *u_f, void *rates, void *hip_stream);
+size_t fl_adjoint_uacc_bytes(const fl_mesh *mesh);
+size_t fl_rk_steps_adjoint_workspace_bytes(const fl_mesh *mesh, int scheme, int n_scalars);
+fl_status fl_rk_steps_adjoint(const fl_mesh *mesh, int limiter, int scheme, double dt,
+                              int n_scalars, int64_t n_steps, const double *stages,
+                              const void *rates, double *lambda, double *u_acc, void *work,
+                              void *hip_stream);
+fl_status fl_adjoint_uacc_scatter(const fl_mesh *mesh, const double *u_acc, double *u_bar,
+                                  void *hip_stream);
+
 /* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
  * with one launch per Runge-Kutta stage for all of them (one fused cell-centric kernel over a
  * work table of (problem, cell tile) entries).  device >= 0 and every mesh created on it (a
@@ -330,10 +354,17 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     or an infinity.  The scan synchronises the caller's stream, so calls made
  *                     with the check on cannot be captured into a graph.  Batches and the
  *                     algebraic path are not checked.
+ *   FL_OPT_FWD_RATES  1 (default): on meshes whose opposite-face pairs line up from cell to
+ *                     cell (lattice meshes: the neighbour across a cell's slot k holds the shared
+ *                     face in its slot k ^ 1), the LDS-staged stages of multi-step calls read the
+ *                     per-call rates of each cell's forward faces only (every face once, half the
+ *                     rate bytes) and take a backward face's rate from the neighbour that holds it
+ *                     as its forward face (through LDS, or gathered for a neighbour outside the
+ *                     tile); 0: a rate per slot.  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3,
-       FL_OPT_CHECK_FINITE = 4 };
+       FL_OPT_CHECK_FINITE = 4, FL_OPT_FWD_RATES = 5 };
 fl_status fl_set_option(int option, int value);
 
 const char *fl_status_str(fl_status status);

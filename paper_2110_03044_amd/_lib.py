@@ -75,6 +75,12 @@ SIGNATURES = {
     "fl_rk_step_store": (_S, [_P, _I, _I, _D, _I, _P, _P, _P, _P, _P]),
     "fl_rk_steps_store": (_S, [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P, _P]),
     "fl_rk_steps_noalloc": (_S, [_P, _I, _I, _D, _I, _I64, _P, _P, _P]),
+    "fl_adjoint_rates_bytes": (_SZ, [_P]),
+    "fl_adjoint_rates": (_S, [_P, _P, _P, _P]),
+    "fl_adjoint_uacc_bytes": (_SZ, [_P]),
+    "fl_rk_steps_adjoint_workspace_bytes": (_SZ, [_P, _I, _I]),
+    "fl_rk_steps_adjoint": (_S, [_P, _I, _I, _D, _I, _I64, _P, _P, _P, _P, _P, _P]),
+    "fl_adjoint_uacc_scatter": (_S, [_P, _P, _P, _P]),
     "fl_batch_create": (_S, [_I, _P, _P, _P, _P, _I, _P, _P, _I, _I, _P]),
     "fl_batch_step": (_S, [_P, _I, _P]),
     "fl_batch_step_unbatched": (_S, [_P, _I, _P]),

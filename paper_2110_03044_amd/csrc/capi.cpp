@@ -116,7 +116,8 @@ int g_slot_velocity = 1;
 // How the stages of one call read the face velocities: gathered through the face index
 // (PLAN_GATHER), from per-call slot records (PLAN_RECORDS), or from per-call rates with the
 // LDS-staged stage (PLAN_LDS).
-enum { PLAN_GATHER = 0, PLAN_RECORDS = 1, PLAN_LDS = 2 };
+enum { PLAN_GATHER = 0, PLAN_RECORDS = 1, PLAN_LDS = 2, PLAN_LDS_FWD = 3 };
+int g_fwd_rates = 1;  // FL_OPT_FWD_RATES
 struct Plan {
     int kind = PLAN_GATHER;
     void *table = nullptr;
@@ -127,6 +128,9 @@ hipError_t stage(const fl_mesh *m, int lim, int S, double dt, double a, double b
                  const double *ts, const double *tn, const double *u, double *out, double *phi,
                  hipStream_t st, double us = 1.0, const Plan &pl = Plan()) {
     if (m->path == FL_PATH_FUSED) {
+        if (pl.kind == PLAN_LDS_FWD)
+            return launch_fused_lds_fwd(m, lim, S, ts, tn, static_cast<const double *>(pl.table),
+                                        a, b, dt, mode, out, st, us);
         if (pl.kind == PLAN_LDS)
             return launch_fused_lds(m, lim, S, ts, tn, static_cast<const double *>(pl.table), a,
                                     b, dt, mode, out, st, us);
@@ -172,6 +176,12 @@ hipError_t prepare_rates(const fl_mesh *m, const double *u, int S, int64_t n_ste
                          const Work &w, hipStream_t st, Plan *pl) {
     *pl = Plan();
     if (m->path != FL_PATH_FUSED || !g_slot_velocity || n_steps < 2) return hipSuccess;
+    const size_t fl = lds_fwd_bytes(m, S);
+    if (g_fwd_rates && fl > 0 && fl <= kMaxStageLds) {
+        hipError_t e = launch_slot_rates_fwd(m, u, static_cast<double *>(w.vs), st);
+        if (e == hipSuccess) *pl = Plan{PLAN_LDS_FWD, w.vs};
+        return e;
+    }
     const size_t lds = lds_stage_bytes(m, S);
     if (lds > 0 && lds <= kMaxStageLds) {
         hipError_t e = launch_slot_rates(m, u, static_cast<double *>(w.vs), st);
@@ -217,6 +227,10 @@ fl_status fl_set_option(int option, int value) {
     }
     if (option == FL_OPT_LDS_STAGE && (value == 0 || value == 1)) {
         set_lds_stage(value);
+        return FL_OK;
+    }
+    if (option == FL_OPT_FWD_RATES && (value == 0 || value == 1)) {
+        g_fwd_rates = value;
         return FL_OK;
     }
     if (option == FL_OPT_CHECK_FINITE && (value == 0 || value == 1)) {
@@ -736,6 +750,112 @@ fl_status fl_rk_step_adjoint(const fl_mesh *m, int lim, int scheme, double dt, i
                                lambda, w2, u_bar, st);
     }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step_adjoint launch");
+}
+
+// ------------------------------------------------------------------------------------------
+// Multi-step reverse sweep
+// ------------------------------------------------------------------------------------------
+static fl_status check_steps_adjoint(const fl_mesh *m, int lim, int S) {
+    fl_status s = check_adjoint(m, lim, S);
+    if (s != FL_OK) return s;
+    if (m->path != FL_PATH_FUSED || !m->h.forward_slots || !m->d_adj_fr)
+        return fail(FL_E_UNSUPPORTED,
+                    "the multi-step reverse sweep needs a fused-path mesh with forward face slots");
+    return FL_OK;
+}
+
+size_t fl_adjoint_uacc_bytes(const fl_mesh *m) {
+    if (!m || m->path != FL_PATH_FUSED || !m->h.forward_slots) return 0;
+    return (size_t)m->h.pairs * m->h.nc * sizeof(double);
+}
+
+size_t fl_adjoint_rates_bytes(const fl_mesh *m) {
+    if (!m || m->path != FL_PATH_FUSED) return 0;
+    return (size_t)2 * m->h.pairs * m->h.nc * kAdjRateBytes;
+}
+
+fl_status fl_adjoint_rates(const fl_mesh *m, const double *u, void *rates, void *stream) {
+    fl_status s = check_steps_adjoint(m, 0, 1);
+    if (s != FL_OK) return s;
+    if (!u || !rates) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(u) || ((uintptr_t)rates & 15u))
+        return fail(FL_E_INVALID, "u must be 8-byte and rates 16-byte aligned");
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    s = finite_inputs(m, {{u, m->h.nf}}, 0.0, st);
+    if (s != FL_OK) return s;
+    hipError_t e = launch_adjoint_rates(m, u, rates, st);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_adjoint_rates launch");
+}
+
+size_t fl_rk_steps_adjoint_workspace_bytes(const fl_mesh *m, int scheme, int S) {
+    if (!m || S < 1 || S > FL_MAX_SCALARS || (scheme != FL_EULER && scheme != FL_SSPRK3) ||
+        m->path != FL_PATH_FUSED)
+        return 0;
+    return 2 * align256((size_t)m->h.nc * S * sizeof(double));
+}
+
+fl_status fl_rk_steps_adjoint(const fl_mesh *m, int lim, int scheme, double dt, int S,
+                              int64_t n_steps, const double *stages, const void *rates,
+                              double *lambda, double *u_acc, void *work, void *stream) {
+    fl_status s = check_steps_adjoint(m, lim, S);
+    if (s != FL_OK) return s;
+    if (scheme != FL_EULER && scheme != FL_SSPRK3) return fail(FL_E_INVALID, "unknown scheme");
+    if (n_steps < 0) return fail(FL_E_INVALID, "n_steps must be >= 0");
+    if ((n_steps > 0 && !stages) || !rates || !lambda || !work)
+        return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(stages) || ((uintptr_t)rates & 15u) || misaligned(lambda) ||
+        misaligned(u_acc) || ((uintptr_t)work & 255u))
+        return fail(FL_E_INVALID,
+                    "stages/lambda/u_acc must be 8-byte, rates 16-byte and work 256-byte aligned");
+    if (n_steps == 0) return FL_OK;
+    DeviceGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cell = (size_t)m->h.nc * S;
+    const int ns = scheme == FL_EULER ? 1 : 3;
+    s = finite_inputs(m, {{stages, (int64_t)(cell * ns * n_steps)}, {lambda, (int64_t)cell}}, dt,
+                      st);
+    if (s != FL_OK) return s;
+    const void *wr = rates;
+    double *w1 = (double *)work;
+    double *w3 = (double *)((char *)work + align256(cell * sizeof(double)));
+    hipError_t e = hipSuccess;
+    double *lam = lambda;  // holds the current step's input cotangent
+    for (int64_t i = n_steps - 1; i >= 0 && e == hipSuccess; --i) {
+        const double *tn = stages + (size_t)i * ns * cell;
+        if (scheme == FL_EULER) {
+            double *dst = (lam == lambda) ? w1 : lambda;
+            e = launch_adjoint_rate_stage(m, lim, S, wr, tn, lam, 0.0, 1.0, 0.0, dt, ADJ_EULER,
+                                          nullptr, nullptr, dst, u_acc, st);
+            lam = dst;
+        } else {
+            // stage 3 (theta2): lam -> w1; stage 2 (theta1): w1 -> w3; stage 1 (theta^n):
+            // w3 -> lam, completed with the theta^n terms of stages 3 and 2
+            e = launch_adjoint_rate_stage(m, lim, S, wr, tn + 2 * cell, lam, kRk3A[2], kRk3B[2],
+                                          0.0, dt, ADJ_LAST, nullptr, nullptr, w1, u_acc, st);
+            if (e == hipSuccess)
+                e = launch_adjoint_rate_stage(m, lim, S, wr, tn + cell, w1, kRk3A[1], kRk3B[1],
+                                              0.0, dt, ADJ_MID, nullptr, nullptr, w3, u_acc, st);
+            if (e == hipSuccess)
+                e = launch_adjoint_rate_stage(m, lim, S, wr, tn, w3, kRk3A[1], kRk3B[0],
+                                              kRk3A[2], dt, ADJ_FIRST, lam, w1, lam, u_acc, st);
+        }
+    }
+    if (e == hipSuccess && lam != lambda)
+        e = hipMemcpyAsync(lambda, lam, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_steps_adjoint launch");
+}
+
+fl_status fl_adjoint_uacc_scatter(const fl_mesh *m, const double *u_acc, double *u_bar,
+                                  void *stream) {
+    fl_status s = check_steps_adjoint(m, 0, 1);
+    if (s != FL_OK) return s;
+    if (!u_acc || !u_bar) return fail(FL_E_INVALID, "NULL device pointer");
+    if (misaligned(u_acc) || misaligned(u_bar))
+        return fail(FL_E_INVALID, "device pointers must be 8-byte aligned");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_adjoint_uacc_scatter(m, u_acc, u_bar, (hipStream_t)stream);
+    return e == hipSuccess ? FL_OK : hip_fail(e, "fl_adjoint_uacc_scatter launch");
 }
 
 fl_status fl_debug_select(const fl_mesh *m, const double *u, int32_t *cdu, void *stream) {

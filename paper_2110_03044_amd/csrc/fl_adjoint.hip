@@ -17,107 +17,10 @@
 // u_bar of a face is written only by the thread of the face's own cell.
 #include <hip/hip_runtime.h>
 
-#include "fl_device.h"
-#include "fl_kernels.h"
+#include "fl_adjoint_device.h"
 
 namespace fl {
 namespace adev {
-
-constexpr int kBlock = 256;
-constexpr double kRBig = 1.0e18;
-
-template <int LIM>
-__device__ __forceinline__ double psi_inf(bool pos) {
-    if constexpr (LIM == FL_MINMOD) return pos ? 1.0 : 0.0;
-    else if constexpr (LIM == FL_VANLEER || LIM == FL_SUPERBEE) return pos ? 2.0 : 0.0;
-    else if constexpr (LIM == FL_VANALBADA || LIM == FL_CENTRAL) return 1.0;
-    else if constexpr (LIM == FL_SMART) return pos ? 4.0 : 0.0;
-    else return 0.0;
-}
-
-// psi(r) and psi'(r) on the branch the evaluation takes (left-closed pieces at break points).
-template <int LIM>
-__device__ __forceinline__ void psi_dpsi(double r, double &p, double &dp) {
-    if constexpr (LIM == FL_MINMOD) {
-        p = fmax(0.0, fmin(1.0, r));
-        dp = (r > 0.0 && r < 1.0) ? 1.0 : 0.0;
-    } else if constexpr (LIM == FL_VANLEER) {
-        const double q = 1.0 / (1.0 + fabs(r));
-        p = (r + fabs(r)) * q;
-        dp = r > 0.0 ? 2.0 * q * q : 0.0;
-    } else if constexpr (LIM == FL_VANALBADA) {
-        const double q = 1.0 / (r * r + 1.0);
-        p = (r * r + r) * q;
-        dp = (1.0 + 2.0 * r - r * r) * q * q;
-    } else if constexpr (LIM == FL_SUPERBEE) {
-        p = fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
-        dp = r <= 0.0 ? 0.0 : r <= 0.5 ? 2.0 : r <= 1.0 ? 0.0 : r <= 2.0 ? 1.0 : 0.0;
-    } else if constexpr (LIM == FL_SMART) {
-        p = fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
-        dp = r <= 0.0 ? 0.0 : r <= 0.2 ? 2.0 : r <= 5.0 ? 0.75 : 0.0;
-    } else if constexpr (LIM == FL_CENTRAL) {
-        p = 1.0;
-        dp = 0.0;
-    } else {
-        p = 0.0;
-        dp = 0.0;
-    }
-}
-
-// theta_f and its partials g_a = d theta_f / d d_U, g_b = d theta_f / d d_u.
-template <int LIM>
-__device__ __forceinline__ double face_value_d(double tC, double tD, double tU, double &ga,
-                                               double &gb) {
-    const double b = tD - tC;  // d_u
-    const double a = tC - tU;  // d_U
-    if constexpr (LIM == FL_UPWIND) {
-        ga = 0.0;
-        gb = 0.0;
-        return tC;
-    }
-    if (b == 0.0) {
-        // g(., 0) = 0; along d_u > 0, g(a, b) / b -> psi(+-inf) / 2, and psi(0) / 2 where a = 0
-        // (g(0, b) = psi(0) b / 2: 1/2 for central differencing, 0 for the others)
-        ga = 0.0;
-        gb = (a == 0.0) ? (LIM == FL_CENTRAL ? 0.5 : 0.0) : 0.5 * psi_inf<LIM>(a > 0.0);
-        return tC;
-    }
-    if constexpr (LIM == FL_VANALBADA) {
-        // psi(a/b) b / 2 = a b (a + b) / (2 (a^2 + b^2)): one reciprocal for value and partials
-        const double q = a * a + b * b;
-        if (q >= 1e-280 && q <= 1e280) {
-            const double iq = 1.0 / q;
-            const double iq2 = iq * iq;
-            ga = 0.5 * (b * b) * (b * b + 2.0 * a * b - a * a) * iq2;
-            gb = 0.5 * (a * a) * (a * a + 2.0 * a * b - b * b) * iq2;
-            return tC + 0.5 * (a * b) * (a + b) * iq;
-        }
-    }
-    const double r = a / b;
-    if (!(fabs(r) <= kRBig)) {
-        const double p = psi_inf<LIM>(r > 0.0);
-        ga = 0.0;
-        gb = 0.5 * p;
-        return tC + 0.5 * p * b;
-    }
-    double p, dp;
-    psi_dpsi<LIM>(r, p, dp);
-    ga = 0.5 * dp;
-    gb = 0.5 * (p - r * dp);
-    return tC + 0.5 * p * b;
-}
-
-template <int S>
-__device__ __forceinline__ void load(const double *__restrict__ a, int64_t c, double *v) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) v[s] = a[c * S + s];
-}
-
-template <int S>
-__device__ __forceinline__ void load_s(const double *src, int64_t i, int stride, double *v) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) v[s] = src[i * stride + s];
-}
 
 // Face velocities and the u_bar entries of the faces the cell owns, requested before the slot
 // loop (the per-slot theta / lambda reads stay next to their use: hoisting them as well raised
@@ -214,9 +117,11 @@ __device__ __forceinline__ void adj_cell(
             const double tD = x_up ? tnk[s] : tx[s];
             const double tU = x_up ? tno[s] : tg[s];
             const double tf = face_value_d<LIM>(tC, tD, tU, ga, gb);
-            const double mu = x_own ? (ln[s] * ivn - lx[s] * ivx) : (lx[s] * ivx - ln[s] * ivn);
+            // one rounding of the difference, then the sign (the same bits from either cell)
+            const double d = cot_diff(ln[s], ivn, lx[s], ivx);
+            const double mu = x_own ? d : -d;
             const double z = af * uf * mu;
-            jt[s] += x_up ? z * (1.0 + ga - gb) : z * gb;
+            jt[s] += x_up ? mul_nc(z, 1.0 + ga - gb) : mul_nc(z, gb);
             usum += tf * mu;
         }
         ubk[k] += scale * (af * usum);
@@ -228,8 +133,9 @@ __device__ __forceinline__ void adj_cell(
             for (int s = 0; s < S; ++s) {
                 double ga, gb;
                 (void)face_value_d<LIM>(tnk[s], tg[s], tx[s], ga, gb);
-                const double mu = n_own ? (lg[s] * ivg - ln[s] * ivn) : (ln[s] * ivn - lg[s] * ivg);
-                jt[s] -= (ar * ur * mu) * ga;
+                const double d = cot_diff(lg[s], ivg, ln[s], ivn);
+                const double mu = n_own ? d : -d;
+                jt[s] -= mul_nc(ar * ur * mu, ga);
             }
         }
     }
@@ -238,21 +144,22 @@ __device__ __forceinline__ void adj_cell(
         for (int k = 0; k < K; ++k)
             if (fw[k] >> 31) ubar[fw[k] & 0x7fffffffu] = ubk[k];
     }
+    // the roundings written out (explicit fma), as in adj_combine
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int64_t i = x * S + s;
         switch (mode) {
             case ADJ_APPLY: out[i] += jt[s]; break;
-            case ADJ_EULER: out[i] = lx[s] + dt * jt[s]; break;
+            case ADJ_EULER: out[i] = fma(dt, jt[s], lx[s]); break;
             case ADJ_LAST:
                 acc[i] = a * lx[s];
-                out[i] = b * (lx[s] + dt * jt[s]);
+                out[i] = b * fma(dt, jt[s], lx[s]);
                 break;
             case ADJ_MID:
-                acc[i] += a * lx[s];
-                out[i] = b * (lx[s] + dt * jt[s]);
+                acc[i] = fma(a, lx[s], acc[i]);
+                out[i] = b * fma(dt, jt[s], lx[s]);
                 break;
-            default: out[i] = acc[i] + b * (lx[s] + dt * jt[s]); break;
+            default: out[i] = fma(b, fma(dt, jt[s], lx[s]), acc[i]); break;
         }
     }
 }
@@ -467,5 +374,6 @@ hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, con
         default: return hipErrorInvalidValue;
     }
 }
+
 
 }  // namespace fl

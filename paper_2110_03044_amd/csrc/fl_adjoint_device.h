@@ -1,0 +1,131 @@
+// Device routines of the discrete adjoint shared by the per-step and the multi-step reverse
+// kernels: the limiter with its derivative and the limited face value with its partials.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fl_device.h"
+#include "fl_kernels.h"
+
+namespace fl {
+namespace adev {
+
+constexpr int kBlock = 256;
+constexpr double kRBig = 1.0e18;
+
+template <int LIM>
+__device__ __forceinline__ double psi_inf(bool pos) {
+    if constexpr (LIM == FL_MINMOD) return pos ? 1.0 : 0.0;
+    else if constexpr (LIM == FL_VANLEER || LIM == FL_SUPERBEE) return pos ? 2.0 : 0.0;
+    else if constexpr (LIM == FL_VANALBADA || LIM == FL_CENTRAL) return 1.0;
+    else if constexpr (LIM == FL_SMART) return pos ? 4.0 : 0.0;
+    else return 0.0;
+}
+
+// psi(r) and psi'(r) on the branch the evaluation takes (left-closed pieces at break points).
+template <int LIM>
+__device__ __forceinline__ void psi_dpsi(double r, double &p, double &dp) {
+#pragma clang fp contract(off)
+    if constexpr (LIM == FL_MINMOD) {
+        p = fmax(0.0, fmin(1.0, r));
+        dp = (r > 0.0 && r < 1.0) ? 1.0 : 0.0;
+    } else if constexpr (LIM == FL_VANLEER) {
+        const double q = 1.0 / (1.0 + fabs(r));
+        p = (r + fabs(r)) * q;
+        dp = r > 0.0 ? 2.0 * q * q : 0.0;
+    } else if constexpr (LIM == FL_VANALBADA) {
+        const double q = 1.0 / (r * r + 1.0);
+        p = (r * r + r) * q;
+        dp = (1.0 + 2.0 * r - r * r) * q * q;
+    } else if constexpr (LIM == FL_SUPERBEE) {
+        p = fmax(0.0, fmax(fmin(1.0, 2.0 * r), fmin(r, 2.0)));
+        dp = r <= 0.0 ? 0.0 : r <= 0.5 ? 2.0 : r <= 1.0 ? 0.0 : r <= 2.0 ? 1.0 : 0.0;
+    } else if constexpr (LIM == FL_SMART) {
+        p = fmax(0.0, fmin(fmin(2.0 * r, 0.25 + 0.75 * r), 4.0));
+        dp = r <= 0.0 ? 0.0 : r <= 0.2 ? 2.0 : r <= 5.0 ? 0.75 : 0.0;
+    } else if constexpr (LIM == FL_CENTRAL) {
+        p = 1.0;
+        dp = 0.0;
+    } else {
+        p = 0.0;
+        dp = 0.0;
+    }
+}
+
+// theta_f and its partials g_a = d theta_f / d d_U, g_b = d theta_f / d d_u.  No multiply-add is
+// fused here (contract off): the value and partials of a face come out with the same bits
+// wherever the routine is inlined, whichever of its results the caller uses (the far-upwind term
+// a neighbour hands over equals the one a cell forms itself).
+template <int LIM>
+__device__ __forceinline__ double face_value_d(double tC, double tD, double tU, double &ga,
+                                               double &gb) {
+#pragma clang fp contract(off)
+    const double b = tD - tC;  // d_u
+    const double a = tC - tU;  // d_U
+    if constexpr (LIM == FL_UPWIND) {
+        ga = 0.0;
+        gb = 0.0;
+        return tC;
+    }
+    if (b == 0.0) {
+        // g(., 0) = 0; along d_u > 0, g(a, b) / b -> psi(+-inf) / 2, and psi(0) / 2 where a = 0
+        // (g(0, b) = psi(0) b / 2: 1/2 for central differencing, 0 for the others)
+        ga = 0.0;
+        gb = (a == 0.0) ? (LIM == FL_CENTRAL ? 0.5 : 0.0) : 0.5 * psi_inf<LIM>(a > 0.0);
+        return tC;
+    }
+    if constexpr (LIM == FL_VANALBADA) {
+        // psi(a/b) b / 2 = a b (a + b) / (2 (a^2 + b^2)): one reciprocal for value and partials
+        const double q = a * a + b * b;
+        if (q >= 1e-280 && q <= 1e280) {
+            const double iq = 1.0 / q;
+            const double iq2 = iq * iq;
+            ga = 0.5 * (b * b) * (b * b + 2.0 * a * b - a * a) * iq2;
+            gb = 0.5 * (a * a) * (a * a + 2.0 * a * b - b * b) * iq2;
+            return tC + 0.5 * (a * b) * (a + b) * iq;
+        }
+    }
+    const double r = a / b;
+    if (!(fabs(r) <= kRBig)) {
+        const double p = psi_inf<LIM>(r > 0.0);
+        ga = 0.0;
+        gb = 0.5 * p;
+        return tC + 0.5 * p * b;
+    }
+    double p, dp;
+    psi_dpsi<LIM>(r, p, dp);
+    ga = 0.5 * dp;
+    gb = 0.5 * (p - r * dp);
+    return tC + 0.5 * p * b;
+}
+
+template <int S>
+__device__ __forceinline__ void load(const double *__restrict__ a, int64_t c, double *v) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s] = a[c * S + s];
+}
+
+template <int S>
+__device__ __forceinline__ void load_s(const double *src, int64_t i, int stride, double *v) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s] = src[i * stride + s];
+}
+
+// lambda_a / V_a - lambda_b / V_b as la * iva - lb * ivb with both products rounded and no fused
+// multiply-add: swapping the two cells negates the result exactly, so the two cells of a face
+// form its cotangent difference with the same bits (up to sign).
+__device__ __forceinline__ double cot_diff(double la, double iva, double lb, double ivb) {
+#pragma clang fp contract(off)
+    return la * iva - lb * ivb;
+}
+
+// a * b rounded on its own: a term formed with it and added to a sum later is never fused into
+// a multiply-add, so every reverse kernel adds the same rounded terms whatever it keeps in
+// registers in between.
+__device__ __forceinline__ double mul_nc(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+}  // namespace adev
+}  // namespace fl

@@ -412,5 +412,106 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
                            dt, mode, lim, out);
 }
 
+// The stage of one tile on a mesh with aligned slots (the neighbour across slot k of a cell holds
+// the shared face in its slot k ^ 1), reading per-call rates of each cell's forward faces only:
+// rf[p][c] = E a_f u_f (E u_f where all areas are area0) of slot 2p.  The rate of a backward slot
+// 2p + 1 is the negated forward rate of the neighbour across it (whose slot 2p is the shared
+// face), read from the tile's LDS copy of the forward rates or, for a neighbour outside the
+// tile, gathered through the halo list: half the rate bytes of fused_tile<RATES>, the same rates
+// w_k (a negation is exact), so the same bits.  The forward rates are loaded between the theta
+// gathers and the slot words, so that their LDS stores wait only for the former and the slot
+// words stay in flight across the barrier.  LDS: fused_tile's chunk area, then P * kTileCells
+// doubles of forward rates at rbase.
+template <int S, int P, bool PRE = true>
+__device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double *lds, int rbase,
+                                               const int32_t *__restrict__ halo_ptr,
+                                               const int32_t *__restrict__ halo,
+                                               const uint32_t *__restrict__ slot_local,
+                                               const double *__restrict__ rf, bool has_area,
+                                               double area0, const double *__restrict__ vol,
+                                               double vol0, const double *__restrict__ ts,
+                                               const double *__restrict__ tn, double a, double b,
+                                               double dt, int mode, int lim,
+                                               double *__restrict__ out, double us) {
+    constexpr int K = 2 * P;
+    constexpr int CS = S >= 2 ? 2 : 1;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t left = nc - c0;
+    const int nt = left < kTileCells ? (int)left : kTileCells;
+    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int64_t c = c0 + (tid < nt ? tid : 0);
+    double tv[CS], hv[kHaloAhead][CS];
+#pragma unroll
+    for (int s = 0; s < CS; ++s) tv[s] = ts[c * S + s];
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * nthr;
+        const int64_t h = halo[h0 + (i < nh ? i : 0)];
+        const int64_t g = i < nh ? h : c;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) hv[j][s] = ts[g * S + s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double rfv[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) rfv[p] = rf[(int64_t)p * nc + c];
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t l[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) l[k] = slot_local[(int64_t)k * nc + c];
+    double tnv[CS];
+    if constexpr (PRE) {
+        const double *tnp = tn ? tn : ts;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) tnv[s] = tnp[c * S + s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < CS; ++s) lds[tid * CS + s] = tv[s];
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * nthr;
+        const int e = kTileCells + (i < nh ? i : nh);
+#pragma unroll
+        for (int s = 0; s < CS; ++s) lds[e * CS + s] = hv[j][s];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) lds[rbase + p * kTileCells + tid] = rfv[p];
+    for (int i = tid + kHaloAhead * nthr; i < nh; i += nthr) {
+        const int64_t g = halo[h0 + i];
+#pragma unroll
+        for (int s = 0; s < CS; ++s) lds[(kTileCells + i) * CS + s] = ts[g * S + s];
+    }
+    __syncthreads();
+    const bool active = tid < nt;
+    const int64_t cc = c0 + tid;
+    int64_t nb[K], gf[K];
+    double w[K];
+    double V = vol0;
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            nb[k] = l[k] & 0xffffu;
+            gf[k] = l[k] >> 16;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double v = rfv[p] * us;
+            w[2 * p] = has_area ? v : area0 * v;
+            const int64_t n = nb[2 * p + 1];
+            const double r = n < kTileCells ? lds[rbase + p * kTileCells + n]
+                                            : rf[(int64_t)p * nc + halo[h0 + n - kTileCells]];
+            const double vb = (-r) * us;
+            w[2 * p + 1] = has_area ? vb : area0 * vb;
+        }
+        if (vol) V = vol[cc];
+        fused_chunk<S, P, 0, CS, CS, 0, PRE>(cc, tid, lds, w, nb, gf, V, tn, a, b, dt, mode, lim,
+                                             out, tnv);
+    }
+    tile_chunks<S, P, CS>(nc, tile, lds, halo_ptr, halo, ts, active, cc, w, nb, gf, V, tn, a, b,
+                          dt, mode, lim, out);
+}
+
 }  // namespace dev
 }  // namespace fl

@@ -34,6 +34,13 @@ struct HostTables {
     int32_t max_degree = 0;
     bool uniform_degree = false;
     int32_t pairs = 0;              // > 0 iff every cell has 2*pairs faces in opposite pairs
+    // Slot 2p of every cell is its forward face of pair p: each face is forward for exactly one
+    // of its cells (true for every fused-path mesh where the orientation was found).
+    bool forward_slots = false;
+    // Every cell's neighbour across its slot k holds the shared face in its slot k ^ 1 (lattice
+    // meshes, whose pairs are ordered by axis): a quantity of slot k of that neighbour describes
+    // the face beyond it in the same direction.
+    bool aligned_slots = false;
     // Fused-path slot tables, structure of arrays [2*pairs][C].
     std::vector<uint32_t> slot_face; // face index | (1u << 31) if the cell is the face's own
     std::vector<int32_t> slot_nbr;   // the other cell of the face

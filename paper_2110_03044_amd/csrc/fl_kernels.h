@@ -30,6 +30,21 @@ hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, con
                           const double *lam, double a, double b, double dt, int mode, double *out,
                           double *acc, double *ubar, hipStream_t st);
 
+// Multi-step reverse sweep (fl_rk_steps_adjoint): per-call slot rates {w, w'} (16 bytes per slot,
+// kAdjRateBytes) from u; one reverse stage in mode ADJ_EULER / ADJ_LAST / ADJ_MID / ADJ_FIRST
+// (FIRST: a = the middle stage's a, a3 = the last stage's, lin / l3 the step's input cotangent
+// and the last stage's output); uacc: the forward faces' u cotangent [P][C] (+=, or NULL); and
+// u_bar[f] += E_f uacc.
+constexpr size_t kAdjRateBytes = 16;
+
+hipError_t launch_adjoint_rates(const fl_mesh *m, const double *u, void *wr, hipStream_t st);
+hipError_t launch_adjoint_rate_stage(const fl_mesh *m, int lim, int S, const void *wr,
+                                     const double *th, const double *lam, double a, double b,
+                                     double a3, double dt, int mode, const double *lin,
+                                     const double *l3, double *out, double *uacc, hipStream_t st);
+hipError_t launch_adjoint_uacc_scatter(const fl_mesh *m, const double *uacc, double *ubar,
+                                       hipStream_t st);
+
 // us scales the face velocities (time-dependent velocity); 1 leaves them untouched.
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,
                             const double *u, double *phi, hipStream_t st, double us = 1.0);
@@ -62,6 +77,13 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
                             const double *rate, double a, double b, double dt, int mode,
                             double *out, hipStream_t st, double us = 1.0,
                             const double *u = nullptr);
+// Forward-rate stage (meshes with aligned slots, fused_tile_fwd): per-call rates of the forward
+// faces rf[P][C]; LDS of lds_fwd_bytes(m, S) (0: not available).
+size_t lds_fwd_bytes(const fl_mesh *m, int S);
+hipError_t launch_slot_rates_fwd(const fl_mesh *m, const double *u, double *rf, hipStream_t st);
+hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *ts,
+                                const double *tn, const double *rf, double a, double b, double dt,
+                                int mode, double *out, hipStream_t st, double us = 1.0);
 hipError_t launch_permute(int64_t n, int S, const int32_t *perm, int to_mesh, const double *in,
                           double *out, hipStream_t st);
 hipError_t launch_select(const fl_mesh *m, const double *u, int32_t *cdu, hipStream_t st);

@@ -232,6 +232,46 @@ __global__ __launch_bounds__(kBlock) void slot_rate_kernel(int64_t nc,
     for (int k = 0; k < K; ++k) rate[(int64_t)k * nc + c] = (fw[k] >> 31) ? x[k] : -x[k];
 }
 
+// rf[p][c] = E a_f u_f of slot 2p (each cell's forward faces: every face once), for the
+// forward-rate stage of meshes with aligned slots.
+template <int P, bool AREA>
+__global__ __launch_bounds__(kBlock) void slot_rate_fwd_kernel(int64_t nc,
+                                                               const uint32_t *__restrict__ sface,
+                                                               const double *__restrict__ u,
+                                                               const double *__restrict__ area,
+                                                               double *__restrict__ rf) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nc) return;
+    uint32_t fw[P];
+    double x[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) fw[p] = sface[(int64_t)(2 * p) * nc + c];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int64_t f = fw[p] & 0x7fffffffu;
+        if constexpr (AREA) x[p] = area[f] * u[f];
+        else x[p] = u[f];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) rf[(int64_t)p * nc + c] = (fw[p] >> 31) ? x[p] : -x[p];
+}
+
+// The LDS-staged stage reading forward rates only (fused_tile_fwd); dynamic LDS of rbase +
+// P * kTileCells doubles.
+template <int S, int P>
+__global__ __launch_bounds__(kBlock) void fused_stage_lds_fwd_kernel(
+    int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
+    const uint32_t *__restrict__ slot_local, const double *__restrict__ rf, int has_area,
+    double area0, const double *__restrict__ vol, double vol0, const double *__restrict__ ts,
+    const double *__restrict__ tn, double a, double b, double dt, int mode, int lim,
+    double *__restrict__ out, double us, int rbase, int remap) {
+    extern __shared__ double lds[];
+    const int64_t tile = block_id(remap);
+    if (tile * kTileCells >= nc) return;
+    fused_tile_fwd<S, P>(nc, tile, lds, rbase, halo_ptr, halo, slot_local, rf, has_area != 0,
+                         area0, vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
+}
+
 // One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
 // min(S, 2) doubles.
 template <int S, int P, bool RATES>
@@ -466,6 +506,51 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
     }
 #undef FL_FUSED_LDS
 #undef FL_FUSED_LDS_R
+    return hipGetLastError();
+}
+
+size_t lds_fwd_bytes(const fl_mesh *m, int S) {
+    const size_t lds = lds_stage_bytes(m, S);
+    if (lds == 0 || !m->h.aligned_slots) return 0;
+    return lds + (size_t)m->h.pairs * kTileCells * sizeof(double);
+}
+
+hipError_t launch_slot_rates_fwd(const fl_mesh *m, const double *u, double *rf, hipStream_t st) {
+    const unsigned nb = (unsigned)((m->h.nc + dev::kBlock - 1) / dev::kBlock);
+#define FL_RATES_FWD(P)                                                                         \
+    (m->d_area ? dev::slot_rate_fwd_kernel<P, true><<<nb, dev::kBlock, 0, st>>>(                \
+                     m->h.nc, m->d_slot_face, u, m->d_area, rf)                                 \
+               : dev::slot_rate_fwd_kernel<P, false><<<nb, dev::kBlock, 0, st>>>(               \
+                     m->h.nc, m->d_slot_face, u, nullptr, rf))
+    switch (m->h.pairs) {
+        case 1: FL_RATES_FWD(1); break;
+        case 2: FL_RATES_FWD(2); break;
+        case 3: FL_RATES_FWD(3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FL_RATES_FWD
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *ts,
+                                const double *tn, const double *rf, double a, double b, double dt,
+                                int mode, double *out, hipStream_t st, double us) {
+    const size_t lds = lds_fwd_bytes(m, S);
+    if (lds == 0 || lds > kMaxStageLds || !rf) return hipErrorInvalidValue;
+    const int rbase = (int)(lds_stage_bytes(m, S) / sizeof(double));
+    const Grid g = grid_for(m->h.nc, g_remap);
+#define FL_FUSED_FWD(P)                                                                          \
+    FL_DISPATCH_S(S, (dev::fused_stage_lds_fwd_kernel<kS, P><<<g.blocks, dev::kBlock, lds, st>>>( \
+                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_slot_local, rf,                  \
+                         m->d_area ? 1 : 0, m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt,    \
+                         mode, lim, out, us, rbase, g.remap)))
+    switch (m->h.pairs) {
+        case 1: FL_FUSED_FWD(1); break;
+        case 2: FL_FUSED_FWD(2); break;
+        case 3: FL_FUSED_FWD(3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FL_FUSED_FWD
     return hipGetLastError();
 }
 

@@ -467,6 +467,53 @@ std::vector<int32_t> face_numbering(int64_t nc, int64_t nf, const int32_t *fc,
     return fnew;
 }
 
+// Each face is the "forward" face of exactly one of its two cells, and every cell has exactly one
+// forward face in each of its opposite-face pairs, so that per-face quantities can be kept in a
+// cell-slot layout of P entries per cell (the adjoint's face-velocity cotangent).  First rule:
+// face f is forward for the cell it points out of along a lexicographically positive direction
+// (own where n_f is lexicographically positive, else nbr).  Opposite faces with exactly opposite
+// outward normals (lattice meshes) then split one forward, one backward.  Where that fails for
+// some pair, the chains of opposite faces (cell -> face -> next cell -> its opposite face ...) are
+// walked and each is oriented along its walk.  Returns fwd[f] = the cell whose forward face f is,
+// or an empty vector if no such orientation was found.
+std::vector<int32_t> forward_cells(int64_t nc, int64_t nf, const int32_t *fc, const double *nrm,
+                                   const Csr &cs, const std::vector<int32_t> &opp) {
+    auto side_of = [&](int64_t f, int64_t c) { return fc[2 * f] == c ? 0 : 1; };
+    std::vector<int32_t> fwd(nf);
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < nf; ++f) {
+        const double *n = nrm + 3 * f;
+        const bool pos = n[0] > 0.0 || (n[0] == 0.0 && (n[1] > 0.0 || (n[1] == 0.0 && n[2] > 0.0)));
+        fwd[f] = pos ? fc[2 * f] : fc[2 * f + 1];
+    }
+    auto valid = [&]() {
+        bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+        for (int64_t c = 0; c < nc; ++c)
+            for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+                const int64_t f = cs.idx[p], g = opp[2 * f + side_of(f, c)];
+                if ((fwd[f] == c) == (fwd[g] == c)) ok = false;
+            }
+        return ok;
+    };
+    if (valid()) return fwd;
+    // chain walk: from face f0 leaving cell c, the next face is the one of the next cell opposite
+    // to the face it was entered by
+    std::vector<char> seen(nf, 0);
+    for (int64_t f0 = 0; f0 < nf; ++f0) {
+        if (seen[f0]) continue;
+        int64_t f = f0, c = fc[2 * f0];
+        while (!seen[f]) {
+            seen[f] = 1;
+            fwd[f] = (int32_t)c;
+            c = other(fc, f, c);
+            f = opp[2 * f + side_of(f, c)];
+        }
+    }
+    if (valid()) return fwd;
+    return std::vector<int32_t>();
+}
+
 void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) {
     t.pairs = 0;
     // the fused kernel is instantiated for 1, 2 and 3 pairs (lines, quadrilaterals, hexahedra)
@@ -484,6 +531,8 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
             if (opp[2 * j + side_of(j, c)] != f) paired = false;
         }
     if (!paired) return;
+    const std::vector<int32_t> fwd = forward_cells(nc, t.nf, fc, t.nrm.data(), cs, opp);
+    t.forward_slots = !fwd.empty();
     const int K = t.max_degree, P = K / 2;
     t.slot_face.assign((size_t)K * nc, 0);
     t.slot_nbr.assign((size_t)K * nc, 0);
@@ -498,8 +547,30 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
             bool placed = false;
             for (int k = 0; k < q; ++k) placed |= (slots[k] == f);
             if (placed) continue;
-            slots[q++] = f;
-            slots[q++] = opp[2 * f + side_of(f, c)];
+            const int32_t g = opp[2 * f + side_of(f, c)];
+            // slot 2p: the pair's forward face (where the orientation was found)
+            const bool swap = t.forward_slots && fwd[g] == c;
+            slots[q++] = swap ? g : f;
+            slots[q++] = swap ? f : g;
+        }
+        // pairs in the order of the axis their forward face's normal is closest to, where that
+        // axis differs between the cell's pairs (lattice meshes: pair p is axis p)
+        if (t.forward_slots) {
+            int key[3] = {0, 0, 0};
+            bool distinct = true;
+            for (int p = 0; p < K / 2; ++p) {
+                const double *n = t.nrm.data() + 3 * (int64_t)slots[2 * p];
+                const double ax = std::fabs(n[0]), ay = std::fabs(n[1]), az = std::fabs(n[2]);
+                key[p] = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+                for (int r = 0; r < p; ++r) distinct &= key[r] != key[p];
+            }
+            if (distinct)
+                for (int p = 1; p < K / 2; ++p)  // insertion sort of at most three pairs
+                    for (int r = p; r > 0 && key[r - 1] > key[r]; --r) {
+                        std::swap(key[r - 1], key[r]);
+                        std::swap(slots[2 * r - 2], slots[2 * r]);
+                        std::swap(slots[2 * r - 1], slots[2 * r + 1]);
+                    }
         }
         for (int k = 0; k < K; ++k) {
             int32_t f = slots[k];
@@ -515,6 +586,20 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
         }
     }
     t.pairs = P;
+    // aligned: the neighbour across slot k of every cell sees the shared face in its slot k ^ 1
+    bool aligned = t.forward_slots;
+    if (aligned) {
+#pragma omp parallel for schedule(static) reduction(&& : aligned)
+        for (int64_t c = 0; c < nc; ++c)
+            for (int k = 0; k < K; ++k) {
+                const size_t at = (size_t)k * nc + c;
+                const int64_t n = t.slot_nbr[at];
+                if ((t.slot_face[(size_t)(k ^ 1) * nc + n] & 0x7fffffffu) !=
+                    (t.slot_face[at] & 0x7fffffffu))
+                    aligned = false;
+            }
+    }
+    t.aligned_slots = aligned;
 }
 
 // Tile halos for the LDS-staged fused stage: for each run of kTileCells consecutive cells, the

@@ -35,7 +35,8 @@ def scheme_id(s) -> int:
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
 
-OPTIONS = {"xcd_remap": 1, "slot_velocity": 2, "lds_stage": 3, "check_finite": 4}
+OPTIONS = {"xcd_remap": 1, "slot_velocity": 2, "lds_stage": 3, "check_finite": 4,
+           "fwd_rates": 5}
 
 
 def set_option(name: str, value: int) -> None:
@@ -43,7 +44,9 @@ def set_option(name: str, value: int) -> None:
     (default 1: multi-step calls read per-call slot tables with the signed face rates),
     "lds_stage" (default 1: those calls stage each tile's theta and halo in LDS) or
     "check_finite" (default 0: 1 makes the compute calls reject non-finite inputs with
-    FL_E_NONFINITE, at the cost of a scan and a stream synchronisation per call)."""
+    FL_E_NONFINITE, at the cost of a scan and a stream synchronisation per call) or
+    "fwd_rates" (default 1: on lattice meshes those multi-step stages read the rates of each
+    cell's forward faces only)."""
     call("fl_set_option", OPTIONS[name], int(value))
 
 
@@ -314,6 +317,50 @@ def rk_step_adjoint(mesh: Mesh, limiter, scheme, dt, stages, u, lam, u_bar=None,
     return lam
 
 
+def adjoint_rates(mesh: Mesh, u, stream=None) -> torch.Tensor:
+    """The face velocities as the signed-rate table that rk_steps_adjoint reads."""
+    n = int(lib().fl_adjoint_rates_bytes(mesh.handle)) // 8
+    rates = torch.empty(n, dtype=torch.float64, device=mesh.device)
+    call("fl_adjoint_rates", mesh.handle, _tptr(mesh._faces(u)), _tptr(rates),
+         _stream(mesh.device, stream))
+    return rates
+
+
+def rk_steps_adjoint(mesh: Mesh, limiter, scheme, dt, stages, rates, lam, n_steps: int,
+                     u_acc: Optional[torch.Tensor] = None, work=None, stream=None):
+    """Reverse of n_steps stored steps (stages[i] = step i's stage inputs; rates from
+    adjoint_rates): lam becomes the cotangent of theta before step 0, in place; u_acc (see
+    uacc_buffer) accumulates the face-velocity cotangent in the mesh's cell-slot layout (None:
+    skipped)."""
+    lam = mesh._cells(lam)
+    S = _S(lam)
+    if work is None:
+        work = _workspace(int(lib().fl_rk_steps_adjoint_workspace_bytes(
+            mesh.handle, scheme_id(scheme), S)), mesh.device)
+    per = n_stages(scheme) * lam.numel()
+    if not stages.is_contiguous() or stages.dtype != torch.float64 or \
+            stages.numel() < n_steps * per or stages.device != lam.device:
+        raise ValueError("stages must be a contiguous float64 [n_steps, stages, n_cells(, S)] buffer")
+    call("fl_rk_steps_adjoint", mesh.handle, limiter_id(limiter), scheme_id(scheme), float(dt), S,
+         int(n_steps), _tptr(stages), _tptr(rates), _tptr(lam), _tptr(u_acc),
+         _tptr(work), _stream(mesh.device, stream))
+    return lam
+
+
+def uacc_buffer(mesh: Mesh) -> Optional[torch.Tensor]:
+    """A zeroed face-velocity cotangent accumulator in the mesh's cell-slot layout (None where the
+    mesh has none: not on the fused path)."""
+    n = int(lib().fl_adjoint_uacc_bytes(mesh.handle)) // 8
+    return torch.zeros(n, dtype=torch.float64, device=mesh.device) if n else None
+
+
+def uacc_scatter(mesh: Mesh, u_acc: torch.Tensor, u_bar: torch.Tensor, stream=None):
+    """u_bar += the accumulated face-velocity cotangent (face order)."""
+    call("fl_adjoint_uacc_scatter", mesh.handle, _tptr(u_acc), _tptr(mesh._faces(u_bar)),
+         _stream(mesh.device, stream))
+    return u_bar
+
+
 def checkpoint_interval(n_steps: int) -> int:
     """ceil(sqrt(n_steps)): sqrt(N) checkpoints, each segment recomputed once in the backward."""
     import math
@@ -366,21 +413,41 @@ class _Advect(torch.autograd.Function):
         lam = grad.detach().to(torch.float64).contiguous().clone()
         S = _S(lam)
         u_bar = torch.zeros_like(u_d)
+        want_u = ctx.needs_input_grad[1]
         work = rk_workspace(mesh, scheme, S)
-        awork = rk_adjoint_workspace(mesh, scheme, S)
+        # the multi-step reverse sweep (one call per segment, u cotangent in cell-slot order,
+        # scattered once at the end) where the mesh has it, else one call per step
+        u_acc = uacc_buffer(mesh)
+        multi = u_acc is not None
+        if multi:
+            awork = _workspace(int(lib().fl_rk_steps_adjoint_workspace_bytes(
+                mesh.handle, scheme_id(scheme), S)), mesh.device)
+            rates = adjoint_rates(mesh, u_d)  # once: u is the same in every segment
+        else:
+            awork = rk_adjoint_workspace(mesh, scheme, S)
         stages = ctx.stages
         last = len(ctx.ckpts) - 1
         for seg in reversed(range(len(ctx.ckpts))):
             start = seg * ctx.every
             count = min(ctx.every, ctx.n_steps - start)
-            if seg != last:  # recompute the segment, storing every stage input
-                th = ctx.ckpts[seg].clone()
+            if seg != last:  # recompute the segment, storing every stage input (the checkpoint
+                # is not needed again: it is advanced in place)
+                th = ctx.ckpts[seg]
+                ctx.ckpts[seg] = None
                 rk_steps_store(mesh, lim, scheme, dt, th, u_d, stages, count, work=work)
-            for j in reversed(range(count)):
-                rk_step_adjoint(mesh, lim, scheme, dt, stages[j], u_d, lam, u_bar, work=awork)
+                del th
+            if multi:
+                rk_steps_adjoint(mesh, lim, scheme, dt, stages, rates, lam, count,
+                                 u_acc if want_u else None, work=awork)
+            else:
+                for j in reversed(range(count)):
+                    rk_step_adjoint(mesh, lim, scheme, dt, stages[j], u_d, lam,
+                                    u_bar if want_u else None, work=awork)
+        if multi and want_u:
+            uacc_scatter(mesh, u_acc, u_bar)
         ctx.ckpts = None
         ctx.stages = None
-        return lam, u_bar, None, None, None, None, None, None
+        return lam, (u_bar if want_u else None), None, None, None, None, None, None
 
 
 def checkpoint_interval_for_budget(mesh: Mesh, scheme, S: int, n_steps: int,

@@ -13,6 +13,7 @@ the velocity direction curves more than theta), against a 1e-6 relative bar.
 """
 
 import dataclasses
+import zlib
 
 import numpy as np
 import pytest
@@ -326,4 +327,77 @@ def test_operator_adjoint_on_flat_fields(lim, lds):
             assert np.abs(host(ub)[fp] - ub_o).max() <= 1e-12 * max(np.abs(ub_o).max(), 1e-300)
     finally:
         FL.set_option("lds_stage", 1)
+    mesh.close()
+
+
+def _zigzag_line(n):
+    """A periodic line along z whose face normals lean by +-1e-300 in x, alternately: opposite
+    faces still project with weight exactly 1, but both outward normals of a cell point to the
+    same side of the plane x = 0, so the forward faces come from the chain walk."""
+    fc = np.array([[i, (i + 1) % n] for i in range(n)], dtype=np.int32)
+    nrm = np.zeros((n, 3))
+    nrm[:, 2] = 1.0
+    nrm[:, 0] = np.where(np.arange(n) % 2 == 0, 1e-300, -1e-300)
+    return W.MeshArrays(fc, nrm, np.ones(n), np.ones(n), n, 1)
+
+
+@pytest.mark.parametrize("case", ["box", "box_varied", "zigzag"])
+@pytest.mark.parametrize("S", [1, 2, 3])
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+@pytest.mark.parametrize("lds", [1, 0], ids=["lds", "global"])
+@pytest.mark.parametrize("lim", ["vanalbada", "superbee", "smart", "central"])
+def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
+    """fl_rk_steps_adjoint over a segment (per-call slot rates, u cotangent accumulated in
+    cell-slot order and scattered at the end) gives the same bits as one fl_rk_step_adjoint per
+    step: lambda, and u_bar starting from zero.  The varied case scales volumes and areas; the
+    zigzag line needs the chain walk for its forward faces."""
+    rng = np.random.default_rng(zlib.crc32(f"{lim}-{scheme}-{S}-{case}".encode()))
+    if case == "zigzag":
+        m = _zigzag_line(40)
+        u0 = np.where(rng.random(m.n_faces) < 0.5, 1.0, -0.7)
+        dt = 0.2
+    else:
+        wl, _, _ = noisy_box(11, seed=S)
+        m, u0, dt = wl.mesh, wl.u, wl.dt
+        if case == "box_varied":
+            m = dataclasses.replace(
+                m, cell_volume=m.cell_volume * rng.uniform(0.7, 1.3, m.n_cells),
+                face_area=m.face_area * rng.uniform(0.7, 1.3, m.n_faces))
+    th0 = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+    th0[::5] = np.round(th0[::5])
+    steps = 5
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=(case != "zigzag"))
+    u = mesh.faces_to_mesh(dev(u0))
+    t = mesh.cells_to_mesh(dev(th0))
+    stages = FL.stage_buffer(mesh, scheme, S, steps)
+    try:
+        FL.set_option("lds_stage", lds)
+        FL.rk_steps_store(mesh, lim, scheme, dt, t.clone(), u, stages, steps)
+        lam0 = mesh.cells_to_mesh(dev(rng.standard_normal(th0.shape)))
+        a = lam0.clone()
+        ua = torch.zeros_like(u)
+        for j in reversed(range(steps)):
+            FL.rk_step_adjoint(mesh, lim, scheme, dt, stages[j], u, a, ua)
+        b = lam0.clone()
+        acc = FL.uacc_buffer(mesh)
+        assert acc is not None and acc.numel() == mesh.info.pairs * mesh.n_cells
+        # two calls, as a checkpointed backward makes them: the later steps first
+        rates = FL.adjoint_rates(mesh, u)
+        FL.rk_steps_adjoint(mesh, lim, scheme, dt, stages[2:], rates, b, steps - 2, acc)
+        FL.rk_steps_adjoint(mesh, lim, scheme, dt, stages, rates, b, 2, acc)
+        ub = FL.uacc_scatter(mesh, acc, torch.zeros_like(u))
+        torch.cuda.synchronize()
+        c = lam0.clone()
+        FL.rk_steps_adjoint(mesh, lim, scheme, dt, stages, rates, c, steps, None)
+        torch.cuda.synchronize()
+    finally:
+        FL.set_option("lds_stage", 1)
+    def diff(x, y):
+        d = (x - y).abs()
+        return f"{int((d > 0).sum())} of {d.numel()} differ, max {float(d.max()):.3e}"
+
+    assert torch.equal(a, b), diff(a, b)
+    assert torch.equal(ua, ub), diff(ua, ub)
+    # and the lambda of a call without the u cotangent
+    assert torch.equal(a, c), diff(a, c)
     mesh.close()

@@ -583,3 +583,53 @@ def test_opt_in_finite_check():
     FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, t, u, 1)  # unchecked: runs
     torch.cuda.synchronize()
     mesh.close()
+
+
+@pytest.mark.parametrize("S", [1, 2, 3, 5])
+@pytest.mark.parametrize("case", ["line", "quad", "hex", "hex_varied", "hex_scaled"])
+def test_forward_rates_give_the_same_bits(case, S):
+    """On lattice meshes (aligned slots) the multi-step LDS stages read only each cell's forward
+    face rates and take the backward ones from the neighbours (FL_OPT_FWD_RATES); the results
+    must equal the per-slot rate tables' bit for bit, also with face areas, volumes and a
+    time-dependent velocity scale, and for a tile count with a ragged end."""
+    import dataclasses
+
+    rng = np.random.default_rng(len(case) * 10 + S)
+    if case == "line":
+        m = W.renumber(W.periodic_box(700, 1), seed=3)
+        u = W.velocity_uniform(m, (1.0, 0.0, 0.0))
+    elif case == "quad":
+        m = W.renumber(W.periodic_box(37, 2), seed=4)
+        u = W.velocity_uniform(m, (0.6, -0.8, 0.0))
+    else:
+        n = 19
+        m = W.renumber(W.periodic_box(n, 3), seed=5)
+        u = m.face_velocity_from_natural(W.velocity_curl(n, seed=2))
+        if case == "hex_varied":
+            m = dataclasses.replace(m, cell_volume=m.cell_volume * rng.uniform(0.7, 1.3, m.n_cells),
+                                    face_area=m.face_area * rng.uniform(0.7, 1.3, m.n_faces))
+    th0 = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+    dt = W.cfl_dt(m, u, 0.3)
+    mesh, cp, fp = mesh_pair(m, reorder=True)
+    assert mesh.info.tile_cells == 256
+    uu = dev(to_mesh_faces(u, fp))
+    res = []
+    try:
+        for on in (1, 0):
+            FL.set_option("fwd_rates", on)
+            t = dev(to_mesh_cells(th0, cp))
+            if case == "hex_scaled":
+                sc = 0.5 + rng.random(3 * 6) if on else sc
+                FL.rk_steps_scaled(mesh, "superbee", "ssprk3", dt, t, uu, sc)
+            else:
+                FL.rk_steps(mesh, "vanleer", "ssprk3", dt, t, uu, 6)
+            torch.cuda.synchronize()
+            res.append(t)
+    finally:
+        FL.set_option("fwd_rates", 1)
+    assert torch.equal(res[0], res[1])
+    om = O.OracleMesh.from_arrays(m)
+    if case != "hex_scaled":
+        want = om.run("vanleer", "ssprk3", dt, th0, u, 6)
+        assert nrel(host(res[0])[cp], want) <= RUN_TOL
+    mesh.close()
