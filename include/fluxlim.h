@@ -112,6 +112,9 @@ typedef struct fl_mesh_info_t {
     int32_t general;        /* 1: some face side projects on several faces or with a weight */
                             /* other than 1 (triangles, tetrahedra, skewed cells)            */
     int32_t max_side;       /* most projected faces on one face side                         */
+    int32_t aligned;        /* 1 if the opposite-face pairs line up from cell to cell (lattice */
+                            /* meshes; the forward-rate stages, FL_OPT_FWD_RATES, apply)      */
+    int32_t reserved;
 } fl_mesh_info_t;
 
 /* Checks an incidence against the mesh model without a GPU (Section 2).  face_cells: host
@@ -360,7 +363,9 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     per-call rates of each cell's forward faces only (every face once, half the
  *                     rate bytes) and take a backward face's rate from the neighbour that holds it
  *                     as its forward face (through LDS, or gathered for a neighbour outside the
- *                     tile); 0: a rate per slot.  Results are bit-identical.
+ *                     tile); 0: a rate per slot.  Likewise the tables of fl_adjoint_rates hold
+ *                     one rate per face or two per slot (a table is read back under the setting
+ *                     it was written with).  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3,

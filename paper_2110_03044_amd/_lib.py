@@ -37,7 +37,8 @@ class MeshInfo(ctypes.Structure):
                 ("uniform_volume", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("tile_cells", ctypes.c_int32), ("max_halo", ctypes.c_int32),
                 ("halo_total", ctypes.c_int64), ("general", ctypes.c_int32),
-                ("max_side", ctypes.c_int32)]
+                ("max_side", ctypes.c_int32), ("aligned", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class AlgebraicInfo(ctypes.Structure):

@@ -69,7 +69,7 @@ void free_device(fl_mesh *m) {
     void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
                     m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local, m->d_side_ptr,
-                    m->d_side_cell, m->d_side_w, m->d_adj_fr};
+                    m->d_side_cell, m->d_side_w, m->d_adj_fr, m->d_halo_pair};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
@@ -79,6 +79,7 @@ void free_device(fl_mesh *m) {
     m->d_adj_fr = nullptr;
     m->d_halo_ptr = m->d_halo = nullptr;
     m->d_slot_local = nullptr;
+    m->d_halo_pair = nullptr;
     m->d_side_ptr = m->d_side_cell = nullptr;
     m->d_side_w = nullptr;
     m->d_area = m->d_vol = nullptr;
@@ -347,6 +348,11 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                     if (st == FL_OK)
                         st = upload(&m->d_slot_local, h.slot_local.data(), h.slot_local.size(), B,
                                     "local slot indices");
+                    if (st == FL_OK && !h.halo_pair.empty()) {
+                        std::vector<uint8_t> hp(h.halo_pair);
+                        hp.resize(h.halo_pair.size() + kHaloPad, 0);
+                        st = upload(&m->d_halo_pair, hp.data(), hp.size(), B, "tile halo pairs");
+                    }
                 }
             }
             if (st == FL_OK && !h.uni_area) st = upload(&m->d_area, h.area.data(), h.area.size(), B, "areas");
@@ -403,6 +409,8 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
     for (size_t i = 0; i + 1 < m->h.side_ptr.size(); ++i)
         ms = std::max(ms, m->h.side_ptr[i + 1] - m->h.side_ptr[i]);
     info->max_side = m->h.general ? ms : 1;
+    info->aligned = m->h.aligned_slots ? 1 : 0;
+    info->reserved = 0;
     return FL_OK;
 }
 
@@ -769,6 +777,10 @@ size_t fl_adjoint_uacc_bytes(const fl_mesh *m) {
     return (size_t)m->h.pairs * m->h.nc * sizeof(double);
 }
 
+// On meshes with aligned slots the reverse stages read one rate per face (the forward rates);
+// otherwise two per-slot planes.
+bool adjoint_fwd_rates(const fl_mesh *m) { return m->h.aligned_slots && g_fwd_rates; }
+
 size_t fl_adjoint_rates_bytes(const fl_mesh *m) {
     if (!m || m->path != FL_PATH_FUSED) return 0;
     return (size_t)2 * m->h.pairs * m->h.nc * kAdjRateBytes;
@@ -784,7 +796,11 @@ fl_status fl_adjoint_rates(const fl_mesh *m, const double *u, void *rates, void 
     hipStream_t st = (hipStream_t)stream;
     s = finite_inputs(m, {{u, m->h.nf}}, 0.0, st);
     if (s != FL_OK) return s;
-    hipError_t e = launch_adjoint_rates(m, u, rates, st);
+    // the form follows the mesh and FL_OPT_FWD_RATES (a table written under one setting of the
+    // option is read under the same setting)
+    const bool fwd = adjoint_fwd_rates(m);
+    hipError_t e = fwd ? launch_adjoint_fwd_rates(m, u, static_cast<double *>(rates), st)
+                       : launch_adjoint_rates(m, u, rates, st);
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_adjoint_rates launch");
 }
 
@@ -817,6 +833,14 @@ fl_status fl_rk_steps_adjoint(const fl_mesh *m, int lim, int scheme, double dt, 
                       st);
     if (s != FL_OK) return s;
     const void *wr = rates;
+    const bool fwd = adjoint_fwd_rates(m);
+    auto rstage = [&](const double *th, const double *lm, double a, double b, double a3, int mode,
+                      const double *lin, const double *l3, double *out) {
+        return fwd ? launch_adjoint_fwd_stage(m, lim, S, static_cast<const double *>(wr), th, lm,
+                                              a, b, a3, dt, mode, lin, l3, out, u_acc, st)
+                   : launch_adjoint_rate_stage(m, lim, S, wr, th, lm, a, b, a3, dt, mode, lin, l3,
+                                               out, u_acc, st);
+    };
     double *w1 = (double *)work;
     double *w3 = (double *)((char *)work + align256(cell * sizeof(double)));
     hipError_t e = hipSuccess;
@@ -825,20 +849,16 @@ fl_status fl_rk_steps_adjoint(const fl_mesh *m, int lim, int scheme, double dt, 
         const double *tn = stages + (size_t)i * ns * cell;
         if (scheme == FL_EULER) {
             double *dst = (lam == lambda) ? w1 : lambda;
-            e = launch_adjoint_rate_stage(m, lim, S, wr, tn, lam, 0.0, 1.0, 0.0, dt, ADJ_EULER,
-                                          nullptr, nullptr, dst, u_acc, st);
+            e = rstage(tn, lam, 0.0, 1.0, 0.0, ADJ_EULER, nullptr, nullptr, dst);
             lam = dst;
         } else {
             // stage 3 (theta2): lam -> w1; stage 2 (theta1): w1 -> w3; stage 1 (theta^n):
             // w3 -> lam, completed with the theta^n terms of stages 3 and 2
-            e = launch_adjoint_rate_stage(m, lim, S, wr, tn + 2 * cell, lam, kRk3A[2], kRk3B[2],
-                                          0.0, dt, ADJ_LAST, nullptr, nullptr, w1, u_acc, st);
+            e = rstage(tn + 2 * cell, lam, kRk3A[2], kRk3B[2], 0.0, ADJ_LAST, nullptr, nullptr, w1);
             if (e == hipSuccess)
-                e = launch_adjoint_rate_stage(m, lim, S, wr, tn + cell, w1, kRk3A[1], kRk3B[1],
-                                              0.0, dt, ADJ_MID, nullptr, nullptr, w3, u_acc, st);
+                e = rstage(tn + cell, w1, kRk3A[1], kRk3B[1], 0.0, ADJ_MID, nullptr, nullptr, w3);
             if (e == hipSuccess)
-                e = launch_adjoint_rate_stage(m, lim, S, wr, tn, w3, kRk3A[1], kRk3B[0],
-                                              kRk3A[2], dt, ADJ_FIRST, lam, w1, lam, u_acc, st);
+                e = rstage(tn, w3, kRk3A[1], kRk3B[0], kRk3A[2], ADJ_FIRST, lam, w1, lam);
         }
     }
     if (e == hipSuccess && lam != lambda)

@@ -51,99 +51,6 @@ __global__ __launch_bounds__(kBlock) void adjoint_rate_kernel(int64_t nc,
     }
 }
 
-// theta / lambda / V of a cell with source index i: tsrc[i * stride + s], lsrc[i * stride + s],
-// vsrc[i * vstride] (vsrc NULL: all volumes 1 / ivol0).  jt = (J^T lambda)_x; ubk[p] += the
-// forward face p's velocity-cotangent term (when UB).
-template <int S, int P, int LIM, bool TNLDS, bool UB>
-__device__ __forceinline__ void adj_cell_rate(int64_t xi, const double2 *wk, const int64_t *nbi,
-                                              const int64_t *gfi, const double *tsrc,
-                                              const double *lsrc, const double *vsrc, int stride,
-                                              int vstride, double ivol0, const double *afk,
-                                              double scale, double *ubk, double *jt,
-                                              double *lx) {
-    constexpr int K = 2 * P;
-    double tx[S], tn[TNLDS ? 1 : K][S];
-    load_s<S>(tsrc, xi, stride, tx);
-    load_s<S>(lsrc, xi, stride, lx);
-    if constexpr (!TNLDS) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) load_s<S>(tsrc, nbi[k], stride, tn[k]);
-    }
-    const double ivx = vsrc ? 1.0 / vsrc[xi * vstride] : ivol0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) jt[s] = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const double w = wk[k].x, wp = wk[k].y;
-        const double ivn = vsrc ? 1.0 / vsrc[nbi[k] * vstride] : ivol0;
-        const double ivg = vsrc ? 1.0 / vsrc[gfi[k] * vstride] : ivol0;
-        double tnk[S], tno[S];
-        if constexpr (TNLDS) {
-            load_s<S>(tsrc, nbi[k], stride, tnk);
-            load_s<S>(tsrc, nbi[k ^ 1], stride, tno);
-        } else {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                tnk[s] = tn[k][s];
-                tno[s] = tn[k ^ 1][s];
-            }
-        }
-        double ln[S], lg[S], tg[S];
-        load_s<S>(lsrc, nbi[k], stride, ln);
-        load_s<S>(lsrc, gfi[k], stride, lg);
-        load_s<S>(tsrc, gfi[k], stride, tg);
-        // face f between x and n: x is its upwind cell where the flow leaves x (w > 0), or where
-        // u_f is zero and x is the face's nbr (w = +0.0)
-        const bool x_up = !signbit(w);
-        double usum = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            double ga, gb;
-            const double tC = x_up ? tx[s] : tnk[s];
-            const double tD = x_up ? tnk[s] : tx[s];
-            const double tU = x_up ? tno[s] : tg[s];
-            const double tf = face_value_d<LIM>(tC, tD, tU, ga, gb);
-            const double d = cot_diff(ln[s], ivn, lx[s], ivx);
-            const double z = w * d;
-            jt[s] += x_up ? mul_nc(z, 1.0 + ga - gb) : mul_nc(z, gb);
-            if (UB && (k & 1) == 0) usum += tf * d;
-        }
-        if constexpr (UB) {
-            if ((k & 1) == 0) ubk[k >> 1] += scale * (afk[k >> 1] * usum);
-        }
-        // face fr between n and g: x is its far-upwind cell where the flow leaves n away from x
-        if (wp > 0.0) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                double ga, gb;
-                (void)face_value_d<LIM>(tnk[s], tg[s], tx[s], ga, gb);
-                jt[s] -= mul_nc(wp * cot_diff(lg[s], ivg, ln[s], ivn), ga);
-            }
-        }
-    }
-}
-
-// Stage combination of the multi-step reverse sweep (modes ADJ_EULER, ADJ_LAST, ADJ_MID,
-// ADJ_FIRST): out = lambda + dt J^T lambda (Euler); out = b (lambda + dt J^T lambda) (the last
-// and middle stages of SSP-RK3); for the first stage the cotangent of theta^n is completed with
-// the terms of the two later stages, a3 lin + a2 l3 (lin: the step's input cotangent, l3: the
-// last stage's output), in the order the per-step path accumulates them.
-// (out may be lin: each thread reads lin only at its own cell before writing it.)
-template <int S>
-__device__ __forceinline__ void adj_combine(int64_t x, const double *jt, const double *lx, double a,
-                                            double b, double a3, double dt, int mode,
-                                            const double *lin, const double *__restrict__ l3,
-                                            double *out) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int64_t i = x * S + s;
-        const double g = fma(dt, jt[s], lx[s]);
-        if (mode == ADJ_EULER) out[i] = g;
-        else if (mode == ADJ_FIRST) out[i] = fma(b, g, fma(a, l3[i], a3 * lin[i]));
-        else out[i] = b * g;
-    }
-}
-
 // Global-gather form (meshes without tile tables or without LDS room).  a is the middle stage's
 // a (3/4) in ADJ_FIRST mode.
 template <int S, int P, int LIM, bool UB>

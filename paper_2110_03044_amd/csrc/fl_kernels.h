@@ -44,6 +44,14 @@ hipError_t launch_adjoint_rate_stage(const fl_mesh *m, int lim, int S, const voi
                                      const double *l3, double *out, double *uacc, hipStream_t st);
 hipError_t launch_adjoint_uacc_scatter(const fl_mesh *m, const double *uacc, double *ubar,
                                        hipStream_t st);
+// The same reverse stage on meshes with aligned slots from the forward rates rf[P][C] (one per
+// face; fl_adjoint_fwd.hip).
+hipError_t launch_adjoint_fwd_rates(const fl_mesh *m, const double *u, double *rf,
+                                    hipStream_t st);
+hipError_t launch_adjoint_fwd_stage(const fl_mesh *m, int lim, int S, const double *rf,
+                                    const double *th, const double *lam, double a, double b,
+                                    double a3, double dt, int mode, const double *lin,
+                                    const double *l3, double *out, double *uacc, hipStream_t st);
 
 // us scales the face velocities (time-dependent velocity); 1 leaves them untouched.
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,

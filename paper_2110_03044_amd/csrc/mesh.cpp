@@ -610,21 +610,29 @@ void build_tiles(HostTables &t) {
     if (t.pairs < 1) return;
     const int64_t nc = t.nc, K = 2 * t.pairs;
     const int64_t ntiles = (nc + kTileCells - 1) / kTileCells;
+    // On meshes with aligned slots a halo entry is a (cell, pair) reference: the cell is reached
+    // from the tile along the axis of that pair (as the neighbour or the far cell of a slot of
+    // that pair), and the adjoint stages that cell's forward rate of that pair beside its values.
+    // A cell reached along two axes (a tile that is not a brick) then appears twice.
+    const bool by_pair = t.aligned_slots;
     std::vector<int32_t> ptr(ntiles + 1, 0), halo;
+    std::vector<uint8_t> halo_pair;
     std::vector<uint32_t> local((size_t)K * nc, 0);
-    std::vector<std::vector<int32_t>> tile_refs(ntiles);
+    std::vector<std::vector<int64_t>> tile_refs(ntiles);
     int32_t max_halo = 0;
     bool fits = true;
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo) reduction(&& : fits)
     for (int64_t tile = 0; tile < ntiles; ++tile) {
         const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
-        std::vector<int32_t> &refs = tile_refs[tile];
-        for (int64_t k = 0; k < K; ++k)
+        std::vector<int64_t> &refs = tile_refs[tile];
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t pk = by_pair ? (k >> 1) : 0;
             for (int64_t c = c0; c < c1; ++c) {
-                const int32_t n = t.slot_nbr[k * nc + c], g = t.slot_far[k * nc + c];
-                if (n < c0 || n >= c1) refs.push_back(n);
-                if (g < c0 || g >= c1) refs.push_back(g);
+                const int64_t n = t.slot_nbr[k * nc + c], g = t.slot_far[k * nc + c];
+                if (n < c0 || n >= c1) refs.push_back(n << 2 | pk);
+                if (g < c0 || g >= c1) refs.push_back(g << 2 | pk);
             }
+        }
         std::sort(refs.begin(), refs.end());
         refs.erase(std::unique(refs.begin(), refs.end()), refs.end());
         if (kTileCells + refs.size() > 65535) {  // local indices are 16-bit
@@ -632,13 +640,17 @@ void build_tiles(HostTables &t) {
             continue;
         }
         max_halo = std::max<int32_t>(max_halo, (int32_t)refs.size());
-        auto loc = [&](int32_t cell) -> uint32_t {
+        auto loc = [&](int64_t cell, int64_t pk) -> uint32_t {
             if (cell >= c0 && cell < c1) return (uint32_t)(cell - c0);
-            return (uint32_t)(kTileCells + (std::lower_bound(refs.begin(), refs.end(), cell) - refs.begin()));
+            return (uint32_t)(kTileCells + (std::lower_bound(refs.begin(), refs.end(), cell << 2 | pk) -
+                                            refs.begin()));
         };
-        for (int64_t k = 0; k < K; ++k)
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t pk = by_pair ? (k >> 1) : 0;
             for (int64_t c = c0; c < c1; ++c)
-                local[k * nc + c] = loc(t.slot_nbr[k * nc + c]) | (loc(t.slot_far[k * nc + c]) << 16);
+                local[k * nc + c] = loc(t.slot_nbr[k * nc + c], pk) |
+                                    (loc(t.slot_far[k * nc + c], pk) << 16);
+        }
     }
     if (!fits) return;
     // the halos one after the other, in tile order
@@ -649,11 +661,16 @@ void build_tiles(HostTables &t) {
         ptr[tile + 1] = (int32_t)total;
     }
     halo.resize(total);
+    if (by_pair) halo_pair.resize(total);
 #pragma omp parallel for schedule(static)
     for (int64_t tile = 0; tile < ntiles; ++tile)
-        std::copy(tile_refs[tile].begin(), tile_refs[tile].end(), halo.begin() + ptr[tile]);
+        for (size_t i = 0; i < tile_refs[tile].size(); ++i) {
+            halo[ptr[tile] + i] = (int32_t)(tile_refs[tile][i] >> 2);
+            if (by_pair) halo_pair[ptr[tile] + i] = (uint8_t)(tile_refs[tile][i] & 3);
+        }
     t.halo_ptr.swap(ptr);
     t.halo.swap(halo);
+    t.halo_pair.swap(halo_pair);
     t.slot_local.swap(local);
     t.max_halo = max_halo;
 }

@@ -344,7 +344,7 @@ def _zigzag_line(n):
 @pytest.mark.parametrize("case", ["box", "box_varied", "zigzag"])
 @pytest.mark.parametrize("S", [1, 2, 3])
 @pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
-@pytest.mark.parametrize("lds", [1, 0], ids=["lds", "global"])
+@pytest.mark.parametrize("lds", [3, 2, 1, 0], ids=["fwd-lds", "fwd-global", "planes-lds", "planes-global"])
 @pytest.mark.parametrize("lim", ["vanalbada", "superbee", "smart", "central"])
 def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
     """fl_rk_steps_adjoint over a segment (per-call slot rates, u cotangent accumulated in
@@ -367,11 +367,13 @@ def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
     th0[::5] = np.round(th0[::5])
     steps = 5
     mesh = FL.Mesh.from_arrays(m, device=0, reorder=(case != "zigzag"))
+    assert mesh.info.aligned == 1
     u = mesh.faces_to_mesh(dev(u0))
     t = mesh.cells_to_mesh(dev(th0))
     stages = FL.stage_buffer(mesh, scheme, S, steps)
     try:
-        FL.set_option("lds_stage", lds)
+        FL.set_option("lds_stage", lds & 1)
+        FL.set_option("fwd_rates", lds >> 1)
         FL.rk_steps_store(mesh, lim, scheme, dt, t.clone(), u, stages, steps)
         lam0 = mesh.cells_to_mesh(dev(rng.standard_normal(th0.shape)))
         a = lam0.clone()
@@ -392,6 +394,8 @@ def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
         torch.cuda.synchronize()
     finally:
         FL.set_option("lds_stage", 1)
+        FL.set_option("fwd_rates", 1)
+
     def diff(x, y):
         d = (x - y).abs()
         return f"{int((d > 0).sum())} of {d.numel()} differ, max {float(d.max()):.3e}"
