@@ -10,11 +10,11 @@ One step = one SSP-RK3 step (three stages) of one limiter; the timed region runs
 steps for every limiter.  A face-update is one face's limited flux in one stage for one scalar:
 value = faces * stages * steps * limiters / time.
 
-Prints one JSON line (see the keys below).  `roofline` is for the dominant kernel
-(fused_stage_rec_kernel, the stage of multi-step calls): its algorithmic bytes per launch (every
-slot record and cell value it must touch, read or written once) divided by its average launch
-duration measured with HIP events on the launch stream (the timed region also holds the one
-slot-record build of each call).  `cpu_baseline` times the CPU oracle on the host cores on
+Prints one JSON line (see the keys below).  `roofline` is for the dominant kernel (the stage of
+multi-step calls, fused_stage_lds_fwd_kernel on this lattice mesh): its algorithmic bytes per
+launch (every slot index, face rate and cell value it must touch, read or written once) divided
+by its average launch duration measured with HIP events on the launch stream (the timed region
+also holds the one rate-table build of each call).  `cpu_baseline` times the CPU oracle on the host cores on
 a bounded sample of the same workload.
 """
 
@@ -38,7 +38,7 @@ def log(*a):
 
 
 TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "fused_stage_lds_kernel_box256_traffic.txt")
+                               "fused_stage_lds_fwd_kernel_box256_traffic.txt")
 KERNEL_SOURCES = ["fl_internal.h", "fl_kernels.h", "fl_device.h", "fl_kernels.hip", "mesh.cpp"]
 
 
@@ -55,7 +55,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n, xcd_remap, slot_velocity, lds_stage):
+def measured_traffic(n, xcd_remap, slot_velocity, lds_stage, fwd_rates=True):
     """HBM bytes per fused-stage launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed
     rocprofv3 counter summary, or None if it was taken on other kernel sources, sizes or launch
     mapping."""
@@ -68,7 +68,8 @@ def measured_traffic(n, xcd_remap, slot_velocity, lds_stage):
         if (kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("n", -1)) != n
                 or int(kv.get("xcd_remap", -1)) != int(xcd_remap)
                 or int(kv.get("slot_velocity", 0)) != int(slot_velocity)
-                or int(kv.get("lds_stage", 0)) != int(lds_stage)):
+                or int(kv.get("lds_stage", 0)) != int(lds_stage)
+                or int(kv.get("fwd_rates", 0)) != int(fwd_rates)):
             return None
         return int(float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
@@ -81,6 +82,18 @@ def lds_stage_bytes(C, K, S, stage, halo_total):
     once, theta_n read once (stages 2, 3) and the output written once.  Halo values are other
     tiles' cells: counted once, with their own tile."""
     b = C * K * 12 + 4 * halo_total + C * S * 8 * 2
+    if stage > 0:
+        b += C * S * 8
+    return b
+
+
+def lds_fwd_stage_bytes(C, K, S, stage, halo_total):
+    """Compulsory bytes of one forward-rate LDS stage launch (lattice meshes): local slot indices
+    (4 B per slot), the per-call rates of each cell's forward faces (8 B per face: K/2 per cell),
+    the tile halo lists (4 B cell + 1 B pair per entry), theta_s read once, theta_n read once
+    (stages 2, 3) and the output written once.  Halo values and halo rates are other tiles'
+    cells' data: counted once, with their own tile."""
+    b = C * K * 4 + C * (K // 2) * 8 + 5 * halo_total + C * S * 8 * 2
     if stage > 0:
         b += C * S * 8
     return b
@@ -129,7 +142,9 @@ def adjoint_ratio(args, torch, FL, W, dev):
         ev[3].synchronize()
         return ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
 
-    once(min(steps, 10), False)  # warm-up
+    # warm-up at full length, so that the caching allocator already holds every checkpoint and
+    # stage buffer when the timed run starts
+    once(steps, False)
     fwd_ms, bwd_ms = once(steps, True)
     # every stage input kept in HBM (20 GB at 128^3 x 400 steps): nothing is recomputed
     full_bytes = FL.n_stages("ssprk3") * mesh.n_cells * 8 * steps
@@ -382,7 +397,13 @@ def main():
                     help="0: multi-step calls use the slot records instead of LDS staging")
     ap.add_argument("--slot-velocity", type=int, default=1,
                     help="0: stages gather u through the face index (FL_OPT_SLOT_VELOCITY)")
+    ap.add_argument("--fwd-rates", type=int, default=1,
+                    help="0: a face rate per slot instead of one per face (FL_OPT_FWD_RATES)")
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 to skip the oracle timing")
+    ap.add_argument("--cpu-steps", type=int, default=10,
+                    help="SSP-RK3 steps of the oracle sample (about 0.6 s each at 256^3 on 16 "
+                         "cores; a fifth of them on the given numbering, half as many Euler "
+                         "stages on one thread)")
     ap.add_argument("--calib-copy-mib", type=int, default=1024,
                     help="size of the untimed calibration copy (0 to skip)")
     ap.add_argument("--compare-order", type=int, default=1,
@@ -408,6 +429,7 @@ def main():
     _lib.call("fl_set_option", 1, int(args.xcd_remap))  # FL_OPT_XCD_REMAP
     _lib.call("fl_set_option", 2, int(args.slot_velocity))  # FL_OPT_SLOT_VELOCITY
     _lib.call("fl_set_option", 3, int(args.lds_stage))  # FL_OPT_LDS_STAGE
+    _lib.call("fl_set_option", 5, int(args.fwd_rates))  # FL_OPT_FWD_RATES
     t0 = time.time()
     wl = W.workload_box(args.n, renumbered=True)
     m = wl.mesh
@@ -452,7 +474,7 @@ def main():
         torch.cuda.synchronize()
         info = mesh.info
         res = dict(mesh=mesh, total_ms=total_ms, per_lim=per_lim, path=mesh.path,
-                   repeats=repeats,
+                   repeats=repeats, aligned=bool(info.aligned),
                    K=int(info.max_degree), th=th, u=u, max_halo=int(info.max_halo),
                    tile_cells=int(info.tile_cells),
                    halo_total=int(info.halo_total))
@@ -519,7 +541,13 @@ def main():
         sv = bool(args.slot_velocity) and args.steps >= 2
         lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
             (r["tile_cells"] + r["max_halo"]) * min(S, 2) * 8 <= 64 * 1024
-        if lds:
+        fwd = lds and r["aligned"] and bool(args.fwd_rates) and \
+            ((r["tile_cells"] + r["max_halo"] + 1) * min(S, 2)
+             + K // 2 * r["tile_cells"] + r["max_halo"] + 1) * 8 <= 64 * 1024
+        if fwd:
+            kname = "fused_stage_lds_fwd_kernel"
+            bytes_per_step = sum(lds_fwd_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
+        elif lds:
             kname = "fused_stage_lds_kernel"
             bytes_per_step = sum(lds_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
         else:
@@ -530,7 +558,10 @@ def main():
         # velocity read, rates or records written) are charged to the call's stage launches.
         table_bytes = 0
         if sv and args.steps >= 2:
-            table_bytes = C * K * 12 + F * 8 if lds else C * K * 28 + F * 8
+            if fwd:  # forward slots' face words, each face velocity once, forward rates written
+                table_bytes = C * (K // 2) * 12 + F * 8
+            else:
+                table_bytes = C * K * 12 + F * 8 if lds else C * K * 28 + F * 8
         total_bytes = bytes_per_step * n_steps_total + table_bytes * len(lims)
         avg_launch_s = r["total_ms"] * 1e-3 / launches
         achieved = total_bytes / launches / avg_launch_s / 1e9
@@ -538,7 +569,7 @@ def main():
                            "bound": "hbm",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds),
+                           "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds, fwd),
                            "algorithmic_bytes_per_launch": int(total_bytes / launches),
                            "stage_bytes_per_launch": int(bytes_per_step / 3),
                            "table_bytes_per_call": int(table_bytes),
@@ -607,42 +638,48 @@ def main():
             mm = (fc, nrm, area, vol)
         t1 = time.time()
         om = O.OracleMesh(*mm, n_cells=C) if reorder else O.OracleMesh.from_arrays(m)
+        cpu_steps = args.cpu_steps
         t2 = time.time()
-        om.run(lim, "ssprk3", wl.dt, th_m, u_m, 1)
+        om.run(lim, "ssprk3", wl.dt, th_m, u_m, cpu_steps)
         cpu_s = time.time() - t2
-        cpu_rate = F * 3 / cpu_s / 1e9
+        cpu_rate = F * 3 * cpu_steps / cpu_s / 1e9
         out["cpu_baseline"] = {"value": round(cpu_rate, 4), "unit": "Gface-updates/s",
                                "cores": O.num_threads(), "kind": "oracle",
-                               "sample": f"1 SSP-RK3 step (3 stages, all {F} faces) of the same "
-                                         f"{args.n}^3 mesh in the numbering the GPU runs on "
-                                         f"({'library renumbering' if reorder else 'as given'}), "
+                               "sample": f"{cpu_steps} SSP-RK3 steps (3 stages each, all {F} "
+                                         f"faces) of the same {args.n}^3 mesh in the numbering "
+                                         f"the GPU runs on ({'library renumbering' if reorder else 'as given'}), "
                                          f"van Leer, {cpu_s:.1f} s"}
         log(f"oracle setup {t2 - t1:.1f}s, step {cpu_s:.1f}s")
         if reorder:
             og = O.OracleMesh.from_arrays(m)
+            given_steps = max(1, cpu_steps // 5)
             t2 = time.time()
-            og.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, 1)
+            og.run(lim, "ssprk3", wl.dt, wl.theta0, wl.u, given_steps)
             given_s = time.time() - t2
             del og
-            out["cpu_baseline"]["as_given_numbering_value"] = round(F * 3 / given_s / 1e9, 4)
-            log(f"oracle on the given numbering: step {given_s:.1f}s")
+            out["cpu_baseline"]["as_given_numbering_value"] = round(
+                F * 3 * given_steps / given_s / 1e9, 4)
+            out["cpu_baseline"]["as_given_numbering_sample"] = (
+                f"{given_steps} SSP-RK3 steps on the given random numbering, {given_s:.1f} s")
+            log(f"oracle on the given numbering: {given_steps} steps {given_s:.1f}s")
         # the same oracle on one thread, over one stage (one forward-Euler step)
         import ctypes
 
         gomp = ctypes.CDLL("libgomp.so.1")
         threads = O.num_threads()
         gomp.omp_set_num_threads(1)
+        one_stages = max(1, cpu_steps // 2)
         try:
             t3 = time.time()
-            om.run(lim, "euler", wl.dt, th_m, u_m, 1)
+            om.run(lim, "euler", wl.dt, th_m, u_m, one_stages)
             one_s = time.time() - t3
         finally:
             gomp.omp_set_num_threads(threads)
-        out["cpu_baseline"]["single_thread_value"] = round(F / one_s / 1e9, 5)
+        out["cpu_baseline"]["single_thread_value"] = round(F * one_stages / one_s / 1e9, 5)
         out["cpu_baseline"]["single_thread_sample"] = (
-            f"1 forward-Euler stage (all {F} faces) of the same mesh and numbering on 1 thread, "
-            f"{one_s:.1f} s")
-        log(f"oracle on 1 thread: one stage {one_s:.1f}s")
+            f"{one_stages} forward-Euler stages (all {F} faces each) of the same mesh and "
+            f"numbering on 1 thread, {one_s:.1f} s")
+        log(f"oracle on 1 thread: {one_stages} stages {one_s:.1f}s")
 
     print(json.dumps(out), flush=True)
 

@@ -362,8 +362,8 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     face in its slot k ^ 1), the LDS-staged stages of multi-step calls read the
  *                     per-call rates of each cell's forward faces only (every face once, half the
  *                     rate bytes) and take a backward face's rate from the neighbour that holds it
- *                     as its forward face (through LDS, or gathered for a neighbour outside the
- *                     tile); 0: a rate per slot.  Likewise the tables of fl_adjoint_rates hold
+ *                     as its forward face, staged in LDS with the tile (and, for the tile's halo
+ *                     entries, with their theta); 0: a rate per slot.  Likewise the tables of fl_adjoint_rates hold
  *                     one rate per face or two per slot (a table is read back under the setting
  *                     it was written with).  Results are bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running

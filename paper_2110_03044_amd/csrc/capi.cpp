@@ -69,7 +69,8 @@ void free_device(fl_mesh *m) {
     void *ptrs[] = {m->d_fc4,      m->d_cf_ptr,  m->d_cf_idx, m->d_slot_face, m->d_slot_nbr,
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
                     m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local, m->d_side_ptr,
-                    m->d_side_cell, m->d_side_w, m->d_adj_fr, m->d_halo_pair};
+                    m->d_side_cell, m->d_side_w, m->d_adj_fr, m->d_halo_pair,
+                    m->d_halo_nrate};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
@@ -80,6 +81,7 @@ void free_device(fl_mesh *m) {
     m->d_halo_ptr = m->d_halo = nullptr;
     m->d_slot_local = nullptr;
     m->d_halo_pair = nullptr;
+    m->d_halo_nrate = nullptr;
     m->d_side_ptr = m->d_side_cell = nullptr;
     m->d_side_w = nullptr;
     m->d_area = m->d_vol = nullptr;
@@ -352,6 +354,9 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                         std::vector<uint8_t> hp(h.halo_pair);
                         hp.resize(h.halo_pair.size() + kHaloPad, 0);
                         st = upload(&m->d_halo_pair, hp.data(), hp.size(), B, "tile halo pairs");
+                        if (st == FL_OK)
+                            st = upload(&m->d_halo_nrate, h.halo_nrate.data(), h.halo_nrate.size(),
+                                        B, "tile halo rate counts");
                     }
                 }
             }

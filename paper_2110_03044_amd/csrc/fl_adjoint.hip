@@ -124,7 +124,7 @@ __device__ __forceinline__ void adj_cell(
             jt[s] += x_up ? mul_nc(z, 1.0 + ga - gb) : mul_nc(z, gb);
             usum += tf * mu;
         }
-        ubk[k] += scale * (af * usum);
+        ubk[k] = fma(scale, af * usum, ubk[k]);
         // face fr between n and g, opposite to f in n: x is its far-upwind cell when the flow
         // runs from n to g
         const bool n_own = (rw[k] >> 31) != 0;

@@ -130,36 +130,45 @@ __device__ __forceinline__ double mul_nc(double a, double b) {
 // ------------------------------------------------------------------------------------------
 // The reverse stage of one cell from signed slot rates (the multi-step reverse sweep).
 // ------------------------------------------------------------------------------------------
+// One slot of a cell for adj_cell_rate: the rates w, w' and the source indices of the
+// neighbour n and the far cell g.
+struct AdjSlot {
+    double w, wp;
+    int64_t n, g;
+};
+
 // theta / lambda / V of a cell with source index i: tsrc[i * stride + s], lsrc[i * stride + s],
-// vsrc[i * vstride] (vsrc NULL: all volumes 1 / ivol0).  jt = (J^T lambda)_x; ubk[p] += the
-// forward face p's velocity-cotangent term (when UB).
-template <int S, int P, int LIM, bool TNLDS, bool UB>
-__device__ __forceinline__ void adj_cell_rate(int64_t xi, const double2 *wk, const int64_t *nbi,
-                                              const int64_t *gfi, const double *tsrc,
+// vsrc[i * vstride] (vsrc NULL: all volumes 1 / ivol0).  slot(k) gives slot k's AdjSlot (read
+// where it is used, so that a kernel can keep its tables in LDS rather than in registers).
+// jt = (J^T lambda)_x; ub(p, t) adds scale * t (one fused multiply-add) to the forward face p's
+// velocity cotangent, t = a_f sum_s theta_f (lambda_n/V_n - lambda_x/V_x) (when UB), with af(p)
+// that face's area.
+template <int S, int P, int LIM, bool TNLDS, bool UB, class SlotFn, class AreaFn, class UbFn>
+__device__ __forceinline__ void adj_cell_rate(int64_t xi, const SlotFn &slot, const double *tsrc,
                                               const double *lsrc, const double *vsrc, int stride,
-                                              int vstride, double ivol0, const double *afk,
-                                              double scale, double *ubk, double *jt,
-                                              double *lx) {
+                                              int vstride, double ivol0, const AreaFn &af,
+                                              const UbFn &ub, double *jt, double *lx) {
     constexpr int K = 2 * P;
     double tx[S], tn[TNLDS ? 1 : K][S];
     load_s<S>(tsrc, xi, stride, tx);
     load_s<S>(lsrc, xi, stride, lx);
     if constexpr (!TNLDS) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) load_s<S>(tsrc, nbi[k], stride, tn[k]);
+        for (int k = 0; k < K; ++k) load_s<S>(tsrc, slot(k).n, stride, tn[k]);
     }
     const double ivx = vsrc ? 1.0 / vsrc[xi * vstride] : ivol0;
 #pragma unroll
     for (int s = 0; s < S; ++s) jt[s] = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double w = wk[k].x, wp = wk[k].y;
-        const double ivn = vsrc ? 1.0 / vsrc[nbi[k] * vstride] : ivol0;
-        const double ivg = vsrc ? 1.0 / vsrc[gfi[k] * vstride] : ivol0;
+        const AdjSlot sl = slot(k);
+        const double w = sl.w, wp = sl.wp;
+        const double ivn = vsrc ? 1.0 / vsrc[sl.n * vstride] : ivol0;
+        const double ivg = vsrc ? 1.0 / vsrc[sl.g * vstride] : ivol0;
         double tnk[S], tno[S];
         if constexpr (TNLDS) {
-            load_s<S>(tsrc, nbi[k], stride, tnk);
-            load_s<S>(tsrc, nbi[k ^ 1], stride, tno);
+            load_s<S>(tsrc, sl.n, stride, tnk);
+            load_s<S>(tsrc, slot(k ^ 1).n, stride, tno);
         } else {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -168,9 +177,9 @@ __device__ __forceinline__ void adj_cell_rate(int64_t xi, const double2 *wk, con
             }
         }
         double ln[S], lg[S], tg[S];
-        load_s<S>(lsrc, nbi[k], stride, ln);
-        load_s<S>(lsrc, gfi[k], stride, lg);
-        load_s<S>(tsrc, gfi[k], stride, tg);
+        load_s<S>(lsrc, sl.n, stride, ln);
+        load_s<S>(lsrc, sl.g, stride, lg);
+        load_s<S>(tsrc, sl.g, stride, tg);
         // face f between x and n: x is its upwind cell where the flow leaves x (w > 0), or where
         // u_f is zero and x is the face's nbr (w = +0.0)
         const bool x_up = !signbit(w);
@@ -188,7 +197,7 @@ __device__ __forceinline__ void adj_cell_rate(int64_t xi, const double2 *wk, con
             if (UB && (k & 1) == 0) usum += tf * d;
         }
         if constexpr (UB) {
-            if ((k & 1) == 0) ubk[k >> 1] += scale * (afk[k >> 1] * usum);
+            if ((k & 1) == 0) ub(k >> 1, af(k >> 1) * usum);
         }
         // face fr between n and g: x is its far-upwind cell where the flow leaves n away from x
         if (wp > 0.0) {

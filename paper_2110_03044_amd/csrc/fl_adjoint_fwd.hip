@@ -64,17 +64,19 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_stage_kernel(
         wk[2 * p + 1].x = -rf[row + nb[2 * p + 1]];
         wk[2 * p + 1].y = -rf[row + gf[2 * p + 1]];
     }
-    double ubk[P], afk[P];
+    double ubk[P];
     if constexpr (UB) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            ubk[p] = uacc[(int64_t)p * nc + x];
-            afk[p] = area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
-        }
+        for (int p = 0; p < P; ++p) ubk[p] = uacc[(int64_t)p * nc + x];
     }
+    auto af = [&](int p) {
+        return area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
+    };
     double jt[S], lx[S];
-    adj_cell_rate<S, P, LIM, false, UB>(x, wk, nb, gf, th, lam, vol, S, 1, ivol0, afk, b * dt,
-                                        ubk, jt, lx);
+    auto slot = [&](int k) { return AdjSlot{wk[k].x, wk[k].y, nb[k], gf[k]}; };
+    const double scale = b * dt;
+    auto ub = [&](int p, double t) { ubk[p] = fma(scale, t, ubk[p]); };
+    adj_cell_rate<S, P, LIM, false, UB>(x, slot, th, lam, vol, S, 1, ivol0, af, ub, jt, lx);
     if constexpr (UB) {
 #pragma unroll
         for (int p = 0; p < P; ++p) uacc[(int64_t)p * nc + x] = ubk[p];
@@ -82,8 +84,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_stage_kernel(
     adj_combine<S>(x, jt, lx, a, b, a3, dt, mode, lin, l3, out);
 }
 
-// LDS-staged form.  LDS: [0, rbase) theta, lambda (and V) of the tile and its halo as in the
-// other reverse kernels; then rates: the tile's forward rates [P][kTileCells], then one per halo
+// LDS-staged form.  LDS: [0, rbase) theta, lambda (and V) of the tile and its halo, one entry
+// per cell;
+// then rates: the tile's forward rates [P][kTileCells], then one per halo
 // entry (the entry's cell's forward rate of the entry's pair).  The tile's rates and the slot
 // words and u-cotangent accumulators are requested after the theta / lambda gathers; the halo
 // rates are gathered with the halo values.
@@ -91,20 +94,24 @@ template <int S, int P, int LIM, bool UB>
 __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
     int64_t nc, const double *__restrict__ rf, const int32_t *__restrict__ halo_ptr,
     const int32_t *__restrict__ halo, const uint8_t *__restrict__ halo_pair,
-    const uint32_t *__restrict__ slot_local, const uint32_t *__restrict__ sface,
+    const int32_t *__restrict__ halo_nrate, const uint32_t *__restrict__ slot_local,
+    const uint32_t *__restrict__ sface,
     const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
     const double *__restrict__ th, const double *__restrict__ lam, double a, double b, double a3,
     double dt, int mode, const double *lin, const double *__restrict__ l3, double *out,
     double *__restrict__ uacc, int rbase, int remap) {
     extern __shared__ double lds[];
     constexpr int K = 2 * P;
-    const int st = 2 * S + (vol ? 1 : 0);
+    const int st = 2 * S + (vol ? 1 : 0);  // LDS entry: theta [S], lambda [S], V
     const int64_t tile = dev::block_id(remap);
     if (tile * kTileCells >= nc) return;
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
     const int nt = left < kTileCells ? (int)left : kTileCells;
     const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    // the leading halo entries carry a needed rate (neighbours, and far cells of backward
+    // slots); the others read their own cell's first rate instead (a line the tile reads anyway)
+    const int nr = halo_nrate[2 * tile + 1];
     const int tid = threadIdx.x;
     double *rt = lds + rbase;                    // tile forward rates [P][kTileCells]
     double *rh = lds + rbase + P * kTileCells;  // one rate per halo entry
@@ -129,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
             ht[j][s] = th[g * S + s];
             hl[j][s] = lam[g * S + s];
         }
-        hr[j] = rf[pr * nc + g];
+        hr[j] = rf[i < nr ? pr * nc + h : xc];
     }
     __builtin_amdgcn_sched_barrier(0);
     double rfv[P];
@@ -139,11 +146,6 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
     uint32_t ll[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ll[k] = slot_local[(int64_t)k * nc + xc];
-    double ubk[P], afk[P];
-    if constexpr (UB) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) ubk[p] = uacc[(int64_t)p * nc + xc];
-    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
             lds[(kTileCells + i) * st + s] = th[g * S + s];
             lds[(kTileCells + i) * st + S + s] = lam[g * S + s];
         }
-        rh[i] = rf[pr * nc + g];
+        if (i < nr) rh[i] = rf[pr * nc + g];
     }
     if (vol) {
         if (tid < nt) lds[tid * st + 2 * S] = vol[c0 + tid];
@@ -181,36 +183,30 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
     __syncthreads();
     if (tid >= nt) return;
     const int64_t x = c0 + tid;
-    int64_t nl[K], gl[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        nl[k] = ll[k] & 0xffffu;
-        gl[k] = ll[k] >> 16;
-    }
     // forward rate of pair p of a cell with local index i (tile cell or halo entry of pair p)
-    auto rate_of = [&](int p, int64_t i) {
-        return i < kTileCells ? rt[p * kTileCells + i] : rh[i - kTileCells];
+    auto rate_of = [&](int p, uint32_t i) {
+        return i < (uint32_t)kTileCells ? rt[p * kTileCells + i] : rh[i - kTileCells];
     };
-    double2 wk[K];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        wk[2 * p].x = rfv[p];
-        wk[2 * p].y = rate_of(p, nl[2 * p]);
-        wk[2 * p + 1].x = -rate_of(p, nl[2 * p + 1]);
-        wk[2 * p + 1].y = -rate_of(p, gl[2 * p + 1]);
-    }
-    if constexpr (UB) {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-            afk[p] = area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
-    }
+    // slot k from its local word: rates from the LDS copies, read where they are used
+    auto slot = [&](int k) {
+        const uint32_t n = ll[k] & 0xffffu, g = ll[k] >> 16;
+        const int p = k >> 1;
+        if (k & 1) return AdjSlot{-rate_of(p, n), -rate_of(p, g), (int64_t)n, (int64_t)g};
+        return AdjSlot{rate_of(p, (uint32_t)tid), rate_of(p, n), (int64_t)n, (int64_t)g};
+    };
+    auto af = [&](int p) {
+        return area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
+    };
     double jt[S], lx[S];
-    adj_cell_rate<S, P, LIM, true, UB>(tid, wk, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr,
-                                       st, st, ivol0, afk, b * dt, ubk, jt, lx);
-    if constexpr (UB) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) uacc[(int64_t)p * nc + x] = ubk[p];
-    }
+    // the u cotangent is read and written where its term is formed (no accumulators held
+    // through the cell's slots: registers decide this kernel's occupancy)
+    const double scale = b * dt;
+    auto ub = [&](int p, double t) {
+        double &v = uacc[(int64_t)p * nc + x];
+        v = fma(scale, t, v);
+    };
+    adj_cell_rate<S, P, LIM, true, UB>(tid, slot, lds, lds + S, vol ? lds + 2 * S : nullptr, st,
+                                       st, ivol0, af, ub, jt, lx);
     adj_combine<S>(x, jt, lx, a, b, a3, dt, mode, lin, l3, out);
 }
 
@@ -225,12 +221,13 @@ hipError_t launch_fwd3(const fl_mesh *m, const double *rf, const double *th, con
     const double iv0 = 1.0 / m->h.vol0;
     const size_t flds =
         lds + ((size_t)P * kTileCells + m->h.max_halo + 1) * sizeof(double);
-    if (lds > 0 && m->d_halo_pair && flds <= kMaxStageLds) {
+    if (lds > 0 && m->d_halo_pair && m->d_halo_nrate && flds <= kMaxStageLds) {
         const Grid g = launch_grid(m->h.nc);
         const int rbase = (int)(lds / sizeof(double));
 #define FL_AFL(UB)                                                                                \
     adev::adjoint_fwd_lds_kernel<S, P, LIM, UB><<<g.blocks, adev::kBlock, flds, st>>>(            \
-        m->h.nc, rf, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_slot_local, m->d_slot_face,  \
+        m->h.nc, rf, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_halo_nrate, m->d_slot_local,  \
+        m->d_slot_face,                                                                           \
         m->d_area, m->h.area0, m->d_vol, iv0, th, lam, a, b, a3, dt, mode, lin, l3, out, uacc,   \
         rbase, g.remap)
         if (uacc) FL_AFL(true);

@@ -73,17 +73,19 @@ __global__ __launch_bounds__(kBlock) void adjoint_rate_stage_kernel(
         nb[k] = snbr[(int64_t)k * nc + x];
         gf[k] = sfar[(int64_t)k * nc + x];
     }
-    double ubk[P], afk[P];
+    double ubk[P];
     if constexpr (UB) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            ubk[p] = uacc[(int64_t)p * nc + x];
-            afk[p] = area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
-        }
+        for (int p = 0; p < P; ++p) ubk[p] = uacc[(int64_t)p * nc + x];
     }
+    auto af = [&](int p) {
+        return area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
+    };
     double jt[S], lx[S];
-    adj_cell_rate<S, P, LIM, false, UB>(x, wk, nb, gf, th, lam, vol, S, 1, ivol0, afk, b * dt,
-                                        ubk, jt, lx);
+    auto slot = [&](int k) { return AdjSlot{wk[k].x, wk[k].y, nb[k], gf[k]}; };
+    const double scale = b * dt;
+    auto ub = [&](int p, double t) { ubk[p] = fma(scale, t, ubk[p]); };
+    adj_cell_rate<S, P, LIM, false, UB>(x, slot, th, lam, vol, S, 1, ivol0, af, ub, jt, lx);
     if constexpr (UB) {
 #pragma unroll
         for (int p = 0; p < P; ++p) uacc[(int64_t)p * nc + x] = ubk[p];
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_rate_lds_kernel(
         wk[k].x = wr[(int64_t)k * nc + xc];
         wk[k].y = wr[(int64_t)(K + k) * nc + xc];
     }
-    double ubk[P], afk[P];
+    double ubk[P];
     if constexpr (UB) {
 #pragma unroll
         for (int p = 0; p < P; ++p) ubk[p] = uacc[(int64_t)p * nc + xc];
@@ -183,14 +185,15 @@ __global__ __launch_bounds__(kBlock) void adjoint_rate_lds_kernel(
         nl[k] = ll[k] & 0xffffu;
         gl[k] = ll[k] >> 16;
     }
-    if constexpr (UB) {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-            afk[p] = area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
-    }
+    auto af = [&](int p) {
+        return area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu] : area0;
+    };
     double jt[S], lx[S];
-    adj_cell_rate<S, P, LIM, true, UB>(tid, wk, nl, gl, lds, lds + S, vol ? lds + 2 * S : nullptr,
-                                       st, st, ivol0, afk, b * dt, ubk, jt, lx);
+    auto slot = [&](int k) { return AdjSlot{wk[k].x, wk[k].y, nl[k], gl[k]}; };
+    const double scale = b * dt;
+    auto ub = [&](int p, double t) { ubk[p] = fma(scale, t, ubk[p]); };
+    adj_cell_rate<S, P, LIM, true, UB>(tid, slot, lds, lds + S, vol ? lds + 2 * S : nullptr, st,
+                                       st, ivol0, af, ub, jt, lx);
     if constexpr (UB) {
 #pragma unroll
         for (int p = 0; p < P; ++p) uacc[(int64_t)p * nc + x] = ubk[p];

@@ -417,15 +417,20 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
 // rf[p][c] = E a_f u_f (E u_f where all areas are area0) of slot 2p.  The rate of a backward slot
 // 2p + 1 is the negated forward rate of the neighbour across it (whose slot 2p is the shared
 // face), read from the tile's LDS copy of the forward rates or, for a neighbour outside the
-// tile, gathered through the halo list: half the rate bytes of fused_tile<RATES>, the same rates
-// w_k (a negation is exact), so the same bits.  The forward rates are loaded between the theta
-// gathers and the slot words, so that their LDS stores wait only for the former and the slot
-// words stay in flight across the barrier.  LDS: fused_tile's chunk area, then P * kTileCells
-// doubles of forward rates at rbase.
+// tile, from the LDS copy of the halo entries' rates (a halo entry is a (cell, pair) reference;
+// the leading ones, the neighbours across backward slots, carry that cell's forward rate of that
+// pair, gathered with its theta): half the rate
+// bytes of fused_tile<RATES>, the same rates w_k (a negation is exact), so the same bits.  The
+// tile's forward rates are loaded between the theta gathers and the slot words, so that their
+// LDS stores wait only for the former and the slot words stay in flight across the barrier.
+// LDS: fused_tile's chunk area, then P * kTileCells doubles of tile rates at rbase, then one
+// double per halo entry.
 template <int S, int P, bool PRE = true>
 __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double *lds, int rbase,
                                                const int32_t *__restrict__ halo_ptr,
                                                const int32_t *__restrict__ halo,
+                                               const uint8_t *__restrict__ halo_pair,
+                                               const int32_t *__restrict__ halo_nrate,
                                                const uint32_t *__restrict__ slot_local,
                                                const double *__restrict__ rf, bool has_area,
                                                double area0, const double *__restrict__ vol,
@@ -439,18 +444,24 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
     const int64_t left = nc - c0;
     const int nt = left < kTileCells ? (int)left : kTileCells;
     const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    // the leading halo entries (neighbours across backward slots) need their rate; the other
+    // lanes read their own cell's first rate instead (a line the tile reads anyway)
+    const int nr = halo_nrate[2 * tile];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int64_t c = c0 + (tid < nt ? tid : 0);
-    double tv[CS], hv[kHaloAhead][CS];
+    double tv[CS], hv[kHaloAhead][CS], hr[kHaloAhead];
 #pragma unroll
     for (int s = 0; s < CS; ++s) tv[s] = ts[c * S + s];
 #pragma unroll
     for (int j = 0; j < kHaloAhead; ++j) {
         const int i = tid + j * nthr;
-        const int64_t h = halo[h0 + (i < nh ? i : 0)];
+        const int ie = i < nh ? i : 0;  // (the arrays are padded: entry 0 exists)
+        const int64_t h = halo[h0 + ie];
+        const int64_t pr = halo_pair[h0 + ie];
         const int64_t g = i < nh ? h : c;
 #pragma unroll
         for (int s = 0; s < CS; ++s) hv[j][s] = ts[g * S + s];
+        hr[j] = rf[i < nr ? pr * nc + h : c];
     }
     __builtin_amdgcn_sched_barrier(0);
     double rfv[P];
@@ -478,10 +489,17 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) lds[rbase + p * kTileCells + tid] = rfv[p];
+    double *rh = lds + rbase + P * kTileCells;
+#pragma unroll
+    for (int j = 0; j < kHaloAhead; ++j) {
+        const int i = tid + j * nthr;
+        rh[i < nh ? i : nh] = hr[j];
+    }
     for (int i = tid + kHaloAhead * nthr; i < nh; i += nthr) {
         const int64_t g = halo[h0 + i];
 #pragma unroll
         for (int s = 0; s < CS; ++s) lds[(kTileCells + i) * CS + s] = ts[g * S + s];
+        if (i < nr) rh[i] = rf[(int64_t)halo_pair[h0 + i] * nc + g];
     }
     __syncthreads();
     const bool active = tid < nt;
@@ -500,8 +518,7 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
             const double v = rfv[p] * us;
             w[2 * p] = has_area ? v : area0 * v;
             const int64_t n = nb[2 * p + 1];
-            const double r = n < kTileCells ? lds[rbase + p * kTileCells + n]
-                                            : rf[(int64_t)p * nc + halo[h0 + n - kTileCells]];
+            const double r = n < kTileCells ? lds[rbase + p * kTileCells + n] : rh[n - kTileCells];
             const double vb = (-r) * us;
             w[2 * p + 1] = has_area ? vb : area0 * vb;
         }

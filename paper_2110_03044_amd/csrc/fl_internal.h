@@ -57,6 +57,9 @@ struct HostTables {
     // Aligned slots: the pair along which each halo entry is reached (halo entries are then
     // (cell, pair) references; a cell may appear once per pair).
     std::vector<uint8_t> halo_pair;
+    // Aligned slots: per tile, how many leading halo entries the forward-rate stage needs the
+    // rate of, and how many the forward-rate adjoint stage does ([2 * tiles]).
+    std::vector<int32_t> halo_nrate;
     int32_t max_halo = -1;           // -1: no tile tables (local indices would not fit 16 bits)
     // Numbering maps user -> mesh (empty = identity).
     std::vector<int32_t> cell_perm, face_perm;
@@ -99,6 +102,7 @@ struct fl_mesh {
     int32_t *d_halo = nullptr;
     uint32_t *d_slot_local = nullptr;
     uint8_t *d_halo_pair = nullptr;  // [halo entries + pad] pair of each halo entry (aligned slots)
+    int32_t *d_halo_nrate = nullptr; // [2 * tiles] halo entries whose rates the stages need
     int32_t *d_adj_fr = nullptr;   // [2P][C][2] LDS adjoint: slot face, the neighbour's face
                                    // opposite it (both with own bits)
     int32_t *d_adj_rec = nullptr;  // [2P][C][4] adjoint: slot face, the neighbour's face opposite

@@ -87,6 +87,7 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
                             const double *u = nullptr);
 // Forward-rate stage (meshes with aligned slots, fused_tile_fwd): per-call rates of the forward
 // faces rf[P][C]; LDS of lds_fwd_bytes(m, S) (0: not available).
+constexpr size_t kMaxFwdLds = 32 * 1024;
 size_t lds_fwd_bytes(const fl_mesh *m, int S);
 hipError_t launch_slot_rates_fwd(const fl_mesh *m, const double *u, double *rf, hipStream_t st);
 hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *ts,

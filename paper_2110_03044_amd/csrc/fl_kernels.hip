@@ -261,15 +261,17 @@ __global__ __launch_bounds__(kBlock) void slot_rate_fwd_kernel(int64_t nc,
 template <int S, int P>
 __global__ __launch_bounds__(kBlock) void fused_stage_lds_fwd_kernel(
     int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
+    const uint8_t *__restrict__ halo_pair, const int32_t *__restrict__ halo_nrate,
     const uint32_t *__restrict__ slot_local, const double *__restrict__ rf, int has_area,
-    double area0, const double *__restrict__ vol, double vol0, const double *__restrict__ ts,
-    const double *__restrict__ tn, double a, double b, double dt, int mode, int lim,
-    double *__restrict__ out, double us, int rbase, int remap) {
+    double area0, const double *__restrict__ vol,
+    double vol0, const double *__restrict__ ts, const double *__restrict__ tn, double a,
+    double b, double dt, int mode, int lim, double *__restrict__ out, double us, int rbase,
+    int remap) {
     extern __shared__ double lds[];
     const int64_t tile = block_id(remap);
     if (tile * kTileCells >= nc) return;
-    fused_tile_fwd<S, P>(nc, tile, lds, rbase, halo_ptr, halo, slot_local, rf, has_area != 0,
-                         area0, vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
+    fused_tile_fwd<S, P>(nc, tile, lds, rbase, halo_ptr, halo, halo_pair, halo_nrate, slot_local, rf,
+                             has_area != 0, area0, vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
 }
 
 // One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
@@ -511,8 +513,11 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
 
 size_t lds_fwd_bytes(const fl_mesh *m, int S) {
     const size_t lds = lds_stage_bytes(m, S);
-    if (lds == 0 || !m->h.aligned_slots) return 0;
-    return lds + (size_t)m->h.pairs * kTileCells * sizeof(double);
+    if (lds == 0 || !m->h.aligned_slots || !m->d_halo_pair || !m->d_halo_nrate) return 0;
+    const size_t b = lds + ((size_t)m->h.pairs * kTileCells + m->h.max_halo + 1) * sizeof(double);
+    // large halos (meshes not renumbered for locality) gain nothing from the rate staging and
+    // would cost occupancy: the per-slot rates serve them
+    return b <= kMaxFwdLds ? b : 0;
 }
 
 hipError_t launch_slot_rates_fwd(const fl_mesh *m, const double *u, double *rf, hipStream_t st) {
@@ -541,7 +546,8 @@ hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *
     const Grid g = grid_for(m->h.nc, g_remap);
 #define FL_FUSED_FWD(P)                                                                          \
     FL_DISPATCH_S(S, (dev::fused_stage_lds_fwd_kernel<kS, P><<<g.blocks, dev::kBlock, lds, st>>>( \
-                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_slot_local, rf,                  \
+                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_halo_nrate,      \
+                         m->d_slot_local, rf,                                                     \
                          m->d_area ? 1 : 0, m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt,    \
                          mode, lim, out, us, rbase, g.remap)))
     switch (m->h.pairs) {

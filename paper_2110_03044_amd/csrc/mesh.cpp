@@ -612,10 +612,15 @@ void build_tiles(HostTables &t) {
     const int64_t ntiles = (nc + kTileCells - 1) / kTileCells;
     // On meshes with aligned slots a halo entry is a (cell, pair) reference: the cell is reached
     // from the tile along the axis of that pair (as the neighbour or the far cell of a slot of
-    // that pair), and the adjoint stages that cell's forward rate of that pair beside its values.
-    // A cell reached along two axes (a tile that is not a brick) then appears twice.
+    // that pair), and the stages that read one rate per face stage that cell's forward rate of
+    // that pair beside its values.  A cell reached along two axes (a tile that is not a brick)
+    // then appears twice.  Entries are ordered by the stages that need their rate: first those
+    // reached as the neighbour across a backward slot (the forward stage and the adjoint need
+    // them), then those reached as the neighbour across a forward slot or as the far cell of a
+    // backward slot (the adjoint needs them), then the rest (far cells of forward slots: no
+    // rate needed); halo_nrate[2 tile + 0 / 1] counts the first group / the first two.
     const bool by_pair = t.aligned_slots;
-    std::vector<int32_t> ptr(ntiles + 1, 0), halo;
+    std::vector<int32_t> ptr(ntiles + 1, 0), halo, nrate(by_pair ? 2 * ntiles : 0, 0);
     std::vector<uint8_t> halo_pair;
     std::vector<uint32_t> local((size_t)K * nc, 0);
     std::vector<std::vector<int64_t>> tile_refs(ntiles);
@@ -624,26 +629,48 @@ void build_tiles(HostTables &t) {
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo) reduction(&& : fits)
     for (int64_t tile = 0; tile < ntiles; ++tile) {
         const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
-        std::vector<int64_t> &refs = tile_refs[tile];
+        // (role << 60 | cell << 2 | pair) while collecting; role 0, 1, 2 as above
+        std::vector<int64_t> keyed;
         for (int64_t k = 0; k < K; ++k) {
             const int64_t pk = by_pair ? (k >> 1) : 0;
+            const int64_t rn = (k & 1) ? 0 : 1, rg = (k & 1) ? 1 : 2;
             for (int64_t c = c0; c < c1; ++c) {
                 const int64_t n = t.slot_nbr[k * nc + c], g = t.slot_far[k * nc + c];
-                if (n < c0 || n >= c1) refs.push_back(n << 2 | pk);
-                if (g < c0 || g >= c1) refs.push_back(g << 2 | pk);
+                if (n < c0 || n >= c1) keyed.push_back((by_pair ? rn : 0) << 60 | n << 2 | pk);
+                if (g < c0 || g >= c1) keyed.push_back((by_pair ? rg : 0) << 60 | g << 2 | pk);
             }
         }
+        // one entry per (cell, pair) with its lowest role, ordered by (role, cell, pair)
+        const int64_t low = (int64_t(1) << 60) - 1;
+        std::sort(keyed.begin(), keyed.end(),
+                  [&](int64_t x, int64_t y) { return (x & low) < (y & low) || ((x & low) == (y & low) && x < y); });
+        std::vector<int64_t> &refs = tile_refs[tile];
+        for (size_t i = 0; i < keyed.size(); ++i)
+            if (i == 0 || (keyed[i] & low) != (keyed[i - 1] & low)) refs.push_back(keyed[i]);
         std::sort(refs.begin(), refs.end());
-        refs.erase(std::unique(refs.begin(), refs.end()), refs.end());
         if (kTileCells + refs.size() > 65535) {  // local indices are 16-bit
             fits = false;
             continue;
         }
         max_halo = std::max<int32_t>(max_halo, (int32_t)refs.size());
+        if (by_pair) {
+            int32_t n0 = 0, n01 = 0;
+            for (int64_t r : refs) {
+                n0 += (r >> 60) == 0;
+                n01 += (r >> 60) <= 1;
+            }
+            nrate[2 * tile] = n0;
+            nrate[2 * tile + 1] = n01;
+        }
+        // position of each (cell, pair) in the ordered halo
+        std::vector<std::pair<int64_t, int32_t>> pos(refs.size());
+        for (size_t i = 0; i < refs.size(); ++i) pos[i] = {refs[i] & low, (int32_t)i};
+        std::sort(pos.begin(), pos.end());
         auto loc = [&](int64_t cell, int64_t pk) -> uint32_t {
             if (cell >= c0 && cell < c1) return (uint32_t)(cell - c0);
-            return (uint32_t)(kTileCells + (std::lower_bound(refs.begin(), refs.end(), cell << 2 | pk) -
-                                            refs.begin()));
+            const auto it = std::lower_bound(pos.begin(), pos.end(),
+                                             std::make_pair(cell << 2 | pk, (int32_t)-1));
+            return (uint32_t)(kTileCells + it->second);
         };
         for (int64_t k = 0; k < K; ++k) {
             const int64_t pk = by_pair ? (k >> 1) : 0;
@@ -662,15 +689,18 @@ void build_tiles(HostTables &t) {
     }
     halo.resize(total);
     if (by_pair) halo_pair.resize(total);
+    const int64_t low = (int64_t(1) << 60) - 1;
 #pragma omp parallel for schedule(static)
     for (int64_t tile = 0; tile < ntiles; ++tile)
         for (size_t i = 0; i < tile_refs[tile].size(); ++i) {
-            halo[ptr[tile] + i] = (int32_t)(tile_refs[tile][i] >> 2);
-            if (by_pair) halo_pair[ptr[tile] + i] = (uint8_t)(tile_refs[tile][i] & 3);
+            const int64_t r = tile_refs[tile][i] & low;
+            halo[ptr[tile] + i] = (int32_t)(r >> 2);
+            if (by_pair) halo_pair[ptr[tile] + i] = (uint8_t)(r & 3);
         }
     t.halo_ptr.swap(ptr);
     t.halo.swap(halo);
     t.halo_pair.swap(halo_pair);
+    t.halo_nrate.swap(nrate);
     t.slot_local.swap(local);
     t.max_halo = max_halo;
 }

@@ -619,7 +619,7 @@ def test_forward_rates_give_the_same_bits(case, S):
             FL.set_option("fwd_rates", on)
             t = dev(to_mesh_cells(th0, cp))
             if case == "hex_scaled":
-                sc = 0.5 + rng.random(3 * 6) if on else sc
+                sc = 0.5 + rng.random(3 * 6) if on == 1 else sc
                 FL.rk_steps_scaled(mesh, "superbee", "ssprk3", dt, t, uu, sc)
             else:
                 FL.rk_steps(mesh, "vanleer", "ssprk3", dt, t, uu, 6)
