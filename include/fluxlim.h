@@ -366,10 +366,17 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
  *                     entries, with their theta); 0: a rate per slot.  Likewise the tables of fl_adjoint_rates hold
  *                     one rate per face or two per slot (a table is read back under the setting
  *                     it was written with).  Results are bit-identical.
+ *   FL_OPT_FACE_SHARE  1 (default): where FL_OPT_FWD_RATES applies and S <= 2, the reverse
+ *                     stages of fl_rk_steps_adjoint evaluate each face a tile needs once and pass
+ *                     its terms to the cells that need them through LDS (a face's limiter
+ *                     partials otherwise come out three times: for both its cells and for its
+ *                     far-upwind cell); 0: each cell evaluates every face it needs.  Every cell
+ *                     adds the same terms in the same order either way: results are
+ *                     bit-identical.
  * Returns FL_E_INVALID for an unknown option or value.  Not synchronised with launches running
  * on other threads. */
 enum { FL_OPT_XCD_REMAP = 1, FL_OPT_SLOT_VELOCITY = 2, FL_OPT_LDS_STAGE = 3,
-       FL_OPT_CHECK_FINITE = 4, FL_OPT_FWD_RATES = 5 };
+       FL_OPT_CHECK_FINITE = 4, FL_OPT_FWD_RATES = 5, FL_OPT_FACE_SHARE = 6 };
 fl_status fl_set_option(int option, int value);
 
 const char *fl_status_str(fl_status status);

@@ -236,6 +236,10 @@ fl_status fl_set_option(int option, int value) {
         g_fwd_rates = value;
         return FL_OK;
     }
+    if (option == FL_OPT_FACE_SHARE && (value == 0 || value == 1)) {
+        set_adjoint_share(value);
+        return FL_OK;
+    }
     if (option == FL_OPT_CHECK_FINITE && (value == 0 || value == 1)) {
         set_check_finite(value);
         return FL_OK;

@@ -84,36 +84,26 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_stage_kernel(
     adj_combine<S>(x, jt, lx, a, b, a3, dt, mode, lin, l3, out);
 }
 
-// LDS-staged form.  LDS: [0, rbase) theta, lambda (and V) of the tile and its halo, one entry
-// per cell;
-// then rates: the tile's forward rates [P][kTileCells], then one per halo
+// LDS-staged forms.  LDS: [0, rbase) theta, lambda (and V) of the tile and its halo, one entry
+// per cell (st doubles); then rates: the tile's forward rates [P][kTileCells], then one per halo
 // entry (the entry's cell's forward rate of the entry's pair).  The tile's rates and the slot
-// words and u-cotangent accumulators are requested after the theta / lambda gathers; the halo
-// rates are gathered with the halo values.
-template <int S, int P, int LIM, bool UB>
-__global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
-    int64_t nc, const double *__restrict__ rf, const int32_t *__restrict__ halo_ptr,
-    const int32_t *__restrict__ halo, const uint8_t *__restrict__ halo_pair,
-    const int32_t *__restrict__ halo_nrate, const uint32_t *__restrict__ slot_local,
-    const uint32_t *__restrict__ sface,
-    const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
-    const double *__restrict__ th, const double *__restrict__ lam, double a, double b, double a3,
-    double dt, int mode, const double *lin, const double *__restrict__ l3, double *out,
-    double *__restrict__ uacc, int rbase, int remap) {
-    extern __shared__ double lds[];
+// words are requested after the theta / lambda gathers; the halo rates are gathered with the
+// halo values (only the leading nr entries carry a rate these stages read: neighbours, and far
+// cells of backward slots; the others read their own cell's first rate, a line the tile reads
+// anyway).  Ends without a barrier; ll receives the thread's slot words.
+template <int S, int P>
+__device__ __forceinline__ void adj_stage_fwd(double *lds, int st, int rbase, int64_t nc,
+                                              int64_t c0, int nt, int h0, int nh, int nr,
+                                              const double *__restrict__ rf,
+                                              const int32_t *__restrict__ halo,
+                                              const uint8_t *__restrict__ halo_pair,
+                                              const uint32_t *__restrict__ slot_local,
+                                              const double *__restrict__ vol,
+                                              const double *__restrict__ th,
+                                              const double *__restrict__ lam, uint32_t *ll) {
     constexpr int K = 2 * P;
-    const int st = 2 * S + (vol ? 1 : 0);  // LDS entry: theta [S], lambda [S], V
-    const int64_t tile = dev::block_id(remap);
-    if (tile * kTileCells >= nc) return;
-    const int64_t c0 = tile * kTileCells;
-    const int64_t left = nc - c0;
-    const int nt = left < kTileCells ? (int)left : kTileCells;
-    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
-    // the leading halo entries carry a needed rate (neighbours, and far cells of backward
-    // slots); the others read their own cell's first rate instead (a line the tile reads anyway)
-    const int nr = halo_nrate[2 * tile + 1];
     const int tid = threadIdx.x;
-    double *rt = lds + rbase;                    // tile forward rates [P][kTileCells]
+    double *rt = lds + rbase;                   // tile forward rates [P][kTileCells]
     double *rh = lds + rbase + P * kTileCells;  // one rate per halo entry
     const int64_t xc = c0 + (tid < nt ? tid : 0);
     double tv[S], lv[S], ht[kHaloAhead][S], hl[kHaloAhead][S], hr[kHaloAhead];
@@ -143,7 +133,6 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
 #pragma unroll
     for (int p = 0; p < P; ++p) rfv[p] = rf[(int64_t)p * nc + xc];
     __builtin_amdgcn_sched_barrier(0);
-    uint32_t ll[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ll[k] = slot_local[(int64_t)k * nc + xc];
     __builtin_amdgcn_sched_barrier(0);
@@ -180,8 +169,38 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
         for (int i = tid; i < nh; i += kTileCells)
             lds[(kTileCells + i) * st + 2 * S] = vol[halo[h0 + i]];
     }
+}
+
+// Cell-wise form: every thread evaluates all its slots' faces (and the faces beyond its
+// neighbours of which it is the far-upwind cell) from the staged values.
+template <int S, int P, int LIM, bool UB>
+__global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
+    int64_t nc, const double *__restrict__ rf, const int32_t *__restrict__ halo_ptr,
+    const int32_t *__restrict__ halo, const uint8_t *__restrict__ halo_pair,
+    const int32_t *__restrict__ halo_nrate, const uint32_t *__restrict__ slot_local,
+    const uint32_t *__restrict__ sface,
+    const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
+    const double *__restrict__ th, const double *__restrict__ lam, double a, double b, double a3,
+    double dt, int mode, const double *lin, const double *__restrict__ l3, double *out,
+    double *__restrict__ uacc, int rbase, int remap) {
+    extern __shared__ double lds[];
+    constexpr int K = 2 * P;
+    const int st = 2 * S + (vol ? 1 : 0);  // LDS entry: theta [S], lambda [S], V
+    const int64_t tile = dev::block_id(remap);
+    if (tile * kTileCells >= nc) return;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t left = nc - c0;
+    const int nt = left < kTileCells ? (int)left : kTileCells;
+    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    const int nr = halo_nrate[2 * tile + 1];
+    const int tid = threadIdx.x;
+    uint32_t ll[K];
+    adj_stage_fwd<S, P>(lds, st, rbase, nc, c0, nt, h0, nh, nr, rf, halo, halo_pair, slot_local,
+                        vol, th, lam, ll);
     __syncthreads();
     if (tid >= nt) return;
+    const double *rt = lds + rbase;
+    const double *rh = lds + rbase + P * kTileCells;
     const int64_t x = c0 + tid;
     // forward rate of pair p of a cell with local index i (tile cell or halo entry of pair p)
     auto rate_of = [&](int p, uint32_t i) {
@@ -210,9 +229,194 @@ __global__ __launch_bounds__(kBlock) void adjoint_fwd_lds_kernel(
     adj_combine<S>(x, jt, lx, a, b, a3, dt, mode, lin, l3, out);
 }
 
+// Face-wise form: each face the tile needs is evaluated once and its terms are shared through
+// LDS, then every cell sums its terms in the cell-wise form's order (the same bits).
+//  * Each tile cell evaluates its P forward faces: its own term, its forward neighbour's term
+//    (rn) and the far-upwind term (ru, subtracted by whichever cell is the face's far-upwind
+//    cell).
+//  * A face owned by a halo entry (the entry's cell's forward face of the entry's pair) is an
+//    item: the leading nr entries are the only ones whose face a tile cell can need (the backward
+//    neighbours, whose face gives that tile cell's own term, and the cells beyond a neighbour,
+//    whose face gives a far-upwind term).  The tile cell that needs an item writes its
+//    descriptor (the face's other cell and its far-upwind cell for the face's flow direction);
+//    the items are then spread over all threads (no thread evaluates a tile-boundary face for
+//    its own cell alone, which would hold a whole wave).
+//  * After the last read of the staged values, the terms go to LDS over the staged values and
+//    each cell gathers its slots' terms.
+// Needs S <= 2 (the terms live in registers across the barriers) and nr <= J kTileCells.
+constexpr uint32_t kNoItem = 0xffffffffu;
+
+template <int S, int P, int LIM, bool UB, int J>
+__global__ __launch_bounds__(kBlock) void adjoint_fwd_share_kernel(
+    int64_t nc, const double *__restrict__ rf, const int32_t *__restrict__ halo_ptr,
+    const int32_t *__restrict__ halo, const uint8_t *__restrict__ halo_pair,
+    const int32_t *__restrict__ halo_nrate, const uint32_t *__restrict__ slot_local,
+    const uint32_t *__restrict__ sface,
+    const double *__restrict__ area, double area0, const double *__restrict__ vol, double ivol0,
+    const double *__restrict__ th, const double *__restrict__ lam, double a, double b, double a3,
+    double dt, int mode, const double *lin, const double *__restrict__ l3, double *out,
+    double *__restrict__ uacc, int rbase, int dbase, int remap) {
+    extern __shared__ double lds[];
+    constexpr int K = 2 * P;
+    constexpr uint32_t T = kTileCells;
+    const int st = 2 * S + (vol ? 1 : 0);
+    const int64_t tile = dev::block_id(remap);
+    if (tile * kTileCells >= nc) return;
+    const int64_t c0 = tile * kTileCells;
+    const int64_t left = nc - c0;
+    const int nt = left < kTileCells ? (int)left : kTileCells;
+    const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
+    const int n0 = halo_nrate[2 * tile], nr = halo_nrate[2 * tile + 1];
+    const int tid = threadIdx.x;
+    uint32_t *desc = reinterpret_cast<uint32_t *>(lds + dbase);  // one per item (nr)
+    uint32_t ll[K];
+    adj_stage_fwd<S, P>(lds, st, rbase, nc, c0, nt, h0, nh, nr, rf, halo, halo_pair, slot_local,
+                        vol, th, lam, ll);
+    for (int e = tid; e < nr; e += kTileCells) desc[e] = kNoItem;
+    __syncthreads();
+    const double *rt = lds + rbase;
+    const double *rh = lds + rbase + P * kTileCells;
+    auto rate_of = [&](int p, uint32_t i) {
+        return i < T ? rt[p * kTileCells + i] : rh[i - T];
+    };
+    auto tv = [&](uint32_t i, int s) { return lds[i * st + s]; };
+    auto lv = [&](uint32_t i, int s) { return lds[i * st + S + s]; };
+    auto iv = [&](uint32_t i) { return vol ? 1.0 / lds[i * st + 2 * S] : ivol0; };
+    const bool live = tid < nt;
+    const int64_t x = c0 + tid;
+    double own[P][S], rn[P][S], ru[P][S], lx[S];
+    uint32_t frm = 0;  // bit k: slot k's far-upwind term applies (w' > 0)
+    if (live) {
+        double tx[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            tx[s] = tv(tid, s);
+            lx[s] = lv(tid, s);
+        }
+        const double ivx = iv(tid);
+        const double scale = b * dt;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const uint32_t n = ll[2 * p] & 0xffffu, g = ll[2 * p] >> 16;
+            const uint32_t bn = ll[2 * p + 1] & 0xffffu, bg = ll[2 * p + 1] >> 16;
+            // the forward face (x, n): x is its upwind cell where !signbit(w)
+            const double w = rt[p * kTileCells + tid];
+            const bool x_up = !signbit(w);
+            const uint32_t u = x_up ? bn : g;
+            const double ivn = iv(n);
+            double usum = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                double ga, gb;
+                const double tn = tv(n, s);
+                const double tf =
+                    face_value_d<LIM>(x_up ? tx[s] : tn, x_up ? tn : tx[s], tv(u, s), ga, gb);
+                const double d = cot_diff(lv(n, s), ivn, lx[s], ivx);
+                const double z = w * d;
+                const double up = mul_nc(z, 1.0 + ga - gb), dn = mul_nc(z, gb);
+                own[p][s] = x_up ? up : dn;
+                rn[p][s] = x_up ? dn : up;
+                ru[p][s] = mul_nc(z, ga);
+                if (UB) usum += tf * d;
+            }
+            if constexpr (UB) {
+                const double af = area ? area[sface[(int64_t)(2 * p) * nc + x] & 0x7fffffffu]
+                                       : area0;
+                double &v = uacc[(int64_t)p * nc + x];
+                v = fma(scale, af * usum, v);
+            }
+            const double wpf = rate_of(p, n), wpb = -rate_of(p, bg);
+            if (wpf > 0.0) frm |= 1u << (2 * p);
+            if (wpb > 0.0) frm |= 1u << (2 * p + 1);
+            // items: the backward face (bn, x) when bn is a halo entry (x's own term; its
+            // far-upwind cell: x's forward neighbour where x is upwind, else bg)
+            if (bn >= T) desc[bn - T] = (uint32_t)tid | (signbit(rate_of(p, bn)) ? n : bg) << 16;
+            // the face (n, g) where the flow leaves n towards g (x is its far-upwind cell), and
+            // the face (bg, bn) where it leaves bn towards bg, when not an item already
+            if (n >= T && (int)(n - T) >= n0 && wpf > 0.0) desc[n - T] = g | (uint32_t)tid << 16;
+            if (bg >= T && (int)(bg - T) >= n0 && wpb > 0.0)
+                desc[bg - T] = bn | (uint32_t)tid << 16;
+        }
+    }
+    __syncthreads();
+    // items: face (h, hf) of halo entry e = h - T with its far-upwind cell fu; io: the term of
+    // hf (a tile cell where the item came from a backward face), ifr: the far-upwind term
+    double io[J][S], ifr[J][S];
+    bool has[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int e = tid + j * kTileCells;
+        const uint32_t dw = e < nr ? desc[e] : kNoItem;
+        has[j] = dw != kNoItem;
+        if (has[j]) {
+            const uint32_t h = T + (uint32_t)e, hf = dw & 0xffffu, fu = dw >> 16;
+            const double wh = rh[e];
+            const bool h_up = !signbit(wh);
+            const uint32_t cc = h_up ? h : hf, cd = h_up ? hf : h;
+            const double ivh = iv(h), ivf = iv(hf);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                double ga, gb;
+                (void)face_value_d<LIM>(tv(cc, s), tv(cd, s), tv(fu, s), ga, gb);
+                const double z = wh * cot_diff(lv(hf, s), ivf, lv(h, s), ivh);
+                io[j][s] = h_up ? mul_nc(z, gb) : mul_nc(z, 1.0 + ga - gb);
+                ifr[j][s] = mul_nc(z, ga);
+            }
+        }
+    }
+    __syncthreads();
+    // terms over the staged values: rn [P][T][S], ru [P][T][S], item terms [nr][S] twice
+    double *trn = lds, *tru = lds + P * kTileCells * S;
+    double *tio = lds + 2 * P * kTileCells * S, *tif = tio + nr * S;
+    if (live) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                trn[(p * kTileCells + tid) * S + s] = rn[p][s];
+                tru[(p * kTileCells + tid) * S + s] = ru[p][s];
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int e = tid + j * kTileCells;
+        if (has[j]) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                tio[e * S + s] = io[j][s];
+                tif[e * S + s] = ifr[j][s];
+            }
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+    // far-upwind term of the forward face of local cell i (tile cell or item) of pair p
+    auto fr_of = [&](int p, uint32_t i, int s) {
+        return i < T ? tru[(p * kTileCells + i) * S + s] : tif[(i - T) * S + s];
+    };
+    double jt[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) jt[s] = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t n = ll[2 * p] & 0xffffu;
+        const uint32_t bn = ll[2 * p + 1] & 0xffffu, bg = ll[2 * p + 1] >> 16;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            jt[s] += own[p][s];
+            if (frm >> (2 * p) & 1u) jt[s] -= fr_of(p, n, s);
+            jt[s] += bn < T ? trn[(p * kTileCells + bn) * S + s] : tio[(bn - T) * S + s];
+            if (frm >> (2 * p + 1) & 1u) jt[s] -= fr_of(p, bg, s);
+        }
+    }
+    adj_combine<S>(x, jt, lx, a, b, a3, dt, mode, lin, l3, out);
+}
+
 }  // namespace adev
 
 namespace {
+int g_adjoint_share = 1;  // FL_OPT_FACE_SHARE
+
 template <int S, int P, int LIM>
 hipError_t launch_fwd3(const fl_mesh *m, const double *rf, const double *th, const double *lam,
                        double a, double b, double a3, double dt, int mode, const double *lin,
@@ -224,6 +428,30 @@ hipError_t launch_fwd3(const fl_mesh *m, const double *rf, const double *th, con
     if (lds > 0 && m->d_halo_pair && m->d_halo_nrate && flds <= kMaxStageLds) {
         const Grid g = launch_grid(m->h.nc);
         const int rbase = (int)(lds / sizeof(double));
+        if constexpr (S <= 2) {
+            // face-wise form: descriptors after the staged rates; the terms over all of it
+            const int nr = m->h.max_nrate;
+            const size_t dlds = flds + ((size_t)nr * sizeof(uint32_t) + 7) / 8 * 8;
+            const size_t tlds = ((size_t)2 * P * kTileCells + 2 * (size_t)nr) * S * sizeof(double);
+            const size_t slds = dlds > tlds ? dlds : tlds;
+            if (g_adjoint_share && nr >= 0 && nr <= 2 * kTileCells && slds <= kMaxStageLds) {
+                const int dbase = (int)(flds / sizeof(double));
+#define FL_AFS(UB, J)                                                                             \
+    adev::adjoint_fwd_share_kernel<S, P, LIM, UB, J><<<g.blocks, adev::kBlock, slds, st>>>(       \
+        m->h.nc, rf, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_halo_nrate, m->d_slot_local,  \
+        m->d_slot_face, m->d_area, m->h.area0, m->d_vol, iv0, th, lam, a, b, a3, dt, mode, lin,   \
+        l3, out, uacc, rbase, dbase, g.remap)
+                if (nr <= kTileCells) {
+                    if (uacc) FL_AFS(true, 1);
+                    else FL_AFS(false, 1);
+                } else {
+                    if (uacc) FL_AFS(true, 2);
+                    else FL_AFS(false, 2);
+                }
+#undef FL_AFS
+                return hipGetLastError();
+            }
+        }
 #define FL_AFL(UB)                                                                                \
     adev::adjoint_fwd_lds_kernel<S, P, LIM, UB><<<g.blocks, adev::kBlock, flds, st>>>(            \
         m->h.nc, rf, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_halo_nrate, m->d_slot_local,  \
@@ -278,6 +506,8 @@ hipError_t launch_fwd1(const fl_mesh *m, int lim, const double *rf, const double
     }
 }
 }  // namespace
+
+void set_adjoint_share(int on) { g_adjoint_share = on; }
 
 hipError_t launch_adjoint_fwd_rates(const fl_mesh *m, const double *u, double *rf,
                                     hipStream_t st) {

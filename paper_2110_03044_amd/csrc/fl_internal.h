@@ -61,6 +61,7 @@ struct HostTables {
     // rate of, and how many the forward-rate adjoint stage does ([2 * tiles]).
     std::vector<int32_t> halo_nrate;
     int32_t max_halo = -1;           // -1: no tile tables (local indices would not fit 16 bits)
+    int32_t max_nrate = -1;          // largest halo_nrate[2 tile + 1] (-1: not aligned)
     // Numbering maps user -> mesh (empty = identity).
     std::vector<int32_t> cell_perm, face_perm;
 };

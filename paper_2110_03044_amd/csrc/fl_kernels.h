@@ -52,6 +52,9 @@ hipError_t launch_adjoint_fwd_stage(const fl_mesh *m, int lim, int S, const doub
                                     const double *th, const double *lam, double a, double b,
                                     double a3, double dt, int mode, const double *lin,
                                     const double *l3, double *out, double *uacc, hipStream_t st);
+// 1 (default): the LDS-staged form evaluates each face once per tile and shares its terms
+// (FL_OPT_FACE_SHARE); 0: each cell evaluates every face it needs.
+void set_adjoint_share(int on);
 
 // us scales the face velocities (time-dependent velocity); 1 leaves them untouched.
 hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *theta,

@@ -624,9 +624,10 @@ void build_tiles(HostTables &t) {
     std::vector<uint8_t> halo_pair;
     std::vector<uint32_t> local((size_t)K * nc, 0);
     std::vector<std::vector<int64_t>> tile_refs(ntiles);
-    int32_t max_halo = 0;
+    int32_t max_halo = 0, max_nrate = 0;
     bool fits = true;
-#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo) reduction(&& : fits)
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo, max_nrate) \
+    reduction(&& : fits)
     for (int64_t tile = 0; tile < ntiles; ++tile) {
         const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
         // (role << 60 | cell << 2 | pair) while collecting; role 0, 1, 2 as above
@@ -661,6 +662,7 @@ void build_tiles(HostTables &t) {
             }
             nrate[2 * tile] = n0;
             nrate[2 * tile + 1] = n01;
+            max_nrate = std::max(max_nrate, n01);
         }
         // position of each (cell, pair) in the ordered halo
         std::vector<std::pair<int64_t, int32_t>> pos(refs.size());
@@ -703,6 +705,7 @@ void build_tiles(HostTables &t) {
     t.halo_nrate.swap(nrate);
     t.slot_local.swap(local);
     t.max_halo = max_halo;
+    t.max_nrate = by_pair ? max_nrate : -1;
 }
 
 }  // namespace

@@ -36,7 +36,7 @@ def scheme_id(s) -> int:
 
 
 OPTIONS = {"xcd_remap": 1, "slot_velocity": 2, "lds_stage": 3, "check_finite": 4,
-           "fwd_rates": 5}
+           "fwd_rates": 5, "face_share": 6}
 
 
 def set_option(name: str, value: int) -> None:
@@ -46,7 +46,8 @@ def set_option(name: str, value: int) -> None:
     "check_finite" (default 0: 1 makes the compute calls reject non-finite inputs with
     FL_E_NONFINITE, at the cost of a scan and a stream synchronisation per call) or
     "fwd_rates" (default 1: on lattice meshes those multi-step stages read the rates of each
-    cell's forward faces only)."""
+    cell's forward faces only) or "face_share" (default 1: there the reverse stages of
+    rk_steps_adjoint evaluate each face once per tile and share its terms; same bits)."""
     call("fl_set_option", OPTIONS[name], int(value))
 
 

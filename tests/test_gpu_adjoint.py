@@ -344,13 +344,15 @@ def _zigzag_line(n):
 @pytest.mark.parametrize("case", ["box", "box_varied", "zigzag"])
 @pytest.mark.parametrize("S", [1, 2, 3])
 @pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
-@pytest.mark.parametrize("lds", [3, 2, 1, 0], ids=["fwd-lds", "fwd-global", "planes-lds", "planes-global"])
+@pytest.mark.parametrize("lds", [3, 7, 2, 1, 0],
+                         ids=["fwd-lds", "fwd-lds-cellwise", "fwd-global", "planes-lds", "planes-global"])
 @pytest.mark.parametrize("lim", ["vanalbada", "superbee", "smart", "central"])
 def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
     """fl_rk_steps_adjoint over a segment (per-call slot rates, u cotangent accumulated in
     cell-slot order and scattered at the end) gives the same bits as one fl_rk_step_adjoint per
     step: lambda, and u_bar starting from zero.  The varied case scales volumes and areas; the
-    zigzag line needs the chain walk for its forward faces."""
+    zigzag line needs the chain walk for its forward faces.  fwd-lds shares each face's terms
+    through LDS for S <= 2 (one evaluation per face and tile); fwd-lds-cellwise does not."""
     rng = np.random.default_rng(zlib.crc32(f"{lim}-{scheme}-{S}-{case}".encode()))
     if case == "zigzag":
         m = _zigzag_line(40)
@@ -373,7 +375,8 @@ def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
     stages = FL.stage_buffer(mesh, scheme, S, steps)
     try:
         FL.set_option("lds_stage", lds & 1)
-        FL.set_option("fwd_rates", lds >> 1)
+        FL.set_option("fwd_rates", (lds >> 1) & 1)
+        FL.set_option("face_share", 0 if lds & 4 else 1)
         FL.rk_steps_store(mesh, lim, scheme, dt, t.clone(), u, stages, steps)
         lam0 = mesh.cells_to_mesh(dev(rng.standard_normal(th0.shape)))
         a = lam0.clone()
@@ -395,6 +398,7 @@ def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
     finally:
         FL.set_option("lds_stage", 1)
         FL.set_option("fwd_rates", 1)
+        FL.set_option("face_share", 1)
 
     def diff(x, y):
         d = (x - y).abs()
