@@ -349,21 +349,23 @@ def algebraic_compare(args, torch, FL, W, dev):
         work = FL.rk_workspace(mesh, "ssprk3", 1)
         tf = torch.empty_like(u)
         steps = 3
-        t_alg = timed(lambda: alg.rk_steps("superbee", "ssprk3", wl.dt, th, u, steps, work=awork),
-                      2) / steps
-        t_fused = timed(lambda: FL.rk_steps(mesh, "superbee", "ssprk3", wl.dt, th, u, steps,
-                                            work=work), 2) / steps
-        t_tf = timed(lambda: alg.face_values("superbee", th, u, out=tf, work=awork), 5)
         C, F = wl.mesh.n_cells, wl.mesh.n_faces
         ell = sum(alg.rows[k] * alg.width[k] * 12 for k in ("D", "UUD", "OUD", "Pi"))
-        rec = {"n": n, "cells": C, "ms_per_step_algebraic": round(t_alg, 4),
-               "ms_per_step_fused": round(t_fused, 4),
-               "speedup_fused_over_algebraic": round(t_alg / t_fused, 2),
-               "ms_theta_f_algebraic": round(t_tf, 4),
-               "ell_bytes_per_cell_theta_f": round(ell / C, 1),
+        rec = {"n": n, "cells": C, "ell_bytes_per_cell_theta_f": round(ell / C, 1),
                "matrix_device_gb": round(alg.device_bytes / 1e9, 2)}
-        log(f"algebraic {n}^3: {t_alg:.3f} ms/step vs fused {t_fused:.3f} ms/step "
-            f"({t_alg / t_fused:.1f}x); theta_f chain {t_tf:.3f} ms")
+        if not args.algebraic_chain_only:
+            t_alg = timed(lambda: alg.rk_steps("superbee", "ssprk3", wl.dt, th, u, steps,
+                                               work=awork), 2) / steps
+            t_fused = timed(lambda: FL.rk_steps(mesh, "superbee", "ssprk3", wl.dt, th, u, steps,
+                                                work=work), 2) / steps
+            rec.update({"ms_per_step_algebraic": round(t_alg, 4),
+                        "ms_per_step_fused": round(t_fused, 4),
+                        "speedup_fused_over_algebraic": round(t_alg / t_fused, 2)})
+            log(f"algebraic {n}^3: {t_alg:.3f} ms/step vs fused {t_fused:.3f} ms/step "
+                f"({t_alg / t_fused:.1f}x)")
+        t_tf = timed(lambda: alg.face_values("superbee", th, u, out=tf, work=awork), 5)
+        rec["ms_theta_f_algebraic"] = round(t_tf, 4)
+        log(f"algebraic {n}^3: theta_f chain {t_tf:.3f} ms")
         out.append(rec)
         alg.close()
         mesh.close()
@@ -376,6 +378,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--algebraic", default="",
                     help="comma-separated box sides for the algebraic-vs-fused comparison")
+    ap.add_argument("--algebraic-chain-only", action="store_true",
+                    help="time only the theta_f chain of the algebraic comparison (no stepping: "
+                         "its kernels are then the run's only SpMV and kbin launches)")
+    ap.add_argument("--headline", type=int, default=1,
+                    help="0: skip the 256^3 headline measurement, its roofline and the oracle "
+                         "timing (profiling runs of the other parts; the line's value is null)")
     ap.add_argument("--deformation", default="",
                     help="comma-separated box sides for the deformation benchmark (e.g. 72,144)")
     ap.add_argument("--batch-count", type=int, default=512, help="problems in the batch (0 to skip)")
@@ -430,10 +438,13 @@ def main():
     _lib.call("fl_set_option", 2, int(args.slot_velocity))  # FL_OPT_SLOT_VELOCITY
     _lib.call("fl_set_option", 3, int(args.lds_stage))  # FL_OPT_LDS_STAGE
     _lib.call("fl_set_option", 5, int(args.fwd_rates))  # FL_OPT_FWD_RATES
-    t0 = time.time()
-    wl = W.workload_box(args.n, renumbered=True)
-    m = wl.mesh
-    log(f"workload generated in {time.time() - t0:.1f}s: C={m.n_cells} F={m.n_faces} dt={wl.dt:.6g}")
+    wl = m = None
+    if args.headline:
+        t0 = time.time()
+        wl = W.workload_box(args.n, renumbered=True)
+        m = wl.mesh
+        log(f"workload generated in {time.time() - t0:.1f}s: C={m.n_cells} F={m.n_faces} "
+            f"dt={wl.dt:.6g}")
 
     def run_case(reorder: bool, reps: int = 1):
         t1 = time.time()
@@ -501,103 +512,115 @@ def main():
         del src, dst
 
     reorder = not args.no_reorder
-    r = run_case(reorder, args.repeats)
-    C, F, S = m.n_cells, m.n_faces, 1
-    n_steps_total = args.steps * len(lims)
-    updates = F * S * 3 * n_steps_total
-    value = updates / (r["total_ms"] * 1e-3) / 1e9
-    ms_per_step = r["total_ms"] / n_steps_total
 
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Gface-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"periodic hex box {args.n}^3, random cell/face numbering and face "
-                        f"orientation (seed 1), curl velocity (seed 0), blob + tanh step, "
-                        f"SSP-RK3 CFL 0.4",
-            "cells": C, "faces": F, "scalars": S, "limiters": lims, "scheme": "ssprk3",
-            "library_reorder": reorder, "path": r["path"],
-        },
-        "per_limiter_ms_per_step": {k: round(v / args.steps, 4) for k, v in r["per_lim"].items()},
-        "repeats": {"ms_per_step": [round(t / n_steps_total, 4) for t in r["repeats"]],
-                    "median_ms_per_step": round(float(np.median(r["repeats"])) / n_steps_total, 4),
-                    "median_value": round(updates / (float(np.median(r["repeats"])) * 1e-3) / 1e9, 3)},
-    }
+    def headline_part():
+        r = run_case(reorder, args.repeats)
+        C, F, S = m.n_cells, m.n_faces, 1
+        n_steps_total = args.steps * len(lims)
+        updates = F * S * 3 * n_steps_total
+        value = updates / (r["total_ms"] * 1e-3) / 1e9
+        ms_per_step = r["total_ms"] / n_steps_total
 
-    # roofline of the dominant kernel
-    if r["path"] == "fused":
-        K = r["K"]
-        launches = 3 * n_steps_total
-        sv = bool(args.slot_velocity) and args.steps >= 2
-        lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
-            (r["tile_cells"] + r["max_halo"]) * min(S, 2) * 8 <= 64 * 1024
-        fwd = lds and r["aligned"] and bool(args.fwd_rates) and \
-            ((r["tile_cells"] + r["max_halo"] + 1) * min(S, 2)
-             + K // 2 * r["tile_cells"] + r["max_halo"] + 1) * 8 <= 64 * 1024
-        if fwd:
-            kname = "fused_stage_lds_fwd_kernel"
-            bytes_per_step = sum(lds_fwd_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
-        elif lds:
-            kname = "fused_stage_lds_kernel"
-            bytes_per_step = sum(lds_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
-        else:
-            kname = "fused_stage_rec_kernel" if sv else "fused_stage_kernel"
-            bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
-        # The timed region also holds the per-call table build of each call (one rk_steps call
-        # per limiter): its time and its compulsory bytes (slot face words and each face
-        # velocity read, rates or records written) are charged to the call's stage launches.
-        table_bytes = 0
-        if sv and args.steps >= 2:
-            if fwd:  # forward slots' face words, each face velocity once, forward rates written
-                table_bytes = C * (K // 2) * 12 + F * 8
+        out = {
+            "metric": METRIC,
+            "value": round(value, 3),
+            "unit": "Gface-updates/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {
+                "workload": f"periodic hex box {args.n}^3, random cell/face numbering and face "
+                            f"orientation (seed 1), curl velocity (seed 0), blob + tanh step, "
+                            f"SSP-RK3 CFL 0.4",
+                "cells": C, "faces": F, "scalars": S, "limiters": lims, "scheme": "ssprk3",
+                "library_reorder": reorder, "path": r["path"],
+            },
+            "per_limiter_ms_per_step": {k: round(v / args.steps, 4) for k, v in r["per_lim"].items()},
+            "repeats": {"ms_per_step": [round(t / n_steps_total, 4) for t in r["repeats"]],
+                        "median_ms_per_step": round(float(np.median(r["repeats"])) / n_steps_total, 4),
+                        "median_value": round(updates / (float(np.median(r["repeats"])) * 1e-3) / 1e9, 3)},
+        }
+
+        # roofline of the dominant kernel
+        if r["path"] == "fused":
+            K = r["K"]
+            launches = 3 * n_steps_total
+            sv = bool(args.slot_velocity) and args.steps >= 2
+            lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
+                (r["tile_cells"] + r["max_halo"]) * min(S, 2) * 8 <= 64 * 1024
+            fwd = lds and r["aligned"] and bool(args.fwd_rates) and \
+                ((r["tile_cells"] + r["max_halo"] + 1) * min(S, 2)
+                 + K // 2 * r["tile_cells"] + r["max_halo"] + 1) * 8 <= 64 * 1024
+            if fwd:
+                kname = "fused_stage_lds_fwd_kernel"
+                bytes_per_step = sum(lds_fwd_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
+            elif lds:
+                kname = "fused_stage_lds_kernel"
+                bytes_per_step = sum(lds_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
             else:
-                table_bytes = C * K * 12 + F * 8 if lds else C * K * 28 + F * 8
-        total_bytes = bytes_per_step * n_steps_total + table_bytes * len(lims)
-        avg_launch_s = r["total_ms"] * 1e-3 / launches
-        achieved = total_bytes / launches / avg_launch_s / 1e9
-        out["roofline"] = {"kernel": kname,
-                           "bound": "hbm",
-                           "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds, fwd),
-                           "algorithmic_bytes_per_launch": int(total_bytes / launches),
-                           "stage_bytes_per_launch": int(bytes_per_step / 3),
-                           "table_bytes_per_call": int(table_bytes),
-                           "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                           "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
-                           "frac_of_copy": None if copy_gbs is None else
-                           round(achieved / copy_gbs, 4)}
-    # context: the face-kernel + cell-kernel byte model (40 B/face + 60 B/cell per stage, with a
-    # flux array written and gathered back); the fused stage never forms that array, so the
-    # model's effective bandwidth can exceed the HBM peak
-    mb = (40 * F + 60 * C) / F
-    out["two_kernel_model"] = {"bytes_per_face_update": round(mb, 2),
-                               "effective_gbs": round(value * mb, 1)}
+                kname = "fused_stage_rec_kernel" if sv else "fused_stage_kernel"
+                bytes_per_step = sum(fused_stage_bytes(C, F, K, S, s, sv) for s in range(3))
+            # The timed region also holds the per-call table build of each call (one rk_steps call
+            # per limiter): its time and its compulsory bytes (slot face words and each face
+            # velocity read, rates or records written) are charged to the call's stage launches.
+            table_bytes = 0
+            if sv and args.steps >= 2:
+                if fwd:  # forward slots' face words, each face velocity once, forward rates written
+                    table_bytes = C * (K // 2) * 12 + F * 8
+                else:
+                    table_bytes = C * K * 12 + F * 8 if lds else C * K * 28 + F * 8
+            total_bytes = bytes_per_step * n_steps_total + table_bytes * len(lims)
+            avg_launch_s = r["total_ms"] * 1e-3 / launches
+            achieved = total_bytes / launches / avg_launch_s / 1e9
+            out["roofline"] = {"kernel": kname,
+                               "bound": "hbm",
+                               "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(achieved / HBM_PEAK_GBS, 4),
+                               "traffic": measured_traffic(args.n, args.xcd_remap, sv, lds, fwd),
+                               "algorithmic_bytes_per_launch": int(total_bytes / launches),
+                               "stage_bytes_per_launch": int(bytes_per_step / 3),
+                               "table_bytes_per_call": int(table_bytes),
+                               "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                               "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+                               "frac_of_copy": None if copy_gbs is None else
+                               round(achieved / copy_gbs, 4)}
+        # context: the face-kernel + cell-kernel byte model (40 B/face + 60 B/cell per stage, with a
+        # flux array written and gathered back); the fused stage never forms that array, so the
+        # model's effective bandwidth can exceed the HBM peak
+        mb = (40 * F + 60 * C) / F
+        out["two_kernel_model"] = {"bytes_per_face_update": round(mb, 2),
+                                   "effective_gbs": round(value * mb, 1)}
 
-    r["mesh"].close()
-    del r
-    torch.cuda.empty_cache()
-    if args.compare_order and reorder:
-        r2 = run_case(False)
-        v2 = updates / (r2["total_ms"] * 1e-3) / 1e9
-        out["as_given_numbering"] = {"value": round(v2, 3), "unit": "Gface-updates/s",
-                                     "ms_per_step": round(r2["total_ms"] / n_steps_total, 4),
-                                     "note": "same mesh and launch sequence without the "
-                                             "library's locality renumbering"}
-        log(f"as-given numbering: {v2:.2f} Gface-updates/s")
-        r2["mesh"].close()
-        del r2
+        r["mesh"].close()
+        del r
         torch.cuda.empty_cache()
+        if args.compare_order and reorder:
+            r2 = run_case(False)
+            v2 = updates / (r2["total_ms"] * 1e-3) / 1e9
+            out["as_given_numbering"] = {"value": round(v2, 3), "unit": "Gface-updates/s",
+                                         "ms_per_step": round(r2["total_ms"] / n_steps_total, 4),
+                                         "note": "same mesh and launch sequence without the "
+                                                 "library's locality renumbering"}
+            log(f"as-given numbering: {v2:.2f} Gface-updates/s")
+            r2["mesh"].close()
+            del r2
+            torch.cuda.empty_cache()
+
+        return out
+
+    if args.headline:
+        out = headline_part()
+    else:
+        out = {"metric": METRIC, "value": None, "unit": "Gface-updates/s", "n_gpus": 1,
+               "steps": 0, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "headline skipped (--headline 0)"}}
 
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_ratio(args, torch, FL, W, dev)
@@ -612,8 +635,10 @@ def main():
     if args.algebraic:
         out["algebraic"] = algebraic_compare(args, torch, FL, W, dev)
 
-    if args.cpu_baseline:
+    if args.cpu_baseline and args.headline:
         from oracle import oracle as O
+
+        C, F = m.n_cells, m.n_faces
 
         lim = "vanleer"
         # the oracle on the numbering the GPU runs on (the library's renumbering, applied on
