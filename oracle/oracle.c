@@ -36,7 +36,10 @@ struct orc_mesh {
     const double *area;
     const double *vol;
     int64_t *cptr; /* [nc+1] */
-    int64_t *cidx; /* [2 nf] faces of each cell, ascending */
+    int64_t *cidx; /* faces of each cell, ascending (a boundary face in its one cell's list) */
+    int64_t n_boundary;
+    const double *inflow; /* [nf][inflow_S] or NULL (see exterior_value) */
+    int inflow_S;
 };
 
 int orc_num_threads(void) {
@@ -50,27 +53,40 @@ int orc_num_threads(void) {
 orc_mesh *orc_mesh_new(int64_t nc, int64_t nf, const int32_t *fc, const double *nrm,
                        const double *area, const double *vol) {
     if (nc <= 0 || nf <= 0 || !fc || !nrm || !area || !vol) return NULL;
+    int64_t nb = 0;
     for (int64_t f = 0; f < nf; ++f) {
         int64_t a = fc[2 * f], b = fc[2 * f + 1];
+        if (b == -1 && a >= 0 && a < nc) { /* boundary face: own is its cell */
+            nb++;
+            continue;
+        }
         if (a < 0 || a >= nc || b < 0 || b >= nc || a == b) return NULL;
     }
     orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
     m->nc = nc; m->nf = nf; m->fc = fc; m->nrm = nrm; m->area = area; m->vol = vol;
+    m->n_boundary = nb;
     m->cptr = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
     m->cidx = (int64_t *)malloc((size_t)(2 * nf) * sizeof(int64_t));
     for (int64_t f = 0; f < nf; ++f) {
         m->cptr[fc[2 * f] + 1]++;
-        m->cptr[fc[2 * f + 1] + 1]++;
+        if (fc[2 * f + 1] >= 0) m->cptr[fc[2 * f + 1] + 1]++;
     }
     for (int64_t c = 0; c < nc; ++c) m->cptr[c + 1] += m->cptr[c];
     int64_t *fill = (int64_t *)malloc((size_t)nc * sizeof(int64_t));
     memcpy(fill, m->cptr, (size_t)nc * sizeof(int64_t));
     for (int64_t f = 0; f < nf; ++f) { /* ascending f => ascending lists */
         m->cidx[fill[fc[2 * f]]++] = f;
-        m->cidx[fill[fc[2 * f + 1]]++] = f;
+        if (fc[2 * f + 1] >= 0) m->cidx[fill[fc[2 * f + 1]]++] = f;
     }
     free(fill);
     return m;
+}
+
+int64_t orc_boundary_faces(const orc_mesh *m) { return m->n_boundary; }
+
+void orc_mesh_set_inflow(orc_mesh *m, const double *inflow, int S) {
+    m->inflow = inflow;
+    m->inflow_S = inflow ? S : 0;
 }
 
 void orc_mesh_free(orc_mesh *m) {
@@ -146,8 +162,25 @@ double orc_dpsi(int lim, double r) {
 /* ------------------------------------------------------------------------------------------
  * Face selection and projection weights.
  * ------------------------------------------------------------------------------------------ */
+/* The cell across face j from c: -1 beyond a boundary face. */
 static inline int64_t other_cell(const orc_mesh *m, int64_t j, int64_t c) {
     return m->fc[2 * j] == c ? m->fc[2 * j + 1] : m->fc[2 * j];
+}
+
+/* Value of the exterior beyond boundary face j, for scalar k.  The flow enters through j where
+ * u_j <= 0 (the normal points out of the mesh): there the exterior holds the caller's inflow
+ * value, if any; everywhere else (outflow, or no inflow values) it repeats the value of j's own
+ * cell, as the cell-to-face shift of Section 2 does on a face with a single cell. */
+static inline double exterior_value(const orc_mesh *m, int S, const double *th, const double *u,
+                                    int64_t j, int k) {
+    if (m->inflow && !(u[j] > 0.0)) return m->inflow[j * S + k];
+    return th[m->fc[2 * j] * S + k];
+}
+
+/* theta of cell c (c >= 0) or of the exterior beyond boundary face j (c == -1). */
+static inline double value_at(const orc_mesh *m, int S, const double *th, const double *u,
+                              int64_t c, int64_t j, int k) {
+    return c >= 0 ? th[c * S + k] : exterior_value(m, S, th, u, j, k);
 }
 
 /* Weight of face j of cell C for face f with flow sign s: s (n_f . t_j), t_j = n_j oriented
@@ -164,6 +197,7 @@ int orc_side_weights(const orc_mesh *m, int64_t f, int side_nbr, double *w, int3
     int64_t C = side_nbr ? m->fc[2 * f + 1] : m->fc[2 * f];
     double s = side_nbr ? -1.0 : 1.0;
     int k = 0;
+    if (C < 0) return 0;
     for (int64_t p = m->cptr[C]; p < m->cptr[C + 1] && k < cap; ++p, ++k) {
         int64_t j = m->cidx[p];
         faces[k] = (int32_t)j;
@@ -192,7 +226,7 @@ void orc_select(const orc_mesh *m, const double *u, int32_t *cdu) {
         face_sel fs = select_face(m, u, f);
         int64_t U = -2;
         int nonzero = 0;
-        for (int64_t p = m->cptr[fs.C]; p < m->cptr[fs.C + 1]; ++p) {
+        for (int64_t p = fs.C >= 0 ? m->cptr[fs.C] : 0; fs.C >= 0 && p < m->cptr[fs.C + 1]; ++p) {
             int64_t j = m->cidx[p];
             if (j == f) continue;
             if (proj_weight(m, f, j, fs.C, fs.s) != 0.0) {
@@ -206,15 +240,17 @@ void orc_select(const orc_mesh *m, const double *u, int32_t *cdu) {
     }
 }
 
-static double upstream_difference(const orc_mesh *m, int S, const double *th, int64_t f,
-                                  face_sel fs, int k) {
+/* The exterior upwind of an inflow face has no other faces: d_U = 0 there. */
+static double upstream_difference(const orc_mesh *m, int S, const double *th, const double *u,
+                                  int64_t f, face_sel fs, int k) {
     double dU = 0.0;
+    if (fs.C < 0) return dU;
     double tC = th[fs.C * S + k];
     for (int64_t p = m->cptr[fs.C]; p < m->cptr[fs.C + 1]; ++p) {
         int64_t j = m->cidx[p];
         if (j == f) continue;
         double w = proj_weight(m, f, j, fs.C, fs.s);
-        dU += w * (tC - th[other_cell(m, j, fs.C) * S + k]);
+        dU += w * (tC - value_at(m, S, th, u, other_cell(m, j, fs.C), j, k));
     }
     return dU;
 }
@@ -249,9 +285,9 @@ static double limited_value(int lim, double tC, double dU, double du, double *ga
 static double face_value(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                          int64_t f, int k) {
     face_sel fs = select_face(m, u, f);
-    double tC = th[fs.C * S + k], tD = th[fs.D * S + k];
+    double tC = value_at(m, S, th, u, fs.C, f, k), tD = value_at(m, S, th, u, fs.D, f, k);
     double du = tD - tC;
-    double dU = upstream_difference(m, S, th, f, fs, k);
+    double dU = upstream_difference(m, S, th, u, f, fs, k);
     return limited_value(lim, tC, dU, du, NULL, NULL);
 }
 
@@ -392,8 +428,19 @@ static double face_value_tangent(const orc_mesh *m, int lim, int S, const double
     return tf;
 }
 
+/* The derivative functions cover closed meshes only: on a mesh with boundary faces they fill
+ * their outputs with NaN (and the run functions return -2). */
+static void fill_nan(double *a, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) a[i] = NAN;
+}
+
 void orc_face_values_jvp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                          const double *dth, double *tf, double *dtf) {
+    if (m->n_boundary) {
+        fill_nan(tf, m->nf * S);
+        fill_nan(dtf, m->nf * S);
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < m->nf; ++f)
         for (int k = 0; k < S; ++k)
@@ -402,6 +449,10 @@ void orc_face_values_jvp(const orc_mesh *m, int lim, int S, const double *th, co
 
 void orc_rhs_jvp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                  const double *dth, const double *du, double *drhs) {
+    if (m->n_boundary) {
+        fill_nan(drhs, m->nc * S);
+        return;
+    }
     double *dphi = (double *)malloc((size_t)(m->nf * S) * sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < m->nf; ++f)
@@ -431,6 +482,11 @@ void orc_rhs_jvp(const orc_mesh *m, int lim, int S, const double *th, const doub
  * ------------------------------------------------------------------------------------------ */
 void orc_rhs_vjp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                  const double *lam, double *tbar, double *ubar) {
+    if (m->n_boundary) {
+        fill_nan(tbar, m->nc * S);
+        if (ubar) fill_nan(ubar, m->nf);
+        return;
+    }
     memset(tbar, 0, (size_t)(m->nc * S) * sizeof(double));
     if (ubar) memset(ubar, 0, (size_t)m->nf * sizeof(double));
     for (int64_t f = 0; f < m->nf; ++f) {
@@ -441,7 +497,7 @@ void orc_rhs_vjp(const orc_mesh *m, int lim, int S, const double *th, const doub
             double mu = lam[nbr * S + k] / m->vol[nbr] - lam[own * S + k] / m->vol[own];
             double tC = th[fs.C * S + k], tD = th[fs.D * S + k];
             double du = tD - tC;
-            double dU = upstream_difference(m, S, th, f, fs, k);
+            double dU = upstream_difference(m, S, th, u, f, fs, k);
             double ga, gb;
             double tf = limited_value(lim, tC, dU, du, &ga, &gb);
             if (ubar) ubar[f] += m->area[f] * tf * mu;
@@ -467,6 +523,7 @@ void orc_rhs_vjp(const orc_mesh *m, int lim, int S, const double *th, const doub
 int orc_run_tangent(const orc_mesh *m, int lim, int scheme, double dt, int S, int64_t nsteps,
                     double *th, double *dth, const double *u, const double *du) {
     if (scheme != ORC_EULER && scheme != ORC_SSPRK3) return -1;
+    if (m->n_boundary) return -2;
     size_t n = (size_t)(m->nc * S);
     int ns = scheme == ORC_EULER ? 1 : 3;
     double *rhs = (double *)malloc(n * sizeof(double));
@@ -500,6 +557,7 @@ int orc_run_adjoint(const orc_mesh *m, int lim, int scheme, double dt, int S, in
                     const double *th0, const double *u, const double *tbar_final, double *th0_bar,
                     double *ubar) {
     if (scheme != ORC_EULER && scheme != ORC_SSPRK3) return -1;
+    if (m->n_boundary) return -2;
     size_t n = (size_t)(m->nc * S);
     int ns = scheme == ORC_EULER ? 1 : 3;
     /* Forward pass storing every stage input: states[it][st] is the argument of L in stage st,

@@ -24,6 +24,16 @@
  *           = theta_C + psi(d_U/d_u) d_u / 2    otherwise;
  *   rhs_c = (sum_{f: nbr_f=c} a_f u_f theta_f - sum_{f: own_f=c} a_f u_f theta_f) / V_c,
  *          summed over the faces of c in ascending face index.
+ *
+ * Boundary faces (a reading: the paper states the operators on the mesh's graph and notes that
+ * its cell-to-face shift handles a face with a single cell by copying that cell, Section 2):
+ * fc[2f+1] == -1 marks a face with one cell, own = fc[2f], its normal pointing out of the mesh.
+ * Beyond it lies an exterior cell with no other faces whose value is the caller's inflow value
+ * of f where the flow enters (u_f <= 0) and inflow values were given (orc_mesh_set_inflow), and
+ * the value of own otherwise.  With that cell the rules above apply unchanged: an outflow face
+ * takes theta_own (d_u = 0), an inflow face the exterior value (d_U = 0 upwind of it: r = 0),
+ * and a boundary face among C's other faces adds w_j (theta_C - exterior value) to d_U.  Each
+ * boundary flux a_f u_f theta_f leaves or enters its one cell.
  */
 #ifndef FLUXLIM_ORACLE_H
 #define FLUXLIM_ORACLE_H
@@ -46,12 +56,18 @@ enum { ORC_EULER = 1, ORC_SSPRK3 = 3 };
 typedef struct orc_mesh orc_mesh;
 
 /* Builds the cell -> faces lists.  Keeps the caller's arrays by pointer (they must outlive the
- * mesh).  Returns NULL on a face index out of range or own == nbr. */
+ * mesh).  Returns NULL on a face index out of range or own == nbr (nbr == -1 marks a boundary
+ * face).  The derivative functions below cover closed meshes only (NaN outputs, or -2, on a mesh
+ * with boundary faces). */
 orc_mesh *orc_mesh_new(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                        const double *face_normal, const double *face_area,
                        const double *cell_volume);
 void orc_mesh_free(orc_mesh *m);
 int64_t orc_cell_degree(const orc_mesh *m, int64_t c);
+int64_t orc_boundary_faces(const orc_mesh *m);
+/* Inflow values of the boundary faces ([F][S], read at boundary faces only; kept by pointer),
+ * or NULL: the exterior then repeats the cell's value on every boundary face. */
+void orc_mesh_set_inflow(orc_mesh *m, const double *inflow, int S);
 
 /* Limiter psi(r) and its derivative on the branch that the evaluation takes. */
 double orc_psi(int limiter, double r);

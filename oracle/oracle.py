@@ -51,6 +51,9 @@ def lib():
         L.orc_mesh_free.argtypes = [_P]
         L.orc_cell_degree.restype = _I64
         L.orc_cell_degree.argtypes = [_P, _I64]
+        L.orc_boundary_faces.restype = _I64
+        L.orc_boundary_faces.argtypes = [_P]
+        L.orc_mesh_set_inflow.argtypes = [_P, _P, _I]
         L.orc_psi.restype = _D
         L.orc_psi.argtypes = [_I, _D]
         L.orc_dpsi.restype = _D
@@ -118,6 +121,30 @@ class OracleMesh:
         if not h:
             raise ValueError("oracle rejected the mesh (index out of range or own == nbr)")
         self._h = h
+        self.n_boundary = int(lib().orc_boundary_faces(h))
+        self._inflow = None
+
+    def set_inflow(self, values) -> None:
+        """Inflow values of the boundary faces ([F] or [F, S], read where u_f <= 0 on boundary
+        faces only), or None: the exterior then repeats the interior cell's value.  Every later
+        call must use the same number of scalars."""
+        if values is None:
+            self._inflow = None
+            lib().orc_mesh_set_inflow(self._h, None, 0)
+            return
+        v = _f64(values)
+        if v.shape[0] != self.n_faces:
+            raise ValueError("inflow values need one row per face")
+        self._inflow = v
+        lib().orc_mesh_set_inflow(self._h, _ptr(v), self._S(v))
+
+    def _check_S(self, theta: np.ndarray) -> None:
+        if self._inflow is not None and self._S(self._inflow) != self._S(theta):
+            raise ValueError("the inflow values were set for another number of scalars")
+
+    def _closed(self) -> None:
+        if self.n_boundary:
+            raise ValueError("the oracle's derivatives cover closed meshes only")
 
     @classmethod
     def from_arrays(cls, m) -> "OracleMesh":
@@ -151,6 +178,7 @@ class OracleMesh:
 
     def face_values(self, limiter, theta, u) -> np.ndarray:
         theta, u = _f64(theta), _f64(u)
+        self._check_S(theta)
         out = np.empty((self.n_faces,) + theta.shape[1:])
         lib().orc_face_values(self._h, lim_id(limiter), self._S(theta), _ptr(theta), _ptr(u),
                               _ptr(out))
@@ -158,6 +186,7 @@ class OracleMesh:
 
     def face_values_jvp(self, limiter, theta, u, dtheta):
         """(theta_f, its tangent along dtheta), u held fixed."""
+        self._closed()
         theta, u, dtheta = _f64(theta), _f64(u), _f64(dtheta)
         tf = np.empty((self.n_faces,) + theta.shape[1:])
         dtf = np.empty_like(tf)
@@ -167,12 +196,14 @@ class OracleMesh:
 
     def rhs(self, limiter, theta, u) -> np.ndarray:
         theta, u = _f64(theta), _f64(u)
+        self._check_S(theta)
         out = np.empty_like(theta)
         lib().orc_rhs(self._h, lim_id(limiter), self._S(theta), _ptr(theta), _ptr(u), _ptr(out))
         return out
 
     def rhs_cells(self, limiter, theta, u, cells) -> np.ndarray:
         theta, u = _f64(theta), _f64(u)
+        self._check_S(theta)
         cells = np.ascontiguousarray(cells, dtype=np.int64)
         out = np.empty((cells.shape[0],) + theta.shape[1:])
         lib().orc_rhs_cells(self._h, lim_id(limiter), self._S(theta), _ptr(theta), _ptr(u),
@@ -181,6 +212,7 @@ class OracleMesh:
 
     def run(self, limiter, scheme, dt, theta0, u, nsteps) -> np.ndarray:
         th = _f64(theta0).copy()
+        self._check_S(th)
         u = _f64(u)
         sc = {"euler": EULER, "ssprk3": SSPRK3}.get(scheme, scheme)
         rc = lib().orc_run(self._h, lim_id(limiter), int(sc), float(dt), self._S(th), int(nsteps),
@@ -191,6 +223,7 @@ class OracleMesh:
 
     def run_scaled(self, limiter, scheme, dt, theta0, u, scales) -> np.ndarray:
         th = _f64(theta0).copy()
+        self._check_S(th)
         u = _f64(u)
         sc = {"euler": EULER, "ssprk3": SSPRK3}.get(scheme, scheme)
         scales = _f64(scales)
@@ -204,6 +237,7 @@ class OracleMesh:
         return th
 
     def rhs_jvp(self, limiter, theta, u, dtheta, du=None) -> np.ndarray:
+        self._closed()
         theta, u, dtheta = _f64(theta), _f64(u), _f64(dtheta)
         out = np.empty_like(theta)
         dup = _ptr(_f64(du)) if du is not None else None
@@ -214,6 +248,7 @@ class OracleMesh:
         return out
 
     def rhs_vjp(self, limiter, theta, u, lam):
+        self._closed()
         theta, u, lam = _f64(theta), _f64(u), _f64(lam)
         tb = np.empty_like(theta)
         ub = np.empty(self.n_faces)
@@ -222,6 +257,7 @@ class OracleMesh:
         return tb, ub
 
     def run_tangent(self, limiter, scheme, dt, theta0, u, nsteps, dtheta0, du=None):
+        self._closed()
         th = _f64(theta0).copy()
         dth = _f64(dtheta0).copy()
         u = _f64(u)
@@ -234,6 +270,7 @@ class OracleMesh:
         return th, dth
 
     def run_adjoint(self, limiter, scheme, dt, theta0, u, nsteps, theta_bar_final):
+        self._closed()
         th0 = _f64(theta0)
         u = _f64(u)
         tbf = _f64(theta_bar_final)

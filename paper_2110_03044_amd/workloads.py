@@ -9,7 +9,8 @@ Mesh model (Section 2 of the paper): a mesh is given by its oriented face-to-cel
 Every face f joins the two cells ``face_cells[f] = (own, nbr)`` and carries a unit normal
 ``face_normal[f]`` that points from ``own`` into ``nbr``; the oriented incidence is then
 ``E[f, nbr] = +1`` and ``E[f, own] = -1`` (the difference ``E theta`` is taken along the normal).
-All meshes built here are periodic, so every face has two cells.
+A boundary face has one cell: ``face_cells[f] = (own, -1)`` with the normal pointing out of the
+mesh (``open_box``); every other mesh built here is periodic, so every face has two cells.
 
 Workload recipes (sizes and distributions of the paper's advection study, Section 4):
 
@@ -71,6 +72,14 @@ class MeshArrays:
             return np.ascontiguousarray(x)
         return np.ascontiguousarray(x[self.cell_new_of_old])
 
+    def face_field_from_natural(self, x: np.ndarray) -> np.ndarray:
+        """Re-index face data that does not change sign with the orientation (axis 0)."""
+        if self.face_new_of_old is None:
+            return np.ascontiguousarray(x)
+        out = np.empty_like(x)
+        out[self.face_new_of_old] = x
+        return out
+
     def face_velocity_from_natural(self, u: np.ndarray) -> np.ndarray:
         """Re-index a normal face velocity from natural numbering; flipped faces change sign."""
         if self.face_new_of_old is None:
@@ -107,6 +116,70 @@ def periodic_box(n: int, dim: int = 3) -> MeshArrays:
     area = np.full(dim * C, h ** (dim - 1), dtype=np.float64)
     vol = np.full(C, h**dim, dtype=np.float64)
     return MeshArrays(face_cells, nrm, area, vol, n=n, dim=dim)
+
+
+def open_box(n: int, dim: int = 3, open_axes=(0,)) -> MeshArrays:
+    """The box of ``periodic_box(n, dim)`` cut open along ``open_axes``: there the wrapped faces
+    become boundary faces on the high side (own = the last cell, normal +e_a) and new boundary
+    faces close the low side (own = the first cell, normal -e_a), appended after the dim blocks
+    of C faces.  Along the other axes the box stays periodic."""
+    base = periodic_box(n, dim)
+    C = base.n_cells
+    c = np.arange(C, dtype=np.int64)
+    fc = base.face_cells.copy()
+    nrm = [base.face_normal]
+    extra_fc = []
+    for a in open_axes:
+        if not 0 <= a < dim:
+            raise ValueError("open axis out of range")
+        ia = (c // n**a) % n
+        last = a * C + c[ia == n - 1]
+        fc[last, 1] = -1
+        first = c[ia == 0]
+        extra_fc.append(np.stack([first, -np.ones_like(first)], axis=1).astype(np.int32))
+        e = np.zeros((first.shape[0], 3))
+        e[:, a] = -1.0
+        nrm.append(e)
+    face_cells = np.concatenate([fc] + extra_fc, axis=0).astype(np.int32)
+    face_normal = np.concatenate(nrm, axis=0)
+    area = np.full(face_cells.shape[0], base.face_area[0], dtype=np.float64)
+    return MeshArrays(face_cells, face_normal, area, base.cell_volume.copy(), n=n, dim=dim)
+
+
+def face_centres(mesh: MeshArrays) -> np.ndarray:
+    """Face centres [F, 3] of a box built by periodic_box or open_box (natural numbering): the
+    own cell's centre moved half a cell along the face normal."""
+    n, dim = mesh.n, mesh.dim
+    c = mesh.face_cells[:, 0].astype(np.int64)
+    x = np.zeros((mesh.n_faces, 3))
+    for a in range(dim):
+        x[:, a] = ((c // n**a) % n + 0.5) / n
+    return x + 0.5 / n * mesh.face_normal
+
+
+def velocity_open_box(mesh: MeshArrays) -> np.ndarray:
+    """A smooth face velocity on a box cut open along x: u_x = 0.3 + cos(2 pi y) cos(2 pi z)
+    (every open side has inflow and outflow faces), u_y = 0.5 sin(2 pi x + 1),
+    u_z = 0.4 cos(2 pi (x + y)); the normal component of that field on each face."""
+    x = face_centres(mesh)
+    v = np.stack([0.3 + np.cos(2 * np.pi * x[:, 1]) * np.cos(2 * np.pi * x[:, 2]),
+                  0.5 * np.sin(2 * np.pi * x[:, 0] + 1.0),
+                  0.4 * np.cos(2 * np.pi * (x[:, 0] + x[:, 1]))], axis=1)
+    return np.einsum("fa,fa->f", v, mesh.face_normal)
+
+
+def inflow_values(mesh: MeshArrays, u: Optional[np.ndarray] = None, S: int = 1) -> np.ndarray:
+    """Inflow values [F] (or [F, S]) of a box's boundary faces: 0.8 + 0.15 sin(2 pi (y + 2z))
+    (+0.1 per extra scalar); NaN on the interior faces, and on the outflow boundary faces
+    (u_f > 0) when u is given, so that a read of a value the boundary rule never uses shows."""
+    x = face_centres(mesh)
+    v = 0.8 + 0.15 * np.sin(2 * np.pi * (x[:, 1] + 2 * x[:, 2]))
+    out = np.stack([v + 0.1 * k for k in range(S)], axis=1) if S > 1 else v.copy()
+    unused = mesh.face_cells[:, 1] >= 0
+    if u is not None:
+        unused |= u > 0.0
+    out[unused] = np.nan
+    return out
 
 
 def periodic_triangles(n: int) -> MeshArrays:
@@ -213,8 +286,10 @@ def renumber(mesh: MeshArrays, seed: int = SEED_RENUMBER, flip: bool = True) -> 
     cnew = rng.permutation(C).astype(np.int64)
     fnew = rng.permutation(F).astype(np.int64)
     flips = (rng.random(F) < 0.5) if flip else np.zeros(F, dtype=bool)
+    bnd = mesh.face_cells[:, 1] < 0
+    flips &= ~bnd  # a boundary face keeps its one cell as own (normal pointing out)
     own = cnew[mesh.face_cells[:, 0]]
-    nbr = cnew[mesh.face_cells[:, 1]]
+    nbr = np.where(bnd, -1, cnew[np.maximum(mesh.face_cells[:, 1], 0)])
     own2 = np.where(flips, nbr, own)
     nbr2 = np.where(flips, own, nbr)
     fc = np.empty((F, 2), dtype=np.int32)
@@ -411,9 +486,10 @@ def cfl_dt(mesh: MeshArrays, u: np.ndarray, cfl: float) -> float:
     own = mesh.face_cells[:, 0].astype(np.int64)
     nbr = mesh.face_cells[:, 1].astype(np.int64)
     q = mesh.face_area * u
+    inner = nbr >= 0  # a boundary face's inflow leaves no cell
     # one pass in the order of a loop over the own sides, then the nbr sides of the faces
-    out = np.bincount(np.concatenate([own, nbr]),
-                      weights=np.concatenate([np.maximum(q, 0.0), np.maximum(-q, 0.0)]),
+    out = np.bincount(np.concatenate([own, nbr[inner]]),
+                      weights=np.concatenate([np.maximum(q, 0.0), np.maximum(-q[inner], 0.0)]),
                       minlength=mesh.n_cells)
     rate = float((out / mesh.cell_volume).max())
     if rate <= 0.0:
@@ -434,6 +510,7 @@ class Workload:
     steps: int
     scheme: str  # "euler" | "ssprk3"
     name: str
+    inflow: Optional[np.ndarray] = None  # [F] or [F][S] inflow values of the boundary faces
 
 
 def workload_line(n: int = 200, cfl: float = 0.5, steps: int = 400) -> Workload:
@@ -456,6 +533,27 @@ def workload_box(n: int, renumbered: bool = False, cfl: float = 0.4, steps: int 
     dt = cfl_dt(mesh, u, cfl)
     name = f"box{n}" + ("_random" if renumbered else "")
     return Workload(mesh, th, u, dt, steps, "ssprk3", name)
+
+
+def workload_open_box(n: int, renumbered: bool = False, cfl: float = 0.4, steps: int = 40,
+                      S: int = 1) -> Workload:
+    """A box cut open along x (boundary faces on both x sides, periodic in y and z) with the
+    smooth velocity of velocity_open_box, the blob + step field (S scalars: shifted copies) and
+    SSP-RK3; the inflow values come from inflow_values(mesh, u, S)."""
+    mesh = open_box(n, 3, (0,))
+    u = velocity_open_box(mesh)
+    th = field_blob_step(n)
+    if S > 1:
+        th = multi_scalar([th + 0.1 * k for k in range(S)])
+    inflow = inflow_values(mesh, u, S)
+    if renumbered:
+        mesh = renumber(mesh, SEED_RENUMBER)
+        u = mesh.face_velocity_from_natural(u)
+        th = mesh.cell_field_from_natural(th)
+        inflow = mesh.face_field_from_natural(inflow)
+    dt = cfl_dt(mesh, u, cfl)
+    return Workload(mesh, th, u, dt, steps, "ssprk3",
+                    f"openbox{n}" + ("_random" if renumbered else ""), inflow)
 
 
 def box_shared_cache(n: int) -> MeshArrays:
