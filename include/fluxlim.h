@@ -52,9 +52,10 @@ typedef int32_t fl_status;
 #define FL_OK 0
 #define FL_E_INVALID -1     /* bad argument: null pointer, size, enum, alignment            */
 #define FL_E_TOPOLOGY -2    /* incidence violates the mesh model (index range, own == nbr,
-                               two faces joining the same two cells, far-upwind == downwind) */
-#define FL_E_UNSUPPORTED -3 /* valid but outside this library: boundary faces (nbr = -1);
-                               the adjoint and batching on cells without opposite face pairs */
+                               own == -1, two faces joining the same two cells)               */
+#define FL_E_UNSUPPORTED -3 /* valid but outside this library: the adjoint and batching on
+                               cells without opposite face pairs or on meshes with boundary
+                               faces; the algebraic chain on meshes with boundary faces      */
 #define FL_E_NOMEM -4       /* host or device allocation failed                              */
 #define FL_E_HIP -5         /* a HIP runtime call failed (message in fl_last_error)          */
 #define FL_E_NONFINITE -6   /* an input holds a NaN or an infinity (only reported while the
@@ -115,6 +116,7 @@ typedef struct fl_mesh_info_t {
     int32_t aligned;        /* 1 if the opposite-face pairs line up from cell to cell (lattice */
                             /* meshes; the forward-rate stages, FL_OPT_FWD_RATES, apply)      */
     int32_t reserved;
+    int64_t n_boundary;     /* boundary faces (one cell: nbr = -1)                           */
 } fl_mesh_info_t;
 
 /* Checks an incidence against the mesh model without a GPU (Section 2).  face_cells: host
@@ -127,12 +129,16 @@ fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face
  * weights on general cells, cell -> face lists, and where every cell's faces form opposite
  * pairs, the per-cell slot tables and tile halos of the fused kernels) and copies them to
  * `device`.  Inputs are host arrays, read only during the call:
- *   face_cells  int32 [n_faces][2] (own, nbr), 0 <= index < n_cells, own != nbr;
- *   face_normal double [n_faces][3], unit, own -> nbr (1-D and 2-D meshes pad with 0);
+ *   face_cells  int32 [n_faces][2] (own, nbr), 0 <= index < n_cells, own != nbr; nbr = -1
+ *               marks a boundary face (one cell, own; see fl_mesh_set_inflow).  A mesh with
+ *               boundary faces runs the face path with the general kernel;
+ *   face_normal double [n_faces][3], unit, own -> nbr (1-D and 2-D meshes pad with 0; out of
+ *               the mesh on a boundary face);
  *   face_area   double [n_faces] or NULL (= 1);   cell_volume double [n_cells] or NULL (= 1).
  * device = -1 builds a host-only mesh (tables, validation and export work; compute calls
- * return FL_E_NODEVICE).  On success *out owns device memory until fl_mesh_destroy; the mesh is
- * immutable and may be used from several streams at once.  The host loops run on the OpenMP
+ * return FL_E_NODEVICE).  On success *out owns device memory until fl_mesh_destroy; apart from
+ * its inflow values (fl_mesh_set_inflow) the mesh is immutable and may be used from several
+ * streams at once.  The host loops run on the OpenMP
  * threads of the calling process (OMP_NUM_THREADS); the tables do not depend on their number.
  * With the environment variable FL_MESH_PROGRESS set, each phase reports its wall time on
  * stderr. */
@@ -141,6 +147,26 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
                          const double *cell_volume, int device, uint32_t flags, fl_mesh **out);
 fl_status fl_mesh_destroy(fl_mesh *mesh);
 fl_status fl_mesh_info(const fl_mesh *mesh, fl_mesh_info_t *info);
+
+/* Boundary faces.  The paper states the operators on the mesh's graph, and its cell-to-face
+ * shift (Section 2, S = D_FF^-1 |T_CF|) gives a face with a single cell that cell's value.  The
+ * library reads a boundary face f (nbr = -1) as bordering an exterior cell with no other faces;
+ * the face selection, differences, gradient ratio and limiter of Section 3 then apply as on
+ * interior faces:
+ *   - the exterior holds inflow[f][s] where the flow enters (u_f <= 0: the normal points out)
+ *     and inflow values are set, and repeats the value of f's own cell otherwise;
+ *   - an outflow face therefore takes theta_own (d_u = 0); an inflow face has C = the exterior
+ *     and d_U = 0 (r = 0: the inflow value itself for every limiter with psi(0) = 0, half-way to
+ *     theta_own for central differencing); a boundary face among the faces of an interior face's
+ *     upwind cell adds w_j (theta_C - exterior value) to that face's d_U;
+ *   - the flux a_f u_f theta_f of a boundary face leaves (or enters) its one cell.
+ * inflow: device [n_faces][n_scalars] doubles in mesh order (only the boundary faces' rows are
+ * read, and only where the flow enters), or NULL to clear (the exterior then repeats the cell's
+ * value on every boundary face).  The mesh keeps the pointer: the caller keeps the memory alive
+ * and unchanged while calls that read it are queued, and every compute call on the mesh must
+ * then use n_scalars scalars (else FL_E_INVALID).  Not synchronised with calls running on other
+ * threads.  Returns FL_E_NODEVICE on a host-only mesh. */
+fl_status fl_mesh_set_inflow(fl_mesh *mesh, const double *inflow, int n_scalars);
 
 /* Numbering maps of a reordered mesh (identity otherwise): cell_perm[user cell] = mesh cell,
  * face_perm[user face] = mesh face (host int32 arrays of n_cells / n_faces, or NULL to skip).

@@ -93,6 +93,8 @@ fl_status check_compute(const fl_mesh *m, int lim, int S) {
     if (m->device < 0) return fail(FL_E_NODEVICE, "the mesh was created host-only (device = -1)");
     if (lim < 0 || lim >= FL_NUM_LIMITERS) return fail(FL_E_INVALID, "unknown limiter");
     if (S < 1 || S > FL_MAX_SCALARS) return fail(FL_E_INVALID, "n_scalars must be in [1, 8]");
+    if (m->inflow && S != m->inflow_S)
+        return fail(FL_E_INVALID, "the mesh's inflow values hold another number of scalars");
     return FL_OK;
 }
 
@@ -420,6 +422,23 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
     info->max_side = m->h.general ? ms : 1;
     info->aligned = m->h.aligned_slots ? 1 : 0;
     info->reserved = 0;
+    info->n_boundary = m->h.n_boundary;
+    return FL_OK;
+}
+
+fl_status fl_mesh_set_inflow(fl_mesh *m, const double *inflow, int n_scalars) {
+    if (!m) return fail(FL_E_INVALID, "mesh is NULL");
+    if (!inflow) {
+        m->inflow = nullptr;
+        m->inflow_S = 0;
+        return FL_OK;
+    }
+    if (m->device < 0) return fail(FL_E_NODEVICE, "the mesh was created host-only (device = -1)");
+    if (n_scalars < 1 || n_scalars > FL_MAX_SCALARS)
+        return fail(FL_E_INVALID, "n_scalars must be in [1, 8]");
+    if (misaligned(inflow)) return fail(FL_E_INVALID, "inflow must be 8-byte aligned");
+    m->inflow = inflow;
+    m->inflow_S = n_scalars;
     return FL_OK;
 }
 

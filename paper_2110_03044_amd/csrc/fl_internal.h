@@ -62,6 +62,7 @@ struct HostTables {
     std::vector<int32_t> halo_nrate;
     int32_t max_halo = -1;           // -1: no tile tables (local indices would not fit 16 bits)
     int32_t max_nrate = -1;          // largest halo_nrate[2 tile + 1] (-1: not aligned)
+    int64_t n_boundary = 0;          // faces with one cell (nbr == -1): general face path only
     // Numbering maps user -> mesh (empty = identity).
     std::vector<int32_t> cell_perm, face_perm;
 };
@@ -112,4 +113,7 @@ struct fl_mesh {
     double *d_vol = nullptr;       // [C] if non-uniform
     int32_t *d_cell_perm = nullptr, *d_face_perm = nullptr;  // user -> mesh
     int64_t device_bytes = 0;
+    // caller's inflow values of the boundary faces ([F][inflow_S], device; fl_mesh_set_inflow)
+    const double *inflow = nullptr;
+    int inflow_S = 0;
 };

@@ -66,24 +66,42 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(
 }
 
 // General cells: the upstream difference of the upwind side sums its projected faces
-// (side lists: far cells and weights, built at mesh creation).
+// (side lists: far cells and weights, built at mesh creation).  Boundary faces (nbr = -1)
+// border an exterior cell: it holds the inflow value of the face where the flow enters through
+// it and inflow values are given, and repeats the face's own cell otherwise.  The exterior side
+// of a boundary face has no side list (d_U = 0); a side-list entry ~j is the exterior beyond
+// boundary face j of the upwind cell.
 template <int S>
 __global__ __launch_bounds__(kBlock) void face_flux_general_kernel(
     int64_t nf, const int4 *__restrict__ fc4, const int32_t *__restrict__ side_ptr,
     const int32_t *__restrict__ side_cell, const double *__restrict__ side_w,
     const double *__restrict__ u, const double *__restrict__ theta,
-    const double *__restrict__ area, double area0, int lim, double *__restrict__ phi, double us) {
+    const double *__restrict__ area, double area0, int lim, double *__restrict__ phi, double us,
+    const double *__restrict__ inflow) {
     const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
     const int4 e = fc4[f];
     const double uf = u[f] * us;
     const bool pos = uf > 0.0;
-    const int64_t C = pos ? e.x : e.y;
-    const int64_t D = pos ? e.y : e.x;
+    const int64_t C = pos ? e.x : e.y;  // -1: the exterior of an inflow face
+    const int64_t D = pos ? e.y : e.x;  // -1: the exterior of an outflow face
     const double au = (area ? area[f] : area0) * uf;
     double tC[S], tD[S], dU[S];
-    load_cell<S>(theta, C, tC);
-    load_cell<S>(theta, D, tD);
+    if (C >= 0) {
+        load_cell<S>(theta, C, tC);
+        if (D >= 0) load_cell<S>(theta, D, tD);
+        else {
+#pragma unroll
+            for (int k = 0; k < S; ++k) tD[k] = tC[k];
+        }
+    } else {
+        load_cell<S>(theta, D, tD);
+        if (inflow) load_cell<S>(inflow, f, tC);
+        else {
+#pragma unroll
+            for (int k = 0; k < S; ++k) tC[k] = tD[k];
+        }
+    }
     if (lim == FL_UPWIND) {
 #pragma unroll
         for (int k = 0; k < S; ++k) phi[f * S + k] = au * tC[k];
@@ -95,8 +113,15 @@ __global__ __launch_bounds__(kBlock) void face_flux_general_kernel(
     for (int64_t p = side_ptr[side]; p < side_ptr[side + 1]; ++p) {
         const int64_t j = side_cell[p];
         const double w = side_w[p];
+        if (j >= 0) {
 #pragma unroll
-        for (int k = 0; k < S; ++k) dU[k] += w * (tC[k] - theta[j * S + k]);
+            for (int k = 0; k < S; ++k) dU[k] += w * (tC[k] - theta[j * S + k]);
+        } else {
+            const int64_t jf = ~j;
+            const bool in = inflow && !(u[jf] * us > 0.0);
+#pragma unroll
+            for (int k = 0; k < S; ++k) dU[k] += w * (tC[k] - (in ? inflow[jf * S + k] : tC[k]));
+        }
     }
 #pragma unroll
     for (int k = 0; k < S; ++k) phi[f * S + k] = au * face_value_d(lim, tC[k], tD[k] - tC[k], dU[k]);
@@ -378,7 +403,7 @@ hipError_t launch_face_flux(const fl_mesh *m, int lim, int S, const double *thet
         FL_DISPATCH_S(S, (dev::face_flux_general_kernel<kS><<<nb, dev::kBlock, 0, st>>>(
                              m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), m->d_side_ptr,
                              m->d_side_cell, m->d_side_w, u, theta, m->d_area, m->h.area0, lim,
-                             phi, us)));
+                             phi, us, m->inflow)));
         return hipGetLastError();
     }
     Grid g = grid_for(m->h.nf, g_remap);

@@ -69,25 +69,29 @@ struct Csr {
     std::vector<int32_t> idx;  // faces of each cell, ascending
 };
 
+// A boundary face (nbr == -1) is in its one cell's list only.
 Csr cell_faces(int64_t nc, int64_t nf, const int32_t *fc) {
     Csr c;
     c.ptr.assign(nc + 1, 0);
-    c.idx.resize(2 * nf);
     int64_t *ptr = c.ptr.data();
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; ++f) {
 #pragma omp atomic
         ptr[fc[2 * f] + 1]++;
+        if (fc[2 * f + 1] >= 0) {
 #pragma omp atomic
-        ptr[fc[2 * f + 1] + 1]++;
+            ptr[fc[2 * f + 1] + 1]++;
+        }
     }
     for (int64_t i = 0; i < nc; ++i) ptr[i + 1] += ptr[i];
+    c.idx.resize(ptr[nc]);
     std::vector<int64_t> fill(c.ptr.begin(), c.ptr.end() - 1);
     int64_t *fl = fill.data();
     int32_t *idx = c.idx.data();
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; ++f)
         for (int side = 0; side < 2; ++side) {
+            if (fc[2 * f + side] < 0) continue;
             int64_t at;
 #pragma omp atomic capture
             at = fl[fc[2 * f + side]]++;
@@ -121,13 +125,13 @@ fl_status check_basic(int64_t nc, int64_t nf, const int32_t *fc, const double *n
 fl_status check_face(int64_t nc, const int32_t *fc, const double *nrm, int64_t f, bool report) {
     auto err = [&](fl_status st, const std::string &m) { return report ? fail(st, m) : st; };
     const int64_t a = fc[2 * f], b = fc[2 * f + 1];
-    if (b == -1 || a == -1) {
+    if (a == -1) {
         std::ostringstream os;
-        os << "face " << f << " is a boundary face (one cell); only closed (periodic) meshes "
-              "are supported";
-        return err(FL_E_UNSUPPORTED, os.str());
+        os << "face " << f << " has no own cell (a boundary face lists its one cell first, "
+              "nbr = -1, with the normal pointing out of the mesh)";
+        return err(FL_E_TOPOLOGY, os.str());
     }
-    if (a < 0 || a >= nc || b < 0 || b >= nc) {
+    if (a < 0 || a >= nc || (b != -1 && (b < 0 || b >= nc))) {
         std::ostringstream os;
         os << "face " << f << " references a cell outside [0, " << nc << ")";
         return err(FL_E_TOPOLOGY, os.str());
@@ -153,7 +157,7 @@ size_t duplicate_at(const int32_t *fc, const Csr &cs, int64_t c,
                     std::vector<std::pair<int32_t, int32_t>> &nb) {
     nb.clear();
     for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p)
-        nb.emplace_back(other(fc, cs.idx[p], c), cs.idx[p]);
+        if (other(fc, cs.idx[p], c) >= 0) nb.emplace_back(other(fc, cs.idx[p], c), cs.idx[p]);
     std::sort(nb.begin(), nb.end());
     for (size_t i = 1; i < nb.size(); ++i)
         if (nb[i].first == nb[i - 1].first) return i;
@@ -232,7 +236,8 @@ bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
 
 // General cells: for every face side, the cells beyond the other faces of C with their nonzero
 // weights (the nonzeros of row f of S_{C->F}, T_{C->F} on that side), in C's face order:
-// d_U = sum_j w_j (theta_C - theta_j).
+// d_U = sum_j w_j (theta_C - theta_j).  Beyond a boundary face j lies the exterior: entry ~j.
+// The exterior side of a boundary face (C = the exterior) has no entries: d_U = 0.
 bool side_lists(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs, HostTables &t) {
     t.side_ptr.assign(2 * nf + 1, 0);
     t.side_cell.clear();
@@ -241,12 +246,13 @@ bool side_lists(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
         for (int side = 0; side < 2; ++side) {
             const int64_t C = fc[2 * f + side];
             const double s = side == 0 ? 1.0 : -1.0;
-            for (int64_t p = cs.ptr[C]; p < cs.ptr[C + 1]; ++p) {
+            for (int64_t p = C >= 0 ? cs.ptr[C] : 0; C >= 0 && p < cs.ptr[C + 1]; ++p) {
                 const int64_t j = cs.idx[p];
                 if (j == f) continue;
                 const double w = projection(fc, nrm, f, j, C, s);
                 if (w != 0.0) {
-                    t.side_cell.push_back(other(fc, j, C));
+                    const int64_t o = other(fc, j, C);
+                    t.side_cell.push_back(o >= 0 ? (int32_t)o : ~(int32_t)j);
                     t.side_w.push_back(w);
                 }
             }
@@ -277,7 +283,7 @@ std::vector<int32_t> bfs_numbering(int64_t nc, const int32_t *fc, const Csr &cs)
                 int64_t c = order[head++];
                 for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
                     int64_t o = other(fc, cs.idx[p], c);
-                    if (!seen[o]) {
+                    if (o >= 0 && !seen[o]) {
                         seen[o] = 1;
                         order.push_back((int32_t)o);
                     }
@@ -300,8 +306,8 @@ std::vector<int32_t> bfs_numbering(int64_t nc, const int32_t *fc, const Csr &cs)
 // cut open opposite the root).  Cells are then sorted by the Morton (bit-interleaved) code of
 // their coordinates, so any run of consecutive cells is a compact block of the mesh and the
 // cells a workgroup gathers from lie in it or in the blocks next to it.  Returns new_of_old.
-std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double *nrm,
-                                     const Csr &cs) {
+std::vector<int32_t> curve_numbering(int64_t nc, int64_t nf, const int32_t *fc,
+                                     const double *nrm, const Csr &cs) {
     // The walk runs level by level on all cores and visits the cells in exactly the order of a
     // serial first-in-first-out walk: a cell's parent is its neighbour of the previous level
     // that comes first in that order (smallest (queue position, face position) claim), and each
@@ -331,6 +337,7 @@ std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double
                 const int64_t c = frontier[q];
                 for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
                     const int64_t o = other(fc, cs.idx[p], c);
+                    if (o < 0) continue;
                     const uint64_t key = 1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c]);
                     uint64_t cur = __atomic_load_n(&claim[o], __ATOMIC_RELAXED);
                     while (key < cur && !__atomic_compare_exchange_n(&claim[o], &cur, key, true,
@@ -344,9 +351,10 @@ std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double
             for (int64_t q = 0; q < nq; ++q) {
                 const int64_t c = frontier[q];
                 int64_t k = 0;
-                for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p)
-                    k += claim[other(fc, cs.idx[p], c)] ==
-                         1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c]);
+                for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
+                    const int64_t o = other(fc, cs.idx[p], c);
+                    k += o >= 0 && claim[o] == 1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c]);
+                }
                 cnt[q + 1] = k;
             }
             for (int64_t q = 0; q < nq; ++q) cnt[q + 1] += cnt[q];
@@ -358,7 +366,8 @@ std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double
                 for (int64_t p = cs.ptr[c]; p < cs.ptr[c + 1]; ++p) {
                     const int64_t f = cs.idx[p];
                     const int64_t o = other(fc, f, c);
-                    if (claim[o] != 1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c])) continue;
+                    if (o < 0 || claim[o] != 1 + (uint64_t)q * D + (uint64_t)(p - cs.ptr[c]))
+                        continue;
                     const double s = fc[2 * f] == c ? 1.0 : -1.0;
                     for (int d = 0; d < 3; ++d) pos[3 * o + d] = pos[3 * c + d] + s * nrm[3 * f + d];
                     hi_x = std::max(hi_x, pos[3 * o]);
@@ -396,13 +405,12 @@ std::vector<int32_t> curve_numbering(int64_t nc, const int32_t *fc, const double
     // lands where depends on the face order), and the tiles along it are ragged.  A face whose
     // step disagrees with its cells' positions crosses that cut; where every such face spans
     // the same whole number P of cells along axis d, the coordinates are folded modulo P.
-    const int64_t nf = (int64_t)cs.idx.size() / 2;
     int64_t pmn[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, pmx[3] = {0, 0, 0};
     int odd[3] = {0, 0, 0};
 #pragma omp parallel for schedule(static) reduction(min : pmn[:3]) reduction(max : pmx[:3], odd[:3])
     for (int64_t f = 0; f < nf; ++f) {
         const int64_t a = fc[2 * f], b = fc[2 * f + 1];
-        for (int d = 0; d < 3; ++d) {
+        for (int d = 0; d < 3 && b >= 0; ++d) {
             const double gap = std::fabs(pos[3 * a + d] + nrm[3 * f + d] - pos[3 * b + d]);
             if (gap <= 0.5) continue;
             const int64_t p = std::llround(gap);
@@ -439,7 +447,15 @@ std::vector<int32_t> face_numbering(int64_t nc, int64_t nf, const int32_t *fc,
     int64_t *cp = cnt.data();
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; ++f) {
-        int32_t a = cnew[fc[2 * f]], b = cnew[fc[2 * f + 1]];
+        // a boundary face sorts with its one cell, after that cell's interior faces
+        int32_t a = cnew[fc[2 * f]], b = fc[2 * f + 1] >= 0 ? cnew[fc[2 * f + 1]] : (int32_t)nc;
+        if (b == (int32_t)nc) {
+            lo[f] = a;
+            hi[f] = b;
+#pragma omp atomic
+            cp[lo[f] + 1]++;
+            continue;
+        }
         lo[f] = std::min(a, b);
         hi[f] = std::max(a, b);
 #pragma omp atomic
@@ -742,7 +758,7 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     if (reorder) {
         std::vector<int32_t> cnew = reorder == REORDER_BFS
                                         ? bfs_numbering(nc, t.fc.data(), cs)
-                                        : curve_numbering(nc, t.fc.data(), t.nrm.data(), cs);
+                                        : curve_numbering(nc, nf, t.fc.data(), t.nrm.data(), cs);
         progress("cells renumbered", nc);
         std::vector<int32_t> fnew = face_numbering(nc, nf, t.fc.data(), cnew);
         std::vector<int32_t> fc2(2 * nf);
@@ -751,7 +767,7 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
         for (int64_t f = 0; f < nf; ++f) {
             int64_t g = fnew[f];
             fc2[2 * g] = cnew[t.fc[2 * f]];
-            fc2[2 * g + 1] = cnew[t.fc[2 * f + 1]];
+            fc2[2 * g + 1] = t.fc[2 * f + 1] >= 0 ? cnew[t.fc[2 * f + 1]] : -1;
             std::memcpy(&nrm2[3 * g], &t.nrm[3 * f], 3 * sizeof(double));
         }
         if (!area.empty()) {
@@ -785,13 +801,22 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     if (!t.uni_vol) t.vol.swap(vol);
 
     std::vector<int32_t> opp;
-    t.general = !far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
+    t.n_boundary = 0;
+    for (int64_t f = 0; f < nf; ++f) t.n_boundary += t.fc[2 * f + 1] < 0;
+    // a mesh with boundary faces runs the general face path: the exterior beyond a boundary
+    // face has no far-upwind cell and no opposite face
+    t.general = t.n_boundary > 0 ||
+                !far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
+    if (t.n_boundary > 0) {
+        t.far.assign(2 * nf, -1);
+        opp.assign(2 * nf, -1);
+    }
     if (t.general && !side_lists(nf, t.fc.data(), t.nrm.data(), cs, t))
         return fail(FL_E_UNSUPPORTED, "too many projected faces for 32-bit side lists");
     progress("far-upwind cells", nc);
 
     t.cf_ptr.resize(nc + 1);
-    t.cf_idx.resize(2 * nf);
+    t.cf_idx.resize(cs.idx.size());
     int32_t max_degree = 0;
     int32_t min_degree = std::numeric_limits<int32_t>::max();
     for (int64_t c = 0; c <= nc; ++c) t.cf_ptr[c] = (int32_t)cs.ptr[c];

@@ -96,6 +96,24 @@ class Mesh:
         self.device = torch.device("cuda", self.device_index) if self.device_index >= 0 else None
         self.path = "fused" if info.path == _lib.FL_PATH_FUSED else "face"
         self.reordered = bool(info.reordered)
+        self.n_boundary = int(info.n_boundary)
+        self._inflow = None
+
+    def set_inflow(self, values: Optional[torch.Tensor]) -> None:
+        """Inflow values of the boundary faces (fl_mesh_set_inflow): a contiguous float64
+        [F] or [F, S] tensor on the mesh's device in mesh order (rows of the other faces are not
+        read), or None to clear.  The mesh keeps a reference until cleared or closed."""
+        if values is None:
+            call("fl_mesh_set_inflow", self.handle, None, 0)
+            self._inflow = None
+            return
+        if values.dtype != torch.float64 or values.device != self.device or \
+                not values.is_contiguous() or values.shape[0] != self.n_faces or \
+                values.dim() not in (1, 2):
+            raise ValueError(f"inflow values must be a contiguous float64 [{self.n_faces}] or "
+                             f"[{self.n_faces}, S] tensor on the mesh's device")
+        call("fl_mesh_set_inflow", self.handle, _tptr(values), _S(values))
+        self._inflow = values
 
     @classmethod
     def from_arrays(cls, m, **kw) -> "Mesh":
@@ -112,6 +130,7 @@ class Mesh:
         if getattr(self, "_h", None) is not None:
             lib().fl_mesh_destroy(self._h)
             self._h = None
+        self._inflow = None
 
     def __del__(self):
         try:

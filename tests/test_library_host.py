@@ -181,7 +181,10 @@ def test_validate_rejections():
     m = W.periodic_box(4, 3)
     fc, nrm, C = m.face_cells.copy(), m.face_normal.copy(), m.n_cells
     bad = fc.copy(); bad[5, 1] = -1
-    assert _err(bad, nrm, C)[0] == -3  # boundary face
+    assert _err(bad, nrm, C)[0] == 0  # a boundary face (one cell)
+    bad = fc.copy(); bad[5] = [-1, bad[5, 0]]
+    st, msg = _err(bad, nrm, C)
+    assert st == -2 and "own" in msg  # a boundary face lists its cell first
     bad = fc.copy(); bad[5, 1] = C
     assert _err(bad, nrm, C)[0] == -2  # out of range
     bad = fc.copy(); bad[5, 1] = bad[5, 0]
@@ -201,6 +204,49 @@ def test_validate_rejections():
     assert st == 0
     mesh = FL.Mesh(fc, badn, n_cells=C, device=-1)
     assert mesh.info.general == 1 and mesh.info.max_side >= 2 and mesh.path == "face"
+    mesh.close()
+
+
+@pytest.mark.parametrize("reorder", [False, True, "bfs"])
+def test_boundary_mesh_tables(reorder):
+    """An open box builds on the face path with the general tables: the boundary faces are in
+    their one cell's face list (as ~f: the cell is own), the permutation keeps each boundary
+    face's cell, and the exterior side of a boundary face has no projected faces."""
+    m = W.renumber(W.open_box(6, 3, (0, 1)), seed=3)
+    nb = int((m.face_cells[:, 1] < 0).sum())
+    assert nb == 2 * 2 * 36
+    mesh = FL.Mesh.from_arrays(m, device=-1, reorder=reorder)
+    assert mesh.path == "face" and mesh.info.general == 1 and mesh.n_boundary == nb
+    assert mesh.info.pairs == 0 and mesh.info.max_halo == -1
+    far, ptr, idx = mesh.export_tables()
+    assert np.all(far == -1)
+    assert ptr[-1] == 2 * m.n_faces - nb
+    cp, fp = mesh.permutation()
+    assert sorted(cp) == list(range(m.n_cells)) and sorted(fp) == list(range(m.n_faces))
+    bmesh = fp[m.face_cells[:, 1] < 0]  # the boundary faces in mesh numbering
+    owner = cp[m.face_cells[m.face_cells[:, 1] < 0, 0]]
+    cell_of = np.repeat(np.arange(m.n_cells), np.diff(ptr))
+    for f, c in zip(bmesh, owner):
+        hits = np.nonzero((idx == ~f) | (idx == f))[0]
+        assert len(hits) == 1 and idx[hits[0]] == ~f and cell_of[hits[0]] == c
+    # every cell keeps its six faces
+    assert np.all(np.diff(ptr) == 6)
+    # the oracle's projected faces: none on the exterior side of a boundary face
+    om = O.OracleMesh.from_arrays(m)
+    f0 = int(np.nonzero(m.face_cells[:, 1] < 0)[0][0])
+    assert om.side_weights(f0, True)[0].size == 0
+    assert om.side_weights(f0, False)[0].size == 6
+    L = _lib.lib()
+    assert L.fl_mesh_set_inflow(mesh.handle, ctypes.c_void_p(8), 1) == -7  # host-only
+    assert L.fl_mesh_set_inflow(mesh.handle, None, 0) == 0
+    mesh.close()
+
+
+def test_algebraic_chain_refuses_boundary_meshes():
+    mesh = FL.Mesh.from_arrays(W.open_box(5, 3, (2,)), device=-1)
+    with pytest.raises(_lib.FluxLimError) as e:
+        FL.Algebraic(mesh)
+    assert e.value.status == -3
     mesh.close()
 
 
