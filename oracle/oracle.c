@@ -40,6 +40,7 @@ struct orc_mesh {
     int64_t n_boundary;
     const double *inflow; /* [nf][inflow_S] or NULL (see exterior_value) */
     int inflow_S;
+    const double *dist;   /* [nf] distance between the cells across each face, or NULL */
 };
 
 int orc_num_threads(void) {
@@ -83,6 +84,8 @@ orc_mesh *orc_mesh_new(int64_t nc, int64_t nf, const int32_t *fc, const double *
 }
 
 int64_t orc_boundary_faces(const orc_mesh *m) { return m->n_boundary; }
+
+void orc_mesh_set_distances(orc_mesh *m, const double *dist) { m->dist = dist; }
 
 void orc_mesh_set_inflow(orc_mesh *m, const double *inflow, int S) {
     m->inflow = inflow;
@@ -240,7 +243,10 @@ void orc_select(const orc_mesh *m, const double *u, int32_t *cdu) {
     }
 }
 
-/* The exterior upwind of an inflow face has no other faces: d_U = 0 there. */
+/* The exterior upwind of an inflow face has no other faces: d_U = 0 there.  With face
+ * distances (Algorithm 1D's d_i / d_U and Algorithm UNS), each projected difference is divided
+ * by the distance d_j across its face and the sum is multiplied by the face's own distance d_f,
+ * so that r = d_U / d_u equals Algorithm UNS's Delta_U / ((theta_D - theta_C) / d_f). */
 static double upstream_difference(const orc_mesh *m, int S, const double *th, const double *u,
                                   int64_t f, face_sel fs, int k) {
     double dU = 0.0;
@@ -250,8 +256,11 @@ static double upstream_difference(const orc_mesh *m, int S, const double *th, co
         int64_t j = m->cidx[p];
         if (j == f) continue;
         double w = proj_weight(m, f, j, fs.C, fs.s);
-        dU += w * (tC - value_at(m, S, th, u, other_cell(m, j, fs.C), j, k));
+        double diff = tC - value_at(m, S, th, u, other_cell(m, j, fs.C), j, k);
+        if (m->dist) dU += w * diff / m->dist[j];
+        else dU += w * diff;
     }
+    if (m->dist) dU *= m->dist[f];
     return dU;
 }
 

@@ -65,6 +65,11 @@ orc_mesh *orc_mesh_new(int64_t n_cells, int64_t n_faces, const int32_t *face_cel
 void orc_mesh_free(orc_mesh *m);
 int64_t orc_cell_degree(const orc_mesh *m, int64_t c);
 int64_t orc_boundary_faces(const orc_mesh *m);
+/* Distance between the cells across each face ([F], kept by pointer; on a boundary face the
+ * distance to the exterior cell), or NULL: d_U = d_f sum_j w_j (theta_C - theta_j) / d_j
+ * (Algorithm 1D's distance ratio, Algorithm UNS's weighted upstream difference).  Without
+ * distances every ratio d_f / d_j is taken as 1.  The derivative functions ignore them. */
+void orc_mesh_set_distances(orc_mesh *m, const double *dist);
 /* Inflow values of the boundary faces ([F][S], read at boundary faces only; kept by pointer),
  * or NULL: the exterior then repeats the cell's value on every boundary face. */
 void orc_mesh_set_inflow(orc_mesh *m, const double *inflow, int S);

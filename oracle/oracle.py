@@ -54,6 +54,7 @@ def lib():
         L.orc_boundary_faces.restype = _I64
         L.orc_boundary_faces.argtypes = [_P]
         L.orc_mesh_set_inflow.argtypes = [_P, _P, _I]
+        L.orc_mesh_set_distances.argtypes = [_P, _P]
         L.orc_psi.restype = _D
         L.orc_psi.argtypes = [_I, _D]
         L.orc_dpsi.restype = _D
@@ -123,6 +124,20 @@ class OracleMesh:
         self._h = h
         self.n_boundary = int(lib().orc_boundary_faces(h))
         self._inflow = None
+        self._dist = None
+
+    def set_distances(self, dist) -> None:
+        """Face distances [F] (Algorithm 1D / UNS weighting of the upstream difference), or
+        None for the unweighted form.  Forward functions only."""
+        if dist is None:
+            self._dist = None
+            lib().orc_mesh_set_distances(self._h, None)
+            return
+        d = _f64(dist)
+        if d.shape != (self.n_faces,) or not np.all(d > 0) or not np.all(np.isfinite(d)):
+            raise ValueError("distances must be finite, positive, one per face")
+        self._dist = d
+        lib().orc_mesh_set_distances(self._h, _ptr(d))
 
     def set_inflow(self, values) -> None:
         """Inflow values of the boundary faces ([F] or [F, S], read where u_f <= 0 on boundary
@@ -143,8 +158,9 @@ class OracleMesh:
             raise ValueError("the inflow values were set for another number of scalars")
 
     def _closed(self) -> None:
-        if self.n_boundary:
-            raise ValueError("the oracle's derivatives cover closed meshes only")
+        if self.n_boundary or self._dist is not None:
+            raise ValueError("the oracle's derivatives cover closed meshes without face "
+                             "distances only")
 
     @classmethod
     def from_arrays(cls, m) -> "OracleMesh":

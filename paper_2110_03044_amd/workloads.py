@@ -50,6 +50,9 @@ class MeshArrays:
     cell_new_of_old: Optional[np.ndarray] = None  # int64 [C]
     face_new_of_old: Optional[np.ndarray] = None  # int64 [F]
     face_flip_old: Optional[np.ndarray] = None  # bool [F], indexed by old face
+    # distance between the cell centres across each face (a boundary face: to the mirror image
+    # of its cell), for the distance-weighted upstream difference; None: not given
+    face_dist: Optional[np.ndarray] = None
 
     @property
     def n_cells(self) -> int:
@@ -144,6 +147,32 @@ def open_box(n: int, dim: int = 3, open_axes=(0,)) -> MeshArrays:
     face_normal = np.concatenate(nrm, axis=0)
     area = np.full(face_cells.shape[0], base.face_area[0], dtype=np.float64)
     return MeshArrays(face_cells, face_normal, area, base.cell_volume.copy(), n=n, dim=dim)
+
+
+def stretched_box(n: int, dim: int = 3, amp: float = 0.5, open_axes=()) -> MeshArrays:
+    """periodic_box (open_box along open_axes) with cell widths along x proportional to
+    1 + amp sin(2 pi (i + 1/2) / n), summing to 1, and uniform widths 1/n along the other axes:
+    face areas, cell volumes and the face distances between cell centres follow (a boundary
+    face's distance is its cell's width along the face normal: to the cell's mirror image)."""
+    m = open_box(n, dim, tuple(open_axes)) if open_axes else periodic_box(n, dim)
+    i = np.arange(n)
+    hx = 1.0 + amp * np.sin(2 * np.pi * (i + 0.5) / n)
+    hx /= hx.sum()
+    h = 1.0 / n
+    C = m.n_cells
+    c = np.arange(C, dtype=np.int64)
+    wx = hx[c % n]  # x width of every cell
+    own = m.face_cells[:, 0].astype(np.int64)
+    nbr = m.face_cells[:, 1].astype(np.int64)
+    axis = np.abs(m.face_normal).argmax(axis=1)
+    dist = np.full(m.n_faces, h)
+    x = axis == 0
+    inner = nbr >= 0
+    dist[x & inner] = 0.5 * (wx[own[x & inner]] + wx[nbr[x & inner]])
+    dist[x & ~inner] = wx[own[x & ~inner]]
+    area = np.where(x, h ** (dim - 1), wx[own] * h ** max(dim - 2, 0))
+    vol = wx * h ** (dim - 1)
+    return dataclasses.replace(m, face_area=area, cell_volume=vol, face_dist=dist)
 
 
 def face_centres(mesh: MeshArrays) -> np.ndarray:
@@ -301,8 +330,13 @@ def renumber(mesh: MeshArrays, seed: int = SEED_RENUMBER, flip: bool = True) -> 
     area[fnew] = mesh.face_area
     vol = np.empty_like(mesh.cell_volume)
     vol[cnew] = mesh.cell_volume
+    dist = None
+    if mesh.face_dist is not None:
+        dist = np.empty_like(mesh.face_dist)
+        dist[fnew] = mesh.face_dist
     return MeshArrays(fc, nrm, area, vol, n=mesh.n, dim=mesh.dim,
-                      cell_new_of_old=cnew, face_new_of_old=fnew, face_flip_old=flips)
+                      cell_new_of_old=cnew, face_new_of_old=fnew, face_flip_old=flips,
+                      face_dist=dist)
 
 
 # ---------------------------------------------------------------------------------------------
