@@ -54,8 +54,9 @@ typedef int32_t fl_status;
 #define FL_E_TOPOLOGY -2    /* incidence violates the mesh model (index range, own == nbr,
                                own == -1, two faces joining the same two cells)               */
 #define FL_E_UNSUPPORTED -3 /* valid but outside this library: the adjoint and batching on
-                               cells without opposite face pairs or on meshes with boundary
-                               faces; the algebraic chain on meshes with boundary faces      */
+                               cells without opposite face pairs, on meshes with boundary
+                               faces or with unequal face distances; the algebraic chain on
+                               meshes with boundary faces or face distances                  */
 #define FL_E_NOMEM -4       /* host or device allocation failed                              */
 #define FL_E_HIP -5         /* a HIP runtime call failed (message in fl_last_error)          */
 #define FL_E_NONFINITE -6   /* an input holds a NaN or an infinity (only reported while the
@@ -115,7 +116,7 @@ typedef struct fl_mesh_info_t {
     int32_t max_side;       /* most projected faces on one face side                         */
     int32_t aligned;        /* 1 if the opposite-face pairs line up from cell to cell (lattice */
                             /* meshes; the forward-rate stages, FL_OPT_FWD_RATES, apply)      */
-    int32_t reserved;
+    int32_t dist_weighted;  /* 1 if unequal face distances weight the upstream difference    */
     int64_t n_boundary;     /* boundary faces (one cell: nbr = -1)                           */
 } fl_mesh_info_t;
 
@@ -145,6 +146,19 @@ fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face
 fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                          const double *face_normal, const double *face_area,
                          const double *cell_volume, int device, uint32_t flags, fl_mesh **out);
+/* As fl_mesh_create, with the distance between the cells across each face (face_dist: host
+ * double [n_faces], finite and positive; on a boundary face the distance from its cell to the
+ * exterior cell, e.g. to the cell's mirror image).  The gradient ratio then weighs distances as
+ * Algorithm 1D (r = (d_i / d_U)(theta_C - theta_U) / (theta_D - theta_C)) and Algorithm UNS
+ * (each projected difference over the distance across its face, the face difference over d_i)
+ * do: the upstream difference becomes d_U = sum_j w_j (d_f / d_j)(theta_C - theta_j).  Where all
+ * distances are equal every ratio is 1 and the mesh is built as without them; otherwise it runs
+ * the face path with the general kernel (the ratios sit in its side weights), and the adjoint
+ * and batches refuse it (FL_E_UNSUPPORTED).  face_dist = NULL is fl_mesh_create. */
+fl_status fl_mesh_create_dist(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
+                              const double *face_normal, const double *face_area,
+                              const double *cell_volume, const double *face_dist, int device,
+                              uint32_t flags, fl_mesh **out);
 fl_status fl_mesh_destroy(fl_mesh *mesh);
 fl_status fl_mesh_info(const fl_mesh *mesh, fl_mesh_info_t *info);
 

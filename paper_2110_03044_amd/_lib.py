@@ -38,7 +38,7 @@ class MeshInfo(ctypes.Structure):
                 ("tile_cells", ctypes.c_int32), ("max_halo", ctypes.c_int32),
                 ("halo_total", ctypes.c_int64), ("general", ctypes.c_int32),
                 ("max_side", ctypes.c_int32), ("aligned", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("n_boundary", ctypes.c_int64)]
+                ("dist_weighted", ctypes.c_int32), ("n_boundary", ctypes.c_int64)]
 
 
 class AlgebraicInfo(ctypes.Structure):
@@ -59,6 +59,7 @@ SIGNATURES = {
     "fl_mesh_create": (_S, [_I64, _I64, _P, _P, _P, _P, _I, ctypes.c_uint32, _P]),
     "fl_mesh_destroy": (_S, [_P]),
     "fl_mesh_info": (_S, [_P, _P]),
+    "fl_mesh_create_dist": (_S, [_I64, _I64, _P, _P, _P, _P, _P, _I, ctypes.c_uint32, _P]),
     "fl_mesh_set_inflow": (_S, [_P, _P, _I]),
     "fl_mesh_permutation": (_S, [_P, _P, _P]),
     "fl_mesh_export_tables": (_S, [_P, _P, _P, _P]),

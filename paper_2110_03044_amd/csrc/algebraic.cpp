@@ -245,8 +245,9 @@ fl_status fl_algebraic_create(const fl_mesh *mesh, fl_algebraic **out) {
     if (!out) return fail(FL_E_INVALID, "NULL output pointer");
     *out = nullptr;
     if (!mesh) return fail(FL_E_INVALID, "NULL mesh");
-    if (mesh->h.n_boundary > 0)
-        return fail(FL_E_UNSUPPORTED, "the algebraic chain covers closed meshes (no boundary faces)");
+    if (mesh->h.n_boundary > 0 || mesh->h.dist_weighted)
+        return fail(FL_E_UNSUPPORTED,
+                    "the algebraic chain covers closed meshes without face distances");
     fl_algebraic *g = new (std::nothrow) fl_algebraic();
     if (!g) return fail(FL_E_NOMEM, "host allocation failed");
     g->mesh = mesh;

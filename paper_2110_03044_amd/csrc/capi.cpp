@@ -254,7 +254,7 @@ fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face
     try {
         HostTables t;
         return build_host_tables(n_cells, n_faces, face_cells, face_normal, nullptr, nullptr,
-                                 REORDER_NONE, t);
+                                 nullptr, REORDER_NONE, t);
     } catch (const std::bad_alloc &) {
         return fail(FL_E_NOMEM, "host allocation failed");
     }
@@ -263,6 +263,14 @@ fl_status fl_mesh_validate(int64_t n_cells, int64_t n_faces, const int32_t *face
 fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                          const double *face_normal, const double *face_area,
                          const double *cell_volume, int device, uint32_t flags, fl_mesh **out) {
+    return fl_mesh_create_dist(n_cells, n_faces, face_cells, face_normal, face_area, cell_volume,
+                               nullptr, device, flags, out);
+}
+
+fl_status fl_mesh_create_dist(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
+                              const double *face_normal, const double *face_area,
+                              const double *cell_volume, const double *face_dist, int device,
+                              uint32_t flags, fl_mesh **out) {
     if (!out) return fail(FL_E_INVALID, "out is NULL");
     *out = nullptr;
     if (flags & ~(uint32_t)(FL_MESH_REORDER | FL_MESH_FACE_PATH | FL_MESH_REORDER_BFS))
@@ -276,7 +284,7 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
     try {
         m = new fl_mesh();
         fl_status st = build_host_tables(n_cells, n_faces, face_cells, face_normal, face_area,
-                                         cell_volume, reorder, m->h);
+                                         cell_volume, face_dist, reorder, m->h);
         if (st != FL_OK) {
             delete m;
             return st;
@@ -421,7 +429,7 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
         ms = std::max(ms, m->h.side_ptr[i + 1] - m->h.side_ptr[i]);
     info->max_side = m->h.general ? ms : 1;
     info->aligned = m->h.aligned_slots ? 1 : 0;
-    info->reserved = 0;
+    info->dist_weighted = m->h.dist_weighted ? 1 : 0;
     info->n_boundary = m->h.n_boundary;
     return FL_OK;
 }

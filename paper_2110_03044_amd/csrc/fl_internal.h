@@ -63,6 +63,7 @@ struct HostTables {
     int32_t max_halo = -1;           // -1: no tile tables (local indices would not fit 16 bits)
     int32_t max_nrate = -1;          // largest halo_nrate[2 tile + 1] (-1: not aligned)
     int64_t n_boundary = 0;          // faces with one cell (nbr == -1): general face path only
+    bool dist_weighted = false;      // side weights scaled by face distance ratios d_f / d_j
     // Numbering maps user -> mesh (empty = identity).
     std::vector<int32_t> cell_perm, face_perm;
 };
@@ -80,7 +81,8 @@ enum { REORDER_NONE = 0, REORDER_CURVE = 1, REORDER_BFS = 2 };
 // Validates and builds every table; returns FL_OK or an error (message set).
 fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
                             const double *face_normal, const double *face_area,
-                            const double *cell_volume, int reorder, HostTables &t);
+                            const double *cell_volume, const double *face_dist, int reorder,
+                            HostTables &t);
 
 }  // namespace fl
 

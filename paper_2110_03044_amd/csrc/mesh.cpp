@@ -236,9 +236,12 @@ bool far_upwind(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
 
 // General cells: for every face side, the cells beyond the other faces of C with their nonzero
 // weights (the nonzeros of row f of S_{C->F}, T_{C->F} on that side), in C's face order:
-// d_U = sum_j w_j (theta_C - theta_j).  Beyond a boundary face j lies the exterior: entry ~j.
+// d_U = sum_j w_j (theta_C - theta_j).  With face distances each weight is scaled by d_f / d_j
+// (Algorithm UNS's division of each projected difference by the distance across its face, and
+// of the face difference by d_f).  Beyond a boundary face j lies the exterior: entry ~j.
 // The exterior side of a boundary face (C = the exterior) has no entries: d_U = 0.
-bool side_lists(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs, HostTables &t) {
+bool side_lists(int64_t nf, const int32_t *fc, const double *nrm, const std::vector<double> &dist,
+                const Csr &cs, HostTables &t) {
     t.side_ptr.assign(2 * nf + 1, 0);
     t.side_cell.clear();
     t.side_w.clear();
@@ -253,7 +256,7 @@ bool side_lists(int64_t nf, const int32_t *fc, const double *nrm, const Csr &cs,
                 if (w != 0.0) {
                     const int64_t o = other(fc, j, C);
                     t.side_cell.push_back(o >= 0 ? (int32_t)o : ~(int32_t)j);
-                    t.side_w.push_back(w);
+                    t.side_w.push_back(dist.empty() ? w : w * (dist[f] / dist[j]));
                 }
             }
             if (t.side_cell.size() > (size_t)INT32_MAX) return false;
@@ -728,7 +731,8 @@ void build_tiles(HostTables &t) {
 
 fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
                             const double *face_normal, const double *face_area,
-                            const double *cell_volume, int reorder, HostTables &t) {
+                            const double *cell_volume, const double *face_dist, int reorder,
+                            HostTables &t) {
     Progress progress;
     fl_status st = check_basic(nc, nf, face_cells, face_normal);
     if (st != FL_OK) return st;
@@ -740,15 +744,23 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
         for (int64_t c = 0; c < nc; ++c)
             if (!(cell_volume[c] > 0.0) || !std::isfinite(cell_volume[c]))
                 return fail(FL_E_INVALID, "cell volumes must be finite and positive");
+    if (face_dist)
+        for (int64_t f = 0; f < nf; ++f)
+            if (!(face_dist[f] > 0.0) || !std::isfinite(face_dist[f]))
+                return fail(FL_E_INVALID, "face distances must be finite and positive");
 
     t = HostTables();
     t.nc = nc;
     t.nf = nf;
     t.fc.assign(face_cells, face_cells + 2 * nf);
     t.nrm.assign(face_normal, face_normal + 3 * nf);
-    std::vector<double> area, vol;
+    std::vector<double> area, vol, dist;
     if (face_area) area.assign(face_area, face_area + nf);
     if (cell_volume) vol.assign(cell_volume, cell_volume + nc);
+    // equal distances leave every ratio d_f / d_j at 1: the unweighted tables
+    if (face_dist)
+        for (int64_t f = 1; f < nf && dist.empty(); ++f)
+            if (face_dist[f] != face_dist[0]) dist.assign(face_dist, face_dist + nf);
 
     Csr cs = cell_faces(nc, nf, t.fc.data());
     st = check_duplicates(nc, t.fc.data(), cs);
@@ -775,6 +787,12 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
 #pragma omp parallel for schedule(static)
             for (int64_t f = 0; f < nf; ++f) a2[fnew[f]] = area[f];
             area.swap(a2);
+        }
+        if (!dist.empty()) {
+            std::vector<double> d2(nf);
+#pragma omp parallel for schedule(static)
+            for (int64_t f = 0; f < nf; ++f) d2[fnew[f]] = dist[f];
+            dist.swap(d2);
         }
         if (!vol.empty()) {
             std::vector<double> v2(nc);
@@ -804,14 +822,16 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     t.n_boundary = 0;
     for (int64_t f = 0; f < nf; ++f) t.n_boundary += t.fc[2 * f + 1] < 0;
     // a mesh with boundary faces runs the general face path: the exterior beyond a boundary
-    // face has no far-upwind cell and no opposite face
-    t.general = t.n_boundary > 0 ||
+    // face has no far-upwind cell and no opposite face; so does a mesh with unequal face
+    // distances (its side weights carry the distance ratios)
+    t.dist_weighted = !dist.empty();
+    t.general = t.n_boundary > 0 || t.dist_weighted ||
                 !far_upwind(nf, t.fc.data(), t.nrm.data(), cs, t.far, opp);
-    if (t.n_boundary > 0) {
+    if (t.n_boundary > 0 || t.dist_weighted) {
         t.far.assign(2 * nf, -1);
         opp.assign(2 * nf, -1);
     }
-    if (t.general && !side_lists(nf, t.fc.data(), t.nrm.data(), cs, t))
+    if (t.general && !side_lists(nf, t.fc.data(), t.nrm.data(), dist, cs, t))
         return fail(FL_E_UNSUPPORTED, "too many projected faces for 32-bit side lists");
     progress("far-upwind cells", nc);
 

@@ -68,7 +68,7 @@ class Mesh:
     """A mesh on one GPU, built from its face-to-cell incidence (see include/fluxlim.h)."""
 
     def __init__(self, face_cells, face_normal, face_area=None, cell_volume=None, n_cells=None,
-                 device=0, reorder=False, face_path: bool = False):
+                 device=0, reorder=False, face_path: bool = False, face_dist=None):
         fc = np.ascontiguousarray(face_cells, dtype=np.int32)
         nrm = np.ascontiguousarray(face_normal, dtype=np.float64)
         if fc.ndim != 2 or fc.shape[1] != 2 or nrm.shape != (fc.shape[0], 3):
@@ -82,10 +82,13 @@ class Mesh:
             raise ValueError("reorder must be False, True/'curve' or 'bfs'")
         flags = ((_lib.FL_MESH_REORDER_BFS if reorder == "bfs" else _lib.FL_MESH_REORDER if reorder else 0)
                  | (_lib.FL_MESH_FACE_PATH if face_path else 0))
+        dist = None if face_dist is None else np.ascontiguousarray(face_dist, dtype=np.float64)
+        if dist is not None and dist.shape != (fc.shape[0],):
+            raise ValueError("face_dist must hold one distance per face")
         h = ctypes.c_void_p()
-        call("fl_mesh_create", C, fc.shape[0], _np_ptr(fc), _np_ptr(nrm),
+        call("fl_mesh_create_dist", C, fc.shape[0], _np_ptr(fc), _np_ptr(nrm),
              _np_ptr(area) if area is not None else None, _np_ptr(vol) if vol is not None else None,
-             int(device), flags, ctypes.byref(h))
+             _np_ptr(dist) if dist is not None else None, int(device), flags, ctypes.byref(h))
         self._h = h
         info = _lib.MeshInfo()
         call("fl_mesh_info", self._h, ctypes.byref(info))
@@ -117,7 +120,9 @@ class Mesh:
 
     @classmethod
     def from_arrays(cls, m, **kw) -> "Mesh":
-        """From a workloads.MeshArrays."""
+        """From a workloads.MeshArrays (with its face distances, if it has any, unless
+        face_dist is given)."""
+        kw.setdefault("face_dist", getattr(m, "face_dist", None))
         return cls(m.face_cells, m.face_normal, m.face_area, m.cell_volume, n_cells=m.n_cells, **kw)
 
     @property

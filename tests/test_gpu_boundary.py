@@ -1,12 +1,13 @@
-"""GPU parity of meshes with boundary faces (inflow values, zero-gradient exterior) against the
-CPU oracle.
+"""GPU parity of meshes with boundary faces (inflow values, zero-gradient exterior) and of
+distance-weighted meshes against the CPU oracle.
 
 The boundary reading (a boundary face borders an exterior cell holding the inflow value where
 the flow enters, the interior cell's value otherwise) is pinned on the oracle in
 test_oracle_boundary.py.  Here the library runs it on the face path with the general kernel:
 one operator application is compared at 1e-13 of max|rhs| and whole runs at the 1e-10 max
 norm-relative error of the cell values, as for closed meshes.  The inflow arrays hold NaN on the
-rows the rule never reads (interior faces and outflow faces), so a stray read shows.
+rows the rule never reads (interior faces and outflow faces), so a stray read shows.  The
+distance weighting (Algorithm 1D / UNS ratios) is pinned in test_oracle_distances.py.
 """
 
 import numpy as np
@@ -49,6 +50,7 @@ def library(m, inflow, **kw):
     mesh = FL.Mesh.from_arrays(m, device=0, **kw)
     cp, fp = mesh.permutation()
     assert mesh.path == "face" and mesh.n_boundary == int((m.face_cells[:, 1] < 0).sum())
+    assert mesh.info.dist_weighted == (m.face_dist is not None)
     if inflow is not None:
         mesh.set_inflow(dev(rows_to_mesh(inflow, fp)))
     return mesh, cp, fp
@@ -157,4 +159,38 @@ def test_adjoint_and_algebraic_refuse_boundary_meshes():
     with pytest.raises(_lib.FluxLimError) as e:
         FL.Algebraic(mesh)
     assert e.value.status == unsupported
+    mesh.close()
+
+
+@pytest.mark.parametrize("case", ["periodic", "open"])
+@pytest.mark.parametrize("S", [1, 2])
+@pytest.mark.parametrize("lim", LIMS)
+def test_distance_weighted_apply_and_run(lim, S, case):
+    """A box stretched along x (cell widths 1 +- 0.5 sin), periodic or cut open along x with
+    inflow values: one application at 1e-13 and 10 SSP-RK3 steps at 1e-10 against the oracle
+    with the same face distances."""
+    open_axes = (0,) if case == "open" else ()
+    nat = W.stretched_box(10, 3, amp=0.5, open_axes=open_axes)
+    u_nat = W.velocity_open_box(nat)
+    th_nat = W.field_blob_step(10)
+    if S > 1:
+        th_nat = W.multi_scalar([th_nat + 0.2 * k for k in range(S)])
+    inflow_nat = W.inflow_values(nat, u_nat, S) if open_axes else None
+    m = W.renumber(nat, seed=12)
+    u = m.face_velocity_from_natural(u_nat)
+    th0 = m.cell_field_from_natural(th_nat)
+    inflow = None if inflow_nat is None else m.face_field_from_natural(inflow_nat)
+    dt = W.cfl_dt(m, u, 0.4)
+    mesh, cp, fp = library(m, inflow, reorder=True)
+    om = O.OracleMesh.from_arrays(m)
+    om.set_distances(m.face_dist)
+    om.set_inflow(inflow)
+    want = om.rhs(lim, th0, u)
+    ud = dev(rows_to_mesh(u, fp))
+    got = host(FL.convect_apply(mesh, lim, dev(rows_to_mesh(th0, cp)), ud))
+    assert np.abs(got[cp] - want).max() <= 1e-13 * np.abs(want).max()
+    want = om.run(lim, "ssprk3", dt, th0, u, 10)
+    th = dev(rows_to_mesh(th0, cp))
+    FL.rk_steps(mesh, lim, "ssprk3", dt, th, ud, 10)
+    assert nrel(host(th)[cp], want) <= RUN_TOL
     mesh.close()

@@ -242,6 +242,31 @@ def test_boundary_mesh_tables(reorder):
     mesh.close()
 
 
+def test_distance_weighted_tables():
+    """Unequal face distances scale each side weight by d_f / d_j (the general path); equal
+    distances build the unweighted tables (the fused path on a hex box); bad distances are
+    refused."""
+    m = W.stretched_box(6, 3, amp=0.5)
+    mesh = FL.Mesh.from_arrays(m, device=-1, reorder=True)
+    assert mesh.info.dist_weighted == 1 and mesh.path == "face" and mesh.info.general == 1
+    mesh.close()
+    same = FL.Mesh.from_arrays(W.periodic_box(6, 3), device=-1,
+                               face_dist=np.full(3 * 216, 1.0 / 6))
+    assert same.info.dist_weighted == 0 and same.path == "fused"
+    same.close()
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        d = m.face_dist.copy()
+        d[4] = bad
+        with pytest.raises(_lib.FluxLimError) as e:
+            FL.Mesh.from_arrays(m, device=-1, face_dist=d)
+        assert e.value.status == -1
+    weighted = FL.Mesh.from_arrays(m, device=-1)
+    with pytest.raises(_lib.FluxLimError) as e:
+        FL.Algebraic(weighted)
+    assert e.value.status == -3
+    weighted.close()
+
+
 def test_algebraic_chain_refuses_boundary_meshes():
     mesh = FL.Mesh.from_arrays(W.open_box(5, 3, (2,)), device=-1)
     with pytest.raises(_lib.FluxLimError) as e:
