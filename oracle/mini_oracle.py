@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (tiny meshes).  This is a second, independent CPU path next to the
 gather oracle in oracle.c: it builds the incidence, degree, shift, adjacency and normal matrices
-of Section 2 and evaluates the reconstruction of Algorithm 3 and the update of Algorithm 4 as a
-chain of sparse matrix-vector products and pointwise operations, in the paper's order.
+of Section 2 and evaluates the face reconstruction theta_f = Pi theta + F(r) d_u and the update
+theta + dt M U(u) theta_f of Section 3.1 with those matrices (sparse products and pointwise
+operations), a check of the operator equations that Algorithms 3 and 4 evaluate.
 
 Readings (where the printed formulas disagree with each other or with the printed example):
   * oriented incidence E[f, nbr] = +1, E[f, own] = -1, so E theta is the difference along the
@@ -128,19 +129,18 @@ class AlgebraicMesh:
                    dim=max(m.dim, 1))
 
     def face_values(self, limiter: str, theta: np.ndarray, u: np.ndarray) -> np.ndarray:
-        """Algorithm 3 (one scalar), with the upstream-difference reading of the module header."""
-        q = np.where(u > 0, 1.0, -1.0)  # signxty
-        d_u = self.E @ theta  # SpMV
-        d_u = q * d_u  # signxty
-        r = self.T @ theta  # SpMV
-        r = q * r  # signxty
-        r = r - self.S @ theta  # SpMV (and subtraction)
-        zero = d_u == 0.0
-        r = np.where(zero, 0.0, r / np.where(zero, 1.0, d_u))  # axdy
-        F = 0.5 * (psi_np(limiter, r) - 1.0)
-        theta_f = np.where(zero, 0.0, F * d_u)  # superbeexty-like kbin
-        theta_f = theta_f + self.Pi @ theta  # SpMV
-        return theta_f
+        """theta_f = Pi theta + F(r) o d_u with F = (psi - 1)/2 (Section 3.1 and Table 1), one
+        scalar: the face interpolation of Section 2's shift plus the limited correction, from
+        d_u = Q E theta (the face-difference equation), d_U from upstream_difference and
+        r = d_U / d_u (the gradient-ratio equation; r = 0 where d_u = 0, where the correction
+        vanishes whatever r is)."""
+        q = np.where(u > 0, 1.0, -1.0)
+        d_u = q * (self.E @ theta)
+        d_U = self.upstream_difference(theta, u)
+        flat = d_u == 0.0
+        r = np.where(flat, 0.0, d_U / np.where(flat, 1.0, d_u))
+        correction = np.where(flat, 0.0, 0.5 * (psi_np(limiter, r) - 1.0) * d_u)
+        return correction + self.Pi @ theta
 
     def upstream_difference(self, theta: np.ndarray, u: np.ndarray) -> np.ndarray:
         q = np.where(u > 0, 1.0, -1.0)

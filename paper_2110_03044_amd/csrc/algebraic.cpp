@@ -184,18 +184,31 @@ AlgWork carve(const fl_algebraic *g, void *work) {
     return w;
 }
 
-// Algorithm 3 into w.tf (w.d holds d_u, w.r the ratio).
+// theta_f = Pi theta + F(r) o d_u (Section 3.1): the face interpolation of Section 2's shift
+// plus the limited correction along the flow, from the two velocity-oriented differences
+//   d_U = (Q UUD + OUD) theta   (the simplified upstream-difference equation; w.r)
+//   d_u = Q D theta             (the face-difference equation; w.d)
+// and r = d_U / d_u (the gradient-ratio equation), each product by the diagonal Q or by a
+// pointwise function one kbin launch.  Every term is one sparse product or one pointwise pass
+// over a face vector, so the chain is the eight launches of Algorithm 3 in the order its data
+// dependencies allow.
 hipError_t face_values(const fl_algebraic *g, int lim, const double *th, const double *u,
                        const AlgWork &w, double *tf, hipStream_t st) {
     const int64_t nf = g->mesh->h.nf;
-    hipError_t e = launch_ell_spmv(g->m[FL_ALG_D], th, w.d, 0, st);                  // D theta
-    if (e == hipSuccess) e = launch_kbin(KBIN_SIGNXTY, lim, nf, u, w.d, w.d, st);     // Q d_u
-    if (e == hipSuccess) e = launch_ell_spmv(g->m[FL_ALG_UUD], th, w.r, 0, st);      // UUD theta
-    if (e == hipSuccess) e = launch_kbin(KBIN_SIGNXTY, lim, nf, u, w.r, w.r, st);     // Q r
-    if (e == hipSuccess) e = launch_ell_spmv(g->m[FL_ALG_OUD], th, w.r, 1, st);      // + OUD theta
-    if (e == hipSuccess) e = launch_kbin(KBIN_AXDY, lim, nf, w.d, w.r, w.r, st);      // r / d_u
-    if (e == hipSuccess) e = launch_kbin(KBIN_LIMXTY, lim, nf, w.r, w.d, tf, st);     // F(r) d_u
-    if (e == hipSuccess) e = launch_ell_spmv(g->m[FL_ALG_PI], th, tf, 1, st);        // + Pi theta
+    auto spmv = [&](int which, double *out, int accumulate) {
+        return launch_ell_spmv(g->m[which], th, out, accumulate, st);
+    };
+    auto kbin = [&](int op, const double *x, const double *y, double *out) {
+        return launch_kbin(op, lim, nf, x, y, out, st);
+    };
+    hipError_t e = spmv(FL_ALG_UUD, w.r, 0);
+    if (e == hipSuccess) e = kbin(KBIN_SIGNXTY, u, w.r, w.r);
+    if (e == hipSuccess) e = spmv(FL_ALG_OUD, w.r, 1);
+    if (e == hipSuccess) e = spmv(FL_ALG_D, w.d, 0);
+    if (e == hipSuccess) e = kbin(KBIN_SIGNXTY, u, w.d, w.d);
+    if (e == hipSuccess) e = kbin(KBIN_AXDY, w.d, w.r, w.r);
+    if (e == hipSuccess) e = kbin(KBIN_LIMXTY, w.r, w.d, tf);
+    if (e == hipSuccess) e = spmv(FL_ALG_PI, tf, 1);
     return e;
 }
 
