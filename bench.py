@@ -87,13 +87,14 @@ def lds_stage_bytes(C, K, S, stage, halo_total):
     return b
 
 
-def lds_fwd_stage_bytes(C, K, S, stage, halo_total):
-    """Compulsory bytes of one forward-rate LDS stage launch (lattice meshes): local slot indices
-    (4 B per slot), the per-call rates of each cell's forward faces (8 B per face: K/2 per cell),
-    the tile halo lists (4 B cell + 1 B pair per entry), theta_s read once, theta_n read once
-    (stages 2, 3) and the output written once.  Halo values and halo rates are other tiles'
+def lds_fwd_stage_bytes(C, K, S, stage, halo_total, halo_nexts):
+    """Compulsory bytes of one forward-rate LDS stage launch (lattice meshes): the neighbours'
+    16-bit local indices (2 B per slot), the per-call rates of each cell's forward faces (8 B per
+    face: K/2 per cell), the tile halo lists (4 B per entry: cell and pair packed) and the next
+    indices of the halo entries reached as neighbours (2 B each), theta_s read once, theta_n read
+    once (stages 2, 3) and the output written once.  Halo values and halo rates are other tiles'
     cells' data: counted once, with their own tile."""
-    b = C * K * 4 + C * (K // 2) * 8 + 5 * halo_total + C * S * 8 * 2
+    b = C * K * 2 + C * (K // 2) * 8 + 4 * halo_total + 2 * halo_nexts + C * S * 8 * 2
     if stage > 0:
         b += C * S * 8
     return b
@@ -488,7 +489,9 @@ def main():
                    repeats=repeats, aligned=bool(info.aligned),
                    K=int(info.max_degree), th=th, u=u, max_halo=int(info.max_halo),
                    tile_cells=int(info.tile_cells),
-                   halo_total=int(info.halo_total))
+                   halo_total=int(info.halo_total), compact=bool(info.compact),
+                   max_rated=int(info.max_rated), max_nexts=int(info.max_nexts),
+                   halo_nexts=int(info.halo_nexts))
         return res
 
     # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the fused
@@ -554,12 +557,16 @@ def main():
             sv = bool(args.slot_velocity) and args.steps >= 2
             lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
                 (r["tile_cells"] + r["max_halo"]) * min(S, 2) * 8 <= 64 * 1024
-            fwd = lds and r["aligned"] and bool(args.fwd_rates) and \
-                ((r["tile_cells"] + r["max_halo"] + 1) * min(S, 2)
-                 + K // 2 * r["tile_cells"] + r["max_halo"] + 1) * 8 <= 64 * 1024
+            # the library's own choice (lds_fwd_bytes): compact tables and a staged tile of at
+            # most 32 KiB
+            words = K // 2 * r["tile_cells"] * 4 + (r["max_nexts"] + 1) * 2
+            fwd = lds and r["aligned"] and r["compact"] and bool(args.fwd_rates) and \
+                ((r["tile_cells"] + r["max_halo"] + 1) * min(S, 2) + K // 2 * r["tile_cells"]
+                 + r["max_rated"] + 1) * 8 + (words + 7) // 8 * 8 <= 32 * 1024
             if fwd:
                 kname = "fused_stage_lds_fwd_kernel"
-                bytes_per_step = sum(lds_fwd_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))
+                bytes_per_step = sum(lds_fwd_stage_bytes(C, K, S, s, r["halo_total"],
+                                                         r["halo_nexts"]) for s in range(3))
             elif lds:
                 kname = "fused_stage_lds_kernel"
                 bytes_per_step = sum(lds_stage_bytes(C, K, S, s, r["halo_total"]) for s in range(3))

@@ -118,6 +118,12 @@ typedef struct fl_mesh_info_t {
                             /* meshes; the forward-rate stages, FL_OPT_FWD_RATES, apply)      */
     int32_t dist_weighted;  /* 1 if unequal face distances weight the upstream difference    */
     int64_t n_boundary;     /* boundary faces (one cell: nbr = -1)                           */
+    int32_t compact;        /* 1 if the forward-rate stage's compact slot tables exist        */
+    int32_t max_rated;      /* most leading halo entries of a tile whose rate the forward-rate */
+                            /* stage stages (neighbours across backward slots), -1 if none   */
+    int32_t max_nexts;      /* most leading halo entries of a tile whose next index it stages */
+    int32_t reserved;
+    int64_t halo_nexts;     /* those entries summed over the tiles                           */
 } fl_mesh_info_t;
 
 /* Checks an incidence against the mesh model without a GPU (Section 2).  face_cells: host

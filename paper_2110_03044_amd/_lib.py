@@ -38,7 +38,10 @@ class MeshInfo(ctypes.Structure):
                 ("tile_cells", ctypes.c_int32), ("max_halo", ctypes.c_int32),
                 ("halo_total", ctypes.c_int64), ("general", ctypes.c_int32),
                 ("max_side", ctypes.c_int32), ("aligned", ctypes.c_int32),
-                ("dist_weighted", ctypes.c_int32), ("n_boundary", ctypes.c_int64)]
+                ("dist_weighted", ctypes.c_int32), ("n_boundary", ctypes.c_int64),
+                ("compact", ctypes.c_int32), ("max_rated", ctypes.c_int32),
+                ("max_nexts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("halo_nexts", ctypes.c_int64)]
 
 
 class AlgebraicInfo(ctypes.Structure):

@@ -70,7 +70,7 @@ void free_device(fl_mesh *m) {
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
                     m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local, m->d_side_ptr,
                     m->d_side_cell, m->d_side_w, m->d_adj_fr, m->d_halo_pair,
-                    m->d_halo_nrate};
+                    m->d_halo_nrate, m->d_slot_nb, m->d_halo_pk, m->d_halo_next};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
@@ -82,6 +82,9 @@ void free_device(fl_mesh *m) {
     m->d_slot_local = nullptr;
     m->d_halo_pair = nullptr;
     m->d_halo_nrate = nullptr;
+    m->d_slot_nb = nullptr;
+    m->d_halo_pk = nullptr;
+    m->d_halo_next = nullptr;
     m->d_side_ptr = m->d_side_cell = nullptr;
     m->d_side_w = nullptr;
     m->d_area = m->d_vol = nullptr;
@@ -372,6 +375,18 @@ fl_status fl_mesh_create_dist(int64_t n_cells, int64_t n_faces, const int32_t *f
                             st = upload(&m->d_halo_nrate, h.halo_nrate.data(), h.halo_nrate.size(),
                                         B, "tile halo rate counts");
                     }
+                    if (st == FL_OK && !h.slot_nb.empty()) {
+                        st = upload(&m->d_slot_nb, h.slot_nb.data(), h.slot_nb.size(), B,
+                                    "compact slot words");
+                        std::vector<int32_t> pk(h.halo_pk);
+                        pk.resize(h.halo_pk.size() + kHaloPad, 0);
+                        if (st == FL_OK)
+                            st = upload(&m->d_halo_pk, pk.data(), pk.size(), B, "packed tile halos");
+                        std::vector<uint16_t> nx(h.halo_next);
+                        nx.resize(h.halo_next.size() + kHaloPad, 0);
+                        if (st == FL_OK)
+                            st = upload(&m->d_halo_next, nx.data(), nx.size(), B, "tile halo next");
+                    }
                 }
             }
             if (st == FL_OK && !h.uni_area) st = upload(&m->d_area, h.area.data(), h.area.size(), B, "areas");
@@ -431,6 +446,13 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
     info->aligned = m->h.aligned_slots ? 1 : 0;
     info->dist_weighted = m->h.dist_weighted ? 1 : 0;
     info->n_boundary = m->h.n_boundary;
+    info->compact = m->d_slot_nb || !m->h.slot_nb.empty() ? 1 : 0;
+    info->max_rated = m->h.max_nrate0;
+    info->max_nexts = m->h.max_nrate;
+    info->reserved = 0;
+    int64_t nx = 0;
+    for (size_t t = 1; t < m->h.halo_nrate.size(); t += 2) nx += m->h.halo_nrate[t];
+    info->halo_nexts = nx;
     return FL_OK;
 }
 

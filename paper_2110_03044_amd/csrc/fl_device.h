@@ -419,19 +419,27 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
 // face), read from the tile's LDS copy of the forward rates or, for a neighbour outside the
 // tile, from the LDS copy of the halo entries' rates (a halo entry is a (cell, pair) reference;
 // the leading ones, the neighbours across backward slots, carry that cell's forward rate of that
-// pair, gathered with its theta): half the rate
-// bytes of fused_tile<RATES>, the same rates w_k (a negation is exact), so the same bits.  The
-// tile's forward rates are loaded between the theta gathers and the slot words, so that their
-// LDS stores wait only for the former and the slot words stay in flight across the barrier.
-// LDS: fused_tile's chunk area, then P * kTileCells doubles of tile rates at rbase, then one
-// double per halo entry.
+// pair, gathered with its theta): half the rate bytes of fused_tile<RATES>, the same rates w_k
+// (a negation is exact), so the same bits.
+// Compact tables: a cell reads only its neighbours' 16-bit local indices (slot_nb, one word per
+// pair); the far cell beyond a neighbour is that neighbour's own neighbour in the same direction,
+// read from the tile's LDS copy of the words or, for a halo neighbour, from the LDS copy of the
+// halo's next indices (halo_next, the leading halo_nrate[2 tile + 1] entries); halo cells and
+// their pairs come packed in one word (halo_pk).  The tile's rates and words are loaded between
+// the theta gathers and the LDS stores, so that the stores wait only for the gathers and the
+// rest stays in flight across the barrier.
+// LDS (doubles): the chunk area [0, rbase); tile rates [P][kTileCells] at rbase, then one rate
+// per leading halo entry (halo_nrate[2 tile] of them, and a spare); at nbase the tile's words
+// (uint32 [P][kTileCells]), then the halo's next indices (uint16, halo_nrate[2 tile + 1] and a
+// spare).
 template <int S, int P, bool PRE = true>
 __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double *lds, int rbase,
-                                               const int32_t *__restrict__ halo_ptr,
+                                               int nbase, const int32_t *__restrict__ halo_ptr,
                                                const int32_t *__restrict__ halo,
-                                               const uint8_t *__restrict__ halo_pair,
+                                               const int32_t *__restrict__ halo_pk,
+                                               const uint16_t *__restrict__ halo_next,
                                                const int32_t *__restrict__ halo_nrate,
-                                               const uint32_t *__restrict__ slot_local,
+                                               const uint32_t *__restrict__ slot_nb,
                                                const double *__restrict__ rf, bool has_area,
                                                double area0, const double *__restrict__ vol,
                                                double vol0, const double *__restrict__ ts,
@@ -440,37 +448,41 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
                                                double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
     constexpr int CS = S >= 2 ? 2 : 1;
+    constexpr uint32_t T = kTileCells;
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
     const int nt = left < kTileCells ? (int)left : kTileCells;
     const int h0 = halo_ptr[tile], nh = halo_ptr[tile + 1] - h0;
-    // the leading halo entries (neighbours across backward slots) need their rate; the other
-    // lanes read their own cell's first rate instead (a line the tile reads anyway)
-    const int nr = halo_nrate[2 * tile];
+    // the leading halo entries (neighbours across backward slots) need their rate, the leading
+    // nx (also neighbours across forward slots) their next index; the other lanes read their own
+    // cell's first rate and the halo's first index instead (lines the tile reads anyway)
+    const int nr = halo_nrate[2 * tile], nx = halo_nrate[2 * tile + 1];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int64_t c = c0 + (tid < nt ? tid : 0);
     double tv[CS], hv[kHaloAhead][CS], hr[kHaloAhead];
+    uint32_t hn[kHaloAhead];
 #pragma unroll
     for (int s = 0; s < CS; ++s) tv[s] = ts[c * S + s];
 #pragma unroll
     for (int j = 0; j < kHaloAhead; ++j) {
         const int i = tid + j * nthr;
         const int ie = i < nh ? i : 0;  // (the arrays are padded: entry 0 exists)
-        const int64_t h = halo[h0 + ie];
-        const int64_t pr = halo_pair[h0 + ie];
+        const uint32_t hw = (uint32_t)halo_pk[h0 + ie];
+        const int64_t h = hw & 0x3fffffffu;
+        const int64_t pr = hw >> 30;
         const int64_t g = i < nh ? h : c;
 #pragma unroll
         for (int s = 0; s < CS; ++s) hv[j][s] = ts[g * S + s];
         hr[j] = rf[i < nr ? pr * nc + h : c];
+        hn[j] = halo_next[h0 + (i < nx ? i : 0)];
     }
     __builtin_amdgcn_sched_barrier(0);
     double rfv[P];
+    uint32_t l[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) rfv[p] = rf[(int64_t)p * nc + c];
-    __builtin_amdgcn_sched_barrier(0);
-    uint32_t l[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) l[k] = slot_local[(int64_t)k * nc + c];
+    for (int p = 0; p < P; ++p) l[p] = slot_nb[(int64_t)p * nc + c];
     double tnv[CS];
     if constexpr (PRE) {
         const double *tnp = tn ? tn : ts;
@@ -478,6 +490,10 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
         for (int s = 0; s < CS; ++s) tnv[s] = tnp[c * S + s];
     }
     __builtin_amdgcn_sched_barrier(0);
+    double *rt = lds + rbase;                   // tile forward rates [P][kTileCells]
+    double *rh = lds + rbase + P * kTileCells;  // rates of the leading halo entries
+    uint32_t *nw = reinterpret_cast<uint32_t *>(lds + nbase);  // tile words [P][kTileCells]
+    uint16_t *nxt = reinterpret_cast<uint16_t *>(nw + P * kTileCells);
 #pragma unroll
     for (int s = 0; s < CS; ++s) lds[tid * CS + s] = tv[s];
 #pragma unroll
@@ -486,20 +502,21 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
         const int e = kTileCells + (i < nh ? i : nh);
 #pragma unroll
         for (int s = 0; s < CS; ++s) lds[e * CS + s] = hv[j][s];
+        rh[i < nr ? i : nr] = hr[j];
+        nxt[i < nx ? i : nx] = (uint16_t)hn[j];
     }
 #pragma unroll
-    for (int p = 0; p < P; ++p) lds[rbase + p * kTileCells + tid] = rfv[p];
-    double *rh = lds + rbase + P * kTileCells;
-#pragma unroll
-    for (int j = 0; j < kHaloAhead; ++j) {
-        const int i = tid + j * nthr;
-        rh[i < nh ? i : nh] = hr[j];
+    for (int p = 0; p < P; ++p) {
+        rt[p * kTileCells + tid] = rfv[p];
+        nw[p * kTileCells + tid] = l[p];
     }
     for (int i = tid + kHaloAhead * nthr; i < nh; i += nthr) {
-        const int64_t g = halo[h0 + i];
+        const uint32_t hw = (uint32_t)halo_pk[h0 + i];
+        const int64_t g = hw & 0x3fffffffu;
 #pragma unroll
         for (int s = 0; s < CS; ++s) lds[(kTileCells + i) * CS + s] = ts[g * S + s];
-        if (i < nr) rh[i] = rf[(int64_t)halo_pair[h0 + i] * nc + g];
+        if (i < nr) rh[i] = rf[(int64_t)(hw >> 30) * nc + g];
+        if (i < nx) nxt[i] = halo_next[h0 + i];
     }
     __syncthreads();
     const bool active = tid < nt;
@@ -509,16 +526,16 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
     double V = vol0;
     if (active) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            nb[k] = l[k] & 0xffffu;
-            gf[k] = l[k] >> 16;
-        }
-#pragma unroll
         for (int p = 0; p < P; ++p) {
+            const uint32_t n0 = l[p] & 0xffffu, n1 = l[p] >> 16;
+            nb[2 * p] = n0;
+            nb[2 * p + 1] = n1;
+            // the far cell beyond a neighbour: the neighbour's own neighbour in that direction
+            gf[2 * p] = n0 < T ? (nw[p * kTileCells + n0] & 0xffffu) : nxt[n0 - T];
+            gf[2 * p + 1] = n1 < T ? (nw[p * kTileCells + n1] >> 16) : nxt[n1 - T];
             const double v = rfv[p] * us;
             w[2 * p] = has_area ? v : area0 * v;
-            const int64_t n = nb[2 * p + 1];
-            const double r = n < kTileCells ? lds[rbase + p * kTileCells + n] : rh[n - kTileCells];
+            const double r = n1 < T ? rt[p * kTileCells + n1] : rh[n1 - T];
             const double vb = (-r) * us;
             w[2 * p + 1] = has_area ? vb : area0 * vb;
         }

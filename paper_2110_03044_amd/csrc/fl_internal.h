@@ -62,6 +62,17 @@ struct HostTables {
     std::vector<int32_t> halo_nrate;
     int32_t max_halo = -1;           // -1: no tile tables (local indices would not fit 16 bits)
     int32_t max_nrate = -1;          // largest halo_nrate[2 tile + 1] (-1: not aligned)
+    int32_t max_nrate0 = -1;         // largest halo_nrate[2 tile]
+    // Compact forward-stage tables (aligned slots, where the far cell of every slot is the
+    // neighbour's neighbour in the same direction and every halo entry reached as a neighbour
+    // is reached along one direction; empty otherwise):
+    //   slot_nb[p][c]  = local index of the neighbour across slot 2p | across slot 2p+1 << 16;
+    //   halo_pk[i]     = halo[i] | halo_pair[i] << 30 (cells < 2^30);
+    //   halo_next[i]   = for an entry reached as the neighbour across slot k of a tile cell, the
+    //                    local index of the cell beyond it in that direction (0xffff if none).
+    std::vector<uint32_t> slot_nb;
+    std::vector<int32_t> halo_pk;
+    std::vector<uint16_t> halo_next;
     int64_t n_boundary = 0;          // faces with one cell (nbr == -1): general face path only
     bool dist_weighted = false;      // side weights scaled by face distance ratios d_f / d_j
     // Numbering maps user -> mesh (empty = identity).
@@ -106,6 +117,9 @@ struct fl_mesh {
     int32_t *d_halo = nullptr;
     uint32_t *d_slot_local = nullptr;
     uint8_t *d_halo_pair = nullptr;  // [halo entries + pad] pair of each halo entry (aligned slots)
+    uint32_t *d_slot_nb = nullptr;   // compact forward-stage tables (HostTables)
+    int32_t *d_halo_pk = nullptr;    // [halo entries + pad]
+    uint16_t *d_halo_next = nullptr; // [halo entries + pad]
     int32_t *d_halo_nrate = nullptr; // [2 * tiles] halo entries whose rates the stages need
     int32_t *d_adj_fr = nullptr;   // [2P][C][2] LDS adjoint: slot face, the neighbour's face
                                    // opposite it (both with own bits)

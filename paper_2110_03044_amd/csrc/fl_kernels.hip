@@ -281,22 +281,23 @@ __global__ __launch_bounds__(kBlock) void slot_rate_fwd_kernel(int64_t nc,
     for (int p = 0; p < P; ++p) rf[(int64_t)p * nc + c] = (fw[p] >> 31) ? x[p] : -x[p];
 }
 
-// The LDS-staged stage reading forward rates only (fused_tile_fwd); dynamic LDS of rbase +
-// P * kTileCells doubles.
+// The LDS-staged stage reading forward rates and the compact slot tables (fused_tile_fwd);
+// dynamic LDS as lds_fwd_bytes.
 template <int S, int P>
 __global__ __launch_bounds__(kBlock) void fused_stage_lds_fwd_kernel(
     int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
-    const uint8_t *__restrict__ halo_pair, const int32_t *__restrict__ halo_nrate,
-    const uint32_t *__restrict__ slot_local, const double *__restrict__ rf, int has_area,
-    double area0, const double *__restrict__ vol,
+    const int32_t *__restrict__ halo_pk, const uint16_t *__restrict__ halo_next,
+    const int32_t *__restrict__ halo_nrate, const uint32_t *__restrict__ slot_nb,
+    const double *__restrict__ rf, int has_area, double area0, const double *__restrict__ vol,
     double vol0, const double *__restrict__ ts, const double *__restrict__ tn, double a,
     double b, double dt, int mode, int lim, double *__restrict__ out, double us, int rbase,
-    int remap) {
+    int nbase, int remap) {
     extern __shared__ double lds[];
     const int64_t tile = block_id(remap);
     if (tile * kTileCells >= nc) return;
-    fused_tile_fwd<S, P>(nc, tile, lds, rbase, halo_ptr, halo, halo_pair, halo_nrate, slot_local, rf,
-                             has_area != 0, area0, vol, vol0, ts, tn, a, b, dt, mode, lim, out, us);
+    fused_tile_fwd<S, P>(nc, tile, lds, rbase, nbase, halo_ptr, halo, halo_pk, halo_next,
+                         halo_nrate, slot_nb, rf, has_area != 0, area0, vol, vol0, ts, tn, a, b,
+                         dt, mode, lim, out, us);
 }
 
 // One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
@@ -536,10 +537,18 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
     return hipGetLastError();
 }
 
+// Offset (in doubles) of the tile words in the forward-rate stage's LDS.
+static size_t fwd_nbase(const fl_mesh *m, int S) {
+    return lds_stage_bytes(m, S) / sizeof(double) + (size_t)m->h.pairs * kTileCells +
+           m->h.max_nrate0 + 1;
+}
+
 size_t lds_fwd_bytes(const fl_mesh *m, int S) {
     const size_t lds = lds_stage_bytes(m, S);
-    if (lds == 0 || !m->h.aligned_slots || !m->d_halo_pair || !m->d_halo_nrate) return 0;
-    const size_t b = lds + ((size_t)m->h.pairs * kTileCells + m->h.max_halo + 1) * sizeof(double);
+    if (lds == 0 || !m->h.aligned_slots || !m->d_slot_nb || !m->d_halo_nrate) return 0;
+    const size_t words = (size_t)m->h.pairs * kTileCells * sizeof(uint32_t) +
+                         ((size_t)m->h.max_nrate + 1) * sizeof(uint16_t);
+    const size_t b = fwd_nbase(m, S) * sizeof(double) + (words + 7) / 8 * 8;
     // large halos (meshes not renumbered for locality) gain nothing from the rate staging and
     // would cost occupancy: the per-slot rates serve them
     return b <= kMaxFwdLds ? b : 0;
@@ -568,13 +577,14 @@ hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *
     const size_t lds = lds_fwd_bytes(m, S);
     if (lds == 0 || lds > kMaxStageLds || !rf) return hipErrorInvalidValue;
     const int rbase = (int)(lds_stage_bytes(m, S) / sizeof(double));
+    const int nbase = (int)fwd_nbase(m, S);
     const Grid g = grid_for(m->h.nc, g_remap);
 #define FL_FUSED_FWD(P)                                                                          \
     FL_DISPATCH_S(S, (dev::fused_stage_lds_fwd_kernel<kS, P><<<g.blocks, dev::kBlock, lds, st>>>( \
-                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_halo_nrate,      \
-                         m->d_slot_local, rf,                                                     \
-                         m->d_area ? 1 : 0, m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b, dt,    \
-                         mode, lim, out, us, rbase, g.remap)))
+                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_halo_pk, m->d_halo_next,         \
+                         m->d_halo_nrate, m->d_slot_nb, rf, m->d_area ? 1 : 0, m->h.area0,        \
+                         m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out, us, rbase,        \
+                         nbase, g.remap)))
     switch (m->h.pairs) {
         case 1: FL_FUSED_FWD(1); break;
         case 2: FL_FUSED_FWD(2); break;

@@ -621,6 +621,46 @@ void build_slots(HostTables &t, const Csr &cs, const std::vector<int32_t> &opp) 
     t.aligned_slots = aligned;
 }
 
+// The compact forward-stage tables (see HostTables): built from the local slot words where they
+// describe them exactly, left empty otherwise.
+void build_compact(HostTables &t) {
+    const int64_t nc = t.nc, P = t.pairs, K = 2 * P;
+    const int64_t ntiles = (nc + kTileCells - 1) / kTileCells;
+    if (nc >= (int64_t(1) << 30)) return;
+    std::vector<uint16_t> next(t.halo.size(), 0xffff);
+    bool ok = true;
+#pragma omp parallel for schedule(dynamic, 64) reduction(&& : ok)
+    for (int64_t tile = 0; tile < ntiles; ++tile) {
+        const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
+        const int64_t h0 = t.halo_ptr[tile];
+        for (int64_t k = 0; k < K && ok; ++k)
+            for (int64_t c = c0; c < c1; ++c) {
+                const uint32_t w = t.slot_local[k * nc + c];
+                const uint32_t n = w & 0xffffu, g = w >> 16;
+                if (n < (uint32_t)kTileCells) {
+                    // the far cell must be the tile neighbour's own neighbour across slot k
+                    if ((t.slot_local[k * nc + c0 + n] & 0xffffu) != g) ok = false;
+                } else {
+                    uint16_t &e = next[h0 + n - kTileCells];
+                    if (e == 0xffff) e = (uint16_t)g;
+                    else if (e != g) ok = false;
+                }
+            }
+    }
+    if (!ok) return;
+    t.slot_nb.resize((size_t)P * nc);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c)
+        for (int64_t p = 0; p < P; ++p)
+            t.slot_nb[p * nc + c] = (t.slot_local[2 * p * nc + c] & 0xffffu) |
+                                    (t.slot_local[(2 * p + 1) * nc + c] & 0xffffu) << 16;
+    t.halo_pk.resize(t.halo.size());
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < (int64_t)t.halo.size(); ++i)
+        t.halo_pk[i] = (int32_t)((uint32_t)t.halo[i] | (uint32_t)t.halo_pair[i] << 30);
+    t.halo_next.swap(next);
+}
+
 // Tile halos for the LDS-staged fused stage: for each run of kTileCells consecutive cells, the
 // sorted list of cells outside the run that its slots name (neighbours and far-upwind cells),
 // and every slot's neighbour and far cell as local indices into [tile cells | halo].
@@ -643,9 +683,9 @@ void build_tiles(HostTables &t) {
     std::vector<uint8_t> halo_pair;
     std::vector<uint32_t> local((size_t)K * nc, 0);
     std::vector<std::vector<int64_t>> tile_refs(ntiles);
-    int32_t max_halo = 0, max_nrate = 0;
+    int32_t max_halo = 0, max_nrate = 0, max_nrate0 = 0;
     bool fits = true;
-#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo, max_nrate) \
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_halo, max_nrate, max_nrate0) \
     reduction(&& : fits)
     for (int64_t tile = 0; tile < ntiles; ++tile) {
         const int64_t c0 = tile * kTileCells, c1 = std::min(nc, c0 + kTileCells);
@@ -682,6 +722,7 @@ void build_tiles(HostTables &t) {
             nrate[2 * tile] = n0;
             nrate[2 * tile + 1] = n01;
             max_nrate = std::max(max_nrate, n01);
+            max_nrate0 = std::max(max_nrate0, n0);
         }
         // position of each (cell, pair) in the ordered halo
         std::vector<std::pair<int64_t, int32_t>> pos(refs.size());
@@ -725,6 +766,8 @@ void build_tiles(HostTables &t) {
     t.slot_local.swap(local);
     t.max_halo = max_halo;
     t.max_nrate = by_pair ? max_nrate : -1;
+    t.max_nrate0 = by_pair ? max_nrate0 : -1;
+    if (by_pair) build_compact(t);
 }
 
 }  // namespace

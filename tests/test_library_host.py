@@ -267,6 +267,23 @@ def test_distance_weighted_tables():
     weighted.close()
 
 
+def test_compact_forward_tables_on_lattice_meshes():
+    """A Morton-ordered periodic box gets the compact forward-stage tables: every tile is an
+    8x8x4 brick, so 128 leading halo entries carry a rate (the neighbours across backward slots)
+    and 384 a next index (also the neighbours across forward slots and the far cells beyond the
+    backward ones)."""
+    m = W.renumber(W.periodic_box(16, 3), seed=6)
+    mesh = FL.Mesh.from_arrays(m, device=-1, reorder=True)
+    i = mesh.info
+    assert i.compact == 1 and i.aligned == 1 and i.max_halo == 512
+    assert i.max_rated == 128 and i.max_nexts == 384
+    assert i.halo_nexts == 384 * (m.n_cells // 256)
+    mesh.close()
+    line = FL.Mesh.from_arrays(W.periodic_box(40, 1), device=-1, reorder=True)
+    assert line.info.compact == 1
+    line.close()
+
+
 def test_algebraic_chain_refuses_boundary_meshes():
     mesh = FL.Mesh.from_arrays(W.open_box(5, 3, (2,)), device=-1)
     with pytest.raises(_lib.FluxLimError) as e:
