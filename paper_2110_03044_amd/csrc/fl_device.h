@@ -55,20 +55,46 @@ __device__ __forceinline__ double psi(int lim, double r) {
     }
 }
 
+// The limited correction psi(r) b / 2 of the Sweby form, r = a / b (a = d_U, b = d_u != 0),
+// written so that the limiter needs no division where its form allows: for r > 0, with
+// A = |a|, B = |b| and s the sign of b (r = A / B), psi(r) B is min(A, B) for minmod,
+// max(min(B, 2A), min(A, 2B)) for superbee and min(2A, B/4 + 3A/4, 4B) for SMART, and
+// psi(r) b / 2 = a b / (a + b) for van Leer; all of them vanish for r <= 0.  Van Albada gives
+// a b (a + b) / (2 (a^2 + b^2)) for every r (one reciprocal; the ratio where a^2 + b^2 would
+// under- or overflow).  Each form tends to psi(+-inf) b / 2 as |r| grows, as the ratio form does
+// past |r| = 1e18.
+__device__ __forceinline__ double limited_half(int lim, double a, double b) {
+    const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);  // r > 0
+    const double A = fabs(a), B = fabs(b);
+    const double s = b > 0.0 ? 0.5 : -0.5;
+    switch (lim) {
+        case FL_MINMOD: return same ? s * fmin(A, B) : 0.0;
+        case FL_SUPERBEE: return same ? s * fmax(fmin(B, 2.0 * A), fmin(A, 2.0 * B)) : 0.0;
+        case FL_SMART: return same ? s * fmin(fmin(2.0 * A, 0.25 * B + 0.75 * A), 4.0 * B) : 0.0;
+        case FL_VANLEER: return same ? a * (b / (a + b)) : 0.0;
+        case FL_VANALBADA: {
+            const double q = a * a + b * b;
+            if (q >= 1e-280 && q <= 1e280) return 0.5 * (a * b) * (a + b) / q;
+            return 0.5 * psi(lim, a / b) * b;
+        }
+        case FL_CENTRAL: return 0.5 * b;
+        default: return 0.0;
+    }
+}
+
 // Limited face value of the Sweby form from the upwind, downwind and far-upwind values:
 // theta_C + psi(r) (theta_D - theta_C) / 2, r = (theta_C - theta_U) / (theta_D - theta_C).
 __device__ __forceinline__ double face_value(int lim, double tC, double tD, double tU) {
     const double du = tD - tC;
     if (lim == FL_UPWIND || du == 0.0) return tC;
-    const double r = (tC - tU) / du;
-    return tC + 0.5 * psi(lim, r) * du;
+    return tC + limited_half(lim, tC - tU, du);
 }
 
 // The same from the differences themselves, for cells whose upstream difference projects on
 // several faces: d_U = sum_j w_j (theta_C - theta_j), d_u = theta_D - theta_C.
 __device__ __forceinline__ double face_value_d(int lim, double tC, double du, double dU) {
     if (lim == FL_UPWIND || du == 0.0) return tC;
-    return tC + 0.5 * psi(lim, dU / du) * du;
+    return tC + limited_half(lim, dU, du);
 }
 
 // Scalars S0 .. S0+CS-1 of cell c.  theta_s of a cell with source index i is
