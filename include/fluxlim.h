@@ -243,8 +243,13 @@ fl_status fl_rk_steps_scaled(const fl_mesh *mesh, int limiter, int scheme, doubl
  * theta are held fixed):
  *   theta_bar += (dL/dtheta)^T rhs_bar,   u_bar += (dL/du_f)^T rhs_bar (skipped if NULL).
  * theta, rhs_bar, theta_bar: device [n_cells][S]; u_f, u_bar: device [n_faces].
- * Where theta_D == theta_C the limit of psi(d_U/d_u) d_u / 2 is differentiated (0 if also
- * d_U == 0). */
+ * Where theta_D == theta_C the limit of psi(d_U/d_u) d_u / 2 is differentiated (see the
+ * readings: psi(+-inf)/2 along d_u for d_U != 0, psi(0)/2 where d_U == 0 too).  Cells with
+ * opposite face pairs gather everything in one kernel (work may be NULL: 0 bytes); general cells
+ * (fl_mesh_info_t.general) run a face kernel that writes each face's terms to work
+ * (fl_adjoint_workspace_bytes bytes, 256-byte aligned) and a cell kernel that gathers them
+ * through the cell's face list and the transposed projection lists (no atomics).  Meshes with
+ * boundary faces or face distances: FL_E_UNSUPPORTED. */
 size_t fl_adjoint_workspace_bytes(const fl_mesh *mesh, int n_scalars);
 fl_status fl_convect_adjoint(const fl_mesh *mesh, int limiter, int n_scalars, const double *theta,
                              const double *u_f, const double *rhs_bar, double *theta_bar,
@@ -253,7 +258,7 @@ fl_status fl_convect_adjoint(const fl_mesh *mesh, int limiter, int n_scalars, co
 /* Reverse of one explicit step.  stages: device [n_stage][n_cells][S], the stage inputs of the
  * step (stage 0 is theta^n; SSP-RK3 also theta1, theta2).  lambda: device [n_cells][S], on entry
  * the cotangent of theta^{n+1}, on exit that of theta^n.  u_bar (+=, nullable): [n_faces].
- * work: fl_rk_adjoint_workspace_bytes bytes. */
+ * work: fl_rk_adjoint_workspace_bytes bytes (on general cells it includes the face terms). */
 size_t fl_rk_adjoint_workspace_bytes(const fl_mesh *mesh, int scheme, int n_scalars);
 fl_status fl_rk_step_adjoint(const fl_mesh *mesh, int limiter, int scheme, double dt,
                              int n_scalars, const double *stages, const double *u_f,

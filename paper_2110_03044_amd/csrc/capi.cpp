@@ -70,7 +70,8 @@ void free_device(fl_mesh *m) {
                     m->d_slot_far, m->d_adj_rec, m->d_area,   m->d_vol,       m->d_cell_perm,
                     m->d_face_perm, m->d_halo_ptr, m->d_halo, m->d_slot_local, m->d_side_ptr,
                     m->d_side_cell, m->d_side_w, m->d_adj_fr, m->d_halo_pair,
-                    m->d_halo_nrate, m->d_slot_nb, m->d_halo_pk, m->d_halo_next};
+                    m->d_halo_nrate, m->d_slot_nb, m->d_halo_pk, m->d_halo_next,
+                    m->d_rev_ptr, m->d_rev_side, m->d_rev_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     m->d_fc4 = m->d_cf_ptr = m->d_cf_idx = nullptr;
@@ -85,6 +86,8 @@ void free_device(fl_mesh *m) {
     m->d_slot_nb = nullptr;
     m->d_halo_pk = nullptr;
     m->d_halo_next = nullptr;
+    m->d_rev_ptr = m->d_rev_side = nullptr;
+    m->d_rev_w = nullptr;
     m->d_side_ptr = m->d_side_cell = nullptr;
     m->d_side_w = nullptr;
     m->d_area = m->d_vol = nullptr;
@@ -323,6 +326,11 @@ fl_status fl_mesh_create_dist(int64_t n_cells, int64_t n_faces, const int32_t *f
                 st = upload(&m->d_side_ptr, h.side_ptr.data(), h.side_ptr.size(), B, "side pointers");
                 if (st == FL_OK) st = upload(&m->d_side_cell, h.side_cell.data(), h.side_cell.size(), B, "side cells");
                 if (st == FL_OK) st = upload(&m->d_side_w, h.side_w.data(), h.side_w.size(), B, "side weights");
+                if (st == FL_OK) st = upload(&m->d_rev_ptr, h.rev_ptr.data(), h.rev_ptr.size(), B, "transposed side pointers");
+                if (st == FL_OK && !h.rev_side.empty()) {
+                    st = upload(&m->d_rev_side, h.rev_side.data(), h.rev_side.size(), B, "transposed sides");
+                    if (st == FL_OK) st = upload(&m->d_rev_w, h.rev_w.data(), h.rev_w.size(), B, "transposed weights");
+                }
             }
             if (st == FL_OK && !h.uniform_degree)
                 st = upload(&m->d_cf_ptr, h.cf_ptr.data(), h.cf_ptr.size(), B, "cell pointers");
@@ -663,25 +671,31 @@ fl_status fl_rk_step(const fl_mesh *m, int lim, int scheme, double dt, int S, do
 // ------------------------------------------------------------------------------------------
 // Adjoint
 // ------------------------------------------------------------------------------------------
+// General cells (no opposite face pairs) run the two-kernel adjoint, whose face terms need a
+// buffer; the paired kernels gather everything they need.
+static bool general_adjoint(const fl_mesh *m) { return m->h.pairs == 0; }
+
 size_t fl_adjoint_workspace_bytes(const fl_mesh *m, int S) {
-    (void)m;
-    (void)S;
-    return 0;  // the fused adjoint kernel gathers everything it needs
+    if (!m || S < 1 || S > FL_MAX_SCALARS || !general_adjoint(m)) return 0;
+    return align256(adjoint_general_term_bytes(m, S));
 }
 
 static fl_status check_adjoint(const fl_mesh *m, int lim, int S) {
     fl_status s = check_compute(m, lim, S);
     if (s != FL_OK) return s;
-    if (m->h.pairs == 0)
+    if (m->h.n_boundary > 0)
+        return fail(FL_E_UNSUPPORTED, "the adjoint covers closed meshes (no boundary faces)");
+    if (m->h.dist_weighted)
+        return fail(FL_E_UNSUPPORTED, "the adjoint covers meshes without face distances");
+    if (m->h.pairs == 0 && !m->h.general)
         return fail(FL_E_UNSUPPORTED,
-                    "the adjoint needs cells whose faces form opposite pairs (uniform degree)");
+                    "the adjoint needs cells whose faces form opposite pairs, or side lists");
     return FL_OK;
 }
 
 fl_status fl_convect_adjoint(const fl_mesh *m, int lim, int S, const double *theta,
                              const double *u, const double *rhs_bar, double *theta_bar,
                              double *u_bar, void *work, void *stream) {
-    (void)work;
     fl_status s = check_adjoint(m, lim, S);
     if (s != FL_OK) return s;
     if (!theta || !u || !rhs_bar || !theta_bar) return fail(FL_E_INVALID, "NULL device pointer");
@@ -694,14 +708,25 @@ fl_status fl_convect_adjoint(const fl_mesh *m, int lim, int S, const double *the
     s = finite_inputs(m, {{theta, m->h.nc * S}, {u, m->h.nf}, {rhs_bar, m->h.nc * S}}, 0.0,
                       (hipStream_t)stream);
     if (s != FL_OK) return s;
-    hipError_t e = launch_adjoint(m, lim, S, u, theta, rhs_bar, 0.0, 1.0, 0.0, ADJ_APPLY,
-                                  theta_bar, nullptr, u_bar, (hipStream_t)stream);
+    hipError_t e;
+    if (general_adjoint(m)) {
+        if (!work || ((uintptr_t)work & 255u))
+            return fail(FL_E_INVALID, "general cells need a 256-byte aligned work buffer of "
+                                      "fl_adjoint_workspace_bytes bytes");
+        e = launch_adjoint_general(m, lim, S, u, theta, rhs_bar, 0.0, 1.0, 0.0, ADJ_APPLY,
+                                   theta_bar, nullptr, u_bar, (double *)work, (hipStream_t)stream);
+    } else {
+        e = launch_adjoint(m, lim, S, u, theta, rhs_bar, 0.0, 1.0, 0.0, ADJ_APPLY, theta_bar,
+                           nullptr, u_bar, (hipStream_t)stream);
+    }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_convect_adjoint launch");
 }
 
 size_t fl_rk_adjoint_workspace_bytes(const fl_mesh *m, int scheme, int S) {
     if (!m || S < 1 || S > FL_MAX_SCALARS || (scheme != FL_EULER && scheme != FL_SSPRK3)) return 0;
-    return (scheme == FL_EULER ? 1 : 3) * align256((size_t)m->h.nc * S * sizeof(double));
+    // cell buffers (Euler: 1, SSP-RK3: 3), then the general cells' face terms
+    return (scheme == FL_EULER ? 1 : 3) * align256((size_t)m->h.nc * S * sizeof(double)) +
+           fl_adjoint_workspace_bytes(m, S);
 }
 
 fl_status fl_rk_step_store(const fl_mesh *m, int lim, int scheme, double dt, int S,
@@ -796,24 +821,26 @@ fl_status fl_rk_step_adjoint(const fl_mesh *m, int lim, int scheme, double dt, i
     double *w1 = (double *)work;
     double *w2 = (double *)((char *)work + slab);
     double *w3 = (double *)((char *)work + 2 * slab);
+    double *term = (double *)((char *)work + (scheme == FL_EULER ? 1 : 3) * slab);  // general
+    auto adj = [&](const double *th, const double *lam, double a, double b, int mode,
+                   double *out, double *acc) {
+        return general_adjoint(m)
+                   ? launch_adjoint_general(m, lim, S, u, th, lam, a, b, dt, mode, out, acc,
+                                            u_bar, term, st)
+                   : launch_adjoint(m, lim, S, u, th, lam, a, b, dt, mode, out, acc, u_bar, st);
+    };
     hipError_t e;
     // Each reverse stage gathers its input cotangent, so it writes a different buffer.
     if (scheme == FL_EULER) {
-        e = launch_adjoint(m, lim, S, u, stages, lambda, 0.0, 1.0, dt, ADJ_EULER, w1, nullptr,
-                           u_bar, st);
+        e = adj(stages, lambda, 0.0, 1.0, ADJ_EULER, w1, nullptr);
         if (e == hipSuccess)
             e = hipMemcpyAsync(lambda, w1, cell * sizeof(double), hipMemcpyDeviceToDevice, st);
     } else {
         // lambda -> w1 (stage 3), w1 -> w3 (stage 2), w3 -> lambda (stage 1); w2 accumulates
         // the theta^n cotangent
-        e = launch_adjoint(m, lim, S, u, stages + 2 * cell, lambda, kRk3A[2], kRk3B[2], dt,
-                           ADJ_LAST, w1, w2, u_bar, st);
-        if (e == hipSuccess)
-            e = launch_adjoint(m, lim, S, u, stages + cell, w1, kRk3A[1], kRk3B[1], dt, ADJ_MID,
-                               w3, w2, u_bar, st);
-        if (e == hipSuccess)
-            e = launch_adjoint(m, lim, S, u, stages, w3, kRk3A[0], kRk3B[0], dt, ADJ_FIRST,
-                               lambda, w2, u_bar, st);
+        e = adj(stages + 2 * cell, lambda, kRk3A[2], kRk3B[2], ADJ_LAST, w1, w2);
+        if (e == hipSuccess) e = adj(stages + cell, w1, kRk3A[1], kRk3B[1], ADJ_MID, w3, w2);
+        if (e == hipSuccess) e = adj(stages, w3, kRk3A[0], kRk3B[0], ADJ_FIRST, lambda, w2);
     }
     return e == hipSuccess ? FL_OK : hip_fail(e, "fl_rk_step_adjoint launch");
 }

@@ -52,16 +52,15 @@ __device__ __forceinline__ void psi_dpsi(double r, double &p, double &dp) {
     }
 }
 
-// theta_f and its partials g_a = d theta_f / d d_U, g_b = d theta_f / d d_u.  No multiply-add is
-// fused here (contract off): the value and partials of a face come out with the same bits
-// wherever the routine is inlined, whichever of its results the caller uses (the far-upwind term
-// a neighbour hands over equals the one a cell forms itself).
+// theta_f and its partials g_a = d theta_f / d d_U, g_b = d theta_f / d d_u from theta_C and the
+// differences a = d_U, b = d_u.  No multiply-add is fused here (contract off): the value and
+// partials of a face come out with the same bits wherever the routine is inlined, whichever of
+// its results the caller uses (the far-upwind term a neighbour hands over equals the one a cell
+// forms itself).
 template <int LIM>
-__device__ __forceinline__ double face_value_d(double tC, double tD, double tU, double &ga,
-                                               double &gb) {
+__device__ __forceinline__ double face_value_ab(double tC, double a, double b, double &ga,
+                                                double &gb) {
 #pragma clang fp contract(off)
-    const double b = tD - tC;  // d_u
-    const double a = tC - tU;  // d_U
     if constexpr (LIM == FL_UPWIND) {
         ga = 0.0;
         gb = 0.0;
@@ -97,6 +96,16 @@ __device__ __forceinline__ double face_value_d(double tC, double tD, double tU, 
     ga = 0.5 * dp;
     gb = 0.5 * (p - r * dp);
     return tC + 0.5 * p * b;
+}
+
+// The same from theta_C, theta_D and the far-upwind theta_U (d_U = theta_C - theta_U).
+template <int LIM>
+__device__ __forceinline__ double face_value_d(double tC, double tD, double tU, double &ga,
+                                               double &gb) {
+#pragma clang fp contract(off)
+    const double b = tD - tC;  // d_u
+    const double a = tC - tU;  // d_U
+    return face_value_ab<LIM>(tC, a, b, ga, gb);
 }
 
 template <int S>

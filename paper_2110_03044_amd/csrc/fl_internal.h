@@ -29,6 +29,11 @@ struct HostTables {
     std::vector<int32_t> side_ptr;   // [2F + 1]
     std::vector<int32_t> side_cell;
     std::vector<double> side_w;
+    // Their transpose for the general adjoint: per cell, the face sides whose d_U names it
+    // (2f + side) with the weight, in ascending side order.
+    std::vector<int32_t> rev_ptr;    // [C + 1]
+    std::vector<int32_t> rev_side;
+    std::vector<double> rev_w;
     std::vector<int32_t> cf_ptr;    // [C+1]
     std::vector<int32_t> cf_idx;    // signed: f (cell is nbr) or ~f (cell is own), ascending f
     int32_t max_degree = 0;
@@ -113,6 +118,9 @@ struct fl_mesh {
     int32_t *d_side_ptr = nullptr; // general cells: per-side far cells and weights
     int32_t *d_side_cell = nullptr;
     double *d_side_w = nullptr;
+    int32_t *d_rev_ptr = nullptr;  // general cells: the transposed side lists
+    int32_t *d_rev_side = nullptr;
+    double *d_rev_w = nullptr;
     int32_t *d_halo_ptr = nullptr; // LDS-staged stage: tile halo lists and local slot indices
     int32_t *d_halo = nullptr;
     uint32_t *d_slot_local = nullptr;

@@ -29,6 +29,13 @@ int xcd_remap();  // the current FL_OPT_XCD_REMAP value
 hipError_t launch_adjoint(const fl_mesh *m, int lim, int S, const double *u, const double *th,
                           const double *lam, double a, double b, double dt, int mode, double *out,
                           double *acc, double *ubar, hipStream_t st);
+// The same on general cells (fl_adjoint_general.hip): a face kernel writes each face's terms to
+// term (adjoint_general_term_bytes), a cell kernel gathers them.
+size_t adjoint_general_term_bytes(const fl_mesh *m, int S);
+hipError_t launch_adjoint_general(const fl_mesh *m, int lim, int S, const double *u,
+                                  const double *th, const double *lam, double a, double b,
+                                  double dt, int mode, double *out, double *acc, double *ubar,
+                                  double *term, hipStream_t st);
 
 // Multi-step reverse sweep (fl_rk_steps_adjoint): per-call slot rates {w, w'} (16 bytes per slot,
 // kAdjRateBytes) from u; one reverse stage in mode ADJ_EULER / ADJ_LAST / ADJ_MID / ADJ_FIRST

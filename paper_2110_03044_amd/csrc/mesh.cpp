@@ -876,6 +876,23 @@ fl_status build_host_tables(int64_t nc, int64_t nf, const int32_t *face_cells,
     }
     if (t.general && !side_lists(nf, t.fc.data(), t.nrm.data(), dist, cs, t))
         return fail(FL_E_UNSUPPORTED, "too many projected faces for 32-bit side lists");
+    if (t.general) {
+        // the transpose of the side lists (cells beyond a boundary face are not cells)
+        t.rev_ptr.assign(nc + 1, 0);
+        for (int32_t c : t.side_cell)
+            if (c >= 0) t.rev_ptr[c + 1]++;
+        for (int64_t c = 0; c < nc; ++c) t.rev_ptr[c + 1] += t.rev_ptr[c];
+        t.rev_side.resize(t.rev_ptr[nc]);
+        t.rev_w.resize(t.rev_ptr[nc]);
+        std::vector<int32_t> fill(t.rev_ptr.begin(), t.rev_ptr.end() - 1);
+        for (int64_t sd = 0; sd < 2 * nf; ++sd)
+            for (int32_t p = t.side_ptr[sd]; p < t.side_ptr[sd + 1]; ++p) {
+                const int32_t c = t.side_cell[p];
+                if (c < 0) continue;
+                t.rev_side[fill[c]] = (int32_t)sd;
+                t.rev_w[fill[c]++] = t.side_w[p];
+            }
+    }
     progress("far-upwind cells", nc);
 
     t.cf_ptr.resize(nc + 1);

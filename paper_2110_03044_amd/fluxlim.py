@@ -294,8 +294,9 @@ def convect_adjoint(mesh: Mesh, limiter, theta: torch.Tensor, u: torch.Tensor,
         theta_bar = torch.zeros_like(theta)
     if u_bar is None:
         u_bar = torch.zeros_like(u)
+    work = _workspace(int(lib().fl_adjoint_workspace_bytes(mesh.handle, _S(theta))), mesh.device)
     call("fl_convect_adjoint", mesh.handle, limiter_id(limiter), _S(theta), _tptr(theta), _tptr(u),
-         _tptr(rhs_bar), _tptr(mesh._cells(theta_bar)), _tptr(mesh._faces(u_bar)), None,
+         _tptr(rhs_bar), _tptr(mesh._cells(theta_bar)), _tptr(mesh._faces(u_bar)), _tptr(work),
          _stream(mesh.device, stream))
     return theta_bar, u_bar
 

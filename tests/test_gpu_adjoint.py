@@ -409,3 +409,117 @@ def test_multi_step_reverse_sweep_equals_per_step(lim, lds, scheme, S, case):
     # and the lambda of a call without the u cotangent
     assert torch.equal(a, c), diff(a, c)
     mesh.close()
+
+
+# ---------------------------------------------------------------------------------------------
+# General cells (triangles; sheared hexahedra): the face-term kernel and the cell gather through
+# the transposed projection lists.  The oracle's reverse sweep walks every face of C with the
+# projection weights (zero weight for a face that does not project), so it shares no structure
+# with the side lists the library builds.
+# ---------------------------------------------------------------------------------------------
+
+GENERAL = [
+    ("tri8r", lambda: W.renumber(W.periodic_triangles(8), seed=21)),
+    ("skew6r", lambda: W.renumber(W.periodic_skewed_box(6), seed=22)),
+]
+
+
+def _general_case(name, make, S, seed):
+    m = make()
+    rng = np.random.default_rng(seed)
+    th = rng.standard_normal((m.n_cells, S)) if S > 1 else rng.standard_normal(m.n_cells)
+    th[::4] = np.round(th[::4])  # plateaus: d_u == 0 and infinite ratios
+    if name.startswith("tri"):
+        u = m.face_velocity_from_natural(W.velocity_stream_triangles(8, seed=seed))
+    else:
+        u = W.velocity_uniform(m, (0.6, -0.3, 0.8), 1.0) + 0.3 * rng.standard_normal(m.n_faces)
+    u[::9] = 0.0
+    return m, th, u, rng
+
+
+@pytest.mark.parametrize("S", [1, 3])
+@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("name,make", GENERAL, ids=[c[0] for c in GENERAL])
+def test_general_cells_operator_adjoint_matches_oracle(name, make, reorder, S):
+    m, th, u, rng = _general_case(name, make, S, seed=30 + S)
+    lam = rng.standard_normal(th.shape)
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=reorder)
+    assert mesh.info.general == 1 and mesh.path == "face"
+    cp, fp = maps(mesh)
+    uf = np.empty_like(u)
+    uf[fp] = u
+    om = O.OracleMesh.from_arrays(m)
+    for lim in LIMS:
+        tb, ub = FL.convect_adjoint(mesh, lim, dev(cells_in(th, cp)), dev(uf),
+                                    dev(cells_in(lam, cp)))
+        tb_o, ub_o = om.rhs_vjp(lim, th, u, lam)
+        got_t, got_u = host(tb)[cp], host(ub)[fp]
+        assert np.abs(got_t - tb_o).max() <= 1e-12 * np.abs(tb_o).max(), lim
+        assert np.abs(got_u - ub_o).max() <= 1e-12 * np.abs(ub_o).max(), lim
+    mesh.close()
+
+
+@pytest.mark.parametrize("name,make", GENERAL, ids=[c[0] for c in GENERAL])
+def test_general_cells_operator_adjoint_accumulates_and_repeats(name, make):
+    """theta_bar and u_bar accumulate; two calls give the same bits (no atomics)."""
+    m, th, u, rng = _general_case(name, make, 2, seed=40)
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=True)
+    t = mesh.cells_to_mesh(dev(th))
+    ud = mesh.faces_to_mesh(dev(u))
+    lam = mesh.cells_to_mesh(dev(rng.standard_normal(th.shape)))
+    tb1, ub1 = FL.convect_adjoint(mesh, "superbee", t, ud, lam)
+    tb2, ub2 = FL.convect_adjoint(mesh, "superbee", t, ud, lam)
+    assert torch.equal(tb1, tb2) and torch.equal(ub1, ub2)
+    FL.convect_adjoint(mesh, "superbee", t, ud, lam, tb2, ub2)
+    assert torch.equal(tb2, 2 * tb1) and torch.equal(ub2, 2 * ub1)
+    mesh.close()
+
+
+@pytest.mark.parametrize("scheme", ["euler", "ssprk3"])
+@pytest.mark.parametrize("lim", ["vanalbada", "superbee", "minmod", "smart"])
+@pytest.mark.parametrize("name,make", GENERAL, ids=[c[0] for c in GENERAL])
+def test_general_cells_run_adjoint_matches_oracle(name, make, lim, scheme):
+    """advect's backward on general cells (one reverse step per stored step, checkpointed)
+    against the oracle's stored reverse sweep."""
+    m, th, u, rng = _general_case(name, make, 1, seed=50)
+    u[::9] = 0.1  # the run needs no stagnant faces; keep them small instead
+    dt = W.cfl_dt(m, u, 0.3)
+    steps = 7
+    lam_N = rng.standard_normal(th.shape)
+    mesh = FL.Mesh.from_arrays(m, device=0, reorder=True)
+    cp, fp = maps(mesh)
+    uf = np.empty_like(u)
+    uf[fp] = u
+    t0 = dev(cells_in(th, cp)).requires_grad_(True)
+    ud = dev(uf).requires_grad_(True)
+    out = FL.advect(mesh, lim, scheme, dt, t0, ud, steps, checkpoint_every=3)
+    out.backward(dev(cells_in(lam_N, cp)))
+    om = O.OracleMesh.from_arrays(m)
+    tb_o, ub_o = om.run_adjoint(lim, scheme, dt, th, u, steps, lam_N)
+    g_t, g_u = host(t0.grad)[cp], host(ud.grad)[fp]
+    assert np.abs(g_t - tb_o).max() <= 1e-10 * np.abs(tb_o).max()
+    assert np.abs(g_u - ub_o).max() <= 1e-10 * np.abs(ub_o).max()
+    want = om.run(lim, scheme, dt, th, u, steps)
+    assert np.abs(host(out)[cp] - want).max() <= 1e-10 * np.abs(want).max()
+    mesh.close()
+
+
+def test_general_cells_dot_product_against_oracle_tangent():
+    """<J v, w> from the oracle's tangent on the triangles equals <v, J^T w> from the GPU."""
+    name, make = GENERAL[0]
+    m, th, u, rng = _general_case(name, make, 1, seed=60)
+    u[::9] = 0.1
+    dt = W.cfl_dt(m, u, 0.3)
+    steps = 5
+    v = rng.standard_normal(th.shape)
+    du = rng.standard_normal(u.shape)
+    w = rng.standard_normal(th.shape)
+    _, jv = O.OracleMesh.from_arrays(m).run_tangent("vanalbada", "ssprk3", dt, th, u, steps, v, du)
+    mesh = FL.Mesh.from_arrays(m, device=0)
+    t0 = dev(th).requires_grad_(True)
+    ud = dev(u).requires_grad_(True)
+    FL.advect(mesh, "vanalbada", "ssprk3", dt, t0, ud, steps).backward(dev(w))
+    lhs = float(jv @ w)
+    rhs = float(v @ host(t0.grad) + du @ host(ud.grad))
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(jv) @ np.abs(w))
+    mesh.close()

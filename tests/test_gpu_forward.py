@@ -434,16 +434,14 @@ def test_general_cells_runs(lim, scheme):
         assert abs((V * got).sum() - (V * th).sum()) <= 1e-13 * (V * np.abs(th)).sum()
 
 
-def test_general_cells_without_adjoint_or_batch():
+def test_general_cells_refuse_batch():
+    """The batched launch covers the fused path only; general cells run one problem per call."""
     from paper_2110_03044_amd import _lib
 
     m = W.periodic_triangles(6)
     mesh = FL.Mesh.from_arrays(m, device=0)
     th = dev(np.ones(m.n_cells))
     u = dev(W.velocity_stream_triangles(6))
-    with pytest.raises(_lib.FluxLimError) as e:
-        FL.convect_adjoint(mesh, "vanalbada", th, u, th.clone())
-    assert e.value.status == -3
     with pytest.raises(_lib.FluxLimError) as e:
         FL.Batch([(mesh, "vanleer", th.clone(), u, 1e-3)])
     assert e.value.status == -3

@@ -469,3 +469,26 @@ def test_periodic_lattice_tiles_are_whole_bricks_whatever_the_input_order():
             assert info.tile_cells == 256
             assert info.max_halo == 512 and info.halo_total == 512 * tiles
             mesh.close()
+
+
+def test_adjoint_workspace_sizes():
+    """General cells' adjoint keeps four face terms per face and scalar in its workspace; the
+    paired kernels need none.  The per-step reverse workspace adds them after its cell buffers."""
+    L = _lib.lib()
+    tri = FL.Mesh.from_arrays(W.periodic_triangles(6), device=-1)
+    box = FL.Mesh.from_arrays(W.periodic_box(6, 3), device=-1)
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    for S in (1, 3, 8):
+        assert L.fl_adjoint_workspace_bytes(tri.handle, S) == a256(tri.n_faces * 4 * S * 8)
+        assert L.fl_adjoint_workspace_bytes(box.handle, S) == 0
+        for scheme, k in ((1, 1), (3, 3)):
+            slab = a256(tri.n_cells * S * 8)
+            assert L.fl_rk_adjoint_workspace_bytes(tri.handle, scheme, S) == \
+                k * slab + a256(tri.n_faces * 4 * S * 8)
+    assert L.fl_adjoint_workspace_bytes(tri.handle, 0) == 0
+    assert L.fl_adjoint_workspace_bytes(tri.handle, 9) == 0
+    tri.close()
+    box.close()
