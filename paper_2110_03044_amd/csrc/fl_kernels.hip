@@ -282,22 +282,23 @@ __global__ __launch_bounds__(kBlock) void slot_rate_fwd_kernel(int64_t nc,
 }
 
 // The LDS-staged stage reading forward rates and the compact slot tables (fused_tile_fwd);
-// dynamic LDS as lds_fwd_bytes.
-template <int S, int P>
+// dynamic LDS as lds_fwd_bytes.  The limiter is fixed at compile time, so that the face
+// evaluations of a cell carry no limiter branch and schedule together.
+template <int S, int P, int LIM>
 __global__ __launch_bounds__(kBlock) void fused_stage_lds_fwd_kernel(
     int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
     const int32_t *__restrict__ halo_pk, const uint16_t *__restrict__ halo_next,
     const int32_t *__restrict__ halo_nrate, const uint32_t *__restrict__ slot_nb,
     const double *__restrict__ rf, int has_area, double area0, const double *__restrict__ vol,
     double vol0, const double *__restrict__ ts, const double *__restrict__ tn, double a,
-    double b, double dt, int mode, int lim, double *__restrict__ out, double us, int rbase,
-    int nbase, int remap) {
+    double b, double dt, int mode, double *__restrict__ out, double us, int rbase, int nbase,
+    int remap) {
     extern __shared__ double lds[];
     const int64_t tile = block_id(remap);
     if (tile * kTileCells >= nc) return;
     fused_tile_fwd<S, P>(nc, tile, lds, rbase, nbase, halo_ptr, halo, halo_pk, halo_next,
                          halo_nrate, slot_nb, rf, has_area != 0, area0, vol, vol0, ts, tn, a, b,
-                         dt, mode, lim, out, us);
+                         dt, mode, LIM, out, us);
 }
 
 // One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
@@ -579,12 +580,23 @@ hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *
     const int rbase = (int)(lds_stage_bytes(m, S) / sizeof(double));
     const int nbase = (int)fwd_nbase(m, S);
     const Grid g = grid_for(m->h.nc, g_remap);
-#define FL_FUSED_FWD(P)                                                                          \
-    FL_DISPATCH_S(S, (dev::fused_stage_lds_fwd_kernel<kS, P><<<g.blocks, dev::kBlock, lds, st>>>( \
-                         m->h.nc, m->d_halo_ptr, m->d_halo, m->d_halo_pk, m->d_halo_next,         \
-                         m->d_halo_nrate, m->d_slot_nb, rf, m->d_area ? 1 : 0, m->h.area0,        \
-                         m->d_vol, m->h.vol0, ts, tn, a, b, dt, mode, lim, out, us, rbase,        \
-                         nbase, g.remap)))
+#define FL_FWD_K(SS, P, L)                                                                     \
+    dev::fused_stage_lds_fwd_kernel<SS, P, L><<<g.blocks, dev::kBlock, lds, st>>>(             \
+        m->h.nc, m->d_halo_ptr, m->d_halo, m->d_halo_pk, m->d_halo_next, m->d_halo_nrate,     \
+        m->d_slot_nb, rf, m->d_area ? 1 : 0, m->h.area0, m->d_vol, m->h.vol0, ts, tn, a, b,   \
+        dt, mode, out, us, rbase, nbase, g.remap)
+#define FL_FWD_LIM(SS, P)                                                  \
+    switch (lim) {                                                         \
+        case FL_UPWIND: FL_FWD_K(SS, P, FL_UPWIND); break;                 \
+        case FL_MINMOD: FL_FWD_K(SS, P, FL_MINMOD); break;                 \
+        case FL_VANLEER: FL_FWD_K(SS, P, FL_VANLEER); break;               \
+        case FL_VANALBADA: FL_FWD_K(SS, P, FL_VANALBADA); break;           \
+        case FL_SUPERBEE: FL_FWD_K(SS, P, FL_SUPERBEE); break;             \
+        case FL_SMART: FL_FWD_K(SS, P, FL_SMART); break;                   \
+        case FL_CENTRAL: FL_FWD_K(SS, P, FL_CENTRAL); break;               \
+        default: return hipErrorInvalidValue;                              \
+    }
+#define FL_FUSED_FWD(P) FL_DISPATCH_S(S, FL_FWD_LIM(kS, P))
     switch (m->h.pairs) {
         case 1: FL_FUSED_FWD(1); break;
         case 2: FL_FUSED_FWD(2); break;
@@ -592,6 +604,8 @@ hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *
         default: return hipErrorInvalidValue;
     }
 #undef FL_FUSED_FWD
+#undef FL_FWD_LIM
+#undef FL_FWD_K
     return hipGetLastError();
 }
 
