@@ -300,11 +300,13 @@ fl_status fl_adjoint_uacc_scatter(const fl_mesh *mesh, const double *u_acc, doub
                                   void *hip_stream);
 
 /* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
- * with one launch per Runge-Kutta stage for all of them (one fused cell-centric kernel over a
- * work table of (problem, cell tile) entries).  device >= 0 and every mesh created on it (a
- * host-only mesh or device: FL_E_NODEVICE; a mesh on another device: FL_E_INVALID); every
- * mesh must support the fused path (faces in opposite pairs, else FL_E_UNSUPPORTED); meshes may
- * be shared between problems.  theta[i] / u_f[i] are device pointers the batch keeps (not
+ * with one launch per Runge-Kutta stage for all the fused-path problems (one cell-centric kernel
+ * over a work table of (problem, cell tile) entries) and two for all the face-path problems
+ * (general cells, boundary faces with the mesh's inflow values, face distances: one launch over
+ * their faces, one over their cells; the batch owns their flux buffers).  device >= 0 and every
+ * mesh created on it (a host-only mesh or device: FL_E_NODEVICE; a mesh on another device:
+ * FL_E_INVALID; inflow values set for another scalar count: FL_E_INVALID); meshes may be shared
+ * between problems.  theta[i] / u_f[i] are device pointers the batch keeps (not
  * owned) until fl_batch_destroy.  tile_cells > 0 fixes the tile size; 0 picks it here, at
  * creation, by timing the candidates (the first stage, which writes only the batch's own stage
  * buffers) after a device synchronisation, or reads the choice from the on-disk tuning cache:

@@ -1,5 +1,7 @@
 // Batched problems: many independent meshes, scalar counts, limiters and time steps advanced
-// by ONE kernel launch per Runge-Kutta stage, replayed from a HIP graph.
+// by ONE kernel launch per Runge-Kutta stage, replayed from a HIP graph.  Problems on the face
+// path (general cells, boundary faces, face distances) join the same graph with two more
+// launches per stage for all of them: one over their faces, one over their cells.
 //
 // Each problem is described once in device memory (mesh slot tables, face velocity, buffers,
 // limiter, dt).  The work table lists (problem, first cell) tiles of `tile` cells; a persistent
@@ -7,7 +9,8 @@
 // one thread per cell.  Tiles never span problems, so the problem descriptor, the limiter and
 // the (pairs, scalars) specialisation chosen per tile are uniform within a workgroup: one kernel
 // serves every problem.  Each cell runs the single-problem kernel's own routine (fl_device.h),
-// so each problem's result equals its single-problem run bit for bit.
+// so each problem's result equals its single-problem run bit for bit; so does each face-path
+// problem's (the face and cell routines of fl_face_device.h).
 #include <hip/hip_runtime.h>
 
 #include <sys/stat.h>
@@ -21,6 +24,7 @@
 #include <vector>
 
 #include "fl_device.h"
+#include "fl_face_device.h"
 
 struct BatchProblem {
     int64_t nc;
@@ -32,6 +36,14 @@ struct BatchProblem {
     double *th, *t1, *t2;
     const int32_t *halo_ptr, *halo;  // tile tables (LDS staging)
     const uint32_t *slot_local;
+    // face path (face != 0): face records, side lists where general, cell face lists, inflow
+    // values (nullable) and the flux buffer
+    int32_t face, general, K, pad2;
+    int64_t nf;
+    const int4 *fc4;
+    const int32_t *side_ptr, *side_cell, *cf_ptr, *cf_idx;
+    const double *side_w, *inflow;
+    double *phi;
 };
 
 struct BatchTile {
@@ -144,6 +156,69 @@ __global__ __launch_bounds__(kBlock) void batch_stage_lds_kernel(
     }
 }
 
+// Face-path problems, stage s (SSP-RK3: th -> t1, (t1, th) -> t2, (t2, th) -> th; forward
+// Euler: th -> th in place, since a cell's update reads only its own theta and the fluxes were
+// formed by the launch before): one launch over every such problem's faces, tiles of kBlock
+// faces, then one over their cells.
+__global__ __launch_bounds__(kBlock) void batch_face_kernel(const BatchProblem *__restrict__ probs,
+                                                            const BatchTile *__restrict__ tiles,
+                                                            int64_t ntiles, int stage) {
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile T = tiles[t];
+        const BatchProblem &pb = probs[T.prob];
+        const double *ts = stage == 0 ? pb.th : stage == 1 ? pb.t1 : pb.t2;
+        const int64_t f = T.c0 + threadIdx.x;
+        if (f >= pb.nf) continue;
+#define FL_BFACE(SS)                                                                            \
+    if (pb.general)                                                                             \
+        dev::face_flux_general_one<SS>(f, pb.fc4, pb.side_ptr, pb.side_cell, pb.side_w, pb.u,   \
+                                       ts, pb.area, pb.area0, pb.lim, pb.phi, 1.0, pb.inflow);  \
+    else                                                                                        \
+        dev::face_flux_one<SS>(f, pb.fc4, pb.u, ts, pb.area, pb.area0, pb.lim, pb.phi, 1.0)
+        switch (pb.S) {
+            case 1: FL_BFACE(1); break;
+            case 2: FL_BFACE(2); break;
+            case 3: FL_BFACE(3); break;
+            case 4: FL_BFACE(4); break;
+            case 5: FL_BFACE(5); break;
+            case 6: FL_BFACE(6); break;
+            case 7: FL_BFACE(7); break;
+            default: FL_BFACE(8); break;
+        }
+#undef FL_BFACE
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_face_cell_kernel(
+    const BatchProblem *__restrict__ probs, const BatchTile *__restrict__ tiles, int64_t ntiles,
+    int stage, int euler) {
+    const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile T = tiles[t];
+        const BatchProblem &pb = probs[T.prob];
+        const double *ts = stage == 0 ? pb.th : stage == 1 ? pb.t1 : pb.t2;
+        double *out = stage == 0 ? (euler ? pb.th : pb.t1) : stage == 1 ? pb.t2 : pb.th;
+        const int mode = stage == 0 ? MODE_EULER : MODE_RK;
+        const int64_t c = T.c0 + threadIdx.x;
+        if (c >= pb.nc) continue;
+#define FL_BCU(SS)                                                                             \
+    dev::cell_update_one<SS>(c, pb.K, pb.cf_ptr, pb.cf_idx, pb.phi, pb.vol, pb.vol0, ts, pb.th, \
+                             A[stage], B[stage], pb.dt, mode, out)
+        switch (pb.S) {
+            case 1: FL_BCU(1); break;
+            case 2: FL_BCU(2); break;
+            case 3: FL_BCU(3); break;
+            case 4: FL_BCU(4); break;
+            case 5: FL_BCU(5); break;
+            case 6: FL_BCU(6); break;
+            case 7: FL_BCU(7); break;
+            default: FL_BCU(8); break;
+        }
+#undef FL_BCU
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void batch_copy_kernel(const BatchProblem *__restrict__ probs,
                                                             const BatchTile *__restrict__ tiles,
                                                             int64_t ntiles, int tile) {
@@ -173,6 +248,11 @@ struct fl_batch {
     BatchProblem *d_probs = nullptr;
     BatchTile *d_tiles = nullptr;
     int64_t ntiles = 0;
+    // face-path problems: tiles of kBlock faces and of kBlock cells
+    BatchTile *d_ftiles = nullptr, *d_ctiles = nullptr;
+    int64_t nftiles = 0, nctiles = 0;
+    int fgrid = 1, cgrid = 1;
+    bool any_fused = false;
     std::vector<double *> owned;  // t1/t2 buffers
     hipStream_t cap = nullptr;    // capture stream (default priority)
     hipGraph_t graph = nullptr;
@@ -208,14 +288,17 @@ void drop_graph(fl_batch *b) {
 fl_status set_tile(fl_batch *b, int tile) {
     std::vector<BatchTile> tiles;
     for (size_t i = 0; i < b->probs.size(); ++i)
-        for (int64_t c0 = 0; c0 < b->probs[i].nc; c0 += tile) tiles.push_back({(int32_t)i, 0, c0});
+        if (!b->probs[i].face)
+            for (int64_t c0 = 0; c0 < b->probs[i].nc; c0 += tile)
+                tiles.push_back({(int32_t)i, 0, c0});
+    tiles.push_back({0, 0, 0});  // (never read past ntiles; keeps the allocation non-empty)
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     b->d_tiles = nullptr;
     hipError_t e = hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(BatchTile));
     if (e != hipSuccess) return fail(FL_E_NOMEM, "batch tile table");
     e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_err(e, "batch tile table upload");
-    b->ntiles = (int64_t)tiles.size();
+    b->ntiles = (int64_t)tiles.size() - 1;
     b->tile = tile;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
@@ -229,7 +312,34 @@ fl_status set_tile(fl_batch *b, int tile) {
     return FL_OK;
 }
 
+// The face-path problems' work tables: tiles of kBlock faces and of kBlock cells.
+fl_status face_tiles(fl_batch *b) {
+    std::vector<BatchTile> ft, ct;
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+        const BatchProblem &p = b->probs[i];
+        if (!p.face) continue;
+        for (int64_t f0 = 0; f0 < p.nf; f0 += bdev::kBlock) ft.push_back({(int32_t)i, 0, f0});
+        for (int64_t c0 = 0; c0 < p.nc; c0 += bdev::kBlock) ct.push_back({(int32_t)i, 0, c0});
+    }
+    b->nftiles = (int64_t)ft.size();
+    b->nctiles = (int64_t)ct.size();
+    if (ft.empty()) return FL_OK;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    b->fgrid = (int)std::max<int64_t>(1, std::min<int64_t>(b->nftiles, (int64_t)cus * 8));
+    b->cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(b->nctiles, (int64_t)cus * 8));
+    for (auto pr : {std::make_pair(&b->d_ftiles, &ft), std::make_pair(&b->d_ctiles, &ct)}) {
+        const size_t n = pr.second->size() * sizeof(BatchTile);
+        hipError_t e = hipMalloc((void **)pr.first, n);
+        if (e != hipSuccess) return fail(FL_E_NOMEM, "batch face tile tables");
+        e = hipMemcpy(*pr.first, pr.second->data(), n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_err(e, "batch face tile table upload");
+    }
+    return FL_OK;
+}
+
 hipError_t launch_stage(const fl_batch *b, int s, hipStream_t st) {
+    if (b->ntiles == 0) return hipSuccess;
     if (b->lds)
         bdev::batch_stage_lds_kernel<<<b->grid, bdev::kBlock, b->lds_bytes, st>>>(
             b->d_probs, b->d_tiles, b->ntiles, s, b->remap);
@@ -244,8 +354,16 @@ hipError_t enqueue_step(const fl_batch *b, hipStream_t st) {
     for (int s = 0; s < ns; ++s) {
         hipError_t e = launch_stage(b, s, st);
         if (e != hipSuccess) return e;
+        if (b->nftiles > 0) {
+            bdev::batch_face_kernel<<<b->fgrid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_ftiles,
+                                                                      b->nftiles, s);
+            bdev::batch_face_cell_kernel<<<b->cgrid, bdev::kBlock, 0, st>>>(
+                b->d_probs, b->d_ctiles, b->nctiles, s, b->scheme == FL_EULER ? 1 : 0);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
-    if (b->scheme == FL_EULER) {
+    if (b->scheme == FL_EULER && b->ntiles > 0) {
         bdev::batch_copy_kernel<<<b->grid, bdev::kBlock, 0, st>>>(b->d_probs, b->d_tiles,
                                                                  b->ntiles, b->tile);
         return hipGetLastError();
@@ -398,6 +516,8 @@ void destroy(fl_batch *b) {
     for (double *p : b->owned) (void)hipFree(p);
     if (b->d_probs) (void)hipFree(b->d_probs);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_ftiles) (void)hipFree(b->d_ftiles);
+    if (b->d_ctiles) (void)hipFree(b->d_ctiles);
     delete b;
 }
 
@@ -437,10 +557,11 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
             destroy(b);
             return fail(FL_E_INVALID, "every mesh must live on the batch's device");
         }
-        if (m->path != FL_PATH_FUSED || m->h.pairs < 1) {
+        const bool face = m->path != FL_PATH_FUSED || m->h.pairs < 1;
+        if (face && m->inflow && m->inflow_S != n_scalars[i]) {
             destroy(b);
-            return fail(FL_E_UNSUPPORTED,
-                        "batched problems need fused-path meshes (faces in opposite pairs)");
+            return fail(FL_E_INVALID, "a problem's inflow values were set for another number of "
+                                      "scalars");
         }
         if (limiter[i] < 0 || limiter[i] >= FL_NUM_LIMITERS || n_scalars[i] < 1 ||
             n_scalars[i] > FL_MAX_SCALARS || !theta[i] || !u_f[i] || !(dt[i] == dt[i])) {
@@ -449,7 +570,7 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         }
         BatchProblem p{};
         p.nc = m->h.nc;
-        p.P = m->h.pairs;
+        p.P = face ? 0 : m->h.pairs;
         p.S = n_scalars[i];
         p.lim = limiter[i];
         p.dt = dt[i];
@@ -465,9 +586,30 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         p.halo_ptr = m->d_halo_ptr;
         p.halo = m->d_halo;
         p.slot_local = m->d_slot_local;
-        const size_t lds = lds_stage_bytes(m, p.S);
-        lds_all = lds_all && lds > 0 && lds <= kMaxStageLds;
-        lds_max = std::max(lds_max, lds);
+        if (face) {
+            p.face = 1;
+            p.general = m->h.general ? 1 : 0;
+            p.K = (int32_t)m->h.max_degree;
+            p.nf = m->h.nf;
+            p.fc4 = reinterpret_cast<const int4 *>(m->d_fc4);
+            p.side_ptr = m->d_side_ptr;
+            p.side_cell = m->d_side_cell;
+            p.side_w = m->d_side_w;
+            p.cf_ptr = m->d_cf_ptr;
+            p.cf_idx = m->d_cf_idx;
+            p.inflow = m->inflow;
+            const size_t fbytes = std::max<size_t>((size_t)p.nf * p.S * sizeof(double), 8);
+            if (hipMalloc((void **)&p.phi, fbytes) != hipSuccess) {
+                destroy(b);
+                return fail(FL_E_NOMEM, "batch flux buffers");
+            }
+            b->owned.push_back(p.phi);
+        } else {
+            b->any_fused = true;
+            const size_t lds = lds_stage_bytes(m, p.S);
+            lds_all = lds_all && lds > 0 && lds <= kMaxStageLds;
+            lds_max = std::max(lds_max, lds);
+        }
         const size_t bytes = (size_t)p.nc * p.S * sizeof(double);
         for (double **dst : {&p.t1, &p.t2}) {
             if (hipMalloc((void **)dst, bytes) != hipSuccess) {
@@ -479,7 +621,7 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         b->probs.push_back(p);
         b->meshes.push_back(m);
     }
-    b->lds_bytes = lds_all ? lds_max : 0;
+    b->lds_bytes = b->any_fused && lds_all ? lds_max : 0;
     hipError_t e = hipMalloc((void **)&b->d_probs, b->probs.size() * sizeof(BatchProblem));
     if (e == hipSuccess)
         e = hipMemcpy(b->d_probs, b->probs.data(), b->probs.size() * sizeof(BatchProblem),
@@ -489,8 +631,16 @@ fl_status fl_batch_create(int n, fl_mesh *const *meshes, const int *limiter, con
         destroy(b);
         return hip_err(e, "batch setup");
     }
-    fl_status s = FL_OK;
-    if (tile_cells > 0) {
+    fl_status s = face_tiles(b);
+    if (s != FL_OK) {
+        destroy(b);
+        return s;
+    }
+    if (!b->any_fused) {
+        // nothing for the autotuner: the fused tile table stays empty
+        s = set_tile(b, kTileCells);
+        b->lds = false;
+    } else if (tile_cells > 0) {
         // a fixed tile of kTileCells cells runs staged in LDS where every mesh allows it
         s = set_tile(b, tile_cells);
         b->lds = tile_cells == kTileCells && b->lds_bytes > 0;
@@ -548,6 +698,13 @@ fl_status fl_batch_step_unbatched(fl_batch *b, int n_steps, void *stream) {
             // the batch's per-cell work, one problem per launch: LDS-staged tiles when the
             // batch runs staged, the gather kernel otherwise
             auto one = [&](const double *ts, double a, double bb, int mode, double *out) {
+                if (p.face) {  // the single-problem face path
+                    hipError_t e = launch_face_flux(m, p.lim, p.S, ts, p.u, p.phi, st, 1.0);
+                    return e != hipSuccess
+                               ? e
+                               : launch_cell_update(m, p.S, p.phi, ts, p.th, a, bb, p.dt, mode,
+                                                    out, st);
+                }
                 return b->lds ? launch_fused_lds(m, p.lim, p.S, ts, p.th, nullptr, a, bb, p.dt,
                                                  mode, out, st, 1.0, p.u)
                               : launch_fused(m, p.lim, p.S, ts, p.th, p.u, a, bb, p.dt, mode,

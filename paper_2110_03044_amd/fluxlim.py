@@ -576,7 +576,8 @@ class Algebraic:
 
 class Batch:
     """Independent problems (mesh, limiter, theta, u, dt) advanced together: one kernel launch per
-    Runge-Kutta stage for all of them, recorded once in a HIP graph and replayed.
+    Runge-Kutta stage for all the fused-path problems and two for all the face-path ones (general
+    cells, boundary faces, face distances), recorded once in a HIP graph and replayed.
 
     problems: sequence of (mesh, limiter, theta, u, dt); theta is updated in place.  Meshes may
     be shared.  tile_cells = 0 lets the library pick the tile size at creation (timing the

@@ -128,10 +128,6 @@ def test_batch_shared_mesh_and_rejections():
     FL.rk_steps(mesh, "vanleer", "ssprk3", 0.5 * p["dt"], r2, u, 3)
     torch.cuda.synchronize()
     assert torch.equal(t1, r1) and torch.equal(t2, r2)
-    face = FL.Mesh.from_arrays(p["mesh"], device=0, face_path=True)
-    with pytest.raises(_lib.FluxLimError):
-        FL.Batch([(face, "minmod", face.cells_to_mesh(torch.from_numpy(p["th"]).to(DEV)),
-                   face.faces_to_mesh(torch.from_numpy(p["u"]).to(DEV)), p["dt"])])
     with pytest.raises(_lib.FluxLimError):
         FL.Batch([(mesh, "minmod", t1, u, p["dt"])], tile_cells=100)
 
@@ -212,3 +208,94 @@ def test_tuning_at_creation_and_on_disk_cache(tmp_path, monkeypatch):
     b = FL.Batch([(m, p["lim"], th, u, p["dt"]) for (m, th, u), p in zip(dev_probs, probs)])
     assert not b.tuned_from_cache
     b.close()
+
+
+def rows_to_mesh(x, perm):
+    out = np.empty_like(x)
+    out[perm] = x
+    return out
+
+
+def face_path_problems():
+    """Problems on the face path: triangles and a sheared box (general cells), an open box with
+    inflow values, a stretched box with face distances, and a box forced onto the face path."""
+    out = []
+    tri = W.renumber(W.periodic_triangles(10), seed=41)
+    rng = np.random.default_rng(42)
+    u = tri.face_velocity_from_natural(W.velocity_stream_triangles(10, seed=3))
+    out.append(dict(mesh=tri, u=u, th=rng.standard_normal((tri.n_cells, 2)), lim="superbee",
+                    dt=W.cfl_dt(tri, u, 0.3)))
+    sk = W.renumber(W.periodic_skewed_box(6), seed=43)
+    u = W.velocity_uniform(sk, (0.6, -0.3, 0.8), 1.0)
+    out.append(dict(mesh=sk, u=u, th=rng.standard_normal(sk.n_cells), lim="vanleer",
+                    dt=W.cfl_dt(sk, u, 0.3)))
+    wl = W.workload_open_box(8, renumbered=True, S=3)
+    out.append(dict(mesh=wl.mesh, u=wl.u, th=wl.theta0, lim="vanalbada", dt=wl.dt,
+                    inflow=wl.inflow))
+    nat = W.stretched_box(9, 3, amp=0.5)
+    st = W.renumber(nat, seed=44)
+    u = st.face_velocity_from_natural(W.velocity_open_box(nat))
+    out.append(dict(mesh=st, u=u, th=st.cell_field_from_natural(W.field_blob_step(9)),
+                    lim="smart", dt=W.cfl_dt(st, u, 0.4)))
+    box = make_problems(count=1, seed=45, dims=(3,))[0]
+    box.update(lim="minmod", face_path=True)
+    out.append(box)
+    return out
+
+
+def to_dev_face(p):
+    mesh = FL.Mesh.from_arrays(p["mesh"], device=0, reorder=True,
+                               **({"face_path": True} if p.get("face_path") else {}))
+    cp, fp = mesh.permutation()
+    assert mesh.path == "face"
+    if p.get("inflow") is not None:
+        mesh.set_inflow(torch.from_numpy(rows_to_mesh(p["inflow"], fp)).to(DEV))
+    th = torch.from_numpy(rows_to_mesh(p["th"], cp)).to(DEV)
+    u = torch.from_numpy(rows_to_mesh(p["u"], fp)).to(DEV)
+    return mesh, th, u
+
+
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+@pytest.mark.parametrize("with_fused", [True, False])
+def test_batch_with_face_path_problems(scheme, with_fused):
+    """Face-path problems (general cells, boundary faces with inflow, face distances) join a
+    batch: two more launches per stage for all of them.  Each equals its single-problem run bit
+    for bit on every replay, the per-problem launches give the same bits, and the oracle agrees."""
+    fprobs = face_path_problems()
+    dev_probs = [to_dev_face(p) for p in fprobs]
+    probs = list(fprobs)
+    if with_fused:
+        extra = make_problems(count=3, seed=46)
+        probs += extra
+        dev_probs += [to_dev(p) for p in extra]
+    batch_th = [th.clone() for _, th, _ in dev_probs]
+    single_th = [th.clone() for _, th, _ in dev_probs]
+    unb_th = [th.clone() for _, th, _ in dev_probs]
+    items = [(m, p["lim"], bt, u, p["dt"]) for (m, _, u), bt, p in zip(dev_probs, batch_th, probs)]
+    b = FL.Batch(items, scheme=scheme)
+    bu = FL.Batch([(m, p["lim"], t, u, p["dt"]) for (m, _, u), t, p in zip(dev_probs, unb_th, probs)],
+                  scheme=scheme, tile_cells=256)
+    steps = 0
+    for replay in range(3):
+        b.step(2)
+        bu.step_unbatched(2)
+        steps += 2
+        torch.cuda.synchronize()
+        for (m, _, u), st, p in zip(dev_probs, single_th, probs):
+            FL.rk_steps(m, p["lim"], scheme, p["dt"], st, u, 2)
+        torch.cuda.synchronize()
+        for i, (bt, st, ut) in enumerate(zip(batch_th, single_th, unb_th)):
+            assert torch.equal(bt, st), (replay, i, probs[i]["lim"])
+            assert torch.equal(ut, st), (replay, i, probs[i]["lim"])
+    for i, p in enumerate(fprobs):
+        m = dev_probs[i][0]
+        om = O.OracleMesh.from_arrays(p["mesh"])
+        if p["mesh"].face_dist is not None:
+            om.set_distances(p["mesh"].face_dist)
+        om.set_inflow(p.get("inflow"))
+        want = om.run(p["lim"], scheme, p["dt"], p["th"], p["u"], steps)
+        cp, _ = m.permutation()
+        got = batch_th[i].cpu().numpy()[cp]
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max(), (i, p["lim"])
+    b.close()
+    bu.close()

@@ -434,17 +434,21 @@ def test_general_cells_runs(lim, scheme):
         assert abs((V * got).sum() - (V * th).sum()) <= 1e-13 * (V * np.abs(th)).sum()
 
 
-def test_general_cells_refuse_batch():
-    """The batched launch covers the fused path only; general cells run one problem per call."""
-    from paper_2110_03044_amd import _lib
-
+def test_general_cells_in_a_batch():
+    """General cells join a batch through the face-path kernels: the same bits as the
+    single-problem call (more cases in test_gpu_batch.py)."""
     m = W.periodic_triangles(6)
     mesh = FL.Mesh.from_arrays(m, device=0)
-    th = dev(np.ones(m.n_cells))
+    th = dev(np.cos(np.arange(m.n_cells) * 0.3))
     u = dev(W.velocity_stream_triangles(6))
-    with pytest.raises(_lib.FluxLimError) as e:
-        FL.Batch([(mesh, "vanleer", th.clone(), u, 1e-3)])
-    assert e.value.status == -3
+    dt = W.cfl_dt(m, W.velocity_stream_triangles(6), 0.3)
+    a, c = th.clone(), th.clone()
+    b = FL.Batch([(mesh, "vanleer", a, u, dt)])
+    b.step(3)
+    FL.rk_steps(mesh, "vanleer", "ssprk3", dt, c, u, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    b.close()
 
 
 def test_full_size_box256_sampled_first_stage_and_conservation():
