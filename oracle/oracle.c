@@ -413,43 +413,52 @@ int orc_run_scaled(const orc_mesh *m, int lim, int scheme, double dt, int S, int
 
 /* ------------------------------------------------------------------------------------------
  * Tangent (forward mode) of L.  theta_f depends on theta_C, theta_D and the far cells through
- * d_U and d_u; the selection Q(u) is piecewise constant and contributes nothing.
+ * d_U and d_u; the selection Q(u) is piecewise constant and contributes nothing.  The exterior
+ * beyond a boundary face holds a constant inflow value (tangent 0) or repeats its face's own
+ * cell (that cell's tangent).
  * ------------------------------------------------------------------------------------------ */
-static double face_value_tangent(const orc_mesh *m, int lim, int S, const double *th,
-                                 const double *dth, const double *u, int64_t f, int k,
-                                 double *dtf) {
-    face_sel fs = select_face(m, u, f);
-    double tC = th[fs.C * S + k], tD = th[fs.D * S + k];
-    double dC = dth[fs.C * S + k], dD = dth[fs.D * S + k];
-    double du = tD - tC, ddu = dD - dC;
-    double dU = 0.0, ddU = 0.0;
+static inline double tangent_at(const orc_mesh *m, int S, const double *dth, const double *u,
+                                int64_t c, int64_t j, int k) {
+    if (c >= 0) return dth[c * S + k];
+    if (m->inflow && !(u[j] > 0.0)) return 0.0;
+    return dth[m->fc[2 * j] * S + k];
+}
+
+/* The tangent of d_U: the upstream difference is linear in the values it reads. */
+static double upstream_difference_tangent(const orc_mesh *m, int S, const double *dth,
+                                          const double *u, int64_t f, face_sel fs, int k) {
+    double ddU = 0.0;
+    if (fs.C < 0) return ddU;
+    double dC = dth[fs.C * S + k];
     for (int64_t p = m->cptr[fs.C]; p < m->cptr[fs.C + 1]; ++p) {
         int64_t j = m->cidx[p];
         if (j == f) continue;
         double w = proj_weight(m, f, j, fs.C, fs.s);
-        int64_t o = other_cell(m, j, fs.C);
-        dU += w * (tC - th[o * S + k]);
-        ddU += w * (dC - dth[o * S + k]);
+        double diff = dC - tangent_at(m, S, dth, u, other_cell(m, j, fs.C), j, k);
+        if (m->dist) ddU += w * diff / m->dist[j];
+        else ddU += w * diff;
     }
+    if (m->dist) ddU *= m->dist[f];
+    return ddU;
+}
+
+static double face_value_tangent(const orc_mesh *m, int lim, int S, const double *th,
+                                 const double *dth, const double *u, int64_t f, int k,
+                                 double *dtf) {
+    face_sel fs = select_face(m, u, f);
+    double tC = value_at(m, S, th, u, fs.C, f, k), tD = value_at(m, S, th, u, fs.D, f, k);
+    double dC = tangent_at(m, S, dth, u, fs.C, f, k), dD = tangent_at(m, S, dth, u, fs.D, f, k);
+    double du = tD - tC, ddu = dD - dC;
+    double dU = upstream_difference(m, S, th, u, f, fs, k);
+    double ddU = upstream_difference_tangent(m, S, dth, u, f, fs, k);
     double ga, gb;
     double tf = limited_value(lim, tC, dU, du, &ga, &gb);
     *dtf = dC + ga * ddU + gb * ddu;
     return tf;
 }
 
-/* The derivative functions cover closed meshes only: on a mesh with boundary faces they fill
- * their outputs with NaN (and the run functions return -2). */
-static void fill_nan(double *a, int64_t n) {
-    for (int64_t i = 0; i < n; ++i) a[i] = NAN;
-}
-
 void orc_face_values_jvp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                          const double *dth, double *tf, double *dtf) {
-    if (m->n_boundary) {
-        fill_nan(tf, m->nf * S);
-        fill_nan(dtf, m->nf * S);
-        return;
-    }
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < m->nf; ++f)
         for (int k = 0; k < S; ++k)
@@ -458,10 +467,6 @@ void orc_face_values_jvp(const orc_mesh *m, int lim, int S, const double *th, co
 
 void orc_rhs_jvp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                  const double *dth, const double *du, double *drhs) {
-    if (m->n_boundary) {
-        fill_nan(drhs, m->nc * S);
-        return;
-    }
     double *dphi = (double *)malloc((size_t)(m->nf * S) * sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < m->nf; ++f)
@@ -487,24 +492,28 @@ void orc_rhs_jvp(const orc_mesh *m, int lim, int S, const double *th, const doub
 
 /* ------------------------------------------------------------------------------------------
  * Adjoint (reverse mode) of L: theta_bar = J^T lam, u_bar = (dL/du)^T lam (both overwritten).
- * Serial scatter over faces: slow and plainly the transpose of the forward chain.
+ * Serial scatter over faces: slow and plainly the transpose of the forward chain.  A cotangent
+ * reaching the exterior beyond a boundary face goes to the face's own cell where the exterior
+ * repeats it, and nowhere where it holds an inflow value.
  * ------------------------------------------------------------------------------------------ */
+static inline void scatter_at(const orc_mesh *m, int S, double *tbar, const double *u, int64_t c,
+                              int64_t j, int k, double v) {
+    if (c >= 0) tbar[c * S + k] += v;
+    else if (!(m->inflow && !(u[j] > 0.0))) tbar[m->fc[2 * j] * S + k] += v;
+}
+
 void orc_rhs_vjp(const orc_mesh *m, int lim, int S, const double *th, const double *u,
                  const double *lam, double *tbar, double *ubar) {
-    if (m->n_boundary) {
-        fill_nan(tbar, m->nc * S);
-        if (ubar) fill_nan(ubar, m->nf);
-        return;
-    }
     memset(tbar, 0, (size_t)(m->nc * S) * sizeof(double));
     if (ubar) memset(ubar, 0, (size_t)m->nf * sizeof(double));
     for (int64_t f = 0; f < m->nf; ++f) {
         face_sel fs = select_face(m, u, f);
         int64_t own = m->fc[2 * f], nbr = m->fc[2 * f + 1];
         for (int k = 0; k < S; ++k) {
-            /* rhs_nbr += a u tf / V_nbr, rhs_own -= a u tf / V_own */
-            double mu = lam[nbr * S + k] / m->vol[nbr] - lam[own * S + k] / m->vol[own];
-            double tC = th[fs.C * S + k], tD = th[fs.D * S + k];
+            /* rhs_nbr += a u tf / V_nbr, rhs_own -= a u tf / V_own (a boundary face has no nbr) */
+            double mu = (nbr >= 0 ? lam[nbr * S + k] / m->vol[nbr] : 0.0) -
+                        lam[own * S + k] / m->vol[own];
+            double tC = value_at(m, S, th, u, fs.C, f, k), tD = value_at(m, S, th, u, fs.D, f, k);
             double du = tD - tC;
             double dU = upstream_difference(m, S, th, u, f, fs, k);
             double ga, gb;
@@ -512,18 +521,20 @@ void orc_rhs_vjp(const orc_mesh *m, int lim, int S, const double *th, const doub
             if (ubar) ubar[f] += m->area[f] * tf * mu;
             double z = m->area[f] * u[f] * mu; /* cotangent of theta_f */
             /* theta_f = theta_C + g(d_U, d_u) */
-            tbar[fs.C * S + k] += z;
+            scatter_at(m, S, tbar, u, fs.C, f, k, z);
             /* d_u = theta_D - theta_C */
-            tbar[fs.D * S + k] += z * gb;
-            tbar[fs.C * S + k] -= z * gb;
-            /* d_U = sum_j w_j (theta_C - theta_other(j)) */
+            scatter_at(m, S, tbar, u, fs.D, f, k, z * gb);
+            scatter_at(m, S, tbar, u, fs.C, f, k, -z * gb);
+            /* d_U = d_f sum_j w_j (theta_C - theta_other(j)) / d_j (no distances: d = 1) */
+            if (fs.C < 0) continue;
             for (int64_t p = m->cptr[fs.C]; p < m->cptr[fs.C + 1]; ++p) {
                 int64_t j = m->cidx[p];
                 if (j == f) continue;
                 double w = proj_weight(m, f, j, fs.C, fs.s);
+                if (m->dist) w = w / m->dist[j] * m->dist[f];
                 int64_t o = other_cell(m, j, fs.C);
                 tbar[fs.C * S + k] += z * ga * w;
-                tbar[o * S + k] -= z * ga * w;
+                scatter_at(m, S, tbar, u, o, j, k, -z * ga * w);
             }
         }
     }
@@ -532,7 +543,6 @@ void orc_rhs_vjp(const orc_mesh *m, int lim, int S, const double *th, const doub
 int orc_run_tangent(const orc_mesh *m, int lim, int scheme, double dt, int S, int64_t nsteps,
                     double *th, double *dth, const double *u, const double *du) {
     if (scheme != ORC_EULER && scheme != ORC_SSPRK3) return -1;
-    if (m->n_boundary) return -2;
     size_t n = (size_t)(m->nc * S);
     int ns = scheme == ORC_EULER ? 1 : 3;
     double *rhs = (double *)malloc(n * sizeof(double));
@@ -566,7 +576,6 @@ int orc_run_adjoint(const orc_mesh *m, int lim, int scheme, double dt, int S, in
                     const double *th0, const double *u, const double *tbar_final, double *th0_bar,
                     double *ubar) {
     if (scheme != ORC_EULER && scheme != ORC_SSPRK3) return -1;
-    if (m->n_boundary) return -2;
     size_t n = (size_t)(m->nc * S);
     int ns = scheme == ORC_EULER ? 1 : 3;
     /* Forward pass storing every stage input: states[it][st] is the argument of L in stage st,

@@ -57,8 +57,9 @@ typedef struct orc_mesh orc_mesh;
 
 /* Builds the cell -> faces lists.  Keeps the caller's arrays by pointer (they must outlive the
  * mesh).  Returns NULL on a face index out of range or own == nbr (nbr == -1 marks a boundary
- * face).  The derivative functions below cover closed meshes only (NaN outputs, or -2, on a mesh
- * with boundary faces). */
+ * face).  The derivative functions below cover boundary faces and face distances too: an
+ * inflow value is a constant, an exterior that repeats its face's own cell passes that cell's
+ * tangent and cotangent on. */
 orc_mesh *orc_mesh_new(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                        const double *face_normal, const double *face_area,
                        const double *cell_volume);

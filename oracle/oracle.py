@@ -157,11 +157,6 @@ class OracleMesh:
         if self._inflow is not None and self._S(self._inflow) != self._S(theta):
             raise ValueError("the inflow values were set for another number of scalars")
 
-    def _closed(self) -> None:
-        if self.n_boundary or self._dist is not None:
-            raise ValueError("the oracle's derivatives cover closed meshes without face "
-                             "distances only")
-
     @classmethod
     def from_arrays(cls, m) -> "OracleMesh":
         return cls(m.face_cells, m.face_normal, m.face_area, m.cell_volume, n_cells=m.n_cells)
@@ -202,7 +197,7 @@ class OracleMesh:
 
     def face_values_jvp(self, limiter, theta, u, dtheta):
         """(theta_f, its tangent along dtheta), u held fixed."""
-        self._closed()
+        self._check_S(theta)
         theta, u, dtheta = _f64(theta), _f64(u), _f64(dtheta)
         tf = np.empty((self.n_faces,) + theta.shape[1:])
         dtf = np.empty_like(tf)
@@ -253,7 +248,7 @@ class OracleMesh:
         return th
 
     def rhs_jvp(self, limiter, theta, u, dtheta, du=None) -> np.ndarray:
-        self._closed()
+        self._check_S(theta)
         theta, u, dtheta = _f64(theta), _f64(u), _f64(dtheta)
         out = np.empty_like(theta)
         dup = _ptr(_f64(du)) if du is not None else None
@@ -264,7 +259,7 @@ class OracleMesh:
         return out
 
     def rhs_vjp(self, limiter, theta, u, lam):
-        self._closed()
+        self._check_S(theta)
         theta, u, lam = _f64(theta), _f64(u), _f64(lam)
         tb = np.empty_like(theta)
         ub = np.empty(self.n_faces)
@@ -273,7 +268,7 @@ class OracleMesh:
         return tb, ub
 
     def run_tangent(self, limiter, scheme, dt, theta0, u, nsteps, dtheta0, du=None):
-        self._closed()
+        self._check_S(theta0)
         th = _f64(theta0).copy()
         dth = _f64(dtheta0).copy()
         u = _f64(u)
@@ -286,7 +281,7 @@ class OracleMesh:
         return th, dth
 
     def run_adjoint(self, limiter, scheme, dt, theta0, u, nsteps, theta_bar_final):
-        self._closed()
+        self._check_S(theta0)
         th0 = _f64(theta0)
         u = _f64(u)
         tbf = _f64(theta_bar_final)

@@ -197,16 +197,6 @@ def test_periodic_line_is_an_open_line_with_its_wrap_value():
     assert np.array_equal(got, want)
 
 
-def test_derivatives_refuse_boundary_meshes():
-    m, u = open_line(6, 1.0)
-    om = O.OracleMesh.from_arrays(m)
-    th = np.linspace(0, 1, 6)
-    with pytest.raises(ValueError):
-        om.rhs_vjp("vanalbada", th, u, th)
-    with pytest.raises(ValueError):
-        om.run_adjoint("vanalbada", "euler", 0.01, th, u, 2, th)
-
-
 def test_mesh_checks():
     """nbr = -1 marks a boundary face; own = -1 is not a face."""
     fc = np.array([[0, 1], [1, -1], [-1, 0]], dtype=np.int32)
