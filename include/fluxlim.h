@@ -53,10 +53,10 @@ typedef int32_t fl_status;
 #define FL_E_INVALID -1     /* bad argument: null pointer, size, enum, alignment            */
 #define FL_E_TOPOLOGY -2    /* incidence violates the mesh model (index range, own == nbr,
                                own == -1, two faces joining the same two cells)               */
-#define FL_E_UNSUPPORTED -3 /* valid but outside this library: the adjoint and batching on
-                               cells without opposite face pairs, on meshes with boundary
-                               faces or with unequal face distances; the algebraic chain on
-                               meshes with boundary faces or face distances                  */
+#define FL_E_UNSUPPORTED -3 /* valid but outside this library: the adjoint on cells with
+                               neither opposite face pairs nor projected-face lists; the
+                               multi-step reverse sweep off the fused path; the algebraic
+                               chain on meshes with boundary faces or face distances         */
 #define FL_E_NOMEM -4       /* host or device allocation failed                              */
 #define FL_E_HIP -5         /* a HIP runtime call failed (message in fl_last_error)          */
 #define FL_E_NONFINITE -6   /* an input holds a NaN or an infinity (only reported while the
@@ -159,8 +159,8 @@ fl_status fl_mesh_create(int64_t n_cells, int64_t n_faces, const int32_t *face_c
  * (each projected difference over the distance across its face, the face difference over d_i)
  * do: the upstream difference becomes d_U = sum_j w_j (d_f / d_j)(theta_C - theta_j).  Where all
  * distances are equal every ratio is 1 and the mesh is built as without them; otherwise it runs
- * the face path with the general kernel (the ratios sit in its side weights), and the adjoint
- * and batches refuse it (FL_E_UNSUPPORTED).  face_dist = NULL is fl_mesh_create. */
+ * the face path with the general kernel (the ratios sit in its side weights; the adjoint and
+ * batches take it there).  face_dist = NULL is fl_mesh_create. */
 fl_status fl_mesh_create_dist(int64_t n_cells, int64_t n_faces, const int32_t *face_cells,
                               const double *face_normal, const double *face_area,
                               const double *cell_volume, const double *face_dist, int device,
@@ -248,8 +248,9 @@ fl_status fl_rk_steps_scaled(const fl_mesh *mesh, int limiter, int scheme, doubl
  * opposite face pairs gather everything in one kernel (work may be NULL: 0 bytes); general cells
  * (fl_mesh_info_t.general) run a face kernel that writes each face's terms to work
  * (fl_adjoint_workspace_bytes bytes, 256-byte aligned) and a cell kernel that gathers them
- * through the cell's face list and the transposed projection lists (no atomics).  Meshes with
- * boundary faces or face distances: FL_E_UNSUPPORTED. */
+ * through the cell's face list and the transposed projection lists (no atomics); so do meshes
+ * with boundary faces (an inflow value is a constant; an exterior that repeats its face's own
+ * cell passes that cell's cotangent on) and with face distances. */
 size_t fl_adjoint_workspace_bytes(const fl_mesh *mesh, int n_scalars);
 fl_status fl_convect_adjoint(const fl_mesh *mesh, int limiter, int n_scalars, const double *theta,
                              const double *u_f, const double *rhs_bar, double *theta_bar,

@@ -671,9 +671,10 @@ fl_status fl_rk_step(const fl_mesh *m, int lim, int scheme, double dt, int S, do
 // ------------------------------------------------------------------------------------------
 // Adjoint
 // ------------------------------------------------------------------------------------------
-// General cells (no opposite face pairs) run the two-kernel adjoint, whose face terms need a
-// buffer; the paired kernels gather everything they need.
-static bool general_adjoint(const fl_mesh *m) { return m->h.pairs == 0; }
+// General cells (side lists: projected faces, boundary faces, face distances) run the
+// two-kernel adjoint, whose face terms need a buffer; the paired kernels gather everything they
+// need.
+static bool general_adjoint(const fl_mesh *m) { return m->h.general != 0; }
 
 size_t fl_adjoint_workspace_bytes(const fl_mesh *m, int S) {
     if (!m || S < 1 || S > FL_MAX_SCALARS || !general_adjoint(m)) return 0;
@@ -683,10 +684,6 @@ size_t fl_adjoint_workspace_bytes(const fl_mesh *m, int S) {
 static fl_status check_adjoint(const fl_mesh *m, int lim, int S) {
     fl_status s = check_compute(m, lim, S);
     if (s != FL_OK) return s;
-    if (m->h.n_boundary > 0)
-        return fail(FL_E_UNSUPPORTED, "the adjoint covers closed meshes (no boundary faces)");
-    if (m->h.dist_weighted)
-        return fail(FL_E_UNSUPPORTED, "the adjoint covers meshes without face distances");
     if (m->h.pairs == 0 && !m->h.general)
         return fail(FL_E_UNSUPPORTED,
                     "the adjoint needs cells whose faces form opposite pairs, or side lists");

@@ -10,6 +10,12 @@
 // upwind side), one thread per cell gathers them through its face list and the transposed side
 // lists (the face sides whose d_U names the cell).  Q(u_f) and the limiter branch are held fixed,
 // as on the paired path.
+// Boundary faces (nbr = -1; the flux leaves or enters own alone, mu_f = -lambda_own / V_own):
+// the exterior beyond one holds a constant inflow value (no cotangent) or repeats own, which then
+// takes the exterior's share; a side-list entry ~j (the exterior beyond boundary face j of the
+// upwind cell) is a constant inflow value, whose weight counts in sum_j w_j, or repeats the
+// upwind cell itself, whose difference theta_C - theta_C is identically zero.  Face distances
+// need nothing here: their ratios sit in the side weights.
 #include <hip/hip_runtime.h>
 
 #include "fl_adjoint_device.h"
@@ -25,35 +31,61 @@ __global__ __launch_bounds__(kBlock) void adjoint_face_general_kernel(
     const int32_t *__restrict__ side_cell, const double *__restrict__ side_w,
     const double *__restrict__ u, const double *__restrict__ area, double area0,
     const double *__restrict__ vol, double ivol0, const double *__restrict__ th,
-    const double *__restrict__ lam, double scale, double *__restrict__ term,
-    double *__restrict__ ubar) {
+    const double *__restrict__ lam, const double *__restrict__ inflow, double scale,
+    double *__restrict__ term, double *__restrict__ ubar) {
     const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (f >= nf) return;
     const int4 e = fc4[f];
-    const int64_t own = e.x, nbr = e.y;
+    const int64_t own = e.x, nbr = e.y;  // nbr = -1: a boundary face
+    const bool bnd = nbr < 0;
     const double uf = u[f];
     const bool pos = uf > 0.0;
-    const int64_t C = pos ? own : nbr, D = pos ? nbr : own;
+    const int64_t C = pos ? own : nbr, D = pos ? nbr : own;  // -1: the exterior
+    const bool c_in = C < 0 && inflow;  // the exterior upwind holds the inflow value
     const double af = area ? area[f] : area0;
-    const double ivo = vol ? 1.0 / vol[own] : ivol0, ivn = vol ? 1.0 / vol[nbr] : ivol0;
+    const double ivo = vol ? 1.0 / vol[own] : ivol0;
+    const double ivn = bnd ? 0.0 : (vol ? 1.0 / vol[nbr] : ivol0);
     const int64_t side = 2 * f + (pos ? 0 : 1);
     const int32_t p0 = side_ptr[side], p1 = side_ptr[side + 1];
+    // the weights of the entries whose value does not follow theta_C
     double wsum = 0.0;
-    for (int32_t p = p0; p < p1; ++p) wsum += side_w[p];
+    for (int32_t p = p0; p < p1; ++p) {
+        const int32_t j = side_cell[p];
+        if (j >= 0 || (inflow && !(u[~j] > 0.0))) wsum += side_w[p];
+    }
     double usum = 0.0;
     double *t = term + f * 4 * S;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const double tC = th[C * S + s], tD = th[D * S + s];
+        double tC, tD;
+        if (C >= 0) {
+            tC = th[C * S + s];
+            tD = D >= 0 ? th[D * S + s] : tC;
+        } else {
+            tD = th[D * S + s];
+            tC = c_in ? inflow[f * S + s] : tD;
+        }
         double dU = 0.0;
-        for (int32_t p = p0; p < p1; ++p) dU += side_w[p] * (tC - th[(int64_t)side_cell[p] * S + s]);
+        for (int32_t p = p0; p < p1; ++p) {
+            const int32_t j = side_cell[p];
+            double v = tC;
+            if (j >= 0) v = th[(int64_t)j * S + s];
+            else if (inflow && !(u[~j] > 0.0)) v = inflow[(int64_t)~j * S + s];
+            dU += side_w[p] * (tC - v);
+        }
         double ga, gb;
         const double tf = face_value_ab<LIM>(tC, dU, tD - tC, ga, gb);
-        const double mu = cot_diff(lam[nbr * S + s], ivn, lam[own * S + s], ivo);
+        const double mu = cot_diff(bnd ? 0.0 : lam[nbr * S + s], ivn, lam[own * S + s], ivo);
         const double z = af * uf * mu;
         const double tc = mul_nc(z, 1.0 - gb + ga * wsum), td = mul_nc(z, gb);
-        t[s] = pos ? tc : td;
-        t[S + s] = pos ? td : tc;
+        if (!bnd) {
+            t[s] = pos ? tc : td;
+            t[S + s] = pos ? td : tc;
+        } else {
+            // own takes the exterior's share where the exterior repeats it
+            t[s] = pos ? tc + td : (c_in ? td : td + tc);
+            t[S + s] = 0.0;
+        }
         const double zg = mul_nc(z, ga);
         t[2 * S + s] = pos ? zg : 0.0;
         t[3 * S + s] = pos ? 0.0 : zg;
@@ -124,8 +156,8 @@ hipError_t launch_g2(const fl_mesh *m, const double *u, const double *th, const 
     const double scale = mode == ADJ_APPLY ? 1.0 : b * dt;
     adev::adjoint_face_general_kernel<S, LIM><<<nbf, adev::kBlock, 0, st>>>(
         m->h.nf, reinterpret_cast<const int4 *>(m->d_fc4), m->d_side_ptr, m->d_side_cell,
-        m->d_side_w, u, m->d_area, m->h.area0, m->d_vol, 1.0 / m->h.vol0, th, lam, scale, term,
-        ubar);
+        m->d_side_w, u, m->d_area, m->h.area0, m->d_vol, 1.0 / m->h.vol0, th, lam, m->inflow,
+        scale, term, ubar);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     adev::adjoint_cell_general_kernel<S><<<nbc, adev::kBlock, 0, st>>>(

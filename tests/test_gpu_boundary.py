@@ -7,7 +7,10 @@ test_oracle_boundary.py.  Here the library runs it on the face path with the gen
 one operator application is compared at 1e-13 of max|rhs| and whole runs at the 1e-10 max
 norm-relative error of the cell values, as for closed meshes.  The inflow arrays hold NaN on the
 rows the rule never reads (interior faces and outflow faces), so a stray read shows.  The
-distance weighting (Algorithm 1D / UNS ratios) is pinned in test_oracle_distances.py.
+distance weighting (Algorithm 1D / UNS ratios) is pinned in test_oracle_distances.py, and the
+oracle's derivatives on such meshes in test_oracle_open_derivatives.py; the adjoint tests at the
+end compare the library's with them (1e-12 of the largest cotangent for one application, 1e-10
+for reverse sweeps, as on closed meshes).
 """
 
 import numpy as np
@@ -147,18 +150,12 @@ def test_inflow_scalar_count_must_match():
     mesh.close()
 
 
-def test_adjoint_and_algebraic_refuse_boundary_meshes():
+def test_algebraic_refuses_boundary_meshes():
     wl = W.workload_open_box(6)
     mesh, cp, fp = library(wl.mesh, None)
-    th = dev(rows_to_mesh(wl.theta0, cp))
-    u = dev(rows_to_mesh(wl.u, fp))
-    unsupported = -3
-    with pytest.raises(_lib.FluxLimError) as e:
-        FL.convect_adjoint(mesh, "vanalbada", th, u, torch.ones_like(th))
-    assert e.value.status == unsupported
     with pytest.raises(_lib.FluxLimError) as e:
         FL.Algebraic(mesh)
-    assert e.value.status == unsupported
+    assert e.value.status == -3  # unsupported
     mesh.close()
 
 
@@ -193,4 +190,72 @@ def test_distance_weighted_apply_and_run(lim, S, case):
     th = dev(rows_to_mesh(th0, cp))
     FL.rk_steps(mesh, lim, "ssprk3", dt, th, ud, 10)
     assert nrel(host(th)[cp], want) <= RUN_TOL
+    mesh.close()
+
+
+def _adjoint_case(case, S):
+    """(mesh arrays, theta, u, inflow or None): an open box with or without inflow values, or a
+    stretched box (face distances), periodic or open with inflow values."""
+    rng = np.random.default_rng(21 + S)
+    if case.startswith("open_box"):
+        wl = W.workload_open_box(7, renumbered=True, S=S)
+        th = wl.theta0 + 0.05 * rng.standard_normal(wl.theta0.shape)
+        th[::5] = np.round(th[::5], 1)  # plateaus next to the boundary too
+        return wl.mesh, th, wl.u, (wl.inflow if case == "open_box_inflow" else None)
+    open_axes = (0,) if case == "stretched_open" else ()
+    nat = W.stretched_box(8, 3, amp=0.5, open_axes=open_axes)
+    u_nat = W.velocity_open_box(nat)
+    th_nat = W.field_blob_step(8)
+    if S > 1:
+        th_nat = W.multi_scalar([th_nat + 0.2 * k for k in range(S)])
+    m = W.renumber(nat, seed=23)
+    inflow = m.face_field_from_natural(W.inflow_values(nat, u_nat, S)) if open_axes else None
+    th = m.cell_field_from_natural(th_nat) + 0.01 * rng.standard_normal((m.n_cells,) + th_nat.shape[1:])
+    return m, th, m.face_velocity_from_natural(u_nat), inflow
+
+
+ADJ_CASES = ["open_box_inflow", "open_box", "stretched", "stretched_open"]
+
+
+@pytest.mark.parametrize("S", [1, 2])
+@pytest.mark.parametrize("case", ADJ_CASES)
+def test_adjoint_matches_oracle_on_boundary_and_distance_meshes(case, S):
+    m, th, u, inflow = _adjoint_case(case, S)
+    mesh, cp, fp = library(m, inflow, reorder=True)
+    om = O.OracleMesh.from_arrays(m)
+    om.set_distances(m.face_dist)
+    om.set_inflow(inflow)
+    rng = np.random.default_rng(31)
+    lam = rng.standard_normal(th.shape)
+    thd, ud, lamd = dev(rows_to_mesh(th, cp)), dev(rows_to_mesh(u, fp)), dev(rows_to_mesh(lam, cp))
+    for lim in LIMS:
+        tb, ub = FL.convect_adjoint(mesh, lim, thd, ud, lamd)
+        tb_o, ub_o = om.rhs_vjp(lim, th, u, lam)
+        assert np.abs(host(tb)[cp] - tb_o).max() <= 1e-12 * np.abs(tb_o).max(), lim
+        assert np.abs(host(ub)[fp] - ub_o).max() <= 1e-12 * np.abs(ub_o).max(), lim
+    mesh.close()
+
+
+@pytest.mark.parametrize("scheme", ["ssprk3", "euler"])
+@pytest.mark.parametrize("lim", ["vanalbada", "superbee", "smart", "minmod"])
+@pytest.mark.parametrize("case", ADJ_CASES)
+def test_run_adjoint_matches_oracle_on_boundary_and_distance_meshes(case, lim, scheme):
+    """advect's backward (per-step reverse, checkpointed) against the oracle's stored sweep."""
+    m, th, u, inflow = _adjoint_case(case, 1)
+    mesh, cp, fp = library(m, inflow, reorder=True)
+    om = O.OracleMesh.from_arrays(m)
+    om.set_distances(m.face_dist)
+    om.set_inflow(inflow)
+    dt = W.cfl_dt(m, u, 0.4)
+    steps = 6
+    lam_N = np.random.default_rng(33).standard_normal(th.shape)
+    t0 = dev(rows_to_mesh(th, cp)).requires_grad_(True)
+    ud = dev(rows_to_mesh(u, fp)).requires_grad_(True)
+    out = FL.advect(mesh, lim, scheme, dt, t0, ud, steps, checkpoint_every=4)
+    out.backward(dev(rows_to_mesh(lam_N, cp)))
+    tb_o, ub_o = om.run_adjoint(lim, scheme, dt, th, u, steps, lam_N)
+    assert np.abs(host(t0.grad)[cp] - tb_o).max() <= 1e-10 * np.abs(tb_o).max()
+    assert np.abs(host(ud.grad)[fp] - ub_o).max() <= 1e-10 * np.abs(ub_o).max()
+    want = om.run(lim, scheme, dt, th, u, steps)
+    assert nrel(host(out)[cp], want) <= RUN_TOL
     mesh.close()
