@@ -113,6 +113,17 @@ def fused_stage_bytes(C, F, K, S, stage, slot_velocity=True):
     return b
 
 
+def batch_stage_bytes(C, F, K, S, stage, halo_total):
+    """Compulsory bytes of one problem's share of a batched LDS-staged stage launch (the face
+    velocities gathered through the face index): local slot indices and slot face words (4 + 4 B
+    per slot), each face velocity once, the tile halo lists (4 B per entry), theta_s read once,
+    theta_n read once (stages 2, 3) and the output written once."""
+    b = C * K * 8 + F * 8 + 4 * halo_total + C * S * 8 * 2
+    if stage > 0:
+        b += C * S * 8
+    return b
+
+
 def adjoint_ratio(args, torch, FL, W, dev):
     """Adjoint configuration: 128^3 periodic box, van Albada, SSP-RK3 at CFL 0.4, 400 steps,
     J = |theta_N - target|^2 / 2 with a seeded smooth target; gradients w.r.t. theta_0 and u_f
@@ -191,6 +202,7 @@ def batch_compare(args, torch, FL, W, dev):
     meshes, vel = {}, {}
     problems = []
     face_updates = 0
+    step_bytes = 0  # compulsory bytes of one batched SSP-RK3 step (LDS-staged kernel)
     for p in recipe:
         if p.n not in meshes:
             m = W.box_shared_cache(p.n)
@@ -202,6 +214,10 @@ def batch_compare(args, torch, FL, W, dev):
         ud = mesh.faces_to_mesh(torch.from_numpy(u).to(dev))
         problems.append((mesh, p.limiter, theta, ud, W.cfl_dt(m, u, p.cfl)))
         face_updates += m.n_faces * p.n_scalars * 3
+        info = mesh.info
+        step_bytes += sum(batch_stage_bytes(m.n_cells, m.n_faces, 2 * int(info.pairs),
+                                            p.n_scalars, s, int(info.halo_total))
+                          for s in range(3))
     W._BOX_CACHE.clear()
     log(f"batch of {len(problems)} problems ({len(meshes)} distinct meshes) built in "
         f"{_t.time() - t0:.1f}s")
@@ -259,9 +275,55 @@ def batch_compare(args, torch, FL, W, dev):
             "unbatched_gather_kernel_ms_per_step": round(gather_ms, 3),
             "speedup": round(best_ms / batched_ms, 3),
             "batched_gface_updates_per_s": round(face_updates / (batched_ms * 1e-3) / 1e9, 2),
+            # the batched step's compulsory bytes (batch_stage_bytes over problems and stages)
+            # over its time: launches, gaps and the stage tails included
+            "roofline": {"bound": "hbm", "bytes_per_step": int(step_bytes),
+                         "achieved": round(step_bytes / (batched_ms * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(step_bytes / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "unbatched_achieved": round(step_bytes / (best_ms * 1e-3) / 1e9, 1)}
+            if staged else None,
             "lds_staged": staged,
             "autotuned_tile_cells": tile,
             "create_s": round(create_s, 3), "tile_from_tuning_cache": from_cache}
+
+
+def scalar_sweep(args, torch, FL, W, dev):
+    """Forward stage against the scalar count S on one periodic box (library reorder, van Leer,
+    SSP-RK3, one multi-step call per S): ms per step, face-scalar updates per second and the
+    compulsory bytes of the forward-rate LDS stage (lds_fwd_stage_bytes) per second."""
+    n = args.scalar_sweep_n
+    wl = W.workload_box(n, renumbered=True)
+    mesh = FL.Mesh.from_arrays(wl.mesh, device=0, reorder=True)
+    info = mesh.info
+    C, F = mesh.n_cells, mesh.n_faces
+    u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = 10
+    rows = []
+    for S in [int(x) for x in args.scalar_sweep.split(",") if x]:
+        th0 = np.stack([wl.theta0 + 0.1 * k for k in range(S)], 1) if S > 1 else wl.theta0
+        th = mesh.cells_to_mesh(torch.from_numpy(np.ascontiguousarray(th0)).to(dev))
+        work = FL.rk_workspace(mesh, "ssprk3", S)
+        FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, u, 2, work=work)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, u, steps, work=work)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        byts = sum(lds_fwd_stage_bytes(C, 2 * int(info.pairs), S, s, int(info.halo_total),
+                                       int(info.halo_nexts)) for s in range(3))
+        rows.append({"scalars": S, "ms_per_step": round(ms, 4),
+                     "gface_scalar_updates_per_s": round(F * S * 3 / (ms * 1e-3) / 1e9, 1),
+                     "compulsory_gbs": round(byts / (ms * 1e-3) / 1e9, 1)})
+        log(f"scalars {S}: {ms:.4f} ms/step, {rows[-1]['gface_scalar_updates_per_s']} G "
+            f"face-scalar updates/s, {rows[-1]['compulsory_gbs']} GB/s")
+        del th, work
+    mesh.close()
+    return {"workload": f"periodic hex box {n}^3, library reorder, van Leer, SSP-RK3, "
+                        f"{steps} steps per scalar count", "rows": rows}
 
 
 def deformation(args, torch, FL, W, dev):
@@ -387,6 +449,9 @@ def main():
                          "timing (profiling runs of the other parts; the line's value is null)")
     ap.add_argument("--deformation", default="",
                     help="comma-separated box sides for the deformation benchmark (e.g. 72,144)")
+    ap.add_argument("--scalar-sweep", default="",
+                    help="comma-separated scalar counts: forward stage against S (e.g. 1,2,4,8)")
+    ap.add_argument("--scalar-sweep-n", type=int, default=128)
     ap.add_argument("--batch-count", type=int, default=512, help="problems in the batch (0 to skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--adjoint-steps", type=int, default=400,
@@ -638,6 +703,9 @@ def main():
 
     if args.deformation:
         out["deformation"] = deformation(args, torch, FL, W, dev)
+
+    if args.scalar_sweep:
+        out["scalar_sweep"] = scalar_sweep(args, torch, FL, W, dev)
 
     if args.algebraic:
         out["algebraic"] = algebraic_compare(args, torch, FL, W, dev)

@@ -101,42 +101,71 @@ __device__ __forceinline__ double face_value_d(int lim, double tC, double du, do
 // src[i * SST + SOFF + s] for s < CS: src is theta_s itself (SST = S, SOFF = S0, global indices)
 // or a tile's LDS copy of this chunk (SST = CS, SOFF = 0, local indices); tn and out are indexed
 // by the global cell c.
-// PRE: theta_n of the chunk was loaded ahead into tnv (stage-combination mode only).
-template <int S, int P, int S0, int CS, int SST, int SOFF, bool PRE = false>
+// PRE: theta_n of the chunk was loaded ahead into tnv (stage-combination mode only).  IDX: the
+// index type (64-bit global cell indices, or 32-bit tile-local ones, fewer registers to keep
+// across the chunks of many scalars).
+template <int S, int P, int S0, int CS, int SST, int SOFF, bool PRE = false,
+          typename IDX = int64_t>
 __device__ __forceinline__ void fused_chunk(int64_t c, int64_t cs, const double *src,
-                                            const double *w, const int64_t *nb, const int64_t *gf,
+                                            const double *w, const IDX *nb, const IDX *gf,
                                             double V, const double *__restrict__ tn, double a,
                                             double b, double dt, int mode, int lim,
                                             double *__restrict__ out,
                                             const double *tnv = nullptr) {
     constexpr int K = 2 * P;
-    double tc[CS], tnb[K][CS], tg[K][CS];
+    double tc[CS], acc[CS];
 #pragma unroll
     for (int i = 0; i < CS; ++i) tc[i] = src[cs * SST + SOFF + i];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int i = 0; i < CS; ++i) tnb[k][i] = src[nb[k] * SST + SOFF + i];
-        if (lim != FL_UPWIND) {
-#pragma unroll
-            for (int i = 0; i < CS; ++i) tg[k][i] = src[gf[k] * SST + SOFF + i];
-        }
-    }
-    double acc[CS];
-#pragma unroll
     for (int i = 0; i < CS; ++i) acc[i] = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        // Q(u_f): c is the upwind cell C of its face k where the flow leaves c (w_k > 0);
-        // where w_k == 0 the flux vanishes whichever cell is taken
+    // Face k of the cell: Q(u_f) makes c the upwind cell C where the flow leaves c (w_k > 0;
+    // where w_k == 0 the flux vanishes whichever cell is taken).  tnk: the neighbour across k,
+    // tno: across the opposite slot k ^ 1, tgk: the far cell beyond the neighbour.
+    auto face = [&](int k, const double *tnk, const double *tno, const double *tgk) {
         const bool c_upwind = w[k] > 0.0;
 #pragma unroll
         for (int i = 0; i < CS; ++i) {
             // pick (theta_C, theta_D, theta_U) first: one evaluation where lanes diverge
-            const double tC = c_upwind ? tc[i] : tnb[k][i];
-            const double tD = c_upwind ? tnb[k][i] : tc[i];
-            const double tU = c_upwind ? tnb[k ^ 1][i] : tg[k][i];
+            const double tC = c_upwind ? tc[i] : tnk[i];
+            const double tD = c_upwind ? tnk[i] : tc[i];
+            const double tU = c_upwind ? tno[i] : tgk[i];
             acc[i] -= w[k] * face_value(lim, tC, tD, tU);
+        }
+    };
+    if constexpr (S <= 2) {
+        // one chunk: every gather issued ahead
+        double tnb[K][CS], tg[K][CS];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = 0; i < CS; ++i) tnb[k][i] = src[nb[k] * SST + SOFF + i];
+            if (lim != FL_UPWIND) {
+#pragma unroll
+                for (int i = 0; i < CS; ++i) tg[k][i] = src[gf[k] * SST + SOFF + i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) face(k, tnb[k], tnb[k ^ 1], tg[k]);
+    } else {
+        // several chunks: the gathers of one slot pair at a time (the slot tables stay live
+        // across the chunks; fewer registers keep more waves resident); same order of the sum
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double t0[CS], t1[CS], g0[CS], g1[CS];
+#pragma unroll
+            for (int i = 0; i < CS; ++i) {
+                t0[i] = src[nb[2 * p] * SST + SOFF + i];
+                t1[i] = src[nb[2 * p + 1] * SST + SOFF + i];
+            }
+            if (lim != FL_UPWIND) {
+#pragma unroll
+                for (int i = 0; i < CS; ++i) {
+                    g0[i] = src[gf[2 * p] * SST + SOFF + i];
+                    g1[i] = src[gf[2 * p + 1] * SST + SOFF + i];
+                }
+            }
+            face(2 * p, t0, t1, g0);
+            face(2 * p + 1, t1, t0, g1);
         }
     }
     // The stage combination with its roundings written out (explicit fma), so that every kernel
@@ -354,8 +383,8 @@ template <int P, bool RATES>
 __device__ __forceinline__ void tile_slots_finish(const SlotRaw<P, RATES> &raw,
                                                   const double *__restrict__ u,
                                                   const double *__restrict__ area, bool has_area,
-                                                  double area0, double us, int64_t *nb,
-                                                  int64_t *gf, double *w) {
+                                                  double area0, double us, int32_t *nb,
+                                                  int32_t *gf, double *w) {
 #pragma unroll
     for (int k = 0; k < 2 * P; ++k) {
         nb[k] = raw.l[k] & 0xffffu;
@@ -379,7 +408,7 @@ __device__ __forceinline__ void tile_chunks(int64_t nc, int64_t tile, double *ld
                                             const int32_t *__restrict__ halo_ptr,
                                             const int32_t *__restrict__ halo,
                                             const double *__restrict__ ts, bool active, int64_t c,
-                                            const double *w, const int64_t *nb, const int64_t *gf,
+                                            const double *w, const int32_t *nb, const int32_t *gf,
                                             double V, const double *__restrict__ tn, double a,
                                             double b, double dt, int mode, int lim,
                                             double *__restrict__ out) {
@@ -418,7 +447,7 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
                                            double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
     constexpr int CS0 = S >= 2 ? 2 : 1;
-    int64_t nb[K], gf[K];
+    int32_t nb[K], gf[K];  // tile-local indices
     double w[K];
     SlotRaw<P, RATES> raw;
     double tnv[CS0];
@@ -547,7 +576,7 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
     __syncthreads();
     const bool active = tid < nt;
     const int64_t cc = c0 + tid;
-    int64_t nb[K], gf[K];
+    int32_t nb[K], gf[K];  // tile-local indices
     double w[K];
     double V = vol0;
     if (active) {
