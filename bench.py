@@ -76,6 +76,11 @@ def measured_traffic(n, xcd_remap, slot_velocity, lds_stage, fwd_rates=True):
         return None
 
 
+def fwd_chunk(S):
+    """Scalars the forward-rate LDS stage stages at a time (the library's fwd_chunk)."""
+    return 2 if S == 4 else min(S, 3)
+
+
 def lds_stage_bytes(C, K, S, stage, halo_total):
     """Compulsory bytes of one LDS-staged stage launch: local slot indices (4 B per slot), the
     per-call signed face rates (8 B per slot), the tile halo lists (4 B per entry), theta_s read
@@ -623,10 +628,10 @@ def main():
             lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
                 (r["tile_cells"] + r["max_halo"]) * min(S, 2) * 8 <= 64 * 1024
             # the library's own choice (lds_fwd_bytes): compact tables and a staged tile of at
-            # most 32 KiB
+            # most 32 KiB (fwd_chunk(S) scalars staged at a time)
             words = K // 2 * r["tile_cells"] * 4 + (r["max_nexts"] + 1) * 2
             fwd = lds and r["aligned"] and r["compact"] and bool(args.fwd_rates) and \
-                ((r["tile_cells"] + r["max_halo"] + 1) * min(S, 2) + K // 2 * r["tile_cells"]
+                ((r["tile_cells"] + r["max_halo"] + 1) * fwd_chunk(S) + K // 2 * r["tile_cells"]
                  + r["max_rated"] + 1) * 8 + (words + 7) // 8 * 8 <= 32 * 1024
             if fwd:
                 kname = "fused_stage_lds_fwd_kernel"

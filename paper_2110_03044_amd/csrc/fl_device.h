@@ -402,8 +402,9 @@ __device__ __forceinline__ void tile_slots_finish(const SlotRaw<P, RATES> &raw,
 }
 
 // Chunks S0.. (S0 > 0) of one tile: barrier (the previous chunk's LDS reads are done), stage the
-// chunk (all threads), barrier, each cell of the tile computes it from LDS.
-template <int S, int P, int S0>
+// chunk (all threads), barrier, each cell of the tile computes it from LDS.  Chunks of at most
+// CMAX scalars.
+template <int S, int P, int S0, int CMAX = 2>
 __device__ __forceinline__ void tile_chunks(int64_t nc, int64_t tile, double *lds,
                                             const int32_t *__restrict__ halo_ptr,
                                             const int32_t *__restrict__ halo,
@@ -413,15 +414,15 @@ __device__ __forceinline__ void tile_chunks(int64_t nc, int64_t tile, double *ld
                                             double b, double dt, int mode, int lim,
                                             double *__restrict__ out) {
     if constexpr (S0 < S) {
-        constexpr int CS = (S - S0) >= 2 ? 2 : 1;
+        constexpr int CS = (S - S0) >= CMAX ? CMAX : S - S0;
         __syncthreads();
         tile_stage<S, S0, CS>(nc, tile, lds, halo_ptr, halo, ts);
         __syncthreads();
         if (active)
             fused_chunk<S, P, S0, CS, CS, 0>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt, mode,
                                              lim, out);
-        tile_chunks<S, P, S0 + CS>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf, V, tn,
-                                   a, b, dt, mode, lim, out);
+        tile_chunks<S, P, S0 + CS, CMAX>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf,
+                                         V, tn, a, b, dt, mode, lim, out);
     }
 }
 
@@ -502,7 +503,7 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
                                                double dt, int mode, int lim,
                                                double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
-    constexpr int CS = S >= 2 ? 2 : 1;
+    constexpr int CS = fwd_chunk(S);
     constexpr uint32_t T = kTileCells;
     const int64_t c0 = tile * kTileCells;
     const int64_t left = nc - c0;
@@ -598,8 +599,8 @@ __device__ __forceinline__ void fused_tile_fwd(int64_t nc, int64_t tile, double 
         fused_chunk<S, P, 0, CS, CS, 0, PRE>(cc, tid, lds, w, nb, gf, V, tn, a, b, dt, mode, lim,
                                              out, tnv);
     }
-    tile_chunks<S, P, CS>(nc, tile, lds, halo_ptr, halo, ts, active, cc, w, nb, gf, V, tn, a, b,
-                          dt, mode, lim, out);
+    tile_chunks<S, P, CS, fwd_chunk(S)>(nc, tile, lds, halo_ptr, halo, ts, active, cc, w, nb, gf, V,
+                                     tn, a, b, dt, mode, lim, out);
 }
 
 }  // namespace dev

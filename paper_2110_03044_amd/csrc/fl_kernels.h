@@ -98,6 +98,10 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
 // Forward-rate stage (meshes with aligned slots, fused_tile_fwd): per-call rates of the forward
 // faces rf[P][C]; LDS of lds_fwd_bytes(m, S) (0: not available).
 constexpr size_t kMaxFwdLds = 32 * 1024;
+// Scalars the forward-rate stage stages in LDS at a time (the other LDS stages: two): three,
+// which halves the barriers and round trips per tile at S = 6, 8 and makes S = 3 one chunk; at
+// S = 4 two chunks of two keep a wave per SIMD more than 3 + 1 (measured on 128^3 boxes).
+constexpr int fwd_chunk(int S) { return S == 4 ? 2 : (S < 3 ? S : 3); }
 size_t lds_fwd_bytes(const fl_mesh *m, int S);
 hipError_t launch_slot_rates_fwd(const fl_mesh *m, const double *u, double *rf, hipStream_t st);
 hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *ts,

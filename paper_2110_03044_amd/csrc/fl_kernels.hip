@@ -362,8 +362,8 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
 int g_lds_stage = 1;
 void set_lds_stage(int on) { g_lds_stage = on; }
 
-// The forward stage stages at most two scalars at a time; the adjoint stages theta and lambda of
-// every scalar at once.
+// The per-slot LDS stage stages at most two scalars at a time (the forward-rate stage fwd_chunk);
+// the adjoint stages theta and lambda of every scalar at once.
 size_t lds_stage_bytes(const fl_mesh *m, int S) {
     if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
     return (size_t)(kTileCells + m->h.max_halo + 1) * (S < 2 ? S : 2) * sizeof(double);
@@ -421,10 +421,14 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
     return hipGetLastError();
 }
 
+// The forward-rate stage's chunk area (doubles): fwd_chunk(S) scalars per cell.
+static size_t fwd_theta_doubles(const fl_mesh *m, int S) {
+    return (size_t)(kTileCells + m->h.max_halo + 1) * fwd_chunk(S);
+}
+
 // Offset (in doubles) of the tile words in the forward-rate stage's LDS.
 static size_t fwd_nbase(const fl_mesh *m, int S) {
-    return lds_stage_bytes(m, S) / sizeof(double) + (size_t)m->h.pairs * kTileCells +
-           m->h.max_nrate0 + 1;
+    return fwd_theta_doubles(m, S) + (size_t)m->h.pairs * kTileCells + m->h.max_nrate0 + 1;
 }
 
 size_t lds_fwd_bytes(const fl_mesh *m, int S) {
@@ -460,7 +464,7 @@ hipError_t launch_fused_lds_fwd(const fl_mesh *m, int lim, int S, const double *
                                 int mode, double *out, hipStream_t st, double us) {
     const size_t lds = lds_fwd_bytes(m, S);
     if (lds == 0 || lds > kMaxStageLds || !rf) return hipErrorInvalidValue;
-    const int rbase = (int)(lds_stage_bytes(m, S) / sizeof(double));
+    const int rbase = (int)fwd_theta_doubles(m, S);
     const int nbase = (int)fwd_nbase(m, S);
     const Grid g = grid_for(m->h.nc, g_remap);
 #define FL_FWD_K(SS, P, L)                                                                     \
