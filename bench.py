@@ -626,7 +626,7 @@ def main():
             launches = 3 * n_steps_total
             sv = bool(args.slot_velocity) and args.steps >= 2
             lds = sv and bool(args.lds_stage) and r["max_halo"] >= 0 and \
-                (r["tile_cells"] + r["max_halo"]) * min(S, 2) * 8 <= 64 * 1024
+                (r["tile_cells"] + r["max_halo"]) * fwd_chunk(S) * 8 <= 64 * 1024
             # the library's own choice (lds_fwd_bytes): compact tables and a staged tile of at
             # most 32 KiB (fwd_chunk(S) scalars staged at a time)
             words = K // 2 * r["tile_cells"] * 4 + (r["max_nexts"] + 1) * 2

@@ -447,7 +447,7 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
                                            double dt, int mode, int lim,
                                            double *__restrict__ out, double us) {
     constexpr int K = 2 * P;
-    constexpr int CS0 = S >= 2 ? 2 : 1;
+    constexpr int CS0 = fwd_chunk(S);
     int32_t nb[K], gf[K];  // tile-local indices
     double w[K];
     SlotRaw<P, RATES> raw;
@@ -464,8 +464,8 @@ __device__ __forceinline__ void fused_tile(int64_t nc, int64_t tile, double *lds
         fused_chunk<S, P, 0, CS0, CS0, 0, PRE>(c, threadIdx.x, lds, w, nb, gf, V, tn, a, b, dt,
                                                mode, lim, out, tnv);
     }
-    tile_chunks<S, P, CS0>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf, V, tn, a, b,
-                           dt, mode, lim, out);
+    tile_chunks<S, P, CS0, fwd_chunk(S)>(nc, tile, lds, halo_ptr, halo, ts, active, c, w, nb, gf,
+                                         V, tn, a, b, dt, mode, lim, out);
 }
 
 // The stage of one tile on a mesh with aligned slots (the neighbour across slot k of a cell holds

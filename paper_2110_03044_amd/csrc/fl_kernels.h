@@ -80,9 +80,9 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
                             const void *rec, double a, double b, double dt, int mode, double *out,
                             hipStream_t st, double us = 1.0);
 // LDS-staged stage (fused path with tile tables): per-call rates rate[2P][C] (8 bytes per slot)
-// and one workgroup per tile with lds_stage_bytes(m, S) = (tile + max halo + 1) * min(S, 2) doubles
-// of dynamic LDS (scalars staged two at a time); used while that is at most kMaxStageLds (0 = no
-// tile tables).
+// and one workgroup per tile with lds_stage_bytes(m, S) = (tile + max halo + 1) * fwd_chunk(S)
+// doubles of dynamic LDS (fwd_chunk(S) scalars staged at a time); used while that is at most
+// kMaxStageLds (0 = no tile tables).
 // The adjoint stage stages theta and lambda: adjoint_lds_bytes(m, S).  Both are 0 while
 // FL_OPT_LDS_STAGE is off (set_lds_stage).
 constexpr size_t kMaxStageLds = 64 * 1024;
@@ -98,7 +98,7 @@ hipError_t launch_fused_lds(const fl_mesh *m, int lim, int S, const double *ts, 
 // Forward-rate stage (meshes with aligned slots, fused_tile_fwd): per-call rates of the forward
 // faces rf[P][C]; LDS of lds_fwd_bytes(m, S) (0: not available).
 constexpr size_t kMaxFwdLds = 32 * 1024;
-// Scalars the forward-rate stage stages in LDS at a time (the other LDS stages: two): three,
+// Scalars the LDS-staged forward stages (single-problem and batched) stage at a time: three,
 // which halves the barriers and round trips per tile at S = 6, 8 and makes S = 3 one chunk; at
 // S = 4 two chunks of two keep a wave per SIMD more than 3 + 1 (measured on 128^3 boxes).
 constexpr int fwd_chunk(int S) { return S == 4 ? 2 : (S < 3 ? S : 3); }

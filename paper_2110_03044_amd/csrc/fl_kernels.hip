@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void fused_stage_lds_fwd_kernel(
 }
 
 // One workgroup per tile of kTileCells cells; dynamic LDS of (kTileCells + max halo + 1) *
-// min(S, 2) doubles.
+// fwd_chunk(S) doubles.
 template <int S, int P, bool RATES>
 __global__ __launch_bounds__(kBlock) void fused_stage_lds_kernel(
     int64_t nc, const int32_t *__restrict__ halo_ptr, const int32_t *__restrict__ halo,
@@ -362,11 +362,11 @@ hipError_t launch_fused_rec(const fl_mesh *m, int lim, int S, const double *ts, 
 int g_lds_stage = 1;
 void set_lds_stage(int on) { g_lds_stage = on; }
 
-// The per-slot LDS stage stages at most two scalars at a time (the forward-rate stage fwd_chunk);
-// the adjoint stages theta and lambda of every scalar at once.
+// The forward LDS stages stage fwd_chunk(S) scalars at a time; the adjoint stages theta and
+// lambda of every scalar at once.
 size_t lds_stage_bytes(const fl_mesh *m, int S) {
     if (!g_lds_stage || m->path != FL_PATH_FUSED || m->h.max_halo < 0 || !m->d_slot_local) return 0;
-    return (size_t)(kTileCells + m->h.max_halo + 1) * (S < 2 ? S : 2) * sizeof(double);
+    return (size_t)(kTileCells + m->h.max_halo + 1) * fwd_chunk(S) * sizeof(double);
 }
 
 size_t adjoint_lds_bytes(const fl_mesh *m, int S) {
