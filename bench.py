@@ -331,6 +331,77 @@ def scalar_sweep(args, torch, FL, W, dev):
                         f"{steps} steps per scalar count", "rows": rows}
 
 
+def face_path_stage_bytes(C, F, S, stage, side_entries, deg_sum, areas, vols):
+    """Compulsory bytes of one stage on the face path (face kernel + cell kernel): per face its
+    record (16 B), velocity (8 B), side pointers (8 B), the entries of its upwind side list (12 B
+    each; half of all entries on average), the flux written and read back (8 B per scalar each);
+    per cell its face list (4 B pointer, 4 B per face), theta_s read by each kernel once, the
+    output written, theta_n read (stages 2, 3); face areas and cell volumes where given."""
+    b = F * (16 + 8 + 8 + 16 * S) + 12 * side_entries // 2 + C * 4 + 4 * deg_sum
+    b += C * S * 8 * 3 + (C * S * 8 if stage > 0 else 0)
+    b += (F * 8 if areas else 0) + (C * 8 if vols else 0)
+    return b
+
+
+def face_path(args, torch, FL, W, dev):
+    """The face path (general cells, boundary faces) on two large meshes: a box cut open along x
+    with inflow values (boundary faces; the general kernel) and the periodic triangles (cells
+    whose faces project with several weights).  10 SSP-RK3 steps, van Leer, one multi-step call
+    each; the compulsory bytes of face_path_stage_bytes over the time."""
+    rows = []
+    cases = []
+    n_box, n_tri = args.face_path_n, 2 * args.face_path_n * 4
+    cases.append(("open box %d^3 with inflow values" % n_box, lambda: W.workload_open_box(n_box)))
+    def tri():
+        m = W.periodic_triangles(n_tri)
+        u = W.velocity_stream_triangles(n_tri, seed=4)
+        xy = W.triangle_centroids(n_tri)
+        th = np.exp(-((xy[:, 0] - 0.4) ** 2 + (xy[:, 1] - 0.6) ** 2) / 0.02) + (xy[:, 0] > 0.5)
+        return W.Workload(m, th, u, W.cfl_dt(m, u, 0.4), 10, "ssprk3", "triangles", None)
+    cases.append(("periodic triangles %d x %d x 2" % (n_tri, n_tri), tri))
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = 10
+    for name, make in cases:
+        wl = make()
+        m = wl.mesh
+        mesh = FL.Mesh.from_arrays(m, device=0, reorder=True)
+        cp, fp = mesh.permutation()
+        info = mesh.info
+        assert mesh.path == "face"
+        if wl.inflow is not None:
+            inf = np.empty_like(wl.inflow)
+            inf[fp] = wl.inflow
+            mesh.set_inflow(torch.from_numpy(inf).to(dev))
+        th = mesh.cells_to_mesh(torch.from_numpy(wl.theta0).to(dev))
+        u = mesh.faces_to_mesh(torch.from_numpy(wl.u).to(dev))
+        work = FL.rk_workspace(mesh, "ssprk3", 1)
+        FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, u, 2, work=work)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        FL.rk_steps(mesh, "vanleer", "ssprk3", wl.dt, th, u, steps, work=work)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        C, F = m.n_cells, m.n_faces
+        byts = sum(face_path_stage_bytes(C, F, 1, s, int(info.side_entries), 2 * F,
+                                         not bool(info.uniform_area),
+                                         not bool(info.uniform_volume)) for s in range(3))
+        rows.append({"workload": name, "cells": C, "faces": F,
+                     "boundary_faces": int(info.n_boundary), "side_entries": int(info.side_entries),
+                     "ms_per_step": round(ms, 4),
+                     "gface_updates_per_s": round(F * 3 / (ms * 1e-3) / 1e9, 1),
+                     "bytes_per_step": int(byts),
+                     "achieved_gbs": round(byts / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        log(f"face path, {name}: {ms:.4f} ms/step, {rows[-1]['gface_updates_per_s']} "
+            f"Gface-updates/s, {rows[-1]['achieved_gbs']} GB/s compulsory")
+        mesh.close()
+        del th, u, work, wl, m
+        torch.cuda.empty_cache()
+    return {"scheme": "ssprk3", "limiter": "vanleer", "rows": rows}
+
+
 def deformation(args, torch, FL, W, dev):
     """The paper's deformation benchmark (Section 4.1): sphere r = 0.15 at (0.35, 0.35, 0.35),
     deformation flow reversed by cos(pi t / T), T = 3, superbee, SSP-RK3 at CFL 0.4, on the
@@ -457,6 +528,8 @@ def main():
     ap.add_argument("--scalar-sweep", default="",
                     help="comma-separated scalar counts: forward stage against S (e.g. 1,2,4,8)")
     ap.add_argument("--scalar-sweep-n", type=int, default=128)
+    ap.add_argument("--face-path-n", type=int, default=0,
+                    help="open box side (triangles: 8x as many squares per side; 0 to skip)")
     ap.add_argument("--batch-count", type=int, default=512, help="problems in the batch (0 to skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--adjoint-steps", type=int, default=400,
@@ -711,6 +784,9 @@ def main():
 
     if args.scalar_sweep:
         out["scalar_sweep"] = scalar_sweep(args, torch, FL, W, dev)
+
+    if args.face_path_n > 0:
+        out["face_path"] = face_path(args, torch, FL, W, dev)
 
     if args.algebraic:
         out["algebraic"] = algebraic_compare(args, torch, FL, W, dev)

@@ -122,7 +122,7 @@ typedef struct fl_mesh_info_t {
     int32_t max_rated;      /* most leading halo entries of a tile whose rate the forward-rate */
                             /* stage stages (neighbours across backward slots), -1 if none   */
     int32_t max_nexts;      /* most leading halo entries of a tile whose next index it stages */
-    int32_t reserved;
+    int32_t side_entries;   /* general cells: side-list entries (projected faces), else 0   */
     int64_t halo_nexts;     /* those entries summed over the tiles                           */
 } fl_mesh_info_t;
 

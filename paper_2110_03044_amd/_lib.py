@@ -40,7 +40,7 @@ class MeshInfo(ctypes.Structure):
                 ("max_side", ctypes.c_int32), ("aligned", ctypes.c_int32),
                 ("dist_weighted", ctypes.c_int32), ("n_boundary", ctypes.c_int64),
                 ("compact", ctypes.c_int32), ("max_rated", ctypes.c_int32),
-                ("max_nexts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_nexts", ctypes.c_int32), ("side_entries", ctypes.c_int32),
                 ("halo_nexts", ctypes.c_int64)]
 
 

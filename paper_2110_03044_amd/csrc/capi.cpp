@@ -457,7 +457,7 @@ fl_status fl_mesh_info(const fl_mesh *m, fl_mesh_info_t *info) {
     info->compact = m->d_slot_nb || !m->h.slot_nb.empty() ? 1 : 0;
     info->max_rated = m->h.max_nrate0;
     info->max_nexts = m->h.max_nrate;
-    info->reserved = 0;
+    info->side_entries = m->h.general && !m->h.side_ptr.empty() ? m->h.side_ptr.back() : 0;
     int64_t nx = 0;
     for (size_t t = 1; t < m->h.halo_nrate.size(); t += 2) nx += m->h.halo_nrate[t];
     info->halo_nexts = nx;
