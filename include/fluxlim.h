@@ -303,8 +303,9 @@ fl_status fl_adjoint_uacc_scatter(const fl_mesh *mesh, const double *u_acc, doub
 /* Batched problems: n independent (mesh, limiter, S, dt, theta, u_f) problems advanced together
  * with one launch per Runge-Kutta stage for all the fused-path problems (one cell-centric kernel
  * over a work table of (problem, cell tile) entries) and two for all the face-path problems
- * (general cells, boundary faces with the mesh's inflow values, face distances: one launch over
- * their faces, one over their cells; the batch owns their flux buffers).  device >= 0 and every
+ * (general cells, boundary faces with the inflow values the mesh holds when the batch is created,
+ * face distances: one launch over their faces, one over their cells; the batch owns their flux
+ * buffers).  device >= 0 and every
  * mesh created on it (a host-only mesh or device: FL_E_NODEVICE; a mesh on another device:
  * FL_E_INVALID; inflow values set for another scalar count: FL_E_INVALID); meshes may be shared
  * between problems.  theta[i] / u_f[i] are device pointers the batch keeps (not
