@@ -542,8 +542,8 @@ def main():
     ap.add_argument("--limiters", default=",".join(LIM_DEFAULT))
     ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--face-path", action="store_true")
-    ap.add_argument("--xcd-remap", type=int, default=8,
-                    help="FL_OPT_XCD_REMAP: M >= 2 runs of M tiles per XCD (default 8), 0 launch "
+    ap.add_argument("--xcd-remap", type=int, default=32,
+                    help="FL_OPT_XCD_REMAP: M >= 2 runs of M tiles per XCD (default 32), 0 launch "
                          "order, 1 each XCD a contiguous eighth of the cells")
     ap.add_argument("--lds-stage", type=int, default=1,
                     help="0: multi-step calls use the slot records instead of LDS staging")

@@ -382,7 +382,7 @@ fl_status fl_algebraic_rk_steps(const fl_algebraic *alg, int limiter, int scheme
                                 void *hip_stream);
 
 /* Process-wide launch tuning, read by later launches of the single-problem kernels:
- *   FL_OPT_XCD_REMAP  M in 2 .. 65536 (default 8): each XCD takes runs of M consecutive
+ *   FL_OPT_XCD_REMAP  M in 2 .. 65536 (default 32): each XCD takes runs of M consecutive
  *                     256-cell tiles (grid padded to a multiple of 8 M), so the tiles sharing one
  *                     L2 are neighbours; 0: workgroups take cells in launch order (the hardware
  *                     deals consecutive workgroups to the 8 XCDs in turn); 1: the grid is padded

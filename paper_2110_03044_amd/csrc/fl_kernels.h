@@ -14,7 +14,7 @@ enum { MODE_RHS = 0, MODE_EULER = 1, MODE_RK = 2 };
 enum { ADJ_APPLY = 0, ADJ_EULER = 1, ADJ_LAST = 2, ADJ_MID = 3, ADJ_FIRST = 4 };
 
 // 0: launch order; 1: each XCD a contiguous eighth of the tiles; M >= 2: runs of M tiles per XCD
-// (default 8).
+// (default 32).
 void set_xcd_remap(int value);
 
 // Grid of 256-thread workgroups for n cells or faces in the current XCD order: `blocks`

@@ -273,9 +273,9 @@ Grid grid_for(int64_t n, int remap) {
         default: return hipErrorInvalidValue;    \
     }
 
-// Block ids map to cells through dev::block_id: runs of 8 consecutive tiles per XCD by default
+// Block ids map to cells through dev::block_id: runs of 32 consecutive tiles per XCD by default
 // (the tiles sharing one L2 are then neighbours), launch order with FL_OPT_XCD_REMAP = 0.
-int g_remap = 8;
+int g_remap = 32;
 void set_xcd_remap(int value) { g_remap = value; }
 Grid launch_grid(int64_t n) { return grid_for(n, g_remap); }
 int xcd_remap() { return g_remap; }

@@ -40,7 +40,7 @@ OPTIONS = {"xcd_remap": 1, "slot_velocity": 2, "lds_stage": 3, "check_finite": 4
 
 
 def set_option(name: str, value: int) -> None:
-    """Process-wide launch option (fl_set_option): "xcd_remap" (default 8), "slot_velocity"
+    """Process-wide launch option (fl_set_option): "xcd_remap" (default 32), "slot_velocity"
     (default 1: multi-step calls read per-call slot tables with the signed face rates),
     "lds_stage" (default 1: those calls stage each tile's theta and halo in LDS) or
     "check_finite" (default 0: 1 makes the compute calls reject non-finite inputs with
