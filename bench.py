@@ -525,10 +525,10 @@ def main():
                          "timing (profiling runs of the other parts; the line's value is null)")
     ap.add_argument("--deformation", default="",
                     help="comma-separated box sides for the deformation benchmark (e.g. 72,144)")
-    ap.add_argument("--scalar-sweep", default="",
-                    help="comma-separated scalar counts: forward stage against S (e.g. 1,2,4,8)")
+    ap.add_argument("--scalar-sweep", default="1,2,3,4,6,8",
+                    help="comma-separated scalar counts: forward stage against S ('' to skip)")
     ap.add_argument("--scalar-sweep-n", type=int, default=128)
-    ap.add_argument("--face-path-n", type=int, default=0,
+    ap.add_argument("--face-path-n", type=int, default=192,
                     help="open box side (triangles: 8x as many squares per side; 0 to skip)")
     ap.add_argument("--batch-count", type=int, default=512, help="problems in the batch (0 to skip)")
     ap.add_argument("--batch-steps", type=int, default=5)

@@ -29,14 +29,15 @@ def test_traffic_summary_is_used_only_for_its_own_configuration():
     import bench
 
     if not os.path.exists(bench.TRAFFIC_SUMMARY):
-        assert bench.measured_traffic(256, 8, 1, 1) is None
+        assert bench.measured_traffic(256, 32, 1, 1) is None
         return
     with open(bench.TRAFFIC_SUMMARY) as f:
         recorded = re.search(r"kernel_source_sha256: (\w+)", f.read()).group(1)
-    t = bench.measured_traffic(256, 8, 1, 1)
+    t = bench.measured_traffic(256, 32, 1, 1)  # the default: runs of 32 tiles per XCD
     if recorded == bench.kernel_source_hash():
         assert t is not None and 1.0e9 < t < 4.0e9
     else:
         assert t is None
-    for other in ((128, 8, 1, 1), (256, 0, 1, 1), (256, 8, 0, 1), (256, 8, 1, 0), (256, 8, 1, 1, 0)):
+    for other in ((128, 32, 1, 1), (256, 8, 1, 1), (256, 0, 1, 1), (256, 32, 0, 1), (256, 32, 1, 0),
+                  (256, 32, 1, 1, 0)):
         assert bench.measured_traffic(*other) is None
