@@ -104,7 +104,7 @@ __device__ __forceinline__ void adj_stage_fwd(double *lds, int st, int rbase, in
     constexpr int K = 2 * P;
     const int tid = threadIdx.x;
     double *rt = lds + rbase;                   // tile forward rates [P][kTileCells]
-    double *rh = lds + rbase + P * kTileCells;  // one rate per halo entry
+    double *rh = lds + rbase + P * kTileCells;  // one rate per rated halo entry
     const int64_t xc = c0 + (tid < nt ? tid : 0);
     double tv[S], lv[S], ht[kHaloAhead][S], hl[kHaloAhead][S], hr[kHaloAhead];
 #pragma unroll
@@ -141,16 +141,18 @@ __device__ __forceinline__ void adj_stage_fwd(double *lds, int st, int rbase, in
         lds[tid * st + s] = tv[s];
         lds[tid * st + S + s] = lv[s];
     }
+    // (lanes past the halo, or past its rated entries, store nothing: no spare entries)
 #pragma unroll
     for (int j = 0; j < kHaloAhead; ++j) {
         const int i = tid + j * kTileCells;
-        const int e = i < nh ? i : nh;
+        if (i < nh) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            lds[(kTileCells + e) * st + s] = ht[j][s];
-            lds[(kTileCells + e) * st + S + s] = hl[j][s];
+            for (int s = 0; s < S; ++s) {
+                lds[(kTileCells + i) * st + s] = ht[j][s];
+                lds[(kTileCells + i) * st + S + s] = hl[j][s];
+            }
         }
-        rh[e] = hr[j];
+        if (i < nr) rh[i] = hr[j];
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) rt[p * kTileCells + tid] = rfv[p];
@@ -429,18 +431,24 @@ hipError_t launch_fwd3(const fl_mesh *m, const double *rf, const double *th, con
         const Grid g = launch_grid(m->h.nc);
         const int rbase = (int)(lds / sizeof(double));
         if constexpr (S <= 2) {
-            // face-wise form: descriptors after the staged rates; the terms over all of it
+            // face-wise form: the staged values and the rates of the rated halo entries with no
+            // spare entries (a workgroup per CU more on brick tiles), descriptors after them;
+            // the terms over all of it
             const int nr = m->h.max_nrate;
-            const size_t dlds = flds + ((size_t)nr * sizeof(uint32_t) + 7) / 8 * 8;
+            const int per = 2 * S + (m->d_vol ? 1 : 0);  // doubles per staged entry
+            const size_t vlds = (size_t)(kTileCells + m->h.max_halo) * per * sizeof(double);
+            const size_t flds2 = vlds + ((size_t)P * kTileCells + (nr > 0 ? nr : 0)) * sizeof(double);
+            const size_t dlds = flds2 + ((size_t)nr * sizeof(uint32_t) + 7) / 8 * 8;
             const size_t tlds = ((size_t)2 * P * kTileCells + 2 * (size_t)nr) * S * sizeof(double);
             const size_t slds = dlds > tlds ? dlds : tlds;
             if (g_adjoint_share && nr >= 0 && nr <= 2 * kTileCells && slds <= kMaxStageLds) {
-                const int dbase = (int)(flds / sizeof(double));
+                const int sbase = (int)(vlds / sizeof(double));
+                const int dbase = (int)(flds2 / sizeof(double));
 #define FL_AFS(UB, J)                                                                             \
     adev::adjoint_fwd_share_kernel<S, P, LIM, UB, J><<<g.blocks, adev::kBlock, slds, st>>>(       \
         m->h.nc, rf, m->d_halo_ptr, m->d_halo, m->d_halo_pair, m->d_halo_nrate, m->d_slot_local,  \
         m->d_slot_face, m->d_area, m->h.area0, m->d_vol, iv0, th, lam, a, b, a3, dt, mode, lin,   \
-        l3, out, uacc, rbase, dbase, g.remap)
+        l3, out, uacc, sbase, dbase, g.remap)
                 if (nr <= kTileCells) {
                     if (uacc) FL_AFS(true, 1);
                     else FL_AFS(false, 1);
